@@ -59,7 +59,7 @@ def _load():
     lib.oracle_kernel_eval.argtypes = [I, D, P, I64, P]
     lib.oracle_num_threads.restype = I
     lib.oracle_set_num_threads.argtypes = [I]
-    lib.oracle_aca_dense.argtypes = [P, I64, I64, D, I64, P, P, P, P, P]
+    lib.oracle_aca_dense.argtypes = [P, I64, I64, D, I64, P, P, P, P, P, P]
     lib.oracle_aca_dense.restype = I64
     lib.oracle_build.argtypes = [P, I64, I, D, I, D, I, I64, P, D, I, ctypes.POINTER(P)]
     lib.oracle_build.restype = I
@@ -145,8 +145,9 @@ def dense_rows(points, x, rows, kernel="laplace", param: float = 1.0) -> np.ndar
     return out[:, 0] if vec else out
 
 
-def aca_dense(A, tol: float, max_rank: int = 0):
-    """Partially pivoted ACA of an explicit matrix: returns U, V, row pivots, column pivots."""
+def aca_dense(A, tol: float, max_rank: int = 0, return_norm: bool = False):
+    """Partially pivoted ACA of an explicit matrix: returns U, V, row pivots, column pivots
+    (and, with ``return_norm``, the running |S_k|_F^2 estimate at the stop)."""
     A = np.asfortranarray(A, dtype=np.float64)
     m, n = A.shape
     kcap = min(m, n) if max_rank <= 0 else min(m, n, max_rank)
@@ -155,9 +156,11 @@ def aca_dense(A, tol: float, max_rank: int = 0):
     rp = np.zeros(max(kcap, 1), dtype=np.int64)
     cp = np.zeros(max(kcap, 1), dtype=np.int64)
     capped = ctypes.c_int(0)
+    norm2 = ctypes.c_double(0.0)
     k = _load().oracle_aca_dense(_ptr(A), m, n, float(tol), kcap, _ptr(U), _ptr(V), _ptr(rp),
-                                 _ptr(cp), ctypes.byref(capped))
-    return U[:, :k].copy(), V[:, :k].copy(), rp[:k].copy(), cp[:k].copy()
+                                 _ptr(cp), ctypes.byref(capped), ctypes.byref(norm2))
+    out = (U[:, :k].copy(), V[:, :k].copy(), rp[:k].copy(), cp[:k].copy())
+    return out + (norm2.value,) if return_norm else out
 
 
 def relation(a, b) -> str:

@@ -162,12 +162,13 @@ typedef double (*entry_fn)(const void *ctx, int64_t i, int64_t j);
  */
 static int64_t aca_core(entry_fn K, const void *ctx, int64_t m, int64_t n,
                         double tol, int64_t kcap, double *U, double *V,
-                        int64_t *rowpiv, int64_t *colpiv, int *capped)
+                        int64_t *rowpiv, int64_t *colpiv, int *capped, double *norm2)
 {
     int64_t mn = m < n ? m : n;
     if (kcap > mn)
         kcap = mn;
     *capped = 0;
+    *norm2 = 0.0;
     if (kcap <= 0)
         return 0;
     char *used_row = calloc((size_t)m, 1);
@@ -274,6 +275,7 @@ static int64_t aca_core(entry_fn K, const void *ctx, int64_t m, int64_t n,
     free(used_col);
     free(dots_u);
     free(dots_v);
+    *norm2 = S2;
     return k;
 }
 
@@ -289,12 +291,13 @@ static double dense_entry(const void *ctx, int64_t i, int64_t j)
     return c->A[j * c->m + i];
 }
 
+/* norm2 receives the running estimate |S_k|_F^2 at the stop */
 int64_t oracle_aca_dense(const double *A, int64_t m, int64_t n, double tol,
                          int64_t kcap, double *U, double *V, int64_t *rowpiv,
-                         int64_t *colpiv, int *capped)
+                         int64_t *colpiv, int *capped, double *norm2)
 {
     dense_ctx c = {A, m};
-    return aca_core(dense_entry, &c, m, n, tol, kcap, U, V, rowpiv, colpiv, capped);
+    return aca_core(dense_entry, &c, m, n, tol, kcap, U, V, rowpiv, colpiv, capped, norm2);
 }
 
 /* ------------------------------------------------------------------ */
@@ -727,7 +730,8 @@ int oracle_build(const double *pts, int64_t n, int kernel, double kp, int leaf_s
         int64_t *cp = malloc(sizeof(int64_t) * (size_t)kcap);
         block_ctx ctx = {h, box_start(h, l, h->far_t[b]), box_start(h, l, h->far_s[b])};
         int capped = 0;
-        int64_t k = aca_core(block_entry, &ctx, m, nn, tol, kcap, U, V, rp, cp, &capped);
+        double norm2 = 0.0;
+        int64_t k = aca_core(block_entry, &ctx, m, nn, tol, kcap, U, V, rp, cp, &capped, &norm2);
         ncapped += capped;
         h->far_rank[b] = k;
         Ub[b] = U;

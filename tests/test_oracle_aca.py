@@ -124,3 +124,29 @@ def test_rank_growth_by_relation(oracle_mod):
     ranks = f["rank"][lv2]
     assert ranks[cheb == 1].mean() > ranks[cheb >= 2].mean()
     assert ranks[cheb >= 3].mean() <= ranks[cheb == 2].mean()
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_norm_estimate_and_stopping_rule(oracle_mod, seed):
+    # The running estimate equals |U V^T|_F^2 computed directly, which needs
+    # every cross term (u_a.u_b)(v_a.v_b); the stop happens at the first term
+    # with |u_k||v_k| <= tol |S_k|_F.
+    rng = np.random.default_rng(seed)
+    m, n = 60, 45
+    # smooth, numerically low-rank, with strongly non-orthogonal ACA terms
+    a = rng.uniform(0, 1, m)
+    b = rng.uniform(2, 3, n)
+    A = 1.0 / (a[:, None] + b[None, :]) + 0.3
+    tol = 1e-9
+    U, V, rp, cp, norm2 = oracle_mod.aca_dense(A, tol, return_norm=True)
+    k = U.shape[1]
+    assert 2 <= k < min(m, n)
+    S = U @ V.T
+    assert norm2 == pytest.approx(np.linalg.norm(S) ** 2, rel=1e-12)
+    for j in range(1, k + 1):
+        term = np.linalg.norm(U[:, j - 1]) * np.linalg.norm(V[:, j - 1])
+        sj = np.linalg.norm(U[:, :j] @ V[:, :j].T)
+        if j < k:
+            assert term > tol * sj * (1 - 1e-9)
+        else:
+            assert term <= tol * sj * (1 + 1e-9)
