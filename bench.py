@@ -1,0 +1,148 @@
+"""Benchmark: HODLR3D mat-vec throughput on one MI355X.
+
+A step is one full mat-vec y = K~x (gather, near-field tiles, both factor
+streams, scatter) over the resident operator of the workload; the build
+(tree, lists, ACA, packing) happens before the timed region and is reported
+separately.  Prints one JSON line.
+
+The roofline object describes the dominant kernel of the step: its
+algorithmic bytes per launch (factor bytes it streams plus the x/z/y vectors
+it must touch) over its average launch time, taken with HIP events recorded
+by the library on the launch stream during the timed steps.
+
+The cpu_baseline object times the CPU oracle's exact dense direct sum on a
+bounded sample of target rows of the same workload (rows per second), and
+reports the GPU result's relative error on those rows.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "HODLR3D matvec points·RHS/s vs plain FP64 GPU at rel err ≤1e-6; HBM GB/s"
+UNIT = "points·RHS/s"
+HBM_PEAK_GBS = 8000.0
+DTYPE_NAMES = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="uniform262k")
+    ap.add_argument("--factor-dtype", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the mat-vec would shard by target box with one all-gather of x).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2307_16303_amd import hodlr3d, inputs
+
+    w = inputs.WORKLOADS[args.workload]
+    n = w["n"]
+    pts = inputs.workload_points(args.workload)
+    x_np = inputs.workload_rhs(args.workload, None if args.nrhs == 1 else args.nrhs)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    op = hodlr3d.build(torch.as_tensor(pts, device=dev), kernel=w["kernel"],
+                       leaf_size=w["leaf_size"], tol=w["tol"], factor_dtype=args.factor_dtype,
+                       box_lo=inputs.CUBE_LO, box_side=inputs.CUBE_SIDE)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    st = op.stats()
+    print(f"[bench] built {args.workload}: depth {st['depth']}, {st['n_far']} far blocks, "
+          f"{st['factor_bytes'] / 1e9:.2f} GB factors, build {build_s:.1f} s", file=sys.stderr,
+          flush=True)
+    x = torch.as_tensor(x_np, device=dev)
+    for _ in range(args.warmup):
+        y = op.matvec(x)
+    torch.cuda.synchronize()
+    op.profile(True)
+    op.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        y = op.matvec(x)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = op.profile_read()
+    op.profile(False)
+    ms = 1e3 * elapsed / args.steps
+    value = n * args.nrhs / (elapsed / args.steps)
+
+    dom = max(prof, key=lambda p: p["total_ms"])
+    avg_ms = dom["total_ms"] / max(dom["launches"], 1)
+    achieved = dom["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": dom["name"], "avg_launch_ms": round(avg_ms, 4),
+                "bytes_per_launch": dom["bytes_per_launch"]}
+    kernels = {p["name"]: round(p["total_ms"] / max(p["launches"], 1), 4) for p in prof}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        threads = min(16, os.cpu_count() or 1)
+        oracle.set_num_threads(threads)
+        y_np = y.detach().cpu().numpy().reshape(n, -1)
+        xs = x_np.reshape(n, -1)
+        probe = inputs.sample_rows(n, 64, seed=3)
+        t0 = time.perf_counter()
+        oracle.dense_rows(pts, xs, probe, kernel=w["kernel"])
+        per_row = (time.perf_counter() - t0) / probe.size
+        count = int(min(n, max(64, args.cpu_seconds / max(per_row, 1e-9))))
+        rows = inputs.sample_rows(n, count, seed=4)
+        t0 = time.perf_counter()
+        yd = oracle.dense_rows(pts, xs, rows, kernel=w["kernel"])
+        cpu_s = time.perf_counter() - t0
+        err = float(np.linalg.norm(y_np[rows] - yd) / np.linalg.norm(yd))
+        cpu = {"value": round(rows.size * args.nrhs / cpu_s, 1), "unit": UNIT,
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"exact FP64 direct sum for {rows.size} sampled target rows of the "
+                         f"same N={n} workload ({cpu_s:.1f} s)",
+               "gpu_rel_err_on_sample": err}
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": UNIT, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPE_NAMES[args.factor_dtype], "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: N={n} i.i.d. uniform points in [-1,1]^3, "
+                        f"{w['kernel']} kernel, leaf <= {w['leaf_size']}, ACA tol {w['tol']}, "
+                        f"{args.factor_dtype} factors, {args.nrhs} RHS",
+            "n": n, "nrhs": args.nrhs, "depth": st["depth"], "far_blocks": st["n_far"],
+            "factor_bytes": st["factor_bytes"], "rank_max": st["rank_max"],
+            "build_s": round(build_s, 2), "aca_s": round(st["aca_ms"] / 1e3, 2),
+            "kernel_ms": kernels, "parallelism": "single GPU",
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    op.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * hodlr3d.h -- C ABI of the MI355X HODLR3D matrix-vector library (libhodlr3d.so).
+ *
+ * The operator is the kernel matrix of an N-body problem in three dimensions,
+ * K(i,j) = f(|r_i - r_j|) with K(i,i) = 0 (Kandappan, Gujjula, Ambikasaran,
+ * "HODLR3D: Hierarchical matrices for N-body problems in three dimensions",
+ * arXiv 2307.16303, Sec. 3.1, eq. (Laplace3D)), held in the HODLR3D format:
+ * a balanced octree (Sec. 2.1), low-rank factors U V^T for every pair of
+ * same-level boxes in each other's interaction list (Sec. 4, Definition of
+ * HODLR3D admissibility and notation table), compressed by ACA (Sec. 4.1,
+ * eq. (prank), Algorithm 1), and dense near-field leaf blocks evaluated on
+ * the fly (Algorithm 2).
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns an h3d_status; nothing throws across the ABI.
+ *    On failure h3d_last_error() returns a message for the calling thread.
+ *  - "device" pointers are HIP device memory of the current device; "host"
+ *    pointers are ordinary process memory.  The caller owns every pointer it
+ *    passes; the library owns the plan and everything reachable from it.
+ *  - All device work is ordered on the hip_stream argument (a hipStream_t,
+ *    NULL = the legacy default stream).  h3d_build synchronises that stream to
+ *    read sizes back; the mat-vec calls are asynchronous and never synchronise.
+ *  - A plan may be used by one stream at a time.
+ */
+#ifndef HODLR3D_H
+#define HODLR3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define H3D_VERSION 1
+#define H3D_MAX_LEVELS 11 /* levels 0..10 */
+
+typedef struct h3d_plan h3d_plan;
+
+typedef enum {
+    H3D_OK = 0,
+    H3D_EINVAL = 1,    /* bad argument (checked before any device work where possible) */
+    H3D_ENOMEM = 2,    /* device or host allocation failed */
+    H3D_EDEVICE = 3,   /* a HIP call failed */
+    H3D_ENOTBUILT = 4, /* plan is NULL or was not built */
+    H3D_EDEPTH = 5,    /* no depth <= max_depth gives leaves of at most leaf_size points */
+    H3D_ENOTIMPL = 6   /* combination not provided by this build */
+} h3d_status;
+
+/* f(r); K(i,i) = 0 and f(0) := 0 for distinct coincident points. */
+typedef enum {
+    H3D_LAPLACE = 0, /* 1/(4 pi r): Green's function of the 3D Laplace equation */
+    H3D_YUKAWA = 1,  /* exp(-kappa r)/r, kappa = kernel_param */
+    H3D_INV_R4 = 2,  /* 1/r^4 (Sec. 5.1) */
+    H3D_COS_R = 3    /* cos(kappa r)/r, kappa = kernel_param (Sec. 5.1 uses kappa = 1) */
+} h3d_kernel;
+
+/* Storage type of the low-rank factors.  ACA always runs in FP64. */
+typedef enum {
+    H3D_F64 = 0,
+    H3D_F32 = 1,
+    H3D_BF16_SCALED = 2 /* bfloat16 with one FP32 scale per factor of each block */
+} h3d_dtype;
+
+/* Optional device allocator (e.g. a framework's caching allocator).  alloc
+ * returns NULL on failure; both are called on the build/mat-vec stream. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *hip_stream, void *ctx);
+    void (*free)(void *ptr, size_t bytes, void *hip_stream, void *ctx);
+    void *ctx;
+} h3d_allocator;
+
+enum {
+    H3D_FLAG_KEEP_PIVOTS = 1 /* keep ACA pivots for h3d_export(H3D_EXPORT_PIVOTS) */
+};
+
+typedef struct {
+    int32_t kernel;        /* h3d_kernel */
+    double kernel_param;   /* kappa for H3D_YUKAWA / H3D_COS_R */
+    int32_t leaf_size;     /* N_max: a leaf holds at most this many points (>= 1) */
+    double tol;            /* ACA tolerance eps, 0 < tol < 1 */
+    int32_t factor_dtype;  /* h3d_dtype */
+    int32_t max_rank;      /* rank cap per block; <= 0 means min(m, n) */
+    int32_t max_depth;     /* deepest octree level allowed, 0..10 */
+    double box_lo[3];      /* lower corner of the cube B ... */
+    double box_side;       /* ... and its side; <= 0 selects the smallest enclosing cube */
+    int64_t workspace_bytes; /* FP64 ACA workspace budget; <= 0 selects 4 GiB */
+    int32_t flags;         /* H3D_FLAG_* */
+} h3d_config;
+
+typedef struct {
+    int64_t n;
+    int32_t depth;        /* L */
+    int32_t factor_dtype;
+    double box_lo[3];
+    double box_side;
+    int64_t n_far;                            /* admissible (V and W) blocks */
+    int64_t n_near;                           /* ordered leaf pairs: self, E, F */
+    int64_t far_per_level[H3D_MAX_LEVELS];
+    int64_t rank_sum;                         /* = number of factor columns */
+    int32_t rank_max;
+    int64_t n_rank_capped;                    /* blocks stopped by max_rank */
+    int64_t factor_entries;                   /* sum over blocks of (m + n) k */
+    int64_t factor_bytes;                     /* stored bytes of U and V (+ scales) */
+    int64_t factor_bytes_per_level[H3D_MAX_LEVELS];
+    int64_t near_pair_evals;                  /* sum over near leaf pairs of m n */
+    int64_t device_bytes;                     /* all device memory held by the plan */
+    double build_ms;                          /* wall time of h3d_build */
+    double aca_ms;                            /* part of it spent in ACA kernels */
+} h3d_stats;
+
+/* Fills *cfg with defaults: Laplace, leaf_size 64, tol 1e-8, FP64 factors, no
+ * rank cap, max_depth 10, smallest enclosing cube, 4 GiB workspace. */
+void h3d_config_init(h3d_config *cfg);
+
+/*
+ * Builds the HODLR3D representation of K on n points.
+ *   points : device, n x 3 FP64, row-major (x, y, z per point); read only
+ *            during the call, not retained.
+ *   cfg    : host; validated before any device work.
+ *   alloc  : host, may be NULL (then hipMalloc/hipFree are used).
+ *   out    : receives the plan; NULL on any failure (nothing leaks).
+ * Errors: H3D_EINVAL for n < 1, leaf_size < 1, tol outside (0,1), max_depth
+ * outside 0..10, a bad dtype/kernel, non-finite coordinates or points outside
+ * a given box; H3D_EDEPTH when max_depth levels cannot separate the points;
+ * H3D_ENOMEM / H3D_EDEVICE from the device.
+ */
+h3d_status h3d_build(const double *points, int64_t n, const h3d_config *cfg,
+                     const h3d_allocator *alloc, void *hip_stream, h3d_plan **out);
+
+/*
+ * y = K~ x (Algorithm 2): near-field leaf blocks plus the low-rank blocks of
+ * every level.  x, y: device, n x nrhs column-major with leading dimensions
+ * ldx, ldy >= n, in the caller's original point order; y is overwritten.
+ * io_dtype is H3D_F64 or H3D_F32 (x and y share it).  x and y must not
+ * overlap.  Deterministic: the same plan, input and nrhs give bitwise the same
+ * output.
+ */
+h3d_status h3d_matvec(h3d_plan *plan, const void *x, void *y, int64_t nrhs, int64_t ldx,
+                      int64_t ldy, int32_t io_dtype, void *hip_stream);
+
+/* y = K~^T x with the same stored blocks: far blocks apply V (U^T x_t) to the
+ * source box, near blocks are applied transposed.  Arguments as h3d_matvec. */
+h3d_status h3d_matvec_adjoint(h3d_plan *plan, const void *x, void *y, int64_t nrhs,
+                              int64_t ldx, int64_t ldy, int32_t io_dtype, void *hip_stream);
+
+h3d_status h3d_get_stats(const h3d_plan *plan, h3d_stats *out);
+
+/* What h3d_export copies to host memory. */
+typedef enum {
+    H3D_EXPORT_PERM = 0,      /* int64[n]: sorted position -> original index */
+    H3D_EXPORT_LEAF_OFF = 1,  /* int64[8^L + 1]: first sorted position of each leaf */
+    H3D_EXPORT_FAR = 2,       /* int64[6][n_far]: level, t, s, m, n, rank */
+    H3D_EXPORT_NEAR = 3,      /* int64[3][n_near]: t, s, relation (0 self, 1 F, 2 E) */
+    H3D_EXPORT_FACTORS_U = 4, /* double[sum m k]: U_b (m x k, column-major), block order */
+    H3D_EXPORT_FACTORS_V = 5, /* double[sum n k]: V_b (n x k, column-major), block order */
+    H3D_EXPORT_PIVOTS = 6     /* int64[2][sum k]: row then column pivots (box-local) */
+} h3d_export_what;
+
+/* Copies one structure to host_buf.  With host_buf == NULL only *bytes is set
+ * to the size needed; otherwise *bytes must hold the buffer size on entry and
+ * receives the bytes written.  Factors are returned in FP64 (scales applied). */
+h3d_status h3d_export(const h3d_plan *plan, int32_t what, void *host_buf, size_t *bytes);
+
+/* Releases the plan (NULL is accepted). */
+h3d_status h3d_destroy(h3d_plan *plan);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *h3d_last_error(void);
+
+/*
+ * Per-kernel timing of the mat-vec calls.  With profiling on, every kernel
+ * launch of h3d_matvec / h3d_matvec_adjoint is bracketed by HIP events on the
+ * stream it runs on.  h3d_profile_read synchronises those events and returns,
+ * per kernel name, the launch count, the summed event time and the
+ * algorithmic bytes and flops of one launch (the last one recorded).
+ */
+typedef struct {
+    char name[48];
+    int64_t launches;
+    double total_ms;
+    double bytes_per_launch;
+    double flops_per_launch;
+} h3d_kernel_profile;
+
+h3d_status h3d_profile_enable(h3d_plan *plan, int32_t enable);
+h3d_status h3d_profile_read(h3d_plan *plan, h3d_kernel_profile *out, int32_t capacity,
+                            int32_t *count);
+h3d_status h3d_profile_reset(h3d_plan *plan);
+
+int32_t h3d_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HODLR3D_H */

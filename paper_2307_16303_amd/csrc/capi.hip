@@ -1,0 +1,367 @@
+// C ABI of libhodlr3d (declared in include/hodlr3d.h): argument validation,
+// plan lifecycle, statistics, export and profiling.  No exception crosses the
+// ABI; failures return an h3d_status and leave a message for h3d_last_error.
+#include <chrono>
+#include <cmath>
+#include <new>
+
+#include "h3d_internal.hpp"
+
+struct h3d_plan {
+    h3d::Plan P;
+};
+
+namespace h3d {
+void near_pair_count(Plan &P, hipStream_t s);
+}
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <class F> h3d_status guarded(F &&f) {
+    try {
+        f();
+        return H3D_OK;
+    } catch (const h3d::Error &e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return H3D_ENOMEM;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return H3D_EDEVICE;
+    } catch (...) {
+        g_last_error = "unknown failure";
+        return H3D_EDEVICE;
+    }
+}
+
+h3d_status invalid(const std::string &m) {
+    g_last_error = m;
+    return H3D_EINVAL;
+}
+
+// Runs f with the plan's device current, restoring the caller's device.
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev)
+            H3D_HIP(hipSetDevice(dev));
+        else
+            prev = -1;
+    }
+    ~DeviceScope() {
+        if (prev >= 0)
+            (void)hipSetDevice(prev);
+    }
+};
+
+size_t io_size(int32_t dt) { return dt == H3D_F32 ? 4 : 8; }
+
+h3d_status matvec_common(h3d_plan *plan, const void *x, void *y, int64_t nrhs, int64_t ldx,
+                         int64_t ldy, int32_t io, void *stream, bool adjoint) {
+    if (!plan || !plan->P.built)
+        return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    h3d::Plan &P = plan->P;
+    if (!x || !y)
+        return invalid("x and y must be device pointers");
+    if (nrhs < 1)
+        return invalid("nrhs must be >= 1");
+    if (ldx < P.n || ldy < P.n)
+        return invalid("leading dimensions must be >= n");
+    if (io != H3D_F64 && io != H3D_F32)
+        return invalid("io_dtype must be H3D_F64 or H3D_F32");
+    const size_t es = io_size(io);
+    const uintptr_t xa = uintptr_t(x), xb = xa + size_t((nrhs - 1) * ldx + P.n) * es;
+    const uintptr_t ya = uintptr_t(y), yb = ya + size_t((nrhs - 1) * ldy + P.n) * es;
+    if (xa < yb && ya < xb)
+        return invalid("x and y overlap");
+    return guarded([&] {
+        DeviceScope ds(P.device);
+        h3d::matvec_run(P, x, y, nrhs, ldx, ldy, io, adjoint, static_cast<hipStream_t>(stream));
+    });
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t h3d_version(void) { return H3D_VERSION; }
+
+const char *h3d_last_error(void) { return g_last_error.c_str(); }
+
+void h3d_config_init(h3d_config *cfg) {
+    if (!cfg)
+        return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->kernel = H3D_LAPLACE;
+    cfg->kernel_param = 1.0;
+    cfg->leaf_size = 64;
+    cfg->tol = 1e-8;
+    cfg->factor_dtype = H3D_F64;
+    cfg->max_rank = 0;
+    cfg->max_depth = 10;
+    cfg->box_side = 0.0;
+    cfg->workspace_bytes = 0;
+    cfg->flags = 0;
+}
+
+h3d_status h3d_build(const double *points, int64_t n, const h3d_config *cfg,
+                     const h3d_allocator *alloc, void *hip_stream, h3d_plan **out) {
+    if (!out)
+        return invalid("out must not be NULL");
+    *out = nullptr;
+    if (!cfg)
+        return invalid("cfg must not be NULL");
+    if (!points)
+        return invalid("points must not be NULL");
+    if (n < 1 || n > int64_t(0x7fffffff) - 1)
+        return invalid("n must be in [1, 2^31 - 2]");
+    if (cfg->kernel < H3D_LAPLACE || cfg->kernel > H3D_COS_R)
+        return invalid("unknown kernel");
+    if (!std::isfinite(cfg->kernel_param))
+        return invalid("kernel_param must be finite");
+    if (cfg->leaf_size < 1)
+        return invalid("leaf_size must be >= 1");
+    if (!(cfg->tol > 0.0 && cfg->tol < 1.0))
+        return invalid("tol must lie in (0, 1)");
+    if (cfg->factor_dtype < H3D_F64 || cfg->factor_dtype > H3D_BF16_SCALED)
+        return invalid("unknown factor_dtype");
+    if (cfg->max_depth < 0 || cfg->max_depth > h3d::kMaxDepth)
+        return invalid("max_depth must lie in [0, 10]");
+    if (!std::isfinite(cfg->box_side))
+        return invalid("box_side must be finite");
+    if (cfg->box_side > 0.0)
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(cfg->box_lo[a]))
+                return invalid("box_lo must be finite");
+    if (alloc && ((alloc->alloc == nullptr) != (alloc->free == nullptr)))
+        return invalid("allocator needs both alloc and free");
+
+    h3d_plan *plan = nullptr;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    h3d_status st = guarded([&] {
+        const auto t0 = std::chrono::steady_clock::now();
+        plan = new h3d_plan();
+        h3d::Plan &P = plan->P;
+        P.cfg = *cfg;
+        H3D_HIP(hipGetDevice(&P.device));
+        P.mem.configure(alloc, s);
+        P.n = n;
+        h3d::tree_build(P, points, s);
+        h3d::lists_build(P, s);
+        h3d::factors_build(P, s);
+        h3d::near_pair_count(P, s);
+        H3D_HIP(hipStreamSynchronize(s));
+        h3d_stats &S = P.stats;
+        S.n = n;
+        S.depth = P.L;
+        S.factor_dtype = P.factor_dtype;
+        for (int a = 0; a < 3; ++a)
+            S.box_lo[a] = P.lo[a];
+        S.box_side = P.side;
+        S.n_far = P.nfar;
+        S.n_near = P.nnear;
+        for (int l = 0; l < H3D_MAX_LEVELS; ++l)
+            S.far_per_level[l] = (l >= 1 && l <= P.L) ? P.lvl_blk[l + 1] - P.lvl_blk[l] : 0;
+        S.device_bytes = int64_t(P.mem.total());
+        S.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        P.built = true;
+    });
+    if (st != H3D_OK) {
+        (void)hipStreamSynchronize(s);
+        (void)hipGetLastError();
+        delete plan;
+        return st;
+    }
+    *out = plan;
+    return H3D_OK;
+}
+
+h3d_status h3d_matvec(h3d_plan *plan, const void *x, void *y, int64_t nrhs, int64_t ldx,
+                      int64_t ldy, int32_t io_dtype, void *hip_stream) {
+    return matvec_common(plan, x, y, nrhs, ldx, ldy, io_dtype, hip_stream, false);
+}
+
+h3d_status h3d_matvec_adjoint(h3d_plan *plan, const void *x, void *y, int64_t nrhs, int64_t ldx,
+                              int64_t ldy, int32_t io_dtype, void *hip_stream) {
+    return matvec_common(plan, x, y, nrhs, ldx, ldy, io_dtype, hip_stream, true);
+}
+
+h3d_status h3d_get_stats(const h3d_plan *plan, h3d_stats *out) {
+    if (!plan || !plan->P.built)
+        return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    if (!out)
+        return invalid("out must not be NULL");
+    *out = plan->P.stats;
+    out->device_bytes = int64_t(plan->P.mem.total());
+    return H3D_OK;
+}
+
+h3d_status h3d_export(const h3d_plan *plan, int32_t what, void *host_buf, size_t *bytes) {
+    if (!plan || !plan->P.built)
+        return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    if (!bytes)
+        return invalid("bytes must not be NULL");
+    h3d::Plan &P = const_cast<h3d::Plan &>(plan->P);
+    const int64_t nf = P.nfar;
+    size_t need = 0;
+    switch (what) {
+    case H3D_EXPORT_PERM:
+        need = size_t(P.n) * 8;
+        break;
+    case H3D_EXPORT_LEAF_OFF:
+        need = P.h_leaf_off.size() * 8;
+        break;
+    case H3D_EXPORT_FAR:
+        need = size_t(nf) * 6 * 8;
+        break;
+    case H3D_EXPORT_NEAR:
+        need = size_t(P.nnear) * 3 * 8;
+        break;
+    case H3D_EXPORT_FACTORS_U:
+    case H3D_EXPORT_FACTORS_V: {
+        const int64_t ev = P.entries_v;
+        need = size_t(what == H3D_EXPORT_FACTORS_V ? ev : P.stats.factor_entries - ev) * 8;
+        break;
+    }
+    case H3D_EXPORT_PIVOTS:
+        if (!P.blk_piv)
+            return invalid("pivots were not kept (build with H3D_FLAG_KEEP_PIVOTS)");
+        need = size_t(P.ncols) * 2 * 8;
+        break;
+    default:
+        return invalid("unknown export id");
+    }
+    if (!host_buf) {
+        *bytes = need;
+        return H3D_OK;
+    }
+    if (*bytes < need)
+        return invalid("host buffer too small");
+    int64_t *o = static_cast<int64_t *>(host_buf);
+    return guarded([&] {
+        DeviceScope ds(P.device);
+        hipStream_t s = nullptr;
+        H3D_HIP(hipDeviceSynchronize());
+        switch (what) {
+        case H3D_EXPORT_PERM: {
+            std::vector<int32_t> v(static_cast<size_t>(P.n));
+            h3d::to_host(v.data(), P.perm, P.n, s);
+            for (int64_t i = 0; i < P.n; ++i)
+                o[i] = v[size_t(i)];
+            break;
+        }
+        case H3D_EXPORT_LEAF_OFF:
+            for (size_t i = 0; i < P.h_leaf_off.size(); ++i)
+                o[i] = P.h_leaf_off[i];
+            break;
+        case H3D_EXPORT_FAR: {
+            std::vector<int32_t> v(static_cast<size_t>(nf));
+            int l = 1;
+            for (int64_t b = 0; b < nf; ++b) {
+                while (b >= P.lvl_blk[l + 1])
+                    ++l;
+                o[b] = l;
+            }
+            const int32_t *cols[5] = {P.blk_t, P.blk_s, P.blk_m, P.blk_n, P.blk_rank};
+            for (int c = 0; c < 5; ++c) {
+                h3d::to_host(v.data(), cols[c], nf, s);
+                for (int64_t b = 0; b < nf; ++b)
+                    o[(c + 1) * nf + b] = v[size_t(b)];
+            }
+            break;
+        }
+        case H3D_EXPORT_NEAR: {
+            const int64_t nn = P.nnear, nleaf = h3d::pow8(P.L);
+            std::vector<int32_t> ptr(static_cast<size_t>(nleaf) + 1);
+            std::vector<int32_t> sv(static_cast<size_t>(nn));
+            std::vector<int8_t> rv(static_cast<size_t>(nn));
+            h3d::to_host(ptr.data(), P.near_ptr, nleaf + 1, s);
+            h3d::to_host(sv.data(), P.near_s, nn, s);
+            h3d::to_host(rv.data(), P.near_rel, nn, s);
+            for (int64_t t = 0; t < nleaf; ++t)
+                for (int32_t e = ptr[size_t(t)]; e < ptr[size_t(t) + 1]; ++e) {
+                    o[e] = t;
+                    o[nn + e] = sv[size_t(e)];
+                    o[2 * nn + e] = rv[size_t(e)];
+                }
+            break;
+        }
+        case H3D_EXPORT_FACTORS_U:
+        case H3D_EXPORT_FACTORS_V:
+            h3d::export_factors(P, what == H3D_EXPORT_FACTORS_U ? 0 : 1,
+                                static_cast<double *>(host_buf));
+            break;
+        case H3D_EXPORT_PIVOTS: {
+            std::vector<int32_t> rank(static_cast<size_t>(nf));
+            std::vector<int64_t> off(size_t(nf) + 1);
+            h3d::to_host(rank.data(), P.blk_rank, nf, s);
+            h3d::to_host(off.data(), P.blk_pivoff, nf + 1, s);
+            std::vector<int32_t> piv(static_cast<size_t>(off[size_t(nf)]));
+            h3d::to_host(piv.data(), P.blk_piv, off[size_t(nf)], s);
+            int64_t c = 0;
+            for (int64_t b = 0; b < nf; ++b)
+                for (int k = 0; k < rank[size_t(b)]; ++k, ++c) {
+                    o[c] = piv[size_t(off[size_t(b)] + 2 * k)];
+                    o[P.ncols + c] = piv[size_t(off[size_t(b)] + 2 * k + 1)];
+                }
+            break;
+        }
+        }
+        *bytes = need;
+    });
+}
+
+h3d_status h3d_destroy(h3d_plan *plan) {
+    if (!plan)
+        return H3D_OK;
+    return guarded([&] {
+        {
+            DeviceScope ds(plan->P.device);
+            (void)hipDeviceSynchronize();
+        }
+        delete plan;
+    });
+}
+
+h3d_status h3d_profile_enable(h3d_plan *plan, int32_t enable) {
+    if (!plan || !plan->P.built)
+        return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    return guarded([&] {
+        plan->P.prof.collect();
+        plan->P.prof.on = enable != 0;
+    });
+}
+
+h3d_status h3d_profile_reset(h3d_plan *plan) {
+    if (!plan || !plan->P.built)
+        return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    return guarded([&] { plan->P.prof.reset(); });
+}
+
+h3d_status h3d_profile_read(h3d_plan *plan, h3d_kernel_profile *out, int32_t capacity,
+                            int32_t *count) {
+    if (!plan || !plan->P.built)
+        return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    if (!count || (capacity > 0 && !out))
+        return invalid("count (and out when capacity > 0) must not be NULL");
+    return guarded([&] {
+        h3d::Profiler &pr = plan->P.prof;
+        pr.collect();
+        const int32_t nk = int32_t(pr.names.size());
+        *count = nk;
+        for (int32_t i = 0; i < nk && i < capacity; ++i) {
+            std::memset(out[i].name, 0, sizeof(out[i].name));
+            std::strncpy(out[i].name, pr.names[size_t(i)].c_str(), sizeof(out[i].name) - 1);
+            out[i].launches = pr.launches[size_t(i)];
+            out[i].total_ms = pr.total_ms[size_t(i)];
+            out[i].bytes_per_launch = pr.bytes[size_t(i)];
+            out[i].flops_per_launch = pr.flops[size_t(i)];
+        }
+    });
+}
+
+}  // extern "C"

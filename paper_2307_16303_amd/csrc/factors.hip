@@ -1,0 +1,403 @@
+// Factor construction: ACA in bounded FP64 workspace batches, then packing of
+// each batch into the stored dtype (FP64, FP32, or BF16 with one FP32 scale per
+// factor), and the column tables the mat-vec kernels stream by.
+//
+// Storage: a chunk per batch holds U_b (m x k, column-major) of its blocks in
+// block order, then V_b (n x k).  Blocks of one target box are consecutive, so
+// the columns of all U_b of a box form one m x (sum k) matrix whenever they
+// land in the same chunk; every kernel nevertheless addresses factors through
+// the per-block pointers, so a box may straddle chunks.
+#include "h3d_internal.hpp"
+
+namespace h3d {
+
+void aca_level_batch(Plan &P, int level, int64_t b0, int64_t b1, double *ws, const int64_t *ws_off,
+                     int64_t ws_base, unsigned int *ncapped, hipStream_t s);
+void aca_workspace_sizes(Plan &P, int64_t *ws, int64_t *kc2, hipStream_t s);
+
+namespace {
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u)
+        return uint16_t((u >> 16) | 0x40u);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);           // round to nearest even
+    return uint16_t(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__global__ void k_pack_sizes(int64_t b0, int64_t b1, const int32_t *__restrict__ m,
+                             const int32_t *__restrict__ n, const int32_t *__restrict__ rank,
+                             int64_t *__restrict__ mk, int64_t *__restrict__ nk) {
+    int64_t b = b0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= b1)
+        return;
+    mk[b - b0] = int64_t(m[b]) * rank[b];
+    nk[b - b0] = int64_t(n[b]) * rank[b];
+}
+
+template <int DT>
+__global__ void __launch_bounds__(256)
+    k_pack(int64_t b0, int64_t b1, const int32_t *__restrict__ m, const int32_t *__restrict__ n,
+           const int32_t *__restrict__ rank, int max_rank, const double *__restrict__ ws,
+           const int64_t *__restrict__ ws_off, int64_t ws_base, const int64_t *__restrict__ uoff,
+           const int64_t *__restrict__ voff, char *cu, char *cv, void **uptr, void **vptr,
+           float *scale2) {
+    const int64_t b = b0 + ((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (b >= b1)
+        return;
+    const int mb = m[b], nb = n[b], k = rank[b];
+    int kcap = mb < nb ? mb : nb;
+    if (max_rank > 0 && max_rank < kcap)
+        kcap = max_rank;
+    const double *U = ws + (ws_off[b] - ws_base);
+    const double *V = U + int64_t(mb) * kcap;
+    const int64_t nu = int64_t(mb) * k, nv = int64_t(nb) * k;
+    const int64_t ou = uoff[b - b0], ov = voff[b - b0];
+    if (DT == H3D_F64) {
+        double *du = reinterpret_cast<double *>(cu) + ou;
+        double *dv = reinterpret_cast<double *>(cv) + ov;
+        for (int64_t e = lane; e < nu; e += 64)
+            du[e] = U[e];
+        for (int64_t e = lane; e < nv; e += 64)
+            dv[e] = V[e];
+        if (lane == 0) {
+            uptr[b] = du;
+            vptr[b] = dv;
+        }
+    } else if (DT == H3D_F32) {
+        float *du = reinterpret_cast<float *>(cu) + ou;
+        float *dv = reinterpret_cast<float *>(cv) + ov;
+        for (int64_t e = lane; e < nu; e += 64)
+            du[e] = float(U[e]);
+        for (int64_t e = lane; e < nv; e += 64)
+            dv[e] = float(V[e]);
+        if (lane == 0) {
+            uptr[b] = du;
+            vptr[b] = dv;
+        }
+    } else {
+        uint16_t *du = reinterpret_cast<uint16_t *>(cu) + ou;
+        uint16_t *dv = reinterpret_cast<uint16_t *>(cv) + ov;
+        double su = 0.0, sv = 0.0;
+        for (int64_t e = lane; e < nu; e += 64)
+            su = fmax(su, fabs(U[e]));
+        for (int64_t e = lane; e < nv; e += 64)
+            sv = fmax(sv, fabs(V[e]));
+        su = wave_max(su);
+        sv = wave_max(sv);
+        // the scales are powers of two, so dividing by them is exact
+        su = su > 0.0 ? exp2(ceil(log2(su))) : 1.0;
+        sv = sv > 0.0 ? exp2(ceil(log2(sv))) : 1.0;
+        for (int64_t e = lane; e < nu; e += 64)
+            du[e] = f32_to_bf16(float(U[e] / su));
+        for (int64_t e = lane; e < nv; e += 64)
+            dv[e] = f32_to_bf16(float(V[e] / sv));
+        if (lane == 0) {
+            uptr[b] = du;
+            vptr[b] = dv;
+            scale2[2 * b] = float(su);
+            scale2[2 * b + 1] = float(sv);
+        }
+    }
+}
+
+__global__ void k_len_rank(int64_t nfar, const int32_t *__restrict__ len,
+                           const int32_t *__restrict__ rank, int64_t *__restrict__ out) {
+    int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b < nfar)
+        out[b] = int64_t(len[b]) * rank[b];
+}
+
+__global__ void k_rank_i64(int64_t nfar, const int32_t *__restrict__ rank, int64_t *__restrict__ out) {
+    int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b < nfar)
+        out[b] = rank[b];
+    if (b == nfar)
+        out[b] = 0;
+}
+
+__global__ void k_col_blk(int64_t nfar, const int32_t *__restrict__ rank,
+                          const int64_t *__restrict__ col0, int32_t *__restrict__ col_blk) {
+    int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= nfar)
+        return;
+    const int64_t c0 = col0[b];
+    for (int c = 0; c < rank[b]; ++c)
+        col_blk[c0 + c] = int32_t(b);
+}
+
+// per-level sums of (m + n) k and of k, and the rank maximum
+__global__ void k_level_sums(int64_t b0, int64_t b1, const int32_t *__restrict__ m,
+                             const int32_t *__restrict__ n, const int32_t *__restrict__ rank,
+                             unsigned long long *__restrict__ out) {
+    __shared__ unsigned long long sh[3][256];
+    __shared__ unsigned int shm[256];
+    unsigned long long e = 0, kk = 0, ev = 0;
+    unsigned int mx = 0;
+    for (int64_t b = b0 + int64_t(blockIdx.x) * 256 + threadIdx.x; b < b1;
+         b += int64_t(gridDim.x) * 256) {
+        e += (unsigned long long)(m[b] + n[b]) * (unsigned long long)rank[b];
+        kk += (unsigned long long)rank[b];
+        ev += (unsigned long long)n[b] * (unsigned long long)rank[b];
+        mx = max(mx, (unsigned int)rank[b]);
+    }
+    sh[0][threadIdx.x] = e;
+    sh[1][threadIdx.x] = kk;
+    sh[2][threadIdx.x] = ev;
+    shm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + off];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + off];
+            sh[2][threadIdx.x] += sh[2][threadIdx.x + off];
+            shm[threadIdx.x] = max(shm[threadIdx.x], shm[threadIdx.x + off]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd(&out[0], sh[0][0]);
+        atomicAdd(&out[1], sh[1][0]);
+        atomicMax(reinterpret_cast<unsigned int *>(&out[2]), shm[0]);
+        atomicAdd(&out[3], sh[2][0]);
+    }
+}
+
+template <int DT>
+__global__ void __launch_bounds__(256)
+    k_export(int64_t nfar, int which, const int32_t *__restrict__ len, const int32_t *__restrict__ rank,
+             void *const *__restrict__ ptr, const float *__restrict__ scale2,
+             const int64_t *__restrict__ off, double *__restrict__ out) {
+    const int64_t b = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (b >= nfar)
+        return;
+    const int64_t cnt = int64_t(len[b]) * rank[b];
+    double *o = out + off[b];
+    if (DT == H3D_F64) {
+        const double *p = reinterpret_cast<const double *>(ptr[b]);
+        for (int64_t e = lane; e < cnt; e += 64)
+            o[e] = p[e];
+    } else if (DT == H3D_F32) {
+        const float *p = reinterpret_cast<const float *>(ptr[b]);
+        for (int64_t e = lane; e < cnt; e += 64)
+            o[e] = double(p[e]);
+    } else {
+        const uint16_t *p = reinterpret_cast<const uint16_t *>(ptr[b]);
+        const double sc = double(scale2[2 * b + which]);
+        for (int64_t e = lane; e < cnt; e += 64)
+            o[e] = double(bf16_to_f32(p[e])) * sc;
+    }
+}
+
+size_t dtype_size(int dt) { return dt == H3D_F64 ? 8 : (dt == H3D_F32 ? 4 : 2); }
+
+}  // namespace
+
+void factors_build(Plan &P, hipStream_t s) {
+    const int64_t nf = P.nfar;
+    const int dt = P.cfg.factor_dtype;
+    P.factor_dtype = dt;
+    P.blk_rank = P.mem.alloc_n<int32_t>(nf);
+    P.blk_uptr = P.mem.alloc_n<void *>(nf);
+    P.blk_vptr = P.mem.alloc_n<void *>(nf);
+    P.blk_col0 = P.mem.alloc_n<int64_t>(nf + 1);
+    if (dt == H3D_BF16_SCALED)
+        P.blk_scale = P.mem.alloc_n<float>(2 * nf);
+    if (nf == 0) {
+        P.ncols = 0;
+        P.col_blk = P.mem.alloc_n<int32_t>(1);
+        H3D_HIP(hipMemsetAsync(P.blk_col0, 0, sizeof(int64_t), s));
+        return;
+    }
+    H3D_HIP(hipMemsetAsync(P.blk_rank, 0, sizeof(int32_t) * size_t(nf), s));
+
+    // workspace sizes and batches
+    int64_t *ws_off = P.mem.alloc_n<int64_t>(nf + 1);
+    int64_t *kc2 = nullptr;
+    const bool keep_piv = (P.cfg.flags & H3D_FLAG_KEEP_PIVOTS) != 0;
+    if (keep_piv)
+        kc2 = P.mem.alloc_n<int64_t>(nf + 1);
+    H3D_HIP(hipMemsetAsync(ws_off + nf, 0, sizeof(int64_t), s));
+    if (kc2)
+        H3D_HIP(hipMemsetAsync(kc2 + nf, 0, sizeof(int64_t), s));
+    aca_workspace_sizes(P, ws_off, kc2, s);
+    const int64_t ws_total = scan_exclusive_i64(P, ws_off, ws_off, nf + 1, s);
+    if (keep_piv) {
+        int64_t tot = scan_exclusive_i64(P, kc2, kc2, nf + 1, s);
+        P.blk_pivoff = kc2;
+        P.blk_piv = P.mem.alloc_n<int32_t>(tot);
+    }
+    std::vector<int64_t> h_ws(size_t(nf) + 1);
+    to_host(h_ws.data(), ws_off, nf + 1, s);
+    int64_t budget = (P.cfg.workspace_bytes > 0 ? P.cfg.workspace_bytes : (int64_t(4) << 30)) / 8;
+    int64_t largest = 0;
+    for (int64_t b = 0; b < nf; ++b)
+        largest = std::max(largest, h_ws[size_t(b) + 1] - h_ws[size_t(b)]);
+    budget = std::max(budget, largest);
+    budget = std::min(budget, ws_total);
+    double *ws = P.mem.alloc_n<double>(budget);
+    unsigned int *ncapped = P.mem.alloc_n<unsigned int>(1);
+    H3D_HIP(hipMemsetAsync(ncapped, 0, sizeof(unsigned int), s));
+    int64_t *mk = P.mem.alloc_n<int64_t>(nf + 1);
+    int64_t *nk = P.mem.alloc_n<int64_t>(nf + 1);
+    const size_t es = dtype_size(dt);
+
+    hipEvent_t ev0, ev1;
+    H3D_HIP(hipEventCreate(&ev0));
+    H3D_HIP(hipEventCreate(&ev1));
+    double aca_ms = 0.0;
+
+    int64_t b0 = 0;
+    while (b0 < nf) {
+        int64_t b1 = b0 + 1;
+        while (b1 < nf && h_ws[size_t(b1) + 1] - h_ws[size_t(b0)] <= budget)
+            ++b1;
+        const int64_t base = h_ws[size_t(b0)];
+        H3D_HIP(hipEventRecord(ev0, s));
+        for (int l = 1; l <= P.L; ++l) {
+            const int64_t lb = std::max(b0, P.lvl_blk[l]);
+            const int64_t le = std::min(b1, P.lvl_blk[l + 1]);
+            if (le > lb)
+                aca_level_batch(P, l, lb, le, ws, ws_off, base, ncapped, s);
+        }
+        H3D_HIP(hipEventRecord(ev1, s));
+        H3D_HIP(hipEventSynchronize(ev1));
+        float ms = 0.f;
+        H3D_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+        aca_ms += ms;
+        // pack the batch into its own chunk
+        const int64_t nb = b1 - b0;
+        k_pack_sizes<<<grid_for(nb, 256), 256, 0, s>>>(b0, b1, P.blk_m, P.blk_n, P.blk_rank, mk, nk);
+        H3D_LAUNCH_CHECK();
+        H3D_HIP(hipMemsetAsync(mk + nb, 0, sizeof(int64_t), s));
+        H3D_HIP(hipMemsetAsync(nk + nb, 0, sizeof(int64_t), s));
+        const int64_t tu = scan_exclusive_i64(P, mk, mk, nb + 1, s);
+        const int64_t tv = scan_exclusive_i64(P, nk, nk, nb + 1, s);
+        const size_t ubytes = (size_t(tu) * es + 255) & ~size_t(255);
+        char *chunk = static_cast<char *>(P.mem.alloc(ubytes + size_t(tv) * es + 256));
+        P.chunks.push_back(chunk);
+        char *cu = chunk, *cv = chunk + ubytes;
+        const int grid = grid_for(nb * 64, 256);
+        switch (dt) {
+        case H3D_F64:
+            k_pack<H3D_F64><<<grid, 256, 0, s>>>(b0, b1, P.blk_m, P.blk_n, P.blk_rank,
+                                                 P.cfg.max_rank, ws, ws_off, base, mk, nk, cu, cv,
+                                                 P.blk_uptr, P.blk_vptr, P.blk_scale);
+            break;
+        case H3D_F32:
+            k_pack<H3D_F32><<<grid, 256, 0, s>>>(b0, b1, P.blk_m, P.blk_n, P.blk_rank,
+                                                 P.cfg.max_rank, ws, ws_off, base, mk, nk, cu, cv,
+                                                 P.blk_uptr, P.blk_vptr, P.blk_scale);
+            break;
+        default:
+            k_pack<H3D_BF16_SCALED><<<grid, 256, 0, s>>>(b0, b1, P.blk_m, P.blk_n, P.blk_rank,
+                                                         P.cfg.max_rank, ws, ws_off, base, mk, nk,
+                                                         cu, cv, P.blk_uptr, P.blk_vptr,
+                                                         P.blk_scale);
+            break;
+        }
+        H3D_LAUNCH_CHECK();
+        H3D_HIP(hipStreamSynchronize(s));
+        b0 = b1;
+    }
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    P.stats.aca_ms = aca_ms;
+    unsigned int hcap = 0;
+    to_host(&hcap, ncapped, 1, s);
+    P.stats.n_rank_capped = hcap;
+    P.mem.release(ws);
+    P.mem.release(ncapped);
+    P.mem.release(mk);
+    P.mem.release(nk);
+    P.mem.release(ws_off);
+
+    // factor columns: z index of every block, owner of every column
+    k_rank_i64<<<grid_for(nf + 1, 256), 256, 0, s>>>(nf, P.blk_rank, P.blk_col0);
+    H3D_LAUNCH_CHECK();
+    P.ncols = scan_exclusive_i64(P, P.blk_col0, P.blk_col0, nf + 1, s);
+    P.col_blk = P.mem.alloc_n<int32_t>(P.ncols);
+    k_col_blk<<<grid_for(nf, 256), 256, 0, s>>>(nf, P.blk_rank, P.blk_col0, P.col_blk);
+    H3D_LAUNCH_CHECK();
+    for (int l = 1; l <= P.L + 1 && l <= kMaxLevels; ++l) {
+        int64_t v = 0;
+        to_host(&v, P.blk_col0 + P.lvl_blk[l], 1, s);
+        P.lvl_col[l] = v;
+    }
+
+    // statistics
+    unsigned long long *sums = P.mem.alloc_n<unsigned long long>(4);
+    int64_t entries = 0, bytes = 0, ev_total = 0;
+    int rmax = 0;
+    for (int l = 1; l <= P.L; ++l) {
+        H3D_HIP(hipMemsetAsync(sums, 0, 4 * sizeof(unsigned long long), s));
+        const int64_t lb = P.lvl_blk[l], le = P.lvl_blk[l + 1];
+        if (le > lb) {
+            k_level_sums<<<int(std::min<int64_t>(1024, ceil_div(le - lb, 256))), 256, 0, s>>>(
+                lb, le, P.blk_m, P.blk_n, P.blk_rank, sums);
+            H3D_LAUNCH_CHECK();
+        }
+        unsigned long long h[4];
+        to_host(h, sums, 4, s);
+        entries += int64_t(h[0]);
+        ev_total += int64_t(h[3]);
+        const int64_t lbytes = int64_t(h[0]) * int64_t(es) +
+                               (dt == H3D_BF16_SCALED ? (le - lb) * 8 : 0);
+        P.stats.factor_bytes_per_level[l] = lbytes;
+        bytes += lbytes;
+        rmax = std::max(rmax, int(uint32_t(h[2])));
+    }
+    P.mem.release(sums);
+    P.stats.factor_entries = entries;
+    P.entries_v = ev_total;
+    P.stats.factor_bytes = bytes;
+    P.stats.rank_sum = P.ncols;
+    P.stats.rank_max = rmax;
+}
+
+// Copies U (which = 0) or V (which = 1) of every block to host as FP64.
+void export_factors(const Plan &Pc, int which, double *host_out) {
+    Plan &P = const_cast<Plan &>(Pc);
+    hipStream_t s = nullptr;
+    const int64_t nf = P.nfar;
+    if (nf == 0)
+        return;
+    const int32_t *len = which == 0 ? P.blk_m : P.blk_n;
+    int64_t *off = P.mem.alloc_n<int64_t>(nf + 1);
+    H3D_HIP(hipMemsetAsync(off + nf, 0, sizeof(int64_t), s));
+    k_len_rank<<<grid_for(nf, 256), 256, 0, s>>>(nf, len, P.blk_rank, off);
+    H3D_LAUNCH_CHECK();
+    const int64_t tot = scan_exclusive_i64(P, off, off, nf + 1, s);
+    double *out = P.mem.alloc_n<double>(tot);
+    void *const *ptr = which == 0 ? P.blk_uptr : P.blk_vptr;
+    const int grid = grid_for(nf * 64, 256);
+    switch (P.factor_dtype) {
+    case H3D_F64:
+        k_export<H3D_F64><<<grid, 256, 0, s>>>(nf, which, len, P.blk_rank, ptr, P.blk_scale, off, out);
+        break;
+    case H3D_F32:
+        k_export<H3D_F32><<<grid, 256, 0, s>>>(nf, which, len, P.blk_rank, ptr, P.blk_scale, off, out);
+        break;
+    default:
+        k_export<H3D_BF16_SCALED><<<grid, 256, 0, s>>>(nf, which, len, P.blk_rank, ptr, P.blk_scale,
+                                                       off, out);
+        break;
+    }
+    H3D_LAUNCH_CHECK();
+    to_host(host_out, out, tot, s);
+    P.mem.release(out);
+    P.mem.release(off);
+}
+
+}  // namespace h3d

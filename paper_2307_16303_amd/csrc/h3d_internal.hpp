@@ -1,0 +1,276 @@
+// Internal definitions of libhodlr3d: the plan (every device array of one
+// HODLR3D operator), allocation, error handling and the kernel profiler.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/hodlr3d.h"
+
+namespace h3d {
+
+struct Error : std::runtime_error {
+    h3d_status code;
+    Error(h3d_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] inline void fail(h3d_status c, const std::string &m) { throw Error(c, m); }
+
+#define H3D_HIP(call)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            ::h3d::fail(e_ == hipErrorOutOfMemory ? H3D_ENOMEM : H3D_EDEVICE,              \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                \
+    } while (0)
+
+#define H3D_LAUNCH_CHECK() H3D_HIP(hipGetLastError())
+
+constexpr int kMaxLevels = H3D_MAX_LEVELS;  // levels 0..10
+constexpr int kMaxDepth = kMaxLevels - 1;
+
+inline int64_t pow8(int l) { return int64_t(1) << (3 * l); }
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Device memory owned by a plan, obtained through the caller's allocator or
+// hipMalloc.
+class DeviceMemory {
+  public:
+    DeviceMemory() = default;
+    DeviceMemory(const DeviceMemory &) = delete;
+    DeviceMemory &operator=(const DeviceMemory &) = delete;
+    ~DeviceMemory() { release_all(); }
+
+    void configure(const h3d_allocator *a, hipStream_t s) {
+        if (a && a->alloc && a->free) {
+            user_ = *a;
+            has_user_ = true;
+        }
+        stream_ = s;
+    }
+    void *alloc(size_t bytes) {
+        if (bytes == 0)
+            bytes = 8;
+        bytes = (bytes + 255) & ~size_t(255);
+        void *p = nullptr;
+        if (has_user_) {
+            p = user_.alloc(bytes, (void *)stream_, user_.ctx);
+            if (!p)
+                fail(H3D_ENOMEM, "allocator returned NULL for " + std::to_string(bytes) + " bytes");
+        } else {
+            hipError_t e = hipMalloc(&p, bytes);
+            if (e != hipSuccess || !p) {
+                (void)hipGetLastError();
+                fail(H3D_ENOMEM, "hipMalloc failed for " + std::to_string(bytes) + " bytes");
+            }
+        }
+        live_[p] = bytes;
+        total_ += bytes;
+        return p;
+    }
+    template <typename T> T *alloc_n(int64_t n) { return (T *)alloc(size_t(n > 0 ? n : 1) * sizeof(T)); }
+    void release(void *p) {
+        if (!p)
+            return;
+        auto it = live_.find(p);
+        if (it == live_.end())
+            return;
+        size_t bytes = it->second;
+        live_.erase(it);
+        total_ -= bytes;
+        if (has_user_)
+            user_.free(p, bytes, (void *)stream_, user_.ctx);
+        else
+            (void)hipFree(p);
+    }
+    void release_all() {
+        while (!live_.empty())
+            release(live_.begin()->first);
+    }
+    size_t total() const { return total_; }
+
+  private:
+    h3d_allocator user_{};
+    bool has_user_ = false;
+    hipStream_t stream_ = nullptr;
+    std::map<void *, size_t> live_;
+    size_t total_ = 0;
+};
+
+// HIP-event timing of the mat-vec kernels, per kernel name.
+struct Profiler {
+    bool on = false;
+    struct Rec {
+        int slot;
+        hipEvent_t a, b;
+    };
+    std::vector<std::string> names;
+    std::vector<int64_t> launches;
+    std::vector<double> total_ms, bytes, flops;
+    std::vector<Rec> pending;
+    std::vector<hipEvent_t> pool;
+
+    int slot_of(const char *name) {
+        for (size_t i = 0; i < names.size(); ++i)
+            if (names[i] == name)
+                return int(i);
+        names.emplace_back(name);
+        launches.push_back(0);
+        total_ms.push_back(0.0);
+        bytes.push_back(0.0);
+        flops.push_back(0.0);
+        return int(names.size() - 1);
+    }
+    hipEvent_t get_event() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        H3D_HIP(hipEventCreate(&e));
+        return e;
+    }
+    // Brackets one launch: begin() before it, end() after it.
+    hipEvent_t begin(hipStream_t s) {
+        if (!on)
+            return nullptr;
+        hipEvent_t a = get_event();
+        H3D_HIP(hipEventRecord(a, s));
+        return a;
+    }
+    void end(hipStream_t s, hipEvent_t a, const char *name, double nbytes, double nflops) {
+        if (!on || !a)
+            return;
+        hipEvent_t b = get_event();
+        H3D_HIP(hipEventRecord(b, s));
+        int slot = slot_of(name);
+        bytes[slot] = nbytes;
+        flops[slot] = nflops;
+        pending.push_back({slot, a, b});
+    }
+    void collect() {
+        for (auto &r : pending) {
+            H3D_HIP(hipEventSynchronize(r.b));
+            float ms = 0.f;
+            H3D_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+            launches[r.slot] += 1;
+            total_ms[r.slot] += ms;
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        pending.clear();
+    }
+    void reset() {
+        collect();
+        for (size_t i = 0; i < names.size(); ++i) {
+            launches[i] = 0;
+            total_ms[i] = 0.0;
+        }
+    }
+    ~Profiler() {
+        for (auto &r : pending) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (auto e : pool)
+            (void)hipEventDestroy(e);
+    }
+};
+
+// Everything one HODLR3D operator owns.  Rows are numbered in sorted (Morton)
+// order; a box b at level l owns rows leaf_off[b 8^(L-l)] .. leaf_off[(b+1) 8^(L-l)].
+struct Plan {
+    h3d_config cfg{};
+    DeviceMemory mem;
+    int device = 0;
+    int64_t n = 0;
+    int L = 0;
+    double lo[3] = {0, 0, 0};
+    double side = 1.0;
+
+    // tree
+    int32_t *perm = nullptr;      // [n] sorted row -> original index
+    double *px = nullptr, *py = nullptr, *pz = nullptr;  // [n] sorted coordinates
+    int32_t *leaf_off = nullptr;  // [8^L + 1]
+    int32_t *leaf_of = nullptr;   // [n] leaf of each sorted row
+    std::vector<int32_t> h_leaf_off;  // host copy
+
+    // boxes of all levels 1..L concatenated: global box id g = box_base[l] + t
+    int64_t box_base[kMaxLevels + 1] = {0};
+    int64_t nbox_all = 0;
+
+    // far blocks in (level, target, source) order
+    int64_t nfar = 0;
+    int64_t lvl_blk[kMaxLevels + 1] = {0};  // blocks of level l: [lvl_blk[l], lvl_blk[l+1])
+    int64_t *tgt_begin = nullptr;  // [nbox_all + 1] blocks of global box g as target
+    int64_t *src_blk = nullptr;    // [nfar] blocks grouped by source box (same offsets)
+    int32_t *blk_t = nullptr, *blk_s = nullptr;        // box ids (per level)
+    int32_t *blk_toff = nullptr, *blk_m = nullptr;     // target rows
+    int32_t *blk_soff = nullptr, *blk_n = nullptr;     // source rows
+    int32_t *blk_rank = nullptr;
+    int64_t *blk_col0 = nullptr;   // first factor column (z index) of each block
+    void **blk_uptr = nullptr;     // device pointer to U_b (m x k, column-major)
+    void **blk_vptr = nullptr;     // device pointer to V_b (n x k, column-major)
+    float *blk_scale = nullptr;    // BF16 form: scale of U_b times scale of V_b
+    int32_t *blk_piv = nullptr;    // optional: 2 kcap ints per block
+    int64_t *blk_pivoff = nullptr;
+    int64_t ncols = 0;             // sum of ranks
+    int64_t entries_v = 0;         // sum of n k (entries of all V_b)
+    int64_t lvl_col[kMaxLevels + 1] = {0};
+    int32_t *col_blk = nullptr;    // [ncols] owning block of each column
+    int mean_box[kMaxLevels + 1] = {0};  // mean size of non-empty boxes per level
+    int max_box[kMaxLevels + 1] = {0};
+
+    // near field at the leaf level
+    int64_t nnear = 0;
+    int32_t *near_ptr = nullptr;  // [8^L + 1]
+    int32_t *near_s = nullptr;    // [nnear]
+    int8_t *near_rel = nullptr;   // [nnear]
+
+    // stored factors
+    int factor_dtype = H3D_F64;
+    std::vector<void *> chunks;
+    h3d_stats stats{};
+
+    // mat-vec scratch, grown on demand
+    int64_t scratch_nrhs = 0;
+    double *xp = nullptr, *yp = nullptr, *z = nullptr;
+
+    Profiler prof;
+    bool built = false;
+};
+
+// ---- building blocks implemented in the .hip files ----
+void tree_build(Plan &P, const double *points, hipStream_t s);
+void lists_build(Plan &P, hipStream_t s);
+void factors_build(Plan &P, hipStream_t s);
+void matvec_run(Plan &P, const void *x, void *y, int64_t nrhs, int64_t ldx, int64_t ldy,
+                int io_dtype, bool adjoint, hipStream_t s);
+void export_factors(const Plan &P, int which, double *host_out);
+
+// device-wide exclusive scan; out may alias in; returns the total
+int64_t scan_exclusive_i64(Plan &P, const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
+void scan_exclusive_i32_nototal(Plan &P, const int32_t *in, int32_t *out, int64_t n, hipStream_t s);
+
+template <typename T> void to_host(T *dst, const T *src, int64_t n, hipStream_t s) {
+    if (n <= 0)
+        return;
+    H3D_HIP(hipMemcpyAsync(dst, src, sizeof(T) * size_t(n), hipMemcpyDeviceToHost, s));
+    H3D_HIP(hipStreamSynchronize(s));
+}
+
+inline int grid_for(int64_t n, int block) {
+    int64_t g = ceil_div(n, block);
+    if (g < 1)
+        g = 1;
+    return int(g);
+}
+
+}  // namespace h3d

@@ -1,0 +1,351 @@
+"""Python binding of libhodlr3d (C ABI in include/hodlr3d.h).
+
+Argument marshalling only: every step of the build and of the mat-vec runs in
+the HIP kernels of ``libhodlr3d.so``.  PyTorch provides device memory (through
+its caching allocator, handed to the library as an h3d_allocator) and the
+stream.  If the library is missing this module raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhodlr3d.so")
+
+H3D_OK, H3D_EINVAL, H3D_ENOMEM, H3D_EDEVICE, H3D_ENOTBUILT, H3D_EDEPTH, H3D_ENOTIMPL = range(7)
+STATUS_NAMES = {0: "H3D_OK", 1: "H3D_EINVAL", 2: "H3D_ENOMEM", 3: "H3D_EDEVICE",
+                4: "H3D_ENOTBUILT", 5: "H3D_EDEPTH", 6: "H3D_ENOTIMPL"}
+KERNELS = {"laplace": 0, "yukawa": 1, "inv_r4": 2, "cos_r": 3}
+DTYPES = {"fp64": 0, "f64": 0, "fp32": 1, "f32": 1, "bf16": 2, "bf16_scaled": 2}
+EXPORTS = {"perm": 0, "leaf_off": 1, "far": 2, "near": 3, "factors_u": 4, "factors_v": 5,
+           "pivots": 6}
+FLAG_KEEP_PIVOTS = 1
+MAX_LEVELS = 11
+
+EXPORTED_SYMBOLS = (
+    "h3d_config_init", "h3d_build", "h3d_matvec", "h3d_matvec_adjoint", "h3d_get_stats",
+    "h3d_export", "h3d_destroy", "h3d_last_error", "h3d_profile_enable", "h3d_profile_read",
+    "h3d_profile_reset", "h3d_version",
+)
+
+
+class H3DError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("kernel", ctypes.c_int32),
+        ("kernel_param", ctypes.c_double),
+        ("leaf_size", ctypes.c_int32),
+        ("tol", ctypes.c_double),
+        ("factor_dtype", ctypes.c_int32),
+        ("max_rank", ctypes.c_int32),
+        ("max_depth", ctypes.c_int32),
+        ("box_lo", ctypes.c_double * 3),
+        ("box_side", ctypes.c_double),
+        ("workspace_bytes", ctypes.c_int64),
+        ("flags", ctypes.c_int32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("depth", ctypes.c_int32),
+        ("factor_dtype", ctypes.c_int32),
+        ("box_lo", ctypes.c_double * 3),
+        ("box_side", ctypes.c_double),
+        ("n_far", ctypes.c_int64),
+        ("n_near", ctypes.c_int64),
+        ("far_per_level", ctypes.c_int64 * MAX_LEVELS),
+        ("rank_sum", ctypes.c_int64),
+        ("rank_max", ctypes.c_int32),
+        ("n_rank_capped", ctypes.c_int64),
+        ("factor_entries", ctypes.c_int64),
+        ("factor_bytes", ctypes.c_int64),
+        ("factor_bytes_per_level", ctypes.c_int64 * MAX_LEVELS),
+        ("near_pair_evals", ctypes.c_int64),
+        ("device_bytes", ctypes.c_int64),
+        ("build_ms", ctypes.c_double),
+        ("aca_ms", ctypes.c_double),
+    ]
+
+    def to_dict(self) -> dict:
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if hasattr(v, "__len__") else v
+        return out
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+class KernelProfile(ctypes.Structure):
+    _fields_ = [
+        ("name", ctypes.c_char * 48),
+        ("launches", ctypes.c_int64),
+        ("total_ms", ctypes.c_double),
+        ("bytes_per_launch", ctypes.c_double),
+        ("flops_per_launch", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def load_library():
+    """Loads libhodlr3d.so (built by ``__graft_entry__.build()``); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -c 'import "
+                           f"__graft_entry__ as g; g.build()'` (no fallback path exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    S = ctypes.c_int
+    lib.h3d_config_init.argtypes = [ctypes.POINTER(Config)]
+    lib.h3d_config_init.restype = None
+    lib.h3d_build.argtypes = [P, I64, ctypes.POINTER(Config), ctypes.POINTER(Allocator), P,
+                              ctypes.POINTER(P)]
+    lib.h3d_build.restype = S
+    for f in ("h3d_matvec", "h3d_matvec_adjoint"):
+        getattr(lib, f).argtypes = [P, P, P, I64, I64, I64, I32, P]
+        getattr(lib, f).restype = S
+    lib.h3d_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
+    lib.h3d_get_stats.restype = S
+    lib.h3d_export.argtypes = [P, I32, P, ctypes.POINTER(ctypes.c_size_t)]
+    lib.h3d_export.restype = S
+    lib.h3d_destroy.argtypes = [P]
+    lib.h3d_destroy.restype = S
+    lib.h3d_last_error.argtypes = []
+    lib.h3d_last_error.restype = ctypes.c_char_p
+    lib.h3d_profile_enable.argtypes = [P, I32]
+    lib.h3d_profile_enable.restype = S
+    lib.h3d_profile_reset.argtypes = [P]
+    lib.h3d_profile_reset.restype = S
+    lib.h3d_profile_read.argtypes = [P, ctypes.POINTER(KernelProfile), I32,
+                                     ctypes.POINTER(ctypes.c_int32)]
+    lib.h3d_profile_read.restype = S
+    lib.h3d_version.argtypes = []
+    lib.h3d_version.restype = I32
+    _lib = lib
+    return lib
+
+
+def _check(status: int) -> None:
+    if status != H3D_OK:
+        raise H3DError(status, load_library().h3d_last_error().decode())
+
+
+def default_config() -> Config:
+    cfg = Config()
+    load_library().h3d_config_init(ctypes.byref(cfg))
+    return cfg
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class _TorchAllocator:
+    """h3d_allocator backed by torch's caching allocator (kept alive with the plan)."""
+
+    def __init__(self, device: int):
+        torch = _torch()
+        self.device = device
+
+        def _alloc(nbytes, stream, ctx):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), device=self.device,
+                                                          stream=int(stream or 0))
+            except Exception:
+                return None
+
+        def _free(ptr, nbytes, stream, ctx):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self._a = ALLOC_FN(_alloc)
+        self._f = FREE_FN(_free)
+        self.struct = Allocator(self._a, self._f, None)
+
+
+class Operator:
+    """The HODLR3D representation of K on one point cloud, resident on the GPU."""
+
+    def __init__(self, handle, n: int, device: int, allocator, config: Config):
+        self._h = handle
+        self.n = int(n)
+        self.device = device
+        self._alloc = allocator
+        self.config = config
+
+    # -- lifecycle --------------------------------------------------------
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load_library().h3d_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- products ---------------------------------------------------------
+    def _apply(self, x, adjoint: bool, out=None):
+        torch = _torch()
+        if not isinstance(x, torch.Tensor) or not x.is_cuda:
+            raise TypeError("x must be a CUDA (HIP) tensor")
+        if x.dtype not in (torch.float64, torch.float32):
+            raise TypeError("x must be float64 or float32")
+        vec = x.dim() == 1
+        x2 = x.reshape(self.n, -1)
+        nrhs = x2.shape[1]
+        xc = x2.t().contiguous()  # nrhs x n row-major == n x nrhs column-major
+        y = torch.empty_like(xc) if out is None else out
+        io = 0 if x.dtype == torch.float64 else 1
+        stream = torch.cuda.current_stream(x.device).cuda_stream
+        fn = load_library().h3d_matvec_adjoint if adjoint else load_library().h3d_matvec
+        _check(fn(self._h, ctypes.c_void_p(xc.data_ptr()), ctypes.c_void_p(y.data_ptr()), nrhs,
+                  self.n, self.n, io, ctypes.c_void_p(stream)))
+        return y.reshape(-1) if vec else y.t()
+
+    def matvec(self, x):
+        """y = K~ x for x of shape (n,) or (n, nrhs) on the GPU."""
+        return self._apply(x, adjoint=False)
+
+    def rmatvec(self, x):
+        """y = K~^T x with the same stored blocks."""
+        return self._apply(x, adjoint=True)
+
+    def __matmul__(self, x):
+        return self.matvec(x)
+
+    # -- introspection ----------------------------------------------------
+    def stats(self) -> dict:
+        s = Stats()
+        _check(load_library().h3d_get_stats(self._h, ctypes.byref(s)))
+        return s.to_dict()
+
+    def export(self, what: str) -> np.ndarray:
+        wid = EXPORTS[what]
+        lib = load_library()
+        nbytes = ctypes.c_size_t(0)
+        _check(lib.h3d_export(self._h, wid, None, ctypes.byref(nbytes)))
+        dtype = np.float64 if what.startswith("factors") else np.int64
+        buf = np.empty(max(nbytes.value // 8, 1), dtype=dtype)
+        _check(lib.h3d_export(self._h, wid, buf.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nbytes)))
+        buf = buf[: nbytes.value // 8]
+        if what == "far":
+            return buf.reshape(6, -1)
+        if what == "near":
+            return buf.reshape(3, -1)
+        if what == "pivots":
+            return buf.reshape(2, -1)
+        return buf
+
+    def profile(self, enable: bool = True) -> None:
+        _check(load_library().h3d_profile_enable(self._h, int(bool(enable))))
+
+    def profile_reset(self) -> None:
+        _check(load_library().h3d_profile_reset(self._h))
+
+    def profile_read(self) -> list[dict]:
+        lib = load_library()
+        cnt = ctypes.c_int32(0)
+        _check(lib.h3d_profile_read(self._h, None, 0, ctypes.byref(cnt)))
+        arr = (KernelProfile * max(cnt.value, 1))()
+        _check(lib.h3d_profile_read(self._h, arr, cnt.value, ctypes.byref(cnt)))
+        return [dict(name=arr[i].name.decode(), launches=arr[i].launches,
+                     total_ms=arr[i].total_ms, bytes_per_launch=arr[i].bytes_per_launch,
+                     flops_per_launch=arr[i].flops_per_launch) for i in range(cnt.value)]
+
+
+def build(points, kernel="laplace", kernel_param: float = 1.0, leaf_size: int = 64,
+          tol: float = 1e-8, factor_dtype="fp64", max_rank: int = 0, max_depth: int = 10,
+          box_lo=None, box_side: float = 0.0, workspace_bytes: int = 0,
+          keep_pivots: bool = False, use_torch_allocator: bool = True) -> Operator:
+    """Builds the HODLR3D operator of the n x 3 FP64 point cloud (moved to the GPU)."""
+    torch = _torch()
+    lib = load_library()
+    if not isinstance(points, torch.Tensor):
+        points = torch.as_tensor(np.ascontiguousarray(points, dtype=np.float64))
+    if not points.is_cuda:
+        points = points.to("cuda")
+    points = points.to(torch.float64).contiguous()
+    if points.dim() != 2 or points.shape[1] != 3:
+        raise ValueError("points must have shape (n, 3)")
+    cfg = default_config()
+    cfg.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    cfg.kernel_param = float(kernel_param)
+    cfg.leaf_size = int(leaf_size)
+    cfg.tol = float(tol)
+    cfg.factor_dtype = DTYPES[factor_dtype] if isinstance(factor_dtype, str) else int(factor_dtype)
+    cfg.max_rank = int(max_rank)
+    cfg.max_depth = int(max_depth)
+    if box_lo is not None:
+        for a in range(3):
+            cfg.box_lo[a] = float(box_lo[a])
+    cfg.box_side = float(box_side)
+    cfg.workspace_bytes = int(workspace_bytes)
+    cfg.flags = FLAG_KEEP_PIVOTS if keep_pivots else 0
+    device = points.device.index if points.device.index is not None else torch.cuda.current_device()
+    alloc = _TorchAllocator(device) if use_torch_allocator else None
+    handle = ctypes.c_void_p()
+    stream = torch.cuda.current_stream(points.device).cuda_stream
+    with torch.cuda.device(device):
+        _check(lib.h3d_build(ctypes.c_void_p(points.data_ptr()), points.shape[0], ctypes.byref(cfg),
+                             ctypes.byref(alloc.struct) if alloc else None,
+                             ctypes.c_void_p(stream), ctypes.byref(handle)))
+    return Operator(handle, points.shape[0], device, alloc, cfg)
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class HODLR3DMatVec(torch.autograd.Function):
+        """y = K~ x; the backward pass applies K~^T through the adjoint kernels."""
+
+        @staticmethod
+        def forward(ctx, op: Operator, x):
+            ctx.op = op
+            return op.matvec(x)
+
+        @staticmethod
+        def backward(ctx, grad_y):
+            return None, ctx.op.rmatvec(grad_y.contiguous())
+
+    return HODLR3DMatVec
+
+
+_AUTOGRAD = None
+
+
+def matvec_autograd(op: Operator, x):
+    """Differentiable y = K~ x (gradient with respect to x only)."""
+    global _AUTOGRAD
+    if _AUTOGRAD is None:
+        _AUTOGRAD = _autograd_function()
+    return _AUTOGRAD.apply(op, x)

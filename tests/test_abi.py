@@ -1,0 +1,112 @@
+"""The C ABI library loads, exports every symbol include/hodlr3d.h declares,
+its structs have the header's layout, and argument validation rejects bad
+input before any device work (no GPU needed for any of this)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2307_16303_amd import hodlr3d
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hodlr3d.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return hodlr3d.load_library()
+
+
+def declared_functions():
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    return sorted(set(re.findall(r"\b(h3d_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) == 12, names
+    out = subprocess.run(["nm", "-D", "--defined-only", hodlr3d.library_path()],
+                         capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r" T (h3d_\w+)", out))
+    for name in names:
+        assert name in exported, name
+        assert hasattr(lib, name)
+    assert set(hodlr3d.EXPORTED_SYMBOLS) == set(names)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "hodlr3d.h"\n'
+        "int main(void){printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(h3d_config),"
+        " sizeof(h3d_stats), sizeof(h3d_allocator), sizeof(h3d_kernel_profile),"
+        " offsetof(h3d_config, box_lo), offsetof(h3d_stats, aca_ms), offsetof(h3d_config, flags));"
+        "return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    want = [ctypes.sizeof(hodlr3d.Config), ctypes.sizeof(hodlr3d.Stats),
+            ctypes.sizeof(hodlr3d.Allocator), ctypes.sizeof(hodlr3d.KernelProfile),
+            hodlr3d.Config.box_lo.offset, hodlr3d.Stats.aca_ms.offset, hodlr3d.Config.flags.offset]
+    assert got == want
+
+
+def test_defaults(lib):
+    cfg = hodlr3d.default_config()
+    assert (cfg.kernel, cfg.leaf_size, cfg.tol, cfg.factor_dtype, cfg.max_depth) == (0, 64, 1e-8, 0, 10)
+    assert lib.h3d_version() == 1
+
+
+def _build_status(lib, cfg, n=10, points=ctypes.c_void_p(0x1000)):
+    out = ctypes.c_void_p(123)
+    st = lib.h3d_build(points, n, ctypes.byref(cfg), None, None, ctypes.byref(out))
+    assert out.value is None  # *out is NULL on failure
+    return st, lib.h3d_last_error().decode()
+
+
+@pytest.mark.parametrize("field,value", [
+    ("leaf_size", 0), ("tol", 0.0), ("tol", 1.0), ("tol", float("nan")), ("max_depth", 11),
+    ("max_depth", -1), ("kernel", 7), ("factor_dtype", 3), ("kernel_param", float("inf")),
+    ("box_side", float("nan")),
+])
+def test_build_rejects_bad_config(lib, field, value):
+    cfg = hodlr3d.default_config()
+    setattr(cfg, field, value)
+    st, msg = _build_status(lib, cfg)
+    assert st == hodlr3d.H3D_EINVAL and msg
+
+
+def test_build_rejects_bad_arguments(lib):
+    cfg = hodlr3d.default_config()
+    assert _build_status(lib, cfg, n=0)[0] == hodlr3d.H3D_EINVAL
+    assert _build_status(lib, cfg, n=2 ** 31)[0] == hodlr3d.H3D_EINVAL
+    assert _build_status(lib, cfg, points=ctypes.c_void_p(0))[0] == hodlr3d.H3D_EINVAL
+    cfg.box_side = 2.0
+    cfg.box_lo[1] = float("inf")
+    assert _build_status(lib, cfg)[0] == hodlr3d.H3D_EINVAL
+    assert lib.h3d_build(ctypes.c_void_p(0x1000), 10, None, None, None,
+                         ctypes.byref(ctypes.c_void_p())) == hodlr3d.H3D_EINVAL
+    half = hodlr3d.Allocator(hodlr3d.ALLOC_FN(lambda a, b, c: None), hodlr3d.FREE_FN(), None)
+    out = ctypes.c_void_p()
+    st = lib.h3d_build(ctypes.c_void_p(0x1000), 10, ctypes.byref(hodlr3d.default_config()),
+                       ctypes.byref(half), None, ctypes.byref(out))
+    assert st == hodlr3d.H3D_EINVAL
+
+
+def test_calls_on_null_plan(lib):
+    buf = np.zeros(4)
+    p = buf.ctypes.data_as(ctypes.c_void_p)
+    assert lib.h3d_matvec(None, p, p, 1, 4, 4, 0, None) == hodlr3d.H3D_ENOTBUILT
+    assert lib.h3d_matvec_adjoint(None, p, p, 1, 4, 4, 0, None) == hodlr3d.H3D_ENOTBUILT
+    s = hodlr3d.Stats()
+    assert lib.h3d_get_stats(None, ctypes.byref(s)) == hodlr3d.H3D_ENOTBUILT
+    nb = ctypes.c_size_t(0)
+    assert lib.h3d_export(None, 0, None, ctypes.byref(nb)) == hodlr3d.H3D_ENOTBUILT
+    assert lib.h3d_destroy(None) == hodlr3d.H3D_OK
+    cnt = ctypes.c_int32(0)
+    assert lib.h3d_profile_read(None, None, 0, ctypes.byref(cnt)) == hodlr3d.H3D_ENOTBUILT
