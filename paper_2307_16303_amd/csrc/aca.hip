@@ -66,12 +66,15 @@ __device__ __forceinline__ double entry(const Geom &g, int64_t gi, int64_t gj) {
 
 struct BlockTab {
     const int32_t *toff, *m, *soff, *n;
-    const int64_t *ws_off;  // per block offset; the batch workspace starts at ws_base
+    const int32_t *list;    // block id of each batch position
+    const int64_t *ws_off;  // per position; the batch workspace starts at ws_base
     int64_t ws_base;
     int32_t *rank;
     int32_t *piv;           // optional: 2 kcap ints per block at pivoff
     const int64_t *pivoff;
     unsigned int *ncapped;
+    int32_t *overflow;      // set when the workspace column cap stopped the block
+    int kws;                // workspace column cap of this pass
 };
 
 __device__ __forceinline__ int kcap_of(int m, int n, int max_rank) {
@@ -79,6 +82,22 @@ __device__ __forceinline__ int kcap_of(int m, int n, int max_rank) {
     if (max_rank > 0 && max_rank < k)
         k = max_rank;
     return k;
+}
+
+// Records how a block ended: a stop at the workspace cap below the real cap
+// is not a result (the block is run again with more room); a stop at a rank
+// cap below min(m, n) is counted.
+__device__ __forceinline__ void finish_block(const BlockTab &T, int64_t b, int k, int m, int n,
+                                             int kcap_true, bool hit_cap) {
+    if (hit_cap && k < kcap_true) {
+        T.overflow[b] = 1;
+        T.rank[b] = 0;
+        return;
+    }
+    T.overflow[b] = 0;
+    T.rank[b] = k;
+    if (hit_cap && kcap_true < (m < n ? m : n))
+        atomicAdd(T.ncapped, 1u);
 }
 
 // (|value|, index, value) argmax with ties to the lowest index
@@ -119,23 +138,26 @@ constexpr int kNone = 0x7fffffff;
 // one sub-wave of SW lanes per block; a workgroup is one wave (64 / SW blocks)
 template <int SW>
 __global__ void __launch_bounds__(64)
-    k_aca_subwave(int64_t b0, int64_t b1, BlockTab T, Geom G, double tol, int max_rank,
+    k_aca_subwave(int64_t q0, int64_t q1, BlockTab T, Geom G, double tol, int max_rank,
                   double *__restrict__ ws) {
     constexpr int NSUB = 64 / SW;
     const int lane = threadIdx.x;
     const int r = lane % SW;
-    const int64_t b = b0 + int64_t(blockIdx.x) * NSUB + lane / SW;
-    const bool valid = b < b1;
-    int m = 0, n = 0, kcap = 0;
+    const int64_t q = q0 + int64_t(blockIdx.x) * NSUB + lane / SW;
+    const bool valid = q < q1;
+    int64_t b = 0;
+    int m = 0, n = 0, kcap = 0, kcap_true = 0;
     int64_t toff = 0, soff = 0;
     double *U = ws, *V = ws, *P = ws;
     if (valid) {
+        b = T.list[q];
         m = T.m[b];
         n = T.n[b];
         toff = T.toff[b];
         soff = T.soff[b];
-        kcap = kcap_of(m, n, max_rank);
-        U = ws + (T.ws_off[b] - T.ws_base);
+        kcap_true = kcap_of(m, n, max_rank);
+        kcap = min(kcap_true, T.kws);
+        U = ws + (T.ws_off[q] - T.ws_base);
         V = U + int64_t(m) * kcap;
         P = V + int64_t(n) * kcap;
     }
@@ -259,11 +281,8 @@ __global__ void __launch_bounds__(64)
         }
         __syncthreads();
     }
-    if (valid && r == 0) {
-        T.rank[b] = k;
-        if (capped)
-            atomicAdd(T.ncapped, 1u);
-    }
+    if (valid && r == 0)
+        finish_block(T, b, k, m, n, kcap_true, capped);
 }
 
 // ---------------------------------------------------------------------------
@@ -285,17 +304,19 @@ __device__ __forceinline__ Arg wg_arg_reduce(Arg x, Arg *sh) {
 }
 
 __global__ void __launch_bounds__(kWG)
-    k_aca_workgroup(int64_t b0, BlockTab T, Geom G, double tol, int max_rank,
+    k_aca_workgroup(int64_t q0, BlockTab T, Geom G, double tol, int max_rank,
                     double *__restrict__ ws) {
     __shared__ Arg sh_arg[kWG / 64];
     __shared__ double sh_uv[2];
     const int tid = threadIdx.x;
-    const int64_t b = b0 + blockIdx.x;
+    const int64_t q = q0 + blockIdx.x;
+    const int64_t b = T.list[q];
     const int m = T.m[b], n = T.n[b];
     const int64_t toff = T.toff[b], soff = T.soff[b];
-    const int kcap = kcap_of(m, n, max_rank);
+    const int kcap_true = kcap_of(m, n, max_rank);
+    const int kcap = min(kcap_true, T.kws);
     const int mn = m < n ? m : n;
-    double *U = ws + (T.ws_off[b] - T.ws_base);
+    double *U = ws + (T.ws_off[q] - T.ws_base);
     double *V = U + int64_t(m) * kcap;
     double *P = V + int64_t(n) * kcap;
     unsigned char *used_r = reinterpret_cast<unsigned char *>(P + kcap);
@@ -408,38 +429,44 @@ __global__ void __launch_bounds__(kWG)
             break;
         i = nx.j;
     }
-    if (tid == 0) {
-        T.rank[b] = k;
-        if (capped)
-            atomicAdd(T.ncapped, 1u);
-    }
+    if (tid == 0)
+        finish_block(T, b, k, m, n, kcap_true, capped);
 }
 
-// workspace doubles of each block
-__global__ void k_ws_size(int64_t nfar, const int32_t *__restrict__ m, const int32_t *__restrict__ n,
-                          int max_rank, int64_t *__restrict__ ws, int64_t *__restrict__ kc) {
-    int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (b >= nfar)
+// workspace doubles of each listed block for a pass with column cap kws
+__global__ void k_ws_size(int64_t cnt, const int32_t *__restrict__ list,
+                          const int32_t *__restrict__ m, const int32_t *__restrict__ n,
+                          int max_rank, int kws, int64_t *__restrict__ ws) {
+    int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= cnt)
         return;
-    int64_t kcap = kcap_of(m[b], n[b], max_rank);
-    ws[b] = (int64_t(m[b]) + n[b]) * kcap + kcap + (int64_t(m[b]) + n[b] + 7) / 8 + 1;
-    if (kc)
-        kc[b] = 2 * kcap;
+    const int64_t b = list[q];
+    int64_t kc = min(kcap_of(m[b], n[b], max_rank), kws);
+    ws[q] = (int64_t(m[b]) + n[b]) * kc + kc + (int64_t(m[b]) + n[b] + 7) / 8 + 1;
+}
+
+// pivot slots (2 per possible rank) of every block
+__global__ void k_piv_size(int64_t nfar, const int32_t *__restrict__ m, const int32_t *__restrict__ n,
+                           int max_rank, int64_t *__restrict__ kc) {
+    int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b < nfar)
+        kc[b] = 2 * int64_t(kcap_of(m[b], n[b], max_rank));
 }
 
 }  // namespace
 
-// Runs ACA over blocks [b0, b1) of one level into the workspace ws whose
-// per-block offsets (relative to ws) are ws_off.
-void aca_level_batch(Plan &P, int level, int64_t b0, int64_t b1, double *ws, const int64_t *ws_off,
-                     int64_t ws_base, unsigned int *ncapped, hipStream_t s) {
-    if (b1 <= b0)
+// Runs ACA over positions [q0, q1) of the batch list (one level) into the
+// workspace ws, whose per-position offsets relative to ws_base are ws_off.
+void aca_level_batch(Plan &P, int level, const int32_t *list, int64_t q0, int64_t q1, double *ws,
+                     const int64_t *ws_off, int64_t ws_base, int kws, int32_t *overflow,
+                     unsigned int *ncapped, hipStream_t s) {
+    if (q1 <= q0)
         return;
     Geom G{P.px, P.py, P.pz, P.cfg.kernel, P.cfg.kernel_param};
-    BlockTab T{P.blk_toff, P.blk_m, P.blk_soff, P.blk_n, ws_off, ws_base, P.blk_rank,
-               P.blk_piv, P.blk_pivoff, ncapped};
+    BlockTab T{P.blk_toff, P.blk_m, P.blk_soff, P.blk_n, list, ws_off, ws_base, P.blk_rank,
+               P.blk_piv, P.blk_pivoff, ncapped, overflow, kws};
     const int mx = P.max_box[level];
-    const int64_t nb = b1 - b0;
+    const int64_t nb = q1 - q0;
     const double tol = P.cfg.tol;
     const int mr = P.cfg.max_rank;
     if (mx <= 32 * 4) {
@@ -451,35 +478,42 @@ void aca_level_batch(Plan &P, int level, int64_t b0, int64_t b1, double *ws, con
             sw *= 2;
         switch (sw) {
         case 4:
-            k_aca_subwave<4><<<grid_for(nb, 16), 64, 0, s>>>(b0, b1, T, G, tol, mr, ws);
+            k_aca_subwave<4><<<grid_for(nb, 16), 64, 0, s>>>(q0, q1, T, G, tol, mr, ws);
             break;
         case 8:
-            k_aca_subwave<8><<<grid_for(nb, 8), 64, 0, s>>>(b0, b1, T, G, tol, mr, ws);
+            k_aca_subwave<8><<<grid_for(nb, 8), 64, 0, s>>>(q0, q1, T, G, tol, mr, ws);
             break;
         case 16:
-            k_aca_subwave<16><<<grid_for(nb, 4), 64, 0, s>>>(b0, b1, T, G, tol, mr, ws);
+            k_aca_subwave<16><<<grid_for(nb, 4), 64, 0, s>>>(q0, q1, T, G, tol, mr, ws);
             break;
         case 32:
-            k_aca_subwave<32><<<grid_for(nb, 2), 64, 0, s>>>(b0, b1, T, G, tol, mr, ws);
+            k_aca_subwave<32><<<grid_for(nb, 2), 64, 0, s>>>(q0, q1, T, G, tol, mr, ws);
             break;
         default:
-            k_aca_subwave<64><<<grid_for(nb, 1), 64, 0, s>>>(b0, b1, T, G, tol, mr, ws);
+            k_aca_subwave<64><<<grid_for(nb, 1), 64, 0, s>>>(q0, q1, T, G, tol, mr, ws);
             break;
         }
     } else if (mx <= 32 * 64) {
-        k_aca_subwave<64><<<grid_for(nb, 1), 64, 0, s>>>(b0, b1, T, G, tol, mr, ws);
+        k_aca_subwave<64><<<grid_for(nb, 1), 64, 0, s>>>(q0, q1, T, G, tol, mr, ws);
     } else {
-        k_aca_workgroup<<<int(nb), kWG, 0, s>>>(b0, T, G, tol, mr, ws);
+        k_aca_workgroup<<<int(nb), kWG, 0, s>>>(q0, T, G, tol, mr, ws);
     }
     H3D_LAUNCH_CHECK();
 }
 
-// per-block workspace sizes (doubles) and, when pivots are kept, their offsets
-void aca_workspace_sizes(Plan &P, int64_t *ws, int64_t *kc2, hipStream_t s) {
-    if (P.nfar == 0)
+void aca_workspace_sizes(Plan &P, const int32_t *list, int64_t cnt, int kws, int64_t *ws,
+                         hipStream_t s) {
+    if (cnt <= 0)
         return;
-    k_ws_size<<<grid_for(P.nfar, 256), 256, 0, s>>>(P.nfar, P.blk_m, P.blk_n, P.cfg.max_rank, ws,
-                                                    kc2);
+    k_ws_size<<<grid_for(cnt, 256), 256, 0, s>>>(cnt, list, P.blk_m, P.blk_n, P.cfg.max_rank, kws,
+                                                 ws);
+    H3D_LAUNCH_CHECK();
+}
+
+void aca_pivot_sizes(Plan &P, int64_t *kc2, hipStream_t s) {
+    if (P.nfar <= 0)
+        return;
+    k_piv_size<<<grid_for(P.nfar, 256), 256, 0, s>>>(P.nfar, P.blk_m, P.blk_n, P.cfg.max_rank, kc2);
     H3D_LAUNCH_CHECK();
 }
 

@@ -11,9 +11,12 @@
 
 namespace h3d {
 
-void aca_level_batch(Plan &P, int level, int64_t b0, int64_t b1, double *ws, const int64_t *ws_off,
-                     int64_t ws_base, unsigned int *ncapped, hipStream_t s);
-void aca_workspace_sizes(Plan &P, int64_t *ws, int64_t *kc2, hipStream_t s);
+void aca_level_batch(Plan &P, int level, const int32_t *list, int64_t q0, int64_t q1, double *ws,
+                     const int64_t *ws_off, int64_t ws_base, int kws, int32_t *overflow,
+                     unsigned int *ncapped, hipStream_t s);
+void aca_workspace_sizes(Plan &P, const int32_t *list, int64_t cnt, int kws, int64_t *ws,
+                         hipStream_t s);
+void aca_pivot_sizes(Plan &P, int64_t *kc2, hipStream_t s);
 
 namespace {
 
@@ -34,35 +37,59 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-__global__ void k_pack_sizes(int64_t b0, int64_t b1, const int32_t *__restrict__ m,
-                             const int32_t *__restrict__ n, const int32_t *__restrict__ rank,
-                             int64_t *__restrict__ mk, int64_t *__restrict__ nk) {
-    int64_t b = b0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (b >= b1)
+__global__ void k_pack_sizes(int64_t q0, int64_t q1, const int32_t *__restrict__ list,
+                             const int32_t *__restrict__ m, const int32_t *__restrict__ n,
+                             const int32_t *__restrict__ rank, int64_t *__restrict__ mk,
+                             int64_t *__restrict__ nk) {
+    int64_t q = q0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= q1)
         return;
-    mk[b - b0] = int64_t(m[b]) * rank[b];
-    nk[b - b0] = int64_t(n[b]) * rank[b];
+    const int64_t b = list[q];
+    mk[q - q0] = int64_t(m[b]) * rank[b];
+    nk[q - q0] = int64_t(n[b]) * rank[b];
+}
+
+__global__ void k_iota(int64_t n, int32_t *__restrict__ v) {
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n)
+        v[i] = int32_t(i);
+}
+
+__global__ void k_flag_i64(int64_t n, const int32_t *__restrict__ flag, int64_t *__restrict__ out) {
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n)
+        out[i] = flag[i] ? 1 : 0;
+}
+
+// deterministic compaction of the flagged blocks (ascending block order)
+__global__ void k_compact(int64_t n, const int32_t *__restrict__ flag, const int64_t *__restrict__ pos,
+                          int32_t *__restrict__ list) {
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n && flag[i])
+        list[pos[i]] = int32_t(i);
 }
 
 template <int DT>
 __global__ void __launch_bounds__(256)
-    k_pack(int64_t b0, int64_t b1, const int32_t *__restrict__ m, const int32_t *__restrict__ n,
-           const int32_t *__restrict__ rank, int max_rank, const double *__restrict__ ws,
-           const int64_t *__restrict__ ws_off, int64_t ws_base, const int64_t *__restrict__ uoff,
-           const int64_t *__restrict__ voff, char *cu, char *cv, void **uptr, void **vptr,
-           float *scale2) {
-    const int64_t b = b0 + ((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6);
+    k_pack(int64_t q0, int64_t q1, const int32_t *__restrict__ list, const int32_t *__restrict__ m,
+           const int32_t *__restrict__ n, const int32_t *__restrict__ rank, int max_rank, int kws,
+           const double *__restrict__ ws, const int64_t *__restrict__ ws_off, int64_t ws_base,
+           const int64_t *__restrict__ uoff, const int64_t *__restrict__ voff, char *cu, char *cv,
+           void **uptr, void **vptr, float *scale2) {
+    const int64_t q = q0 + ((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6);
     const int lane = threadIdx.x & 63;
-    if (b >= b1)
+    if (q >= q1)
         return;
+    const int64_t b = list[q];
     const int mb = m[b], nb = n[b], k = rank[b];
     int kcap = mb < nb ? mb : nb;
     if (max_rank > 0 && max_rank < kcap)
         kcap = max_rank;
-    const double *U = ws + (ws_off[b] - ws_base);
+    kcap = min(kcap, kws);
+    const double *U = ws + (ws_off[q] - ws_base);
     const double *V = U + int64_t(mb) * kcap;
     const int64_t nu = int64_t(mb) * k, nv = int64_t(nb) * k;
-    const int64_t ou = uoff[b - b0], ov = voff[b - b0];
+    const int64_t ou = uoff[q - q0], ov = voff[q - q0];
     if (DT == H3D_F64) {
         double *du = reinterpret_cast<double *>(cu) + ou;
         double *dv = reinterpret_cast<double *>(cv) + ov;
@@ -126,14 +153,25 @@ __global__ void k_rank_i64(int64_t nfar, const int32_t *__restrict__ rank, int64
         out[b] = 0;
 }
 
-__global__ void k_col_blk(int64_t nfar, const int32_t *__restrict__ rank,
-                          const int64_t *__restrict__ col0, int32_t *__restrict__ col_blk) {
-    int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (b >= nfar)
+// stage-1 work items: block b contributes ceil(rank / span) items
+__global__ void k_item_count(int64_t b0, int64_t b1, int span, const int32_t *__restrict__ rank,
+                             int64_t *__restrict__ cnt) {
+    int64_t b = b0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= b1)
         return;
-    const int64_t c0 = col0[b];
-    for (int c = 0; c < rank[b]; ++c)
-        col_blk[c0 + c] = int32_t(b);
+    cnt[b] = (rank[b] + span - 1) / span;
+}
+
+__global__ void k_item_fill(int64_t b0, int64_t b1, int span, const int32_t *__restrict__ rank,
+                            const int64_t *__restrict__ off, int32_t *__restrict__ items) {
+    int64_t b = b0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= b1)
+        return;
+    const int64_t o = off[b];
+    for (int c = 0, q = 0; c < rank[b]; c += span, ++q) {
+        items[2 * (o + q)] = int32_t(b);
+        items[2 * (o + q) + 1] = c;
+    }
 }
 
 // per-level sums of (m + n) k and of k, and the rank maximum
@@ -202,6 +240,50 @@ __global__ void __launch_bounds__(256)
 
 size_t dtype_size(int dt) { return dt == H3D_F64 ? 8 : (dt == H3D_F32 ? 4 : 2); }
 
+// Stage-1 shape per level: S lanes per column (about the level's box size),
+// and a span of columns per work item of roughly 16K factor entries.
+void build_items(Plan &P, hipStream_t s) {
+    const int64_t nf = P.nfar;
+    int64_t *cnt = P.mem.alloc_n<int64_t>(nf + 1);
+    H3D_HIP(hipMemsetAsync(cnt + nf, 0, sizeof(int64_t), s));
+    for (int l = 1; l <= P.L; ++l) {
+        int S = 4;
+        while (S < 64 && S < P.mean_box[l])
+            S *= 2;
+        const int ns = 64 / S, u = S >= 32 ? 8 : 4;
+        const int per_pass = ns * u;
+        const int mean = std::max(1, P.mean_box[l]);
+        const int reps = std::max(1, 16384 / (per_pass * mean));
+        P.s1_width[l] = S;
+        P.s1_span[l] = per_pass * reps;
+        const int64_t b0 = P.lvl_blk[l], b1 = P.lvl_blk[l + 1];
+        if (b1 > b0) {
+            k_item_count<<<grid_for(b1 - b0, 256), 256, 0, s>>>(b0, b1, P.s1_span[l], P.blk_rank, cnt);
+            H3D_LAUNCH_CHECK();
+        }
+    }
+    P.nitems = scan_exclusive_i64(P, cnt, cnt, nf + 1, s);
+    P.items = P.mem.alloc_n<int32_t>(2 * std::max<int64_t>(P.nitems, 1));
+    for (int l = 1; l <= P.L; ++l) {
+        const int64_t b0 = P.lvl_blk[l], b1 = P.lvl_blk[l + 1];
+        if (b1 > b0) {
+            k_item_fill<<<grid_for(b1 - b0, 256), 256, 0, s>>>(b0, b1, P.s1_span[l], P.blk_rank, cnt,
+                                                               P.items);
+            H3D_LAUNCH_CHECK();
+        }
+    }
+    for (int l = 1; l <= P.L + 1 && l <= kMaxLevels; ++l) {
+        int64_t v = 0;
+        to_host(&v, cnt + P.lvl_blk[l], 1, s);
+        P.lvl_item[l] = v;
+    }
+    P.mem.release(cnt);
+    int lc = P.L;
+    while (lc > 0 && P.mean_box[lc] < 48)
+        --lc;
+    P.chunk_level = lc;
+}
+
 }  // namespace
 
 void factors_build(Plan &P, hipStream_t s) {
@@ -216,100 +298,129 @@ void factors_build(Plan &P, hipStream_t s) {
         P.blk_scale = P.mem.alloc_n<float>(2 * nf);
     if (nf == 0) {
         P.ncols = 0;
-        P.col_blk = P.mem.alloc_n<int32_t>(1);
+        P.nitems = 0;
+        P.items = P.mem.alloc_n<int32_t>(2);
         H3D_HIP(hipMemsetAsync(P.blk_col0, 0, sizeof(int64_t), s));
         return;
     }
     H3D_HIP(hipMemsetAsync(P.blk_rank, 0, sizeof(int32_t) * size_t(nf), s));
 
-    // workspace sizes and batches
-    int64_t *ws_off = P.mem.alloc_n<int64_t>(nf + 1);
-    int64_t *kc2 = nullptr;
     const bool keep_piv = (P.cfg.flags & H3D_FLAG_KEEP_PIVOTS) != 0;
-    if (keep_piv)
-        kc2 = P.mem.alloc_n<int64_t>(nf + 1);
-    H3D_HIP(hipMemsetAsync(ws_off + nf, 0, sizeof(int64_t), s));
-    if (kc2)
-        H3D_HIP(hipMemsetAsync(kc2 + nf, 0, sizeof(int64_t), s));
-    aca_workspace_sizes(P, ws_off, kc2, s);
-    const int64_t ws_total = scan_exclusive_i64(P, ws_off, ws_off, nf + 1, s);
     if (keep_piv) {
-        int64_t tot = scan_exclusive_i64(P, kc2, kc2, nf + 1, s);
+        int64_t *kc2 = P.mem.alloc_n<int64_t>(nf + 1);
+        H3D_HIP(hipMemsetAsync(kc2 + nf, 0, sizeof(int64_t), s));
+        aca_pivot_sizes(P, kc2, s);
+        const int64_t tot = scan_exclusive_i64(P, kc2, kc2, nf + 1, s);
         P.blk_pivoff = kc2;
         P.blk_piv = P.mem.alloc_n<int32_t>(tot);
     }
-    std::vector<int64_t> h_ws(size_t(nf) + 1);
-    to_host(h_ws.data(), ws_off, nf + 1, s);
-    int64_t budget = (P.cfg.workspace_bytes > 0 ? P.cfg.workspace_bytes : (int64_t(4) << 30)) / 8;
-    int64_t largest = 0;
-    for (int64_t b = 0; b < nf; ++b)
-        largest = std::max(largest, h_ws[size_t(b) + 1] - h_ws[size_t(b)]);
-    budget = std::max(budget, largest);
-    budget = std::min(budget, ws_total);
-    double *ws = P.mem.alloc_n<double>(budget);
+    const int64_t budget0 =
+        (P.cfg.workspace_bytes > 0 ? P.cfg.workspace_bytes : (int64_t(4) << 30)) / 8;
     unsigned int *ncapped = P.mem.alloc_n<unsigned int>(1);
     H3D_HIP(hipMemsetAsync(ncapped, 0, sizeof(unsigned int), s));
+    int32_t *overflow = P.mem.alloc_n<int32_t>(nf);
+    H3D_HIP(hipMemsetAsync(overflow, 0, sizeof(int32_t) * size_t(nf), s));
     int64_t *mk = P.mem.alloc_n<int64_t>(nf + 1);
     int64_t *nk = P.mem.alloc_n<int64_t>(nf + 1);
+    int64_t *ws_off = P.mem.alloc_n<int64_t>(nf + 1);
+    int32_t *list = P.mem.alloc_n<int32_t>(nf);
+    k_iota<<<grid_for(nf, 256), 256, 0, s>>>(nf, list);
+    H3D_LAUNCH_CHECK();
+    int64_t cnt = nf;
     const size_t es = dtype_size(dt);
-
     hipEvent_t ev0, ev1;
     H3D_HIP(hipEventCreate(&ev0));
     H3D_HIP(hipEventCreate(&ev1));
     double aca_ms = 0.0;
 
-    int64_t b0 = 0;
-    while (b0 < nf) {
-        int64_t b1 = b0 + 1;
-        while (b1 < nf && h_ws[size_t(b1) + 1] - h_ws[size_t(b0)] <= budget)
-            ++b1;
-        const int64_t base = h_ws[size_t(b0)];
-        H3D_HIP(hipEventRecord(ev0, s));
-        for (int l = 1; l <= P.L; ++l) {
-            const int64_t lb = std::max(b0, P.lvl_blk[l]);
-            const int64_t le = std::min(b1, P.lvl_blk[l + 1]);
-            if (le > lb)
-                aca_level_batch(P, l, lb, le, ws, ws_off, base, ncapped, s);
+    // Passes with a growing workspace column cap: a block stopped by the cap
+    // before finishing is run again from the start with four times the room.
+    // ACA is deterministic, so the result equals one run with unlimited room.
+    for (int kws = 128; cnt > 0; kws = kws >= (1 << 28) ? kws : kws * 4) {
+        H3D_HIP(hipMemsetAsync(ws_off + cnt, 0, sizeof(int64_t), s));
+        aca_workspace_sizes(P, list, cnt, kws, ws_off, s);
+        const int64_t ws_total = scan_exclusive_i64(P, ws_off, ws_off, cnt + 1, s);
+        std::vector<int64_t> h_ws(size_t(cnt) + 1);
+        std::vector<int32_t> h_list(static_cast<size_t>(cnt));
+        to_host(h_ws.data(), ws_off, cnt + 1, s);
+        to_host(h_list.data(), list, cnt, s);
+        int64_t largest = 0;
+        for (int64_t q = 0; q < cnt; ++q)
+            largest = std::max(largest, h_ws[size_t(q) + 1] - h_ws[size_t(q)]);
+        const int64_t budget = std::min(std::max(budget0, largest), ws_total);
+        double *ws = P.mem.alloc_n<double>(budget);
+        int64_t q0 = 0;
+        while (q0 < cnt) {
+            int64_t q1 = q0 + 1;
+            while (q1 < cnt && h_ws[size_t(q1) + 1] - h_ws[size_t(q0)] <= budget)
+                ++q1;
+            const int64_t base = h_ws[size_t(q0)];
+            H3D_HIP(hipEventRecord(ev0, s));
+            for (int l = 1; l <= P.L; ++l) {
+                // the list is in block order: find this level's positions
+                const auto lo = std::lower_bound(h_list.begin() + q0, h_list.begin() + q1,
+                                                 int32_t(P.lvl_blk[l]));
+                const auto hi = std::lower_bound(lo, h_list.begin() + q1, int32_t(P.lvl_blk[l + 1]));
+                const int64_t a = lo - h_list.begin(), e = hi - h_list.begin();
+                if (e > a)
+                    aca_level_batch(P, l, list, a, e, ws, ws_off, base, kws, overflow, ncapped, s);
+            }
+            H3D_HIP(hipEventRecord(ev1, s));
+            H3D_HIP(hipEventSynchronize(ev1));
+            float ms = 0.f;
+            H3D_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+            aca_ms += ms;
+            // pack the finished blocks of the batch into their own chunk
+            const int64_t nb = q1 - q0;
+            k_pack_sizes<<<grid_for(nb, 256), 256, 0, s>>>(q0, q1, list, P.blk_m, P.blk_n,
+                                                           P.blk_rank, mk, nk);
+            H3D_LAUNCH_CHECK();
+            H3D_HIP(hipMemsetAsync(mk + nb, 0, sizeof(int64_t), s));
+            H3D_HIP(hipMemsetAsync(nk + nb, 0, sizeof(int64_t), s));
+            const int64_t tu = scan_exclusive_i64(P, mk, mk, nb + 1, s);
+            const int64_t tv = scan_exclusive_i64(P, nk, nk, nb + 1, s);
+            if (tu + tv > 0) {
+                const size_t ubytes = (size_t(tu) * es + 255) & ~size_t(255);
+                char *chunk = static_cast<char *>(P.mem.alloc(ubytes + size_t(tv) * es + 256));
+                P.chunks.push_back(chunk);
+                char *cu = chunk, *cv = chunk + ubytes;
+                const int grid = grid_for(nb * 64, 256);
+                const int mr = P.cfg.max_rank;
+                switch (dt) {
+                case H3D_F64:
+                    k_pack<H3D_F64><<<grid, 256, 0, s>>>(q0, q1, list, P.blk_m, P.blk_n, P.blk_rank, mr,
+                                                         kws, ws, ws_off, base, mk, nk, cu, cv,
+                                                         P.blk_uptr, P.blk_vptr, P.blk_scale);
+                    break;
+                case H3D_F32:
+                    k_pack<H3D_F32><<<grid, 256, 0, s>>>(q0, q1, list, P.blk_m, P.blk_n, P.blk_rank, mr,
+                                                         kws, ws, ws_off, base, mk, nk, cu, cv,
+                                                         P.blk_uptr, P.blk_vptr, P.blk_scale);
+                    break;
+                default:
+                    k_pack<H3D_BF16_SCALED><<<grid, 256, 0, s>>>(
+                        q0, q1, list, P.blk_m, P.blk_n, P.blk_rank, mr, kws, ws, ws_off, base, mk,
+                        nk, cu, cv, P.blk_uptr, P.blk_vptr, P.blk_scale);
+                    break;
+                }
+                H3D_LAUNCH_CHECK();
+            }
+            H3D_HIP(hipStreamSynchronize(s));
+            q0 = q1;
         }
-        H3D_HIP(hipEventRecord(ev1, s));
-        H3D_HIP(hipEventSynchronize(ev1));
-        float ms = 0.f;
-        H3D_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-        aca_ms += ms;
-        // pack the batch into its own chunk
-        const int64_t nb = b1 - b0;
-        k_pack_sizes<<<grid_for(nb, 256), 256, 0, s>>>(b0, b1, P.blk_m, P.blk_n, P.blk_rank, mk, nk);
+        P.mem.release(ws);
+        // blocks to run again
+        int64_t *pos = mk;  // reuse as scan buffer of nf + 1 entries
+        k_flag_i64<<<grid_for(nf, 256), 256, 0, s>>>(nf, overflow, pos);
         H3D_LAUNCH_CHECK();
-        H3D_HIP(hipMemsetAsync(mk + nb, 0, sizeof(int64_t), s));
-        H3D_HIP(hipMemsetAsync(nk + nb, 0, sizeof(int64_t), s));
-        const int64_t tu = scan_exclusive_i64(P, mk, mk, nb + 1, s);
-        const int64_t tv = scan_exclusive_i64(P, nk, nk, nb + 1, s);
-        const size_t ubytes = (size_t(tu) * es + 255) & ~size_t(255);
-        char *chunk = static_cast<char *>(P.mem.alloc(ubytes + size_t(tv) * es + 256));
-        P.chunks.push_back(chunk);
-        char *cu = chunk, *cv = chunk + ubytes;
-        const int grid = grid_for(nb * 64, 256);
-        switch (dt) {
-        case H3D_F64:
-            k_pack<H3D_F64><<<grid, 256, 0, s>>>(b0, b1, P.blk_m, P.blk_n, P.blk_rank,
-                                                 P.cfg.max_rank, ws, ws_off, base, mk, nk, cu, cv,
-                                                 P.blk_uptr, P.blk_vptr, P.blk_scale);
-            break;
-        case H3D_F32:
-            k_pack<H3D_F32><<<grid, 256, 0, s>>>(b0, b1, P.blk_m, P.blk_n, P.blk_rank,
-                                                 P.cfg.max_rank, ws, ws_off, base, mk, nk, cu, cv,
-                                                 P.blk_uptr, P.blk_vptr, P.blk_scale);
-            break;
-        default:
-            k_pack<H3D_BF16_SCALED><<<grid, 256, 0, s>>>(b0, b1, P.blk_m, P.blk_n, P.blk_rank,
-                                                         P.cfg.max_rank, ws, ws_off, base, mk, nk,
-                                                         cu, cv, P.blk_uptr, P.blk_vptr,
-                                                         P.blk_scale);
-            break;
+        H3D_HIP(hipMemsetAsync(pos + nf, 0, sizeof(int64_t), s));
+        // only listed blocks can have the flag set; others were cleared before
+        cnt = scan_exclusive_i64(P, pos, pos, nf + 1, s);
+        if (cnt > 0) {
+            k_compact<<<grid_for(nf, 256), 256, 0, s>>>(nf, overflow, pos, list);
+            H3D_LAUNCH_CHECK();
+            H3D_HIP(hipMemsetAsync(overflow, 0, sizeof(int32_t) * size_t(nf), s));
         }
-        H3D_LAUNCH_CHECK();
-        H3D_HIP(hipStreamSynchronize(s));
-        b0 = b1;
     }
     (void)hipEventDestroy(ev0);
     (void)hipEventDestroy(ev1);
@@ -317,19 +428,18 @@ void factors_build(Plan &P, hipStream_t s) {
     unsigned int hcap = 0;
     to_host(&hcap, ncapped, 1, s);
     P.stats.n_rank_capped = hcap;
-    P.mem.release(ws);
     P.mem.release(ncapped);
+    P.mem.release(overflow);
     P.mem.release(mk);
     P.mem.release(nk);
     P.mem.release(ws_off);
+    P.mem.release(list);
 
     // factor columns: z index of every block, owner of every column
     k_rank_i64<<<grid_for(nf + 1, 256), 256, 0, s>>>(nf, P.blk_rank, P.blk_col0);
     H3D_LAUNCH_CHECK();
     P.ncols = scan_exclusive_i64(P, P.blk_col0, P.blk_col0, nf + 1, s);
-    P.col_blk = P.mem.alloc_n<int32_t>(P.ncols);
-    k_col_blk<<<grid_for(nf, 256), 256, 0, s>>>(nf, P.blk_rank, P.blk_col0, P.col_blk);
-    H3D_LAUNCH_CHECK();
+    build_items(P, s);
     for (int l = 1; l <= P.L + 1 && l <= kMaxLevels; ++l) {
         int64_t v = 0;
         to_host(&v, P.blk_col0 + P.lvl_blk[l], 1, s);

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
 #include <map>
@@ -224,7 +225,13 @@ struct Plan {
     int64_t ncols = 0;             // sum of ranks
     int64_t entries_v = 0;         // sum of n k (entries of all V_b)
     int64_t lvl_col[kMaxLevels + 1] = {0};
-    int32_t *col_blk = nullptr;    // [ncols] owning block of each column
+    // stage-1 work items (block, first column), in block order
+    int64_t nitems = 0;
+    int32_t *items = nullptr;      // [2 nitems]
+    int64_t lvl_item[kMaxLevels + 1] = {0};
+    int s1_width[kMaxLevels + 1] = {0};  // lanes per column at each level
+    int s1_span[kMaxLevels + 1] = {0};   // columns per work item at each level
+    int chunk_level = 0;           // stage-2 boxes: about 64 rows per wave
     int mean_box[kMaxLevels + 1] = {0};  // mean size of non-empty boxes per level
     int max_box[kMaxLevels + 1] = {0};
 

@@ -152,20 +152,29 @@ __global__ void __launch_bounds__(64)
 }
 
 // ---------------------------------------------------------------------------
-// stage 1: z[col] = dot(column col of its block's factor, x segment)
+// stage 1: z[col] = dot(column col of its block's factor, x segment).
+// Work item = (block, first column); a wave streams up to `span` columns of
+// the block, NS = 64/S columns side by side (S lanes per column) and U such
+// groups per pass, so every lane keeps U independent loads in flight.
 struct S1Level {
-    int64_t c0, c1;  // columns of this level
-    int64_t w0;      // first wave of this level
+    int64_t i0, i1;  // items of this level
     int S;           // lanes per column
+    int span;        // columns per item
 };
 struct S1Tab {
     S1Level lv[kMaxLevels + 1];
     int nlev;
 };
 
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v)));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
+    return int64_t((uint64_t(hi) << 32) | lo);
+}
+
 template <int S, int DT, int NR>
-__device__ __forceinline__ void stage1_cols(int64_t wave, const S1Level &L, const int32_t *__restrict__ col_blk,
-                                            const int64_t *__restrict__ blk_col0,
+__device__ __forceinline__ void stage1_item(int2 item, int span, const int64_t *__restrict__ blk_col0,
+                                            const int32_t *__restrict__ rank,
                                             const int32_t *__restrict__ seg_len,
                                             const int32_t *__restrict__ seg_off,
                                             void *const *__restrict__ seg_ptr,
@@ -173,89 +182,136 @@ __device__ __forceinline__ void stage1_cols(int64_t wave, const S1Level &L, cons
                                             const double *__restrict__ xp, int64_t n,
                                             double *__restrict__ z, int64_t ldz) {
     using T = typename Fac<DT>::T;
+    constexpr int NS = 64 / S;
+    constexpr int U = S >= 32 ? 8 : 4;
     const int lane = threadIdx.x & 63;
-    const int r = lane % S;
-    const int64_t col = L.c0 + wave * (64 / S) + lane / S;
-    const bool act = col < L.c1;
-    int len = 0;
-    int64_t off = 0;
-    const T *p = nullptr;
+    const int r = lane % S, sub = lane / S;
+    const int b = item.x;
+    const int len = seg_len[b];
+    const int64_t off = seg_off[b];
+    const int64_t col0 = blk_col0[b];
+    const int k = rank[b];
+    const T *p = static_cast<const T *>(seg_ptr[b]);
     double sc = 1.0;
-    if (act) {
-        const int32_t b = col_blk[col];
-        len = seg_len[b];
-        off = seg_off[b];
-        p = static_cast<const T *>(seg_ptr[b]) + (col - blk_col0[b]) * len;
-        if (DT == H3D_BF16_SCALED)
-            sc = double(scale2[2 * b]) * double(scale2[2 * b + 1]);
-    }
+    if (DT == H3D_BF16_SCALED)
+        sc = double(scale2[2 * b]) * double(scale2[2 * b + 1]);
+    const int cend = min(item.y + span, k);
     for (int rb = 0; rb < nrhs; rb += NR) {
-        double acc[NR];
+        for (int cb = item.y; cb < cend; cb += NS * U) {
+            double acc[U][NR];
 #pragma unroll
-        for (int c = 0; c < NR; ++c)
-            acc[c] = 0.0;
-        if (act) {
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int q = 0; q < NR; ++q)
+                    acc[u][q] = 0.0;
             for (int j = r; j < len; j += S) {
-                const double v = Fac<DT>::ld(p + j);
+                double xv[NR];
 #pragma unroll
-                for (int c = 0; c < NR; ++c)
-                    if (NR == 1 || rb + c < nrhs)
-                        acc[c] += v * xp[(rb + c) * n + off + j];
+                for (int q = 0; q < NR; ++q)
+                    xv[q] = (NR == 1 || rb + q < nrhs) ? xp[(rb + q) * n + off + j] : 0.0;
+                double v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int c = cb + sub + u * NS;
+                    v[u] = c < cend ? Fac<DT>::ld(p + int64_t(c) * len + j) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int q = 0; q < NR; ++q)
+                        acc[u][q] += v[u] * xv[q];
+            }
+#pragma unroll
+            for (int o = S / 2; o > 0; o >>= 1)
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int q = 0; q < NR; ++q)
+                        acc[u][q] += __shfl_xor(acc[u][q], o, S);
+            if (r == 0) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int c = cb + sub + u * NS;
+                    if (c < cend)
+#pragma unroll
+                        for (int q = 0; q < NR; ++q)
+                            if (NR == 1 || rb + q < nrhs)
+                                z[(rb + q) * ldz + col0 + c] = acc[u][q] * sc;
+                }
             }
         }
-#pragma unroll
-        for (int o = S / 2; o > 0; o >>= 1)
-#pragma unroll
-            for (int c = 0; c < NR; ++c)
-                acc[c] += __shfl_xor(acc[c], o, S);
-        if (act && r == 0)
-#pragma unroll
-            for (int c = 0; c < NR; ++c)
-                if (NR == 1 || rb + c < nrhs)
-                    z[(rb + c) * ldz + col] = acc[c] * sc;
     }
 }
 
 template <int DT, int NR>
 __global__ void __launch_bounds__(256)
-    k_stage1(S1Tab tab, int64_t nwaves, const int32_t *__restrict__ col_blk,
-             const int64_t *__restrict__ blk_col0, const int32_t *__restrict__ seg_len,
-             const int32_t *__restrict__ seg_off, void *const *__restrict__ seg_ptr,
-             const float *__restrict__ scale2, int nrhs, const double *__restrict__ xp, int64_t n,
-             double *__restrict__ z, int64_t ldz) {
-    const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-    if (wave >= nwaves)
+    k_stage1(S1Tab tab, int64_t nitems, const int2 *__restrict__ items,
+             const int64_t *__restrict__ blk_col0, const int32_t *__restrict__ rank,
+             const int32_t *__restrict__ seg_len, const int32_t *__restrict__ seg_off,
+             void *const *__restrict__ seg_ptr, const float *__restrict__ scale2, int nrhs,
+             const double *__restrict__ xp, int64_t n, double *__restrict__ z, int64_t ldz) {
+    const int64_t w = uniform64((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6);
+    if (w >= nitems)
         return;
     int li = 0;
-    while (li + 1 < tab.nlev && wave >= tab.lv[li + 1].w0)
+    while (li + 1 < tab.nlev && w >= tab.lv[li + 1].i0)
         ++li;
-    const S1Level L = tab.lv[li];
-    const int64_t w = wave - L.w0;
-    switch (L.S) {
+    const int S = tab.lv[li].S, span = tab.lv[li].span;
+    const int2 it = items[w];
+    switch (S) {
     case 4:
-        stage1_cols<4, DT, NR>(w, L, col_blk, blk_col0, seg_len, seg_off, seg_ptr, scale2, nrhs, xp, n, z, ldz);
+        stage1_item<4, DT, NR>(it, span, blk_col0, rank, seg_len, seg_off, seg_ptr, scale2, nrhs, xp, n, z, ldz);
         break;
     case 8:
-        stage1_cols<8, DT, NR>(w, L, col_blk, blk_col0, seg_len, seg_off, seg_ptr, scale2, nrhs, xp, n, z, ldz);
+        stage1_item<8, DT, NR>(it, span, blk_col0, rank, seg_len, seg_off, seg_ptr, scale2, nrhs, xp, n, z, ldz);
         break;
     case 16:
-        stage1_cols<16, DT, NR>(w, L, col_blk, blk_col0, seg_len, seg_off, seg_ptr, scale2, nrhs, xp, n, z, ldz);
+        stage1_item<16, DT, NR>(it, span, blk_col0, rank, seg_len, seg_off, seg_ptr, scale2, nrhs, xp, n, z, ldz);
         break;
     case 32:
-        stage1_cols<32, DT, NR>(w, L, col_blk, blk_col0, seg_len, seg_off, seg_ptr, scale2, nrhs, xp, n, z, ldz);
+        stage1_item<32, DT, NR>(it, span, blk_col0, rank, seg_len, seg_off, seg_ptr, scale2, nrhs, xp, n, z, ldz);
         break;
     default:
-        stage1_cols<64, DT, NR>(w, L, col_blk, blk_col0, seg_len, seg_off, seg_ptr, scale2, nrhs, xp, n, z, ldz);
+        stage1_item<64, DT, NR>(it, span, blk_col0, rank, seg_len, seg_off, seg_ptr, scale2, nrhs, xp, n, z, ldz);
         break;
     }
 }
 
 // ---------------------------------------------------------------------------
-// stage 2: one wave per box of the chunk level, one lane per row
+// stage 2: one wave per box of the chunk level, one lane per row.  At levels
+// up to the chunk level every lane of the wave lies in the same box, so the
+// block metadata and z are wave-uniform (scalar loads) and each lane streams
+// one column slice of U per load, U2 loads in flight.
 struct S2Tab {
     int64_t box_base[kMaxLevels + 1];
     int L, lc;
 };
+
+template <int DT, int NR, int U2>
+__device__ __forceinline__ void stage2_block(const typename Fac<DT>::T *__restrict__ p, int bm, int k,
+                                             const double *__restrict__ zz, int64_t ldz, int rb,
+                                             int nrhs, double (&acc)[NR]) {
+    int c = 0;
+    for (; c + U2 <= k; c += U2) {
+        double v[U2];
+#pragma unroll
+        for (int u = 0; u < U2; ++u)
+            v[u] = Fac<DT>::ld(p + int64_t(c + u) * bm);
+#pragma unroll
+        for (int u = 0; u < U2; ++u)
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+                if (NR == 1 || rb + q < nrhs)
+                    acc[q] += v[u] * zz[(rb + q) * ldz + c + u];
+    }
+    for (; c < k; ++c) {
+        const double v = Fac<DT>::ld(p + int64_t(c) * bm);
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+            if (NR == 1 || rb + q < nrhs)
+                acc[q] += v * zz[(rb + q) * ldz + c];
+    }
+}
 
 template <int DT, int NR>
 __global__ void __launch_bounds__(256)
@@ -267,7 +323,7 @@ __global__ void __launch_bounds__(256)
              void *__restrict__ yout, int64_t ldy, int io_f32) {
     using T = typename Fac<DT>::T;
     const int L = tab.L, lc = tab.lc;
-    const int64_t B = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    const int64_t B = uniform64((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6);
     const int lane = threadIdx.x & 63;
     if (B >= (int64_t(1) << (3 * lc)))
         return;
@@ -283,7 +339,23 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
             for (int c = 0; c < NR; ++c)
                 acc[c] = (NR == 1 || rb + c < nrhs) ? yn[(rb + c) * n + rr] : 0.0;
-            for (int l = 1; l <= L; ++l) {
+            // levels whose boxes contain the whole chunk box: wave-uniform
+            for (int l = 1; l <= lc; ++l) {
+                const int sh = 3 * (L - l);
+                const int64_t t = B >> (3 * (lc - l));
+                const int64_t g = tab.box_base[l] + t;
+                const int32_t bs = leaf_off[t << sh];
+                const int32_t bm = leaf_off[(t + 1) << sh] - bs;
+                const int32_t loc = rr - bs;
+                const int64_t e0 = grp_begin[g], e1 = grp_begin[g + 1];
+                for (int64_t e = e0; e < e1; ++e) {
+                    const int64_t bi = grp_blk ? grp_blk[e] : e;
+                    const T *p = static_cast<const T *>(fptr[bi]) + loc;
+                    stage2_block<DT, NR, 8>(p, bm, rank[bi], z + blk_col0[bi], ldz, rb, nrhs, acc);
+                }
+            }
+            // finer levels: every lane follows the box of its own row
+            for (int l = lc + 1; l <= L; ++l) {
                 const int sh = 3 * (L - l);
                 const int64_t t = int64_t(leaf) >> sh;
                 const int64_t g = tab.box_base[l] + t;
@@ -293,16 +365,8 @@ __global__ void __launch_bounds__(256)
                 const int64_t e0 = grp_begin[g], e1 = grp_begin[g + 1];
                 for (int64_t e = e0; e < e1; ++e) {
                     const int64_t bi = grp_blk ? grp_blk[e] : e;
-                    const int k = rank[bi];
-                    const int64_t c0 = blk_col0[bi];
                     const T *p = static_cast<const T *>(fptr[bi]) + loc;
-                    for (int c = 0; c < k; ++c) {
-                        const double v = Fac<DT>::ld(p + int64_t(c) * bm);
-#pragma unroll
-                        for (int q = 0; q < NR; ++q)
-                            if (NR == 1 || rb + q < nrhs)
-                                acc[q] += v * z[(rb + q) * ldz + c0 + c];
-                    }
+                    stage2_block<DT, NR, 4>(p, bm, rank[bi], z + blk_col0[bi], ldz, rb, nrhs, acc);
                 }
             }
             if (act) {
@@ -320,13 +384,6 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-int pick_subwave(int mean) {
-    int S = 4;
-    while (S < 64 && S < mean)
-        S *= 2;
-    return S;
-}
-
 template <int DT, int NR>
 void launch_far(Plan &P, bool adjoint, int nrhs, const double *xp, double *z, const double *yn,
                 void *y, int64_t ldy, int io_f32, hipStream_t s) {
@@ -334,17 +391,15 @@ void launch_far(Plan &P, bool adjoint, int nrhs, const double *xp, double *z, co
     const int L = P.L;
     const size_t es = DT == H3D_F64 ? 8 : (DT == H3D_F32 ? 4 : 2);
     // stage 1
-    if (P.ncols > 0) {
+    if (P.nitems > 0) {
         S1Tab tab{};
-        int64_t w = 0;
         int nl = 0;
         for (int l = 1; l <= L; ++l) {
             S1Level lv;
-            lv.c0 = P.lvl_col[l];
-            lv.c1 = P.lvl_col[l + 1];
-            lv.S = pick_subwave(P.mean_box[l]);
-            lv.w0 = w;
-            w += ceil_div(lv.c1 - lv.c0, 64 / lv.S);
+            lv.i0 = P.lvl_item[l];
+            lv.i1 = P.lvl_item[l + 1];
+            lv.S = P.s1_width[l];
+            lv.span = P.s1_span[l];
             tab.lv[nl++] = lv;
         }
         tab.nlev = nl;
@@ -352,9 +407,9 @@ void launch_far(Plan &P, bool adjoint, int nrhs, const double *xp, double *z, co
         const int32_t *len = adjoint ? P.blk_m : P.blk_n;
         const int32_t *off = adjoint ? P.blk_toff : P.blk_soff;
         void *const *ptr = adjoint ? P.blk_uptr : P.blk_vptr;
-        k_stage1<DT, NR><<<grid_for(w * 64, 256), 256, 0, s>>>(tab, w, P.col_blk, P.blk_col0, len,
-                                                                off, ptr, P.blk_scale, nrhs, xp, n,
-                                                                z, P.ncols);
+        k_stage1<DT, NR><<<grid_for(P.nitems * 64, 256), 256, 0, s>>>(
+            tab, P.nitems, reinterpret_cast<const int2 *>(P.items), P.blk_col0, P.blk_rank, len,
+            off, ptr, P.blk_scale, nrhs, xp, n, z, P.ncols);
         H3D_LAUNCH_CHECK();
         const double side_entries =
             double(adjoint ? P.stats.factor_entries - P.entries_v : P.entries_v);
@@ -365,16 +420,13 @@ void launch_far(Plan &P, bool adjoint, int nrhs, const double *xp, double *z, co
     }
     // stage 2 (always: it also writes y)
     {
-        int lc = L;
-        while (lc > 0 && P.mean_box[lc] < 48)
-            --lc;
         S2Tab tab{};
         for (int l = 0; l <= kMaxLevels; ++l)
             tab.box_base[l] = P.box_base[l];
         tab.L = L;
-        tab.lc = lc;
+        tab.lc = P.chunk_level;
         hipEvent_t ev = P.prof.begin(s);
-        const int64_t nchunk = pow8(lc);
+        const int64_t nchunk = pow8(P.chunk_level);
         k_stage2<DT, NR><<<grid_for(nchunk * 64, 256), 256, 0, s>>>(
             tab, P.leaf_off, P.leaf_of, P.tgt_begin, adjoint ? P.src_blk : nullptr,
             adjoint ? P.blk_vptr : P.blk_uptr, P.blk_rank, P.blk_col0, z, P.ncols, yn, n, nrhs,
