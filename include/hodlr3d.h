@@ -71,7 +71,8 @@ typedef struct {
 } h3d_allocator;
 
 enum {
-    H3D_FLAG_KEEP_PIVOTS = 1 /* keep ACA pivots for h3d_export(H3D_EXPORT_PIVOTS) */
+    H3D_FLAG_KEEP_PIVOTS = 1, /* keep ACA pivots for h3d_export(H3D_EXPORT_PIVOTS) */
+    H3D_FLAG_NO_AUTOTUNE = 2  /* keep the default launch shapes (no timing at build) */
 };
 
 typedef struct {
@@ -144,6 +145,16 @@ h3d_status h3d_matvec(h3d_plan *plan, const void *x, void *y, int64_t nrhs, int6
 h3d_status h3d_matvec_adjoint(h3d_plan *plan, const void *x, void *y, int64_t nrhs,
                               int64_t ldx, int64_t ldy, int32_t io_dtype, void *hip_stream);
 
+/*
+ * Chooses the launch shapes of the factor streams for products with nrhs
+ * right-hand sides (nrhs == 1, or any nrhs > 1 for the multi-column kernels)
+ * by timing candidates on the plan's own factors on hip_stream.  h3d_build
+ * runs it for nrhs == 1 unless H3D_FLAG_NO_AUTOTUNE is set.  The shapes only
+ * change the order of floating-point sums inside a product, never which
+ * entries are summed; a plan's products stay bitwise reproducible.
+ */
+h3d_status h3d_autotune(h3d_plan *plan, int64_t nrhs, void *hip_stream);
+
 h3d_status h3d_get_stats(const h3d_plan *plan, h3d_stats *out);
 
 /* What h3d_export copies to host memory. */
@@ -174,6 +185,9 @@ const char *h3d_last_error(void);
  * stream it runs on.  h3d_profile_read synchronises those events and returns,
  * per kernel name, the launch count, the summed event time and the
  * algorithmic bytes and flops of one launch (the last one recorded).
+ * enable >= 2 additionally launches each factor stream level by level (names
+ * suffixed _L<level>), so that every level's stream rate can be read; the
+ * result of the product is the same up to the summation order of stage 2.
  */
 typedef struct {
     char name[48];

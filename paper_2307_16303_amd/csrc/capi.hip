@@ -154,6 +154,8 @@ h3d_status h3d_build(const double *points, int64_t n, const h3d_config *cfg,
         h3d::lists_build(P, s);
         h3d::factors_build(P, s);
         h3d::near_pair_count(P, s);
+        if (!(P.cfg.flags & H3D_FLAG_NO_AUTOTUNE))
+            h3d::autotune(P, 1, s);
         H3D_HIP(hipStreamSynchronize(s));
         h3d_stats &S = P.stats;
         S.n = n;
@@ -188,6 +190,17 @@ h3d_status h3d_matvec(h3d_plan *plan, const void *x, void *y, int64_t nrhs, int6
 h3d_status h3d_matvec_adjoint(h3d_plan *plan, const void *x, void *y, int64_t nrhs, int64_t ldx,
                               int64_t ldy, int32_t io_dtype, void *hip_stream) {
     return matvec_common(plan, x, y, nrhs, ldx, ldy, io_dtype, hip_stream, true);
+}
+
+h3d_status h3d_autotune(h3d_plan *plan, int64_t nrhs, void *hip_stream) {
+    if (!plan || !plan->P.built)
+        return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    if (nrhs < 1)
+        return invalid("nrhs must be >= 1");
+    return guarded([&] {
+        DeviceScope ds(plan->P.device);
+        h3d::autotune(plan->P, nrhs, static_cast<hipStream_t>(hip_stream));
+    });
 }
 
 h3d_status h3d_get_stats(const h3d_plan *plan, h3d_stats *out) {
@@ -333,6 +346,7 @@ h3d_status h3d_profile_enable(h3d_plan *plan, int32_t enable) {
     return guarded([&] {
         plan->P.prof.collect();
         plan->P.prof.on = enable != 0;
+        plan->P.prof.levels = enable >= 2;
     });
 }
 
@@ -358,8 +372,9 @@ h3d_status h3d_profile_read(h3d_plan *plan, h3d_kernel_profile *out, int32_t cap
             std::strncpy(out[i].name, pr.names[size_t(i)].c_str(), sizeof(out[i].name) - 1);
             out[i].launches = pr.launches[size_t(i)];
             out[i].total_ms = pr.total_ms[size_t(i)];
-            out[i].bytes_per_launch = pr.bytes[size_t(i)];
-            out[i].flops_per_launch = pr.flops[size_t(i)];
+            const double nl = double(std::max<int64_t>(pr.launches[size_t(i)], 1));
+            out[i].bytes_per_launch = pr.bytes[size_t(i)] / nl;
+            out[i].flops_per_launch = pr.flops[size_t(i)] / nl;
         }
     });
 }

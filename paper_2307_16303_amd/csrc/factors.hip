@@ -153,13 +153,33 @@ __global__ void k_rank_i64(int64_t nfar, const int32_t *__restrict__ rank, int64
         out[b] = 0;
 }
 
-// stage-1 work items: block b contributes ceil(rank / span) items
+// stage-1 work items of the blocks [b0, b1) of one level; counts and offsets
+// are indexed by b - b0
 __global__ void k_item_count(int64_t b0, int64_t b1, int span, const int32_t *__restrict__ rank,
                              int64_t *__restrict__ cnt) {
     int64_t b = b0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (b >= b1)
         return;
-    cnt[b] = (rank[b] + span - 1) / span;
+    cnt[b - b0] = (rank[b] + span - 1) / span;
+}
+
+// packed items: the first block of every group of g consecutive blocks
+// carries one item (first block, number of blocks)
+__global__ void k_item_count_packed(int64_t b0, int64_t b1, int g, int64_t *__restrict__ cnt) {
+    int64_t b = b0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= b1)
+        return;
+    cnt[b - b0] = ((b - b0) % g) == 0 ? 1 : 0;
+}
+
+__global__ void k_item_fill_packed(int64_t b0, int64_t b1, int g, const int64_t *__restrict__ off,
+                                   int32_t *__restrict__ items) {
+    int64_t b = b0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= b1 || ((b - b0) % g) != 0)
+        return;
+    const int64_t o = off[b - b0];
+    items[2 * o] = int32_t(b);
+    items[2 * o + 1] = int32_t(min<int64_t>(g, b1 - b));
 }
 
 __global__ void k_item_fill(int64_t b0, int64_t b1, int span, const int32_t *__restrict__ rank,
@@ -167,7 +187,7 @@ __global__ void k_item_fill(int64_t b0, int64_t b1, int span, const int32_t *__r
     int64_t b = b0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (b >= b1)
         return;
-    const int64_t o = off[b];
+    const int64_t o = off[b - b0];
     for (int c = 0, q = 0; c < rank[b]; c += span, ++q) {
         items[2 * (o + q)] = int32_t(b);
         items[2 * (o + q) + 1] = c;
@@ -240,50 +260,6 @@ __global__ void __launch_bounds__(256)
 
 size_t dtype_size(int dt) { return dt == H3D_F64 ? 8 : (dt == H3D_F32 ? 4 : 2); }
 
-// Stage-1 shape per level: S lanes per column (about the level's box size),
-// and a span of columns per work item of roughly 16K factor entries.
-void build_items(Plan &P, hipStream_t s) {
-    const int64_t nf = P.nfar;
-    int64_t *cnt = P.mem.alloc_n<int64_t>(nf + 1);
-    H3D_HIP(hipMemsetAsync(cnt + nf, 0, sizeof(int64_t), s));
-    for (int l = 1; l <= P.L; ++l) {
-        int S = 4;
-        while (S < 64 && S < P.mean_box[l])
-            S *= 2;
-        const int ns = 64 / S, u = S >= 32 ? 8 : 4;
-        const int per_pass = ns * u;
-        const int mean = std::max(1, P.mean_box[l]);
-        const int reps = std::max(1, 16384 / (per_pass * mean));
-        P.s1_width[l] = S;
-        P.s1_span[l] = per_pass * reps;
-        const int64_t b0 = P.lvl_blk[l], b1 = P.lvl_blk[l + 1];
-        if (b1 > b0) {
-            k_item_count<<<grid_for(b1 - b0, 256), 256, 0, s>>>(b0, b1, P.s1_span[l], P.blk_rank, cnt);
-            H3D_LAUNCH_CHECK();
-        }
-    }
-    P.nitems = scan_exclusive_i64(P, cnt, cnt, nf + 1, s);
-    P.items = P.mem.alloc_n<int32_t>(2 * std::max<int64_t>(P.nitems, 1));
-    for (int l = 1; l <= P.L; ++l) {
-        const int64_t b0 = P.lvl_blk[l], b1 = P.lvl_blk[l + 1];
-        if (b1 > b0) {
-            k_item_fill<<<grid_for(b1 - b0, 256), 256, 0, s>>>(b0, b1, P.s1_span[l], P.blk_rank, cnt,
-                                                               P.items);
-            H3D_LAUNCH_CHECK();
-        }
-    }
-    for (int l = 1; l <= P.L + 1 && l <= kMaxLevels; ++l) {
-        int64_t v = 0;
-        to_host(&v, cnt + P.lvl_blk[l], 1, s);
-        P.lvl_item[l] = v;
-    }
-    P.mem.release(cnt);
-    int lc = P.L;
-    while (lc > 0 && P.mean_box[lc] < 48)
-        --lc;
-    P.chunk_level = lc;
-}
-
 }  // namespace
 
 void factors_build(Plan &P, hipStream_t s) {
@@ -298,8 +274,6 @@ void factors_build(Plan &P, hipStream_t s) {
         P.blk_scale = P.mem.alloc_n<float>(2 * nf);
     if (nf == 0) {
         P.ncols = 0;
-        P.nitems = 0;
-        P.items = P.mem.alloc_n<int32_t>(2);
         H3D_HIP(hipMemsetAsync(P.blk_col0, 0, sizeof(int64_t), s));
         return;
     }
@@ -439,7 +413,6 @@ void factors_build(Plan &P, hipStream_t s) {
     k_rank_i64<<<grid_for(nf + 1, 256), 256, 0, s>>>(nf, P.blk_rank, P.blk_col0);
     H3D_LAUNCH_CHECK();
     P.ncols = scan_exclusive_i64(P, P.blk_col0, P.blk_col0, nf + 1, s);
-    build_items(P, s);
     for (int l = 1; l <= P.L + 1 && l <= kMaxLevels; ++l) {
         int64_t v = 0;
         to_host(&v, P.blk_col0 + P.lvl_blk[l], 1, s);
@@ -462,6 +435,9 @@ void factors_build(Plan &P, hipStream_t s) {
         to_host(h, sums, 4, s);
         entries += int64_t(h[0]);
         ev_total += int64_t(h[3]);
+        P.lvl_entries_v[l] = int64_t(h[3]);
+        P.lvl_rank_sum[l] = int64_t(h[1]);
+        P.lvl_entries_u[l] = int64_t(h[0]) - int64_t(h[3]);
         const int64_t lbytes = int64_t(h[0]) * int64_t(es) +
                                (dt == H3D_BF16_SCALED ? (le - lb) * 8 : 0);
         P.stats.factor_bytes_per_level[l] = lbytes;
@@ -474,6 +450,74 @@ void factors_build(Plan &P, hipStream_t s) {
     P.stats.factor_bytes = bytes;
     P.stats.rank_sum = P.ncols;
     P.stats.rank_max = rmax;
+
+    // stage-1 shapes and work items (defaults; the autotuner may replace them)
+    for (int cls = 0; cls < 2; ++cls)
+        for (int l = 1; l <= P.L; ++l)
+            set_level_shape(P, cls, l, default_shape(P, l, cls), s);
+    int lc = P.L;
+    while (lc > 0 && P.mean_box[lc] < 48)
+        --lc;
+    P.chunk_level = lc;
+}
+
+// Default stage-1 shape of level l: about four rows per lane, several tiny
+// blocks per wave, and long columns split into single-pass items.
+S1Shape default_shape(const Plan &P, int l, int cls) {
+    const int m = P.mean_box[l];
+    S1Shape sh;
+    if (m <= 12) {
+        sh.packed = 1;
+        sh.S = 4;
+        sh.U = 4;
+    } else if (m <= 24) {
+        sh.packed = 1;
+        sh.S = 8;
+        sh.U = 4;
+    } else if (m <= 96) {
+        sh.S = 16;
+        sh.U = 4;
+        sh.reps = 64;
+    } else {
+        sh.S = 64;
+        sh.U = cls == 0 ? 8 : 4;
+        sh.reps = m > 2048 ? 1 : 64;
+    }
+    return sh;
+}
+
+// (Re)builds the work items of level l for shape sh.
+void set_level_shape(Plan &P, int cls, int l, const S1Shape &sh, hipStream_t s) {
+    const int64_t b0 = P.lvl_blk[l], b1 = P.lvl_blk[l + 1];
+    P.s1_shape[cls][l] = sh;
+    P.mem.release(P.s1_items[cls][l]);
+    P.s1_items[cls][l] = nullptr;
+    P.s1_nitems[cls][l] = 0;
+    if (b1 <= b0)
+        return;
+    const int64_t nb = b1 - b0;
+    int64_t *cnt = P.mem.alloc_n<int64_t>(nb + 1);
+    H3D_HIP(hipMemsetAsync(cnt + nb, 0, sizeof(int64_t), s));
+    int span = 0;
+    if (sh.packed) {
+        k_item_count_packed<<<grid_for(nb, 256), 256, 0, s>>>(b0, b1, 64 / sh.S, cnt);
+    } else {
+        span = (64 / sh.S) * sh.U * std::max(1, sh.reps);
+        k_item_count<<<grid_for(nb, 256), 256, 0, s>>>(b0, b1, span, P.blk_rank, cnt);
+    }
+    H3D_LAUNCH_CHECK();
+    const int64_t ni = scan_exclusive_i64(P, cnt, cnt, nb + 1, s);
+    int32_t *items = P.mem.alloc_n<int32_t>(2 * std::max<int64_t>(ni, 1));
+    if (sh.packed)
+        k_item_fill_packed<<<grid_for(nb, 256), 256, 0, s>>>(b0, b1, 64 / sh.S, cnt, items);
+    else
+        k_item_fill<<<grid_for(nb, 256), 256, 0, s>>>(b0, b1, span, P.blk_rank, cnt, items);
+    H3D_LAUNCH_CHECK();
+    H3D_HIP(hipStreamSynchronize(s));
+    P.mem.release(cnt);
+    P.s1_items[cls][l] = items;
+    P.s1_nitems[cls][l] = ni;
+    P.s1_span[cls][l] = span;
 }
 
 // Copies U (which = 0) or V (which = 1) of every block to host as FP64.

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <stdexcept>
@@ -107,6 +108,7 @@ class DeviceMemory {
 // HIP-event timing of the mat-vec kernels, per kernel name.
 struct Profiler {
     bool on = false;
+    bool levels = false;  // launch the factor streams level by level
     struct Rec {
         int slot;
         hipEvent_t a, b;
@@ -152,8 +154,8 @@ struct Profiler {
         hipEvent_t b = get_event();
         H3D_HIP(hipEventRecord(b, s));
         int slot = slot_of(name);
-        bytes[slot] = nbytes;
-        flops[slot] = nflops;
+        bytes[slot] += nbytes;
+        flops[slot] += nflops;
         pending.push_back({slot, a, b});
     }
     void collect() {
@@ -173,6 +175,8 @@ struct Profiler {
         for (size_t i = 0; i < names.size(); ++i) {
             launches[i] = 0;
             total_ms[i] = 0.0;
+            bytes[i] = 0.0;
+            flops[i] = 0.0;
         }
     }
     ~Profiler() {
@@ -183,6 +187,14 @@ struct Profiler {
         for (auto e : pool)
             (void)hipEventDestroy(e);
     }
+};
+
+// Shape of one level's stage-1 launch (see the stage-1 kernels).
+struct S1Shape {
+    int packed = 0;  // 1: one sub-wave per block, 64/S blocks per wave
+    int S = 64;      // lanes per factor column
+    int U = 8;       // columns in flight per lane and pass
+    int reps = 1;    // wide form: passes per work item
 };
 
 // Everything one HODLR3D operator owns.  Rows are numbered in sorted (Morton)
@@ -224,13 +236,18 @@ struct Plan {
     int64_t *blk_pivoff = nullptr;
     int64_t ncols = 0;             // sum of ranks
     int64_t entries_v = 0;         // sum of n k (entries of all V_b)
+    int64_t lvl_entries_u[kMaxLevels + 1] = {0};  // per level: sum of m k
+    int64_t lvl_entries_v[kMaxLevels + 1] = {0};  // per level: sum of n k
     int64_t lvl_col[kMaxLevels + 1] = {0};
-    // stage-1 work items (block, first column), in block order
-    int64_t nitems = 0;
-    int32_t *items = nullptr;      // [2 nitems]
-    int64_t lvl_item[kMaxLevels + 1] = {0};
-    int s1_width[kMaxLevels + 1] = {0};  // lanes per column at each level
-    int s1_span[kMaxLevels + 1] = {0};   // columns per work item at each level
+    // stage-1 launch shape and work items per level, for one right-hand side
+    // (class 0) and for several (class 1)
+    S1Shape s1_shape[2][kMaxLevels + 1];
+    int32_t *s1_items[2][kMaxLevels + 1] = {};  // [2 count]: (block, c0) or (first, count)
+    int64_t s1_nitems[2][kMaxLevels + 1] = {};
+    int s1_span[2][kMaxLevels + 1] = {};        // wide form: columns per item
+    int s2_waves[2] = {4, 4};                    // waves per stage-2 chunk box
+    bool tuned[2] = {false, false};
+    int64_t lvl_rank_sum[kMaxLevels + 1] = {0};
     int chunk_level = 0;           // stage-2 boxes: about 64 rows per wave
     int mean_box[kMaxLevels + 1] = {0};  // mean size of non-empty boxes per level
     int max_box[kMaxLevels + 1] = {0};
@@ -261,6 +278,9 @@ void factors_build(Plan &P, hipStream_t s);
 void matvec_run(Plan &P, const void *x, void *y, int64_t nrhs, int64_t ldx, int64_t ldy,
                 int io_dtype, bool adjoint, hipStream_t s);
 void export_factors(const Plan &P, int which, double *host_out);
+void set_level_shape(Plan &P, int cls, int l, const S1Shape &sh, hipStream_t s);
+S1Shape default_shape(const Plan &P, int l, int cls);
+void autotune(Plan &P, int64_t nrhs, hipStream_t s);
 
 // device-wide exclusive scan; out may alias in; returns the total
 int64_t scan_exclusive_i64(Plan &P, const int64_t *in, int64_t *out, int64_t n, hipStream_t s);

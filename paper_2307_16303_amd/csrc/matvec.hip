@@ -152,51 +152,62 @@ __global__ void __launch_bounds__(64)
 }
 
 // ---------------------------------------------------------------------------
-// stage 1: z[col] = dot(column col of its block's factor, x segment).
-// Work item = (block, first column); a wave streams up to `span` columns of
-// the block, NS = 64/S columns side by side (S lanes per column) and U such
-// groups per pass, so every lane keeps U independent loads in flight.
-struct S1Level {
-    int64_t i0, i1;  // items of this level
-    int S;           // lanes per column
-    int span;        // columns per item
-};
-struct S1Tab {
-    S1Level lv[kMaxLevels + 1];
-    int nlev;
-};
-
+// stage 1: z[col] = dot(column col of its block's factor, x segment), one
+// launch per level with a shape chosen for that level's box size and rank.
+//
+//  wide   <S, U>: item = (block, first column); NS = 64/S columns side by side
+//                 (S lanes each, rows strided by S), U such groups per pass,
+//                 so each lane has U independent loads in flight; block
+//                 metadata is wave-uniform.
+//  packed <S, U>: item = (first block, count); one sub-wave of S lanes per
+//                 block, 64/S consecutive blocks per wave, U columns per pass;
+//                 the column loop runs to the wave's largest rank so the
+//                 shuffles stay in uniform control flow.
 __device__ __forceinline__ int64_t uniform64(int64_t v) {
     const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v)));
     const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
     return int64_t((uint64_t(hi) << 32) | lo);
 }
 
-template <int S, int DT, int NR>
-__device__ __forceinline__ void stage1_item(int2 item, int span, const int64_t *__restrict__ blk_col0,
-                                            const int32_t *__restrict__ rank,
-                                            const int32_t *__restrict__ seg_len,
-                                            const int32_t *__restrict__ seg_off,
-                                            void *const *__restrict__ seg_ptr,
-                                            const float *__restrict__ scale2, int nrhs,
-                                            const double *__restrict__ xp, int64_t n,
-                                            double *__restrict__ z, int64_t ldz) {
+struct S1Args {
+    const int2 *items;
+    int64_t nitems;
+    int span;
+    const int64_t *blk_col0;
+    const int32_t *rank;
+    const int32_t *seg_len;
+    const int32_t *seg_off;
+    void *const *seg_ptr;
+    const float *scale2;
+    int nrhs;
+    const double *xp;
+    int64_t n;
+    double *z;
+    int64_t ldz;
+};
+
+template <int S, int U, int DT, int NR>
+__global__ void __launch_bounds__(256) k_s1_wide(S1Args a) {
     using T = typename Fac<DT>::T;
     constexpr int NS = 64 / S;
-    constexpr int U = S >= 32 ? 8 : 4;
+    const int64_t w = uniform64((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6);
+    if (w >= a.nitems)
+        return;
+    const int2 item = a.items[w];
     const int lane = threadIdx.x & 63;
     const int r = lane % S, sub = lane / S;
     const int b = item.x;
-    const int len = seg_len[b];
-    const int64_t off = seg_off[b];
-    const int64_t col0 = blk_col0[b];
-    const int k = rank[b];
-    const T *p = static_cast<const T *>(seg_ptr[b]);
+    const int len = a.seg_len[b];
+    const int64_t off = a.seg_off[b];
+    const int64_t col0 = a.blk_col0[b];
+    const int k = a.rank[b];
+    const T *__restrict__ p = static_cast<const T *>(a.seg_ptr[b]);
     double sc = 1.0;
     if (DT == H3D_BF16_SCALED)
-        sc = double(scale2[2 * b]) * double(scale2[2 * b + 1]);
-    const int cend = min(item.y + span, k);
-    for (int rb = 0; rb < nrhs; rb += NR) {
+        sc = double(a.scale2[2 * b]) * double(a.scale2[2 * b + 1]);
+    const int cend = min(item.y + a.span, k);
+    const double *__restrict__ xp = a.xp;
+    for (int rb = 0; rb < a.nrhs; rb += NR) {
         for (int cb = item.y; cb < cend; cb += NS * U) {
             double acc[U][NR];
 #pragma unroll
@@ -208,7 +219,7 @@ __device__ __forceinline__ void stage1_item(int2 item, int span, const int64_t *
                 double xv[NR];
 #pragma unroll
                 for (int q = 0; q < NR; ++q)
-                    xv[q] = (NR == 1 || rb + q < nrhs) ? xp[(rb + q) * n + off + j] : 0.0;
+                    xv[q] = (NR == 1 || rb + q < a.nrhs) ? xp[(rb + q) * a.n + off + j] : 0.0;
                 double v[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
@@ -235,46 +246,103 @@ __device__ __forceinline__ void stage1_item(int2 item, int span, const int64_t *
                     if (c < cend)
 #pragma unroll
                         for (int q = 0; q < NR; ++q)
-                            if (NR == 1 || rb + q < nrhs)
-                                z[(rb + q) * ldz + col0 + c] = acc[u][q] * sc;
+                            if (NR == 1 || rb + q < a.nrhs)
+                                a.z[(rb + q) * a.ldz + col0 + c] = acc[u][q] * sc;
                 }
             }
         }
     }
 }
 
-template <int DT, int NR>
-__global__ void __launch_bounds__(256)
-    k_stage1(S1Tab tab, int64_t nitems, const int2 *__restrict__ items,
-             const int64_t *__restrict__ blk_col0, const int32_t *__restrict__ rank,
-             const int32_t *__restrict__ seg_len, const int32_t *__restrict__ seg_off,
-             void *const *__restrict__ seg_ptr, const float *__restrict__ scale2, int nrhs,
-             const double *__restrict__ xp, int64_t n, double *__restrict__ z, int64_t ldz) {
+template <int S, int U, int DT, int NR>
+__global__ void __launch_bounds__(256) k_s1_packed(S1Args a) {
+    using T = typename Fac<DT>::T;
     const int64_t w = uniform64((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6);
-    if (w >= nitems)
+    if (w >= a.nitems)
         return;
-    int li = 0;
-    while (li + 1 < tab.nlev && w >= tab.lv[li + 1].i0)
-        ++li;
-    const int S = tab.lv[li].S, span = tab.lv[li].span;
-    const int2 it = items[w];
-    switch (S) {
-    case 4:
-        stage1_item<4, DT, NR>(it, span, blk_col0, rank, seg_len, seg_off, seg_ptr, scale2, nrhs, xp, n, z, ldz);
-        break;
-    case 8:
-        stage1_item<8, DT, NR>(it, span, blk_col0, rank, seg_len, seg_off, seg_ptr, scale2, nrhs, xp, n, z, ldz);
-        break;
-    case 16:
-        stage1_item<16, DT, NR>(it, span, blk_col0, rank, seg_len, seg_off, seg_ptr, scale2, nrhs, xp, n, z, ldz);
-        break;
-    case 32:
-        stage1_item<32, DT, NR>(it, span, blk_col0, rank, seg_len, seg_off, seg_ptr, scale2, nrhs, xp, n, z, ldz);
-        break;
-    default:
-        stage1_item<64, DT, NR>(it, span, blk_col0, rank, seg_len, seg_off, seg_ptr, scale2, nrhs, xp, n, z, ldz);
-        break;
+    const int2 item = a.items[w];
+    const int lane = threadIdx.x & 63;
+    const int r = lane % S, sub = lane / S;
+    const bool valid = sub < item.y;
+    const int b = item.x + (valid ? sub : 0);
+    const int len = valid ? a.seg_len[b] : 0;
+    const int64_t off = a.seg_off[b];
+    const int64_t col0 = a.blk_col0[b];
+    const int k = valid ? a.rank[b] : 0;
+    const T *__restrict__ p = static_cast<const T *>(a.seg_ptr[b]);
+    double sc = 1.0;
+    if (DT == H3D_BF16_SCALED)
+        sc = double(a.scale2[2 * b]) * double(a.scale2[2 * b + 1]);
+    int kmax = k;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        kmax = max(kmax, __shfl_xor(kmax, o, 64));
+    const double *__restrict__ xp = a.xp;
+    for (int rb = 0; rb < a.nrhs; rb += NR) {
+        for (int cb = 0; cb < kmax; cb += U) {
+            double acc[U][NR];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int q = 0; q < NR; ++q)
+                    acc[u][q] = 0.0;
+            for (int j = r; j < len; j += S) {
+                double xv[NR];
+#pragma unroll
+                for (int q = 0; q < NR; ++q)
+                    xv[q] = (NR == 1 || rb + q < a.nrhs) ? xp[(rb + q) * a.n + off + j] : 0.0;
+                double v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    v[u] = cb + u < k ? Fac<DT>::ld(p + int64_t(cb + u) * len + j) : 0.0;
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int q = 0; q < NR; ++q)
+                        acc[u][q] += v[u] * xv[q];
+            }
+#pragma unroll
+            for (int o = S / 2; o > 0; o >>= 1)
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int q = 0; q < NR; ++q)
+                        acc[u][q] += __shfl_xor(acc[u][q], o, S);
+            if (r == 0) {
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (cb + u < k)
+#pragma unroll
+                        for (int q = 0; q < NR; ++q)
+                            if (NR == 1 || rb + q < a.nrhs)
+                                a.z[(rb + q) * a.ldz + col0 + cb + u] = acc[u][q] * sc;
+            }
+        }
     }
+}
+
+// one launch of level l's stage 1 with its current shape
+template <int DT, int NR> void launch_s1(const S1Shape &sh, S1Args a, hipStream_t s) {
+    const int grid = grid_for(a.nitems * 64, 256);
+    if (sh.packed) {
+#define H3D_S1P(SS, UU)                                                                   \
+    if (sh.S == SS && sh.U == UU) {                                                       \
+        k_s1_packed<SS, UU, DT, NR><<<grid, 256, 0, s>>>(a);                              \
+        return;                                                                           \
+    }
+        H3D_S1P(4, 2) H3D_S1P(4, 4) H3D_S1P(8, 2) H3D_S1P(8, 4) H3D_S1P(16, 2) H3D_S1P(16, 4)
+#undef H3D_S1P
+    } else {
+#define H3D_S1W(SS, UU)                                                                   \
+    if (sh.S == SS && sh.U == UU) {                                                       \
+        k_s1_wide<SS, UU, DT, NR><<<grid, 256, 0, s>>>(a);                                \
+        return;                                                                           \
+    }
+        H3D_S1W(8, 4) H3D_S1W(8, 8) H3D_S1W(16, 4) H3D_S1W(16, 8) H3D_S1W(32, 4) H3D_S1W(32, 8)
+        H3D_S1W(64, 2) H3D_S1W(64, 4) H3D_S1W(64, 8)
+#undef H3D_S1W
+    }
+    fail(H3D_EDEVICE, "internal: no stage-1 kernel for this shape");
 }
 
 // ---------------------------------------------------------------------------
@@ -313,20 +381,20 @@ __device__ __forceinline__ void stage2_block(const typename Fac<DT>::T *__restri
     }
 }
 
-template <int DT, int NR>
-__global__ void __launch_bounds__(256)
+template <int DT, int NR, int kS2Waves>
+__global__ void __launch_bounds__(512)
     k_stage2(S2Tab tab, const int32_t *__restrict__ leaf_off, const int32_t *__restrict__ leaf_of,
              const int64_t *__restrict__ grp_begin, const int64_t *__restrict__ grp_blk,
              void *const *__restrict__ fptr, const int32_t *__restrict__ rank,
              const int64_t *__restrict__ blk_col0, const double *__restrict__ z, int64_t ldz,
-             const double *__restrict__ yn, int64_t n, int nrhs, const int32_t *__restrict__ perm,
-             void *__restrict__ yout, int64_t ldy, int io_f32) {
+             const double *yn, int64_t n, int nrhs, const int32_t *__restrict__ perm,
+             void *__restrict__ yout, int64_t ldy, int io_f32, int lb, int le, double *ypart) {
     using T = typename Fac<DT>::T;
+    __shared__ double part[kS2Waves][NR][64];
     const int L = tab.L, lc = tab.lc;
-    const int64_t B = uniform64((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6);
+    const int64_t B = blockIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (B >= (int64_t(1) << (3 * lc)))
-        return;
     const int shc = 3 * (L - lc);
     const int32_t r0 = leaf_off[B << shc], r1 = leaf_off[(B + 1) << shc];
     for (int32_t rowb = r0; rowb < r1; rowb += 64) {
@@ -338,9 +406,10 @@ __global__ void __launch_bounds__(256)
             double acc[NR];
 #pragma unroll
             for (int c = 0; c < NR; ++c)
-                acc[c] = (NR == 1 || rb + c < nrhs) ? yn[(rb + c) * n + rr] : 0.0;
-            // levels whose boxes contain the whole chunk box: wave-uniform
-            for (int l = 1; l <= lc; ++l) {
+                acc[c] = (wv == 0 && (NR == 1 || rb + c < nrhs)) ? yn[(rb + c) * n + rr] : 0.0;
+            // levels whose boxes contain the whole chunk box: wave-uniform;
+            // the waves of the workgroup take every kS2Waves-th block
+            for (int l = lb; l <= min(lc, le); ++l) {
                 const int sh = 3 * (L - l);
                 const int64_t t = B >> (3 * (lc - l));
                 const int64_t g = tab.box_base[l] + t;
@@ -348,14 +417,14 @@ __global__ void __launch_bounds__(256)
                 const int32_t bm = leaf_off[(t + 1) << sh] - bs;
                 const int32_t loc = rr - bs;
                 const int64_t e0 = grp_begin[g], e1 = grp_begin[g + 1];
-                for (int64_t e = e0; e < e1; ++e) {
+                for (int64_t e = e0 + wv; e < e1; e += kS2Waves) {
                     const int64_t bi = grp_blk ? grp_blk[e] : e;
                     const T *p = static_cast<const T *>(fptr[bi]) + loc;
                     stage2_block<DT, NR, 8>(p, bm, rank[bi], z + blk_col0[bi], ldz, rb, nrhs, acc);
                 }
             }
             // finer levels: every lane follows the box of its own row
-            for (int l = lc + 1; l <= L; ++l) {
+            for (int l = max(lc + 1, lb); l <= le; ++l) {
                 const int sh = 3 * (L - l);
                 const int64_t t = int64_t(leaf) >> sh;
                 const int64_t g = tab.box_base[l] + t;
@@ -363,25 +432,86 @@ __global__ void __launch_bounds__(256)
                 const int32_t bm = leaf_off[(t + 1) << sh] - bs;
                 const int32_t loc = rr - bs;
                 const int64_t e0 = grp_begin[g], e1 = grp_begin[g + 1];
-                for (int64_t e = e0; e < e1; ++e) {
+                for (int64_t e = e0 + wv; e < e1; e += kS2Waves) {
                     const int64_t bi = grp_blk ? grp_blk[e] : e;
                     const T *p = static_cast<const T *>(fptr[bi]) + loc;
                     stage2_block<DT, NR, 4>(p, bm, rank[bi], z + blk_col0[bi], ldz, rb, nrhs, acc);
                 }
             }
-            if (act) {
-                const int64_t dst = perm[row];
+            // combine the waves' partial sums in a fixed order
 #pragma unroll
-                for (int q = 0; q < NR; ++q)
-                    if (NR == 1 || rb + q < nrhs) {
-                        if (io_f32)
-                            static_cast<float *>(yout)[(rb + q) * ldy + dst] = float(acc[q]);
-                        else
-                            static_cast<double *>(yout)[(rb + q) * ldy + dst] = acc[q];
-                    }
+            for (int q = 0; q < NR; ++q)
+                part[wv][q][lane] = acc[q];
+            __syncthreads();
+            if (wv == 0) {
+#pragma unroll
+                for (int q = 0; q < NR; ++q) {
+                    double v = part[0][q][lane];
+#pragma unroll
+                    for (int w2 = 1; w2 < kS2Waves; ++w2)
+                        v += part[w2][q][lane];
+                    acc[q] = v;
+                }
+                if (act && ypart) {
+                    // partial sums in sorted order (level-by-level profiling)
+#pragma unroll
+                    for (int q = 0; q < NR; ++q)
+                        if (NR == 1 || rb + q < nrhs)
+                            ypart[(rb + q) * n + row] = acc[q];
+                } else if (act) {
+                    const int64_t dst = perm[row];
+#pragma unroll
+                    for (int q = 0; q < NR; ++q)
+                        if (NR == 1 || rb + q < nrhs) {
+                            if (io_f32)
+                                static_cast<float *>(yout)[(rb + q) * ldy + dst] = float(acc[q]);
+                            else
+                                static_cast<double *>(yout)[(rb + q) * ldy + dst] = acc[q];
+                        }
+                }
             }
+            __syncthreads();
         }
     }
+}
+
+template <int DT, int NR>
+void launch_s2_kernel(int waves, int64_t nchunk, hipStream_t s, const S2Tab &tab, const Plan &P,
+                      const int64_t *grp_blk, void *const *fptr, const double *z, const double *yn,
+                      int nrhs, void *y, int64_t ldy, int io_f32, int lb, int le, double *ypart) {
+#define H3D_S2(W)                                                                           \
+    k_stage2<DT, NR, W><<<int(nchunk), 64 * W, 0, s>>>(                                     \
+        tab, P.leaf_off, P.leaf_of, P.tgt_begin, grp_blk, fptr, P.blk_rank, P.blk_col0, z,  \
+        P.ncols, yn, P.n, nrhs, P.perm, y, ldy, io_f32, lb, le, ypart)
+    if (waves <= 2)
+        H3D_S2(2);
+    else if (waves <= 4)
+        H3D_S2(4);
+    else
+        H3D_S2(8);
+#undef H3D_S2
+    H3D_LAUNCH_CHECK();
+}
+
+template <int DT, int NR>
+S1Args stage1_args(const Plan &P, int cls, int l, bool adjoint, int nrhs, const double *xp,
+                   double *z) {
+    S1Args a;
+    a.items = reinterpret_cast<const int2 *>(P.s1_items[cls][l]);
+    a.nitems = P.s1_nitems[cls][l];
+    a.span = P.s1_span[cls][l];
+    a.blk_col0 = P.blk_col0;
+    a.rank = P.blk_rank;
+    a.seg_len = adjoint ? P.blk_m : P.blk_n;
+    a.seg_off = adjoint ? P.blk_toff : P.blk_soff;
+    a.seg_ptr = adjoint ? P.blk_uptr : P.blk_vptr;
+    a.scale2 = P.blk_scale;
+    a.nrhs = nrhs;
+    a.xp = xp;
+    a.n = P.n;
+    a.z = z;
+    a.ldz = P.ncols;
+    return a;
 }
 
 template <int DT, int NR>
@@ -389,56 +519,155 @@ void launch_far(Plan &P, bool adjoint, int nrhs, const double *xp, double *z, co
                 void *y, int64_t ldy, int io_f32, hipStream_t s) {
     const int64_t n = P.n;
     const int L = P.L;
-    const size_t es = DT == H3D_F64 ? 8 : (DT == H3D_F32 ? 4 : 2);
-    // stage 1
-    if (P.nitems > 0) {
-        S1Tab tab{};
-        int nl = 0;
-        for (int l = 1; l <= L; ++l) {
-            S1Level lv;
-            lv.i0 = P.lvl_item[l];
-            lv.i1 = P.lvl_item[l + 1];
-            lv.S = P.s1_width[l];
-            lv.span = P.s1_span[l];
-            tab.lv[nl++] = lv;
+    const int cls = NR == 1 ? 0 : 1;
+    const double es = DT == H3D_F64 ? 8.0 : (DT == H3D_F32 ? 4.0 : 2.0);
+    // stage 1: one launch per level
+    for (int l = 1; l <= L; ++l) {
+        const S1Args a = stage1_args<DT, NR>(P, cls, l, adjoint, nrhs, xp, z);
+        if (a.nitems == 0)
+            continue;
+        const S1Shape &sh = P.s1_shape[cls][l];
+        const double ent = double(adjoint ? P.lvl_entries_u[l] : P.lvl_entries_v[l]);
+        const double cols = double(P.lvl_rank_sum[l]);
+        const double bytes = ent * es + cols * 8.0 * nrhs + double(n) * 8.0 * nrhs;
+        hipEvent_t ev = P.prof.begin(s);
+        launch_s1<DT, NR>(sh, a, s);
+        H3D_LAUNCH_CHECK();
+        char name[48];
+        if (P.prof.levels)
+            snprintf(name, sizeof(name), "%s_L%d", sh.packed ? "k_s1_packed" : "k_s1_wide", l);
+        else
+            snprintf(name, sizeof(name), "%s", sh.packed ? "k_s1_packed" : "k_s1_wide");
+        P.prof.end(s, ev, name, bytes, 2.0 * ent * nrhs);
+    }
+    // stage 2 (always: it also writes y); level by level when profiling
+    // levels, carrying the partial sums in yn
+    S2Tab tab{};
+    for (int l = 0; l <= kMaxLevels; ++l)
+        tab.box_base[l] = P.box_base[l];
+    tab.L = L;
+    tab.lc = P.chunk_level;
+    const int64_t nchunk = pow8(P.chunk_level);
+    const int parts = (P.prof.levels && L > 1) ? L : 1;
+    for (int part = 1; part <= parts; ++part) {
+        const int lb = parts == 1 ? 1 : part, le = parts == 1 ? L : part;
+        const bool last = part == parts;
+        double ent = double(adjoint ? P.entries_v : P.stats.factor_entries - P.entries_v);
+        double cols = double(P.ncols);
+        if (parts > 1) {
+            ent = double(adjoint ? P.lvl_entries_v[part] : P.lvl_entries_u[part]);
+            cols = double(P.lvl_rank_sum[part]);
         }
-        tab.nlev = nl;
-        hipEvent_t ev = P.prof.begin(s);
-        const int32_t *len = adjoint ? P.blk_m : P.blk_n;
-        const int32_t *off = adjoint ? P.blk_toff : P.blk_soff;
-        void *const *ptr = adjoint ? P.blk_uptr : P.blk_vptr;
-        k_stage1<DT, NR><<<grid_for(P.nitems * 64, 256), 256, 0, s>>>(
-            tab, P.nitems, reinterpret_cast<const int2 *>(P.items), P.blk_col0, P.blk_rank, len,
-            off, ptr, P.blk_scale, nrhs, xp, n, z, P.ncols);
-        H3D_LAUNCH_CHECK();
-        const double side_entries =
-            double(adjoint ? P.stats.factor_entries - P.entries_v : P.entries_v);
-        const double bytes = side_entries * double(es) + double(P.ncols) * 8.0 * nrhs +
-                             double(n) * 8.0 * nrhs * L;
-        P.prof.end(s, ev, adjoint ? "far_stage1_adj" : "far_stage1", bytes,
-                   2.0 * side_entries * nrhs);
-    }
-    // stage 2 (always: it also writes y)
-    {
-        S2Tab tab{};
-        for (int l = 0; l <= kMaxLevels; ++l)
-            tab.box_base[l] = P.box_base[l];
-        tab.L = L;
-        tab.lc = P.chunk_level;
-        hipEvent_t ev = P.prof.begin(s);
-        const int64_t nchunk = pow8(P.chunk_level);
-        k_stage2<DT, NR><<<grid_for(nchunk * 64, 256), 256, 0, s>>>(
-            tab, P.leaf_off, P.leaf_of, P.tgt_begin, adjoint ? P.src_blk : nullptr,
-            adjoint ? P.blk_vptr : P.blk_uptr, P.blk_rank, P.blk_col0, z, P.ncols, yn, n, nrhs,
-            P.perm, y, ldy, io_f32);
-        H3D_LAUNCH_CHECK();
-        const double side_entries =
-            double(adjoint ? P.entries_v : P.stats.factor_entries - P.entries_v);
-        const double bytes = side_entries * double(es) + double(P.ncols) * 8.0 * nrhs +
+        const double bytes = ent * es + cols * 8.0 * nrhs +
                              double(n) * (8.0 + (io_f32 ? 4.0 : 8.0)) * nrhs + double(n) * 8.0;
-        P.prof.end(s, ev, adjoint ? "far_stage2_adj" : "far_stage2", bytes,
-                   2.0 * side_entries * nrhs);
+        hipEvent_t ev = P.prof.begin(s);
+        launch_s2_kernel<DT, NR>(P.s2_waves[cls], nchunk, s, tab, P, adjoint ? P.src_blk : nullptr,
+                                 adjoint ? P.blk_vptr : P.blk_uptr, z, yn, nrhs, y, ldy, io_f32,
+                                 lb, le, last ? nullptr : const_cast<double *>(yn));
+        char name[48];
+        if (parts > 1)
+            snprintf(name, sizeof(name), "k_stage2_L%d", part);
+        else
+            snprintf(name, sizeof(name), "k_stage2");
+        P.prof.end(s, ev, name, bytes, 2.0 * ent * nrhs);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: times candidate stage-1 shapes level by level and stage-2 wave
+// counts on the plan's own factor streams, keeps the fastest of each.
+std::vector<S1Shape> s1_candidates(const Plan &P, int l) {
+    std::vector<S1Shape> c;
+    const int m = std::max(1, P.mean_box[l]);
+    auto add = [&](int packed, int S, int U, int reps) {
+        S1Shape sh;
+        sh.packed = packed;
+        sh.S = S;
+        sh.U = U;
+        sh.reps = reps;
+        c.push_back(sh);
+    };
+    if (m <= 32) {
+        add(1, 4, 2, 1);
+        add(1, 4, 4, 1);
+        add(1, 8, 2, 1);
+        add(1, 8, 4, 1);
+    }
+    if (m >= 8 && m <= 128) {
+        add(1, 16, 2, 1);
+        add(1, 16, 4, 1);
+    }
+    for (int S : {8, 16, 32, 64}) {
+        if (S > std::max(8, 2 * m) || 16 * S < m)
+            continue;
+        for (int U : {4, 8}) {
+            add(0, S, U, 1);
+            add(0, S, U, 64);
+        }
+        if (S == 64)
+            add(0, 64, 2, 1);
+    }
+    return c;
+}
+
+template <int DT, int NR>
+void autotune_dt(Plan &P, int nrhs, hipStream_t s) {
+    const int cls = NR == 1 ? 0 : 1;
+    hipEvent_t e0, e1;
+    H3D_HIP(hipEventCreate(&e0));
+    H3D_HIP(hipEventCreate(&e1));
+    auto time_it = [&](auto &&launch) {
+        launch();  // warm-up
+        float best = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            H3D_HIP(hipEventRecord(e0, s));
+            launch();
+            H3D_HIP(hipEventRecord(e1, s));
+            H3D_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            H3D_HIP(hipEventElapsedTime(&ms, e0, e1));
+            best = std::min(best, ms);
+        }
+        return best;
+    };
+    for (int l = 1; l <= P.L; ++l) {
+        if (P.lvl_blk[l + 1] <= P.lvl_blk[l])
+            continue;
+        S1Shape best_sh = P.s1_shape[cls][l];
+        float best_ms = 1e30f;
+        for (const S1Shape &sh : s1_candidates(P, l)) {
+            set_level_shape(P, cls, l, sh, s);
+            const S1Args a = stage1_args<DT, NR>(P, cls, l, false, nrhs, P.xp, P.z);
+            const float ms = time_it([&] { launch_s1<DT, NR>(sh, a, s); });
+            if (ms < best_ms) {
+                best_ms = ms;
+                best_sh = sh;
+            }
+        }
+        set_level_shape(P, cls, l, best_sh, s);
+    }
+    S2Tab tab{};
+    for (int l = 0; l <= kMaxLevels; ++l)
+        tab.box_base[l] = P.box_base[l];
+    tab.L = P.L;
+    tab.lc = P.chunk_level;
+    const int64_t nchunk = pow8(P.chunk_level);
+    float best_ms = 1e30f;
+    int best_w = P.s2_waves[cls];
+    for (int w : {2, 4, 8}) {
+        const float ms = time_it([&] {
+            launch_s2_kernel<DT, NR>(w, nchunk, s, tab, P, nullptr, P.blk_uptr, P.z, P.yp, nrhs,
+                                     P.yp + P.n * nrhs, P.n, 0, 1, P.L, nullptr);
+        });
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_w = w;
+        }
+    }
+    P.s2_waves[cls] = best_w;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    P.tuned[cls] = true;
 }
 
 template <int NR>
@@ -448,30 +677,63 @@ void launch_near(Plan &P, int nrhs, const double *xp, double *yn, hipStream_t s)
                                               P.pz, P.cfg.kernel, P.cfg.kernel_param, nrhs, xp,
                                               P.n, yn);
     H3D_LAUNCH_CHECK();
-    P.prof.end(s, ev, "near_field", double(P.n) * (32.0 + 8.0 * nrhs),
+    P.prof.end(s, ev, "k_near", double(P.n) * (32.0 + 8.0 * nrhs),
                double(P.stats.near_pair_evals) * (10.0 + 2.0 * nrhs));
 }
 
 }  // namespace
 
+static void ensure_scratch(Plan &P, int64_t nrhs, hipStream_t s) {
+    if (nrhs <= P.scratch_nrhs)
+        return;
+    const int64_t n = P.n;
+    P.mem.release(P.xp);
+    P.mem.release(P.yp);
+    P.mem.release(P.z);
+    P.xp = P.mem.alloc_n<double>(n * nrhs);
+    P.yp = P.mem.alloc_n<double>(2 * n * nrhs);  // second half: tuner output
+    P.z = P.mem.alloc_n<double>(std::max<int64_t>(P.ncols, 1) * nrhs);
+    H3D_HIP(hipMemsetAsync(P.xp, 0, sizeof(double) * size_t(n * nrhs), s));
+    H3D_HIP(hipMemsetAsync(P.yp, 0, sizeof(double) * size_t(2 * n * nrhs), s));
+    P.scratch_nrhs = nrhs;
+}
+
+void autotune(Plan &P, int64_t nrhs, hipStream_t s) {
+    if (P.nfar == 0)
+        return;
+    const int nr = nrhs == 1 ? 1 : int(std::min<int64_t>(nrhs, 4));
+    ensure_scratch(P, std::max<int64_t>(nrhs, nr), s);
+    auto go = [&](auto dt_tag) {
+        constexpr int DT = decltype(dt_tag)::value;
+        if (nrhs == 1)
+            autotune_dt<DT, 1>(P, 1, s);
+        else
+            autotune_dt<DT, 4>(P, int(nrhs), s);
+    };
+    switch (P.factor_dtype) {
+    case H3D_F64:
+        go(std::integral_constant<int, H3D_F64>{});
+        break;
+    case H3D_F32:
+        go(std::integral_constant<int, H3D_F32>{});
+        break;
+    default:
+        go(std::integral_constant<int, H3D_BF16_SCALED>{});
+        break;
+    }
+    H3D_HIP(hipStreamSynchronize(s));
+}
+
 void matvec_run(Plan &P, const void *x, void *y, int64_t nrhs, int64_t ldx, int64_t ldy,
                 int io_dtype, bool adjoint, hipStream_t s) {
     const int64_t n = P.n;
-    if (nrhs > P.scratch_nrhs) {
-        P.mem.release(P.xp);
-        P.mem.release(P.yp);
-        P.mem.release(P.z);
-        P.xp = P.mem.alloc_n<double>(n * nrhs);
-        P.yp = P.mem.alloc_n<double>(n * nrhs);
-        P.z = P.mem.alloc_n<double>(std::max<int64_t>(P.ncols, 1) * nrhs);
-        P.scratch_nrhs = nrhs;
-    }
+    ensure_scratch(P, nrhs, s);
     const int io_f32 = io_dtype == H3D_F32;
     {
         hipEvent_t ev = P.prof.begin(s);
         k_gather<<<grid_for(n, 256), 256, 0, s>>>(x, io_f32, ldx, n, int(nrhs), P.perm, P.xp);
         H3D_LAUNCH_CHECK();
-        P.prof.end(s, ev, "gather", double(n) * (4.0 + (io_f32 ? 4.0 : 8.0) * nrhs + 8.0 * nrhs), 0.0);
+        P.prof.end(s, ev, "k_gather", double(n) * (4.0 + (io_f32 ? 4.0 : 8.0) * nrhs + 8.0 * nrhs), 0.0);
     }
     // The near list is symmetric (t in Near(s) iff s in Near(t)), and the
     // kernels are radial, so K(t,s)^T = K(s,t): the adjoint near field walks

@@ -23,12 +23,13 @@ DTYPES = {"fp64": 0, "f64": 0, "fp32": 1, "f32": 1, "bf16": 2, "bf16_scaled": 2}
 EXPORTS = {"perm": 0, "leaf_off": 1, "far": 2, "near": 3, "factors_u": 4, "factors_v": 5,
            "pivots": 6}
 FLAG_KEEP_PIVOTS = 1
+FLAG_NO_AUTOTUNE = 2
 MAX_LEVELS = 11
 
 EXPORTED_SYMBOLS = (
     "h3d_config_init", "h3d_build", "h3d_matvec", "h3d_matvec_adjoint", "h3d_get_stats",
     "h3d_export", "h3d_destroy", "h3d_last_error", "h3d_profile_enable", "h3d_profile_read",
-    "h3d_profile_reset", "h3d_version",
+    "h3d_profile_reset", "h3d_version", "h3d_autotune",
 )
 
 
@@ -143,6 +144,8 @@ def load_library():
     lib.h3d_profile_read.argtypes = [P, ctypes.POINTER(KernelProfile), I32,
                                      ctypes.POINTER(ctypes.c_int32)]
     lib.h3d_profile_read.restype = S
+    lib.h3d_autotune.argtypes = [P, I64, P]
+    lib.h3d_autotune.restype = S
     lib.h3d_version.argtypes = []
     lib.h3d_version.restype = I32
     _lib = lib
@@ -244,6 +247,12 @@ class Operator:
         return self.matvec(x)
 
     # -- introspection ----------------------------------------------------
+    def autotune(self, nrhs: int = 1) -> None:
+        """Times the stream-kernel shapes for products with nrhs columns and keeps the fastest."""
+        torch = _torch()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        _check(load_library().h3d_autotune(self._h, int(nrhs), ctypes.c_void_p(stream)))
+
     def stats(self) -> dict:
         s = Stats()
         _check(load_library().h3d_get_stats(self._h, ctypes.byref(s)))
@@ -266,8 +275,9 @@ class Operator:
             return buf.reshape(2, -1)
         return buf
 
-    def profile(self, enable: bool = True) -> None:
-        _check(load_library().h3d_profile_enable(self._h, int(bool(enable))))
+    def profile(self, enable=True) -> None:
+        """Turns kernel timing on (True or 1), on and level by level (2), or off."""
+        _check(load_library().h3d_profile_enable(self._h, int(enable)))
 
     def profile_reset(self) -> None:
         _check(load_library().h3d_profile_reset(self._h))
@@ -286,7 +296,8 @@ class Operator:
 def build(points, kernel="laplace", kernel_param: float = 1.0, leaf_size: int = 64,
           tol: float = 1e-8, factor_dtype="fp64", max_rank: int = 0, max_depth: int = 10,
           box_lo=None, box_side: float = 0.0, workspace_bytes: int = 0,
-          keep_pivots: bool = False, use_torch_allocator: bool = True) -> Operator:
+          keep_pivots: bool = False, use_torch_allocator: bool = True,
+          autotune: bool = True) -> Operator:
     """Builds the HODLR3D operator of the n x 3 FP64 point cloud (moved to the GPU)."""
     torch = _torch()
     lib = load_library()
@@ -310,7 +321,7 @@ def build(points, kernel="laplace", kernel_param: float = 1.0, leaf_size: int = 
             cfg.box_lo[a] = float(box_lo[a])
     cfg.box_side = float(box_side)
     cfg.workspace_bytes = int(workspace_bytes)
-    cfg.flags = FLAG_KEEP_PIVOTS if keep_pivots else 0
+    cfg.flags = (FLAG_KEEP_PIVOTS if keep_pivots else 0) | (0 if autotune else FLAG_NO_AUTOTUNE)
     device = points.device.index if points.device.index is not None else torch.cuda.current_device()
     alloc = _TorchAllocator(device) if use_torch_allocator else None
     handle = ctypes.c_void_p()

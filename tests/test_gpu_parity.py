@@ -144,12 +144,12 @@ def test_multiple_rhs_are_columns(case):
     Y = gpu_apply(op, X)
     Ya = gpu_apply(op, X, adjoint=True)
     Yo = ref.matvec(X)
+    # the multi-column kernels may sum in another order than the (tuned)
+    # single-column ones: equal to rounding in the 2-norm
     for c in range(5):
         assert rel(Y[:, c], Yo[:, c]) <= 1e-13
-        np.testing.assert_allclose(Y[:, c], gpu_apply(op, X[:, c]), rtol=1e-14,
-                                   atol=1e-15 * np.abs(Y[:, c]).max())
-        np.testing.assert_allclose(Ya[:, c], gpu_apply(op, X[:, c], adjoint=True), rtol=1e-14,
-                                   atol=1e-15 * np.abs(Ya[:, c]).max())
+        assert rel(Y[:, c], gpu_apply(op, X[:, c])) <= 1e-14
+        assert rel(Ya[:, c], gpu_apply(op, X[:, c], adjoint=True)) <= 1e-14
 
 
 def test_bitwise_reproducible(case):
@@ -223,8 +223,8 @@ def test_rank_cap():
 def test_small_workspace_batches():
     pts = inputs.uniform_points(20000, seed=16)
     kw = dict(leaf_size=32, tol=1e-8, **CUBE)
-    a = gpu_build(pts, **kw)
-    b = gpu_build(pts, workspace_bytes=1 << 20, **kw)  # many ACA batches, many chunks
+    a = gpu_build(pts, autotune=False, **kw)
+    b = gpu_build(pts, workspace_bytes=1 << 20, autotune=False, **kw)  # many ACA batches, chunks
     x = inputs.normal_rhs(20000, seed=17)
     np.testing.assert_array_equal(gpu_apply(a, x), gpu_apply(b, x))
     np.testing.assert_array_equal(a.export("factors_v"), b.export("factors_v"))
@@ -234,8 +234,8 @@ def test_small_workspace_batches():
 
 def test_own_allocator_matches_torch_allocator():
     pts = inputs.uniform_points(5000, seed=18)
-    a = gpu_build(pts, leaf_size=32, tol=1e-8)
-    b = gpu_build(pts, leaf_size=32, tol=1e-8, use_torch_allocator=False)
+    a = gpu_build(pts, leaf_size=32, tol=1e-8, autotune=False)
+    b = gpu_build(pts, leaf_size=32, tol=1e-8, use_torch_allocator=False, autotune=False)
     x = inputs.normal_rhs(5000, seed=19)
     np.testing.assert_array_equal(gpu_apply(a, x), gpu_apply(b, x))
     a.close()
@@ -351,4 +351,18 @@ def test_full_size_sampled_rows(name):
     ea = rel(ya[rows], yd)
     print(f"[{name}] sampled rel err {e:.3e} adjoint {ea:.3e}", flush=True)
     assert e <= 10 * w["tol"] and ea <= 10 * w["tol"]
+    op.close()
+
+
+def test_autotune_changes_only_summation_order():
+    pts = inputs.uniform_points(30000, seed=25)
+    op = gpu_build(pts, leaf_size=32, tol=1e-8, autotune=False, **CUBE)
+    x = inputs.normal_rhs(30000, seed=26)
+    X = inputs.normal_rhs(30000, seed=27, nrhs=6)
+    y0, Y0, A0 = gpu_apply(op, x), gpu_apply(op, X), gpu_apply(op, X, adjoint=True)
+    op.autotune(1)
+    op.autotune(6)
+    y1, Y1, A1 = gpu_apply(op, x), gpu_apply(op, X), gpu_apply(op, X, adjoint=True)
+    assert rel(y1, y0) <= 1e-14 and rel(Y1, Y0) <= 1e-14 and rel(A1, A0) <= 1e-14
+    np.testing.assert_array_equal(y1, gpu_apply(op, x))  # still reproducible
     op.close()
