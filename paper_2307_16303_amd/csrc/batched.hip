@@ -1,0 +1,544 @@
+// Products with many right-hand sides on the matrix cores.
+//
+// With nrhs columns every block apply of Algorithm 2 is a small dense GEMM:
+//   near   Y_t += K(t,s) X_s        (m x n) (n x nrhs), K entries evaluated
+//                                   on the fly straight into the A operand
+//   stage1 Z_b  = V_b^T X_s         (k x n) (n x nrhs)
+//   stage2 Y_t += U_b Z_b           (m x k) (k x nrhs), level by level
+// All three run on 16x16x4 MFMA tiles (FP64 MFMA for FP64 factors, FP32 MFMA
+// for FP32 and BF16 factors).  Right-hand sides are held point-major (a row of
+// NP = 16 ceil(nrhs/16) values per point) so that every B fragment is four
+// 64-byte segments.  FP32 tiles are flushed into FP64 registers every 64
+// K-steps (and after every block in stage 2), so long dot products and the
+// sums over blocks and levels carry FP64 accumulation.  The adjoint swaps
+// U and V and walks the blocks by source box, as in the one-column kernels.
+#include "h3d_internal.hpp"
+
+namespace h3d {
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <int DT> struct FacB;
+template <> struct FacB<H3D_F64> {
+    using T = double;
+    static __device__ __forceinline__ double ld(const T *p) { return *p; }
+};
+template <> struct FacB<H3D_F32> {
+    using T = float;
+    static __device__ __forceinline__ float ld(const T *p) { return *p; }
+};
+template <> struct FacB<H3D_BF16_SCALED> {
+    using T = uint16_t;
+    static __device__ __forceinline__ float ld(const T *p) {
+        return __uint_as_float(uint32_t(*p) << 16);
+    }
+};
+
+// compute type: FP64 factors -> double tiles, otherwise float tiles
+template <int DT> struct CT {
+    using T = float;
+    using V4 = f4;
+    static __device__ __forceinline__ V4 mfma(float a, float b, V4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // row of the 16x16 output tile held in element j of this lane
+    static __device__ __forceinline__ int row(int lane, int j) { return 4 * (lane >> 4) + j; }
+};
+template <> struct CT<H3D_F64> {
+    using T = double;
+    using V4 = d4;
+    static __device__ __forceinline__ V4 mfma(double a, double b, V4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int j) { return 4 * j + (lane >> 4); }
+};
+
+__device__ __forceinline__ double kernel_f(int kind, double kp, double r) {
+    if (r == 0.0)
+        return 0.0;
+    switch (kind) {
+    case H3D_LAPLACE:
+        return 1.0 / (4.0 * 3.14159265358979323846 * r);
+    case H3D_YUKAWA:
+        return exp(-kp * r) / r;
+    case H3D_INV_R4: {
+        double r2 = r * r;
+        return 1.0 / (r2 * r2);
+    }
+    case H3D_COS_R:
+        return cos(kp * r) / r;
+    default:
+        return 0.0;
+    }
+}
+
+__device__ __forceinline__ float kernel_f32(int kind, float kp, float r2) {
+    if (r2 == 0.0f)
+        return 0.0f;
+    const float ir = __frsqrt_rn(r2);
+    switch (kind) {
+    case H3D_LAPLACE:
+        return ir * 0.0795774715459476679f;  // 1/(4 pi)
+    case H3D_YUKAWA:
+        return __expf(-kp * r2 * ir) * ir;
+    case H3D_INV_R4:
+        return ir * ir * ir * ir;
+    case H3D_COS_R:
+        return __cosf(kp * r2 * ir) * ir;
+    default:
+        return 0.0f;
+    }
+}
+
+constexpr int kNT = 4;  // 16-wide RHS tiles per pass (64 columns)
+
+// x (caller order, column-major, io type) -> Xs (sorted, point-major, width NP)
+__global__ void k_gather_pm(const void *__restrict__ x, int io_f32, int64_t ldx, int64_t n,
+                            int nrhs, int NP, const int32_t *__restrict__ perm, int ct_f64,
+                            void *__restrict__ Xs) {
+    const int64_t p = int64_t(blockIdx.x) * blockDim.y + threadIdx.y;
+    if (p >= n)
+        return;
+    const int64_t src = perm[p];
+    for (int r = threadIdx.x; r < NP; r += blockDim.x) {
+        double v = 0.0;
+        if (r < nrhs)
+            v = io_f32 ? double(static_cast<const float *>(x)[r * ldx + src])
+                       : static_cast<const double *>(x)[r * ldx + src];
+        if (ct_f64)
+            static_cast<double *>(Xs)[p * NP + r] = v;
+        else
+            static_cast<float *>(Xs)[p * NP + r] = float(v);
+    }
+}
+
+// Y (sorted, point-major FP64) -> y (caller order, column-major, io type)
+__global__ void k_scatter_pm(const double *__restrict__ Y, int64_t n, int nrhs, int NP,
+                             const int32_t *__restrict__ perm, void *__restrict__ y, int64_t ldy,
+                             int io_f32) {
+    const int64_t p = int64_t(blockIdx.x) * blockDim.y + threadIdx.y;
+    if (p >= n)
+        return;
+    const int64_t dst = perm[p];
+    for (int r = threadIdx.x; r < nrhs; r += blockDim.x) {
+        const double v = Y[p * NP + r];
+        if (io_f32)
+            static_cast<float *>(y)[r * ldy + dst] = float(v);
+        else
+            static_cast<double *>(y)[r * ldy + dst] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// near field: one wave per (leaf, 16-row tile) and pass of kNT RHS tiles
+template <int DT>
+__global__ void __launch_bounds__(64)
+    k_near_mfma(const int2 *__restrict__ items, int64_t nitems, const int32_t *__restrict__ leaf_off,
+                const int32_t *__restrict__ near_ptr, const int32_t *__restrict__ near_s,
+                const double *__restrict__ px, const double *__restrict__ py,
+                const double *__restrict__ pz, int kind, double kp,
+                const typename CT<DT>::T *__restrict__ Xs, int NP, double *__restrict__ Y) {
+    using C = CT<DT>;
+    using T = typename C::T;
+    const int64_t w = blockIdx.x;
+    if (w >= nitems)
+        return;
+    const int lane = threadIdx.x;
+    const int2 it = items[w];
+    const int t = it.x;
+    const int32_t t0 = leaf_off[t], m = leaf_off[t + 1] - t0;
+    const int i = it.y * 16 + (lane & 15);
+    const bool ai = i < m;
+    const int64_t gi = t0 + (ai ? i : 0);
+    const double xi = px[gi], yi = py[gi], zi = pz[gi];
+    for (int nb = 0; nb < NP; nb += 16 * kNT) {
+        const int ntl = min(kNT, (NP - nb) / 16);
+        typename C::V4 acc[kNT];
+#pragma unroll
+        for (int q = 0; q < kNT; ++q)
+            acc[q] = typename C::V4{0, 0, 0, 0};
+        for (int e = near_ptr[t]; e < near_ptr[t + 1]; ++e) {
+            const int32_t s = near_s[e];
+            const int32_t s0 = leaf_off[s], ns = leaf_off[s + 1] - s0;
+            constexpr int KU = 1;
+            for (int j0 = 0; j0 < ns; j0 += 4 * KU) {
+                T a[KU], bv[KU][kNT];
+#pragma unroll
+                for (int u = 0; u < KU; ++u) {
+                    const int j = j0 + 4 * u + (lane >> 4);
+                    const int64_t gj = s0 + j;
+                    a[u] = T(0);
+                    if (ai && j < ns && gj != gi) {
+                        const double dx = xi - px[gj], dy = yi - py[gj], dz = zi - pz[gj];
+                        if (DT == H3D_F64)
+                            a[u] = T(kernel_f(kind, kp, sqrt(dx * dx + dy * dy + dz * dz)));
+                        else
+                            a[u] = T(kernel_f32(kind, float(kp), float(dx * dx + dy * dy + dz * dz)));
+                    }
+#pragma unroll
+                    for (int q = 0; q < kNT; ++q)
+                        bv[u][q] = (j < ns && q < ntl) ? Xs[gj * NP + nb + 16 * q + (lane & 15)] : T(0);
+                }
+#pragma unroll
+                for (int u = 0; u < KU; ++u)
+#pragma unroll
+                    for (int q = 0; q < kNT; ++q)
+                        if (q < ntl)
+                            acc[q] = C::mfma(a[u], bv[u][q], acc[q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kNT; ++q)
+            if (q < ntl)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int r = it.y * 16 + C::row(lane, jj);
+                    if (r < m)
+                        Y[(t0 + r) * int64_t(NP) + nb + 16 * q + (lane & 15)] = double(acc[q][jj]);
+                }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// stage 1: one wave per (block, 16-column tile of its factor)
+template <int DT>
+__global__ void __launch_bounds__(64)
+    k_s1_mfma(const int2 *__restrict__ items, int64_t nitems, const int32_t *__restrict__ seg_len,
+              const int32_t *__restrict__ seg_off, void *const *__restrict__ seg_ptr,
+              const int32_t *__restrict__ rank, const int64_t *__restrict__ blk_col0,
+              const float *__restrict__ scale2, const typename CT<DT>::T *__restrict__ Xs, int NP,
+              typename CT<DT>::T *__restrict__ Z) {
+    using C = CT<DT>;
+    using T = typename C::T;
+    using F = typename FacB<DT>::T;
+    const int64_t w = blockIdx.x;
+    if (w >= nitems)
+        return;
+    const int lane = threadIdx.x;
+    const int2 it = items[w];
+    const int b = it.x, c0 = it.y * 16;
+    const int len = seg_len[b], k = rank[b];
+    const int64_t off = seg_off[b], col0 = blk_col0[b];
+    const F *__restrict__ p = static_cast<const F *>(seg_ptr[b]);
+    double sc = 1.0;
+    if (DT == H3D_BF16_SCALED)
+        sc = double(scale2[2 * b]) * double(scale2[2 * b + 1]);
+    const int ca = c0 + (lane & 15);  // A row (factor column) of this lane
+    const bool ac = ca < k;
+    for (int nb = 0; nb < NP; nb += 16 * kNT) {
+        const int ntl = min(kNT, (NP - nb) / 16);
+        typename C::V4 acc[kNT];
+        double acc64[kNT][4];
+#pragma unroll
+        for (int q = 0; q < kNT; ++q) {
+            acc[q] = typename C::V4{0, 0, 0, 0};
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj)
+                acc64[q][jj] = 0.0;
+        }
+        // KU K-steps per round: all their fragments are loaded before the
+        // MFMAs of the round are issued
+        constexpr int KU = 1;
+        int steps = 0;
+        for (int j0 = 0; j0 < len; j0 += 4 * KU) {
+            T a[KU], bv[KU][kNT];
+#pragma unroll
+            for (int u = 0; u < KU; ++u) {
+                const int j = j0 + 4 * u + (lane >> 4);
+                const bool aj = j < len;
+                a[u] = (ac && aj) ? T(FacB<DT>::ld(p + int64_t(ca) * len + j)) : T(0);
+#pragma unroll
+                for (int q = 0; q < kNT; ++q)
+                    bv[u][q] = (aj && q < ntl) ? Xs[(off + j) * NP + nb + 16 * q + (lane & 15)] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < KU; ++u)
+#pragma unroll
+                for (int q = 0; q < kNT; ++q)
+                    if (q < ntl)
+                        acc[q] = C::mfma(a[u], bv[u][q], acc[q]);
+            steps += KU;
+            if (DT != H3D_F64 && steps >= 64) {
+                steps = 0;
+#pragma unroll
+                for (int q = 0; q < kNT; ++q) {
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj)
+                        acc64[q][jj] += double(acc[q][jj]);
+                    acc[q] = typename C::V4{0, 0, 0, 0};
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kNT; ++q)
+            if (q < ntl)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int c = c0 + C::row(lane, jj);
+                    if (c < k)
+                        Z[(col0 + c) * NP + nb + 16 * q + (lane & 15)] =
+                            T((acc64[q][jj] + double(acc[q][jj])) * sc);
+                }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// stage 2 of one level: one wave per (box, 16-row tile); Y updated in place
+template <int DT>
+__global__ void __launch_bounds__(64)
+    k_s2_mfma(const int2 *__restrict__ items, int64_t nitems, int64_t gbase,
+              const int32_t *__restrict__ leaf_off, int sh, const int64_t *__restrict__ grp_begin,
+              const int64_t *__restrict__ grp_blk, void *const *__restrict__ fptr,
+              const int32_t *__restrict__ rank, const int64_t *__restrict__ blk_col0,
+              const typename CT<DT>::T *__restrict__ Z, int NP, double *__restrict__ Y) {
+    using C = CT<DT>;
+    using T = typename C::T;
+    using F = typename FacB<DT>::T;
+    const int64_t w = blockIdx.x;
+    if (w >= nitems)
+        return;
+    const int lane = threadIdx.x;
+    const int2 it = items[w];
+    const int64_t tb = it.x;
+    const int32_t bs = leaf_off[tb << sh], bm = leaf_off[(tb + 1) << sh] - bs;
+    const int r0 = it.y * 16;
+    const int ia = r0 + (lane & 15);  // A row (box row) of this lane
+    const bool ar = ia < bm;
+    const int64_t e0 = grp_begin[gbase + tb], e1 = grp_begin[gbase + tb + 1];
+    for (int nb = 0; nb < NP; nb += 16 * kNT) {
+        const int ntl = min(kNT, (NP - nb) / 16);
+        double acc64[kNT][4];
+#pragma unroll
+        for (int q = 0; q < kNT; ++q)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const int r = r0 + C::row(lane, jj);
+                acc64[q][jj] = (q < ntl && r < bm) ? Y[(bs + r) * int64_t(NP) + nb + 16 * q + (lane & 15)] : 0.0;
+            }
+        for (int64_t e = e0; e < e1; ++e) {
+            const int64_t bi = grp_blk ? grp_blk[e] : e;
+            const int k = rank[bi];
+            const int64_t col0 = blk_col0[bi];
+            const F *__restrict__ p = static_cast<const F *>(fptr[bi]);
+            typename C::V4 acc[kNT];
+#pragma unroll
+            for (int q = 0; q < kNT; ++q)
+                acc[q] = typename C::V4{0, 0, 0, 0};
+            constexpr int KU = 1;
+            for (int c0 = 0; c0 < k; c0 += 4 * KU) {
+                T a[KU], bv[KU][kNT];
+#pragma unroll
+                for (int u = 0; u < KU; ++u) {
+                    const int c = c0 + 4 * u + (lane >> 4);
+                    const bool ak = c < k;
+                    a[u] = (ar && ak) ? T(FacB<DT>::ld(p + int64_t(c) * bm + ia)) : T(0);
+#pragma unroll
+                    for (int q = 0; q < kNT; ++q)
+                        bv[u][q] = (ak && q < ntl) ? Z[(col0 + c) * NP + nb + 16 * q + (lane & 15)] : T(0);
+                }
+#pragma unroll
+                for (int u = 0; u < KU; ++u)
+#pragma unroll
+                    for (int q = 0; q < kNT; ++q)
+                        if (q < ntl)
+                            acc[q] = C::mfma(a[u], bv[u][q], acc[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < kNT; ++q)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+                    acc64[q][jj] += double(acc[q][jj]);
+        }
+#pragma unroll
+        for (int q = 0; q < kNT; ++q)
+            if (q < ntl)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int r = r0 + C::row(lane, jj);
+                    if (r < bm)
+                        Y[(bs + r) * int64_t(NP) + nb + 16 * q + (lane & 15)] = acc64[q][jj];
+                }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// work items: (leaf, row tile), (block, column tile), (box, row tile)
+__global__ void k_cnt_rowtiles(int64_t nb, int sh, const int32_t *__restrict__ leaf_off,
+                               int64_t *__restrict__ cnt) {
+    const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b < nb)
+        cnt[b] = (leaf_off[(b + 1) << sh] - leaf_off[b << sh] + 15) / 16;
+}
+
+__global__ void k_fill_tiles(int64_t nb, const int64_t *__restrict__ cnt_scan,
+                             const int64_t *__restrict__ cnt_raw, int64_t id0,
+                             int32_t *__restrict__ items) {
+    const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= nb)
+        return;
+    const int64_t o = cnt_scan[b];
+    for (int64_t q = 0; q < cnt_raw[b]; ++q) {
+        items[2 * (o + q)] = int32_t(id0 + b);
+        items[2 * (o + q) + 1] = int32_t(q);
+    }
+}
+
+__global__ void k_cnt_coltiles(int64_t b0, int64_t nb, const int32_t *__restrict__ rank,
+                               int64_t *__restrict__ cnt) {
+    const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b < nb)
+        cnt[b] = (rank[b0 + b] + 15) / 16;
+}
+
+// builds items for nb consecutive units whose tile counts are in cnt[0..nb)
+int32_t *make_items(Plan &P, int64_t nb, int64_t id0, int64_t *cnt, int64_t *count, hipStream_t s) {
+    int64_t *raw = P.mem.alloc_n<int64_t>(nb + 1);
+    H3D_HIP(hipMemcpyAsync(raw, cnt, sizeof(int64_t) * size_t(nb), hipMemcpyDeviceToDevice, s));
+    H3D_HIP(hipMemsetAsync(cnt + nb, 0, sizeof(int64_t), s));
+    const int64_t tot = scan_exclusive_i64(P, cnt, cnt, nb + 1, s);
+    int32_t *items = P.mem.alloc_n<int32_t>(2 * std::max<int64_t>(tot, 1));
+    k_fill_tiles<<<grid_for(nb, 256), 256, 0, s>>>(nb, cnt, raw, id0, items);
+    H3D_LAUNCH_CHECK();
+    H3D_HIP(hipStreamSynchronize(s));
+    P.mem.release(raw);
+    *count = tot;
+    return items;
+}
+
+void ensure_batched_tables(Plan &P, hipStream_t s) {
+    if (P.bt_ready)
+        return;
+    const int L = P.L;
+    // near: (leaf, row tile)
+    {
+        const int64_t nl = pow8(L);
+        int64_t *cnt = P.mem.alloc_n<int64_t>(nl + 1);
+        k_cnt_rowtiles<<<grid_for(nl, 256), 256, 0, s>>>(nl, 0, P.leaf_off, cnt);
+        H3D_LAUNCH_CHECK();
+        P.bt_near = make_items(P, nl, 0, cnt, &P.bt_nnear, s);
+        P.mem.release(cnt);
+    }
+    for (int l = 1; l <= L; ++l) {
+        // stage 1: (block, column tile)
+        const int64_t b0 = P.lvl_blk[l], nb = P.lvl_blk[l + 1] - b0;
+        P.bt_s1[l] = nullptr;
+        P.bt_ns1[l] = 0;
+        if (nb > 0) {
+            int64_t *cnt = P.mem.alloc_n<int64_t>(nb + 1);
+            k_cnt_coltiles<<<grid_for(nb, 256), 256, 0, s>>>(b0, nb, P.blk_rank, cnt);
+            H3D_LAUNCH_CHECK();
+            P.bt_s1[l] = make_items(P, nb, b0, cnt, &P.bt_ns1[l], s);
+            P.mem.release(cnt);
+        }
+        // stage 2: (box, row tile) for the boxes of level l
+        const int64_t nbox = pow8(l);
+        int64_t *cnt = P.mem.alloc_n<int64_t>(nbox + 1);
+        k_cnt_rowtiles<<<grid_for(nbox, 256), 256, 0, s>>>(nbox, 3 * (L - l), P.leaf_off, cnt);
+        H3D_LAUNCH_CHECK();
+        P.bt_s2[l] = make_items(P, nbox, 0, cnt, &P.bt_ns2[l], s);
+        P.mem.release(cnt);
+    }
+    P.bt_ready = true;
+}
+
+template <int DT>
+void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t ldy, int io_f32,
+                bool adjoint, hipStream_t s) {
+    using T = typename CT<DT>::T;
+    const int64_t n = P.n;
+    const int NP = 16 * ((nrhs + 15) / 16);
+    const size_t need_x = size_t(n) * NP * sizeof(T);
+    const size_t need_y = size_t(n) * NP * sizeof(double);
+    const size_t need_z = size_t(std::max<int64_t>(P.ncols, 1)) * NP * sizeof(T);
+    if (need_x > P.bx_bytes || need_y > P.by_bytes || need_z > P.bz_bytes) {
+        P.mem.release(P.bx);
+        P.mem.release(P.by);
+        P.mem.release(P.bz);
+        P.bx = P.mem.alloc(need_x);
+        P.by = P.mem.alloc(need_y);
+        P.bz = P.mem.alloc(need_z);
+        P.bx_bytes = need_x;
+        P.by_bytes = need_y;
+        P.bz_bytes = need_z;
+    }
+    ensure_batched_tables(P, s);
+    T *Xs = static_cast<T *>(P.bx);
+    double *Y = static_cast<double *>(P.by);
+    T *Z = static_cast<T *>(P.bz);
+    const double es = DT == H3D_F64 ? 8.0 : (DT == H3D_F32 ? 4.0 : 2.0);
+    {
+        hipEvent_t ev = P.prof.begin(s);
+        dim3 blk(16, 16);
+        k_gather_pm<<<grid_for(n, 16), blk, 0, s>>>(x, io_f32, ldx, n, nrhs, NP, P.perm,
+                                                    DT == H3D_F64, Xs);
+        H3D_LAUNCH_CHECK();
+        P.prof.end(s, ev, "k_gather_pm", double(n) * (4.0 + (io_f32 ? 4 : 8) * nrhs + sizeof(T) * NP), 0.0);
+    }
+    {
+        hipEvent_t ev = P.prof.begin(s);
+        if (P.bt_nnear > 0)
+            k_near_mfma<DT><<<int(P.bt_nnear), 64, 0, s>>>(
+                reinterpret_cast<const int2 *>(P.bt_near), P.bt_nnear, P.leaf_off, P.near_ptr,
+                P.near_s, P.px, P.py, P.pz, P.cfg.kernel, P.cfg.kernel_param, Xs, NP, Y);
+        H3D_LAUNCH_CHECK();
+        P.prof.end(s, ev, "k_near_mfma", double(n) * (32.0 + 16.0 * NP),
+                   double(P.stats.near_pair_evals) * (10.0 + 2.0 * NP));
+    }
+    for (int l = 1; l <= P.L; ++l) {
+        if (P.bt_ns1[l] == 0)
+            continue;
+        hipEvent_t ev = P.prof.begin(s);
+        k_s1_mfma<DT><<<int(P.bt_ns1[l]), 64, 0, s>>>(
+            reinterpret_cast<const int2 *>(P.bt_s1[l]), P.bt_ns1[l], adjoint ? P.blk_m : P.blk_n,
+            adjoint ? P.blk_toff : P.blk_soff, adjoint ? P.blk_uptr : P.blk_vptr, P.blk_rank,
+            P.blk_col0, P.blk_scale, Xs, NP, Z);
+        H3D_LAUNCH_CHECK();
+        const double ent = double(adjoint ? P.lvl_entries_u[l] : P.lvl_entries_v[l]);
+        P.prof.end(s, ev, "k_s1_mfma", ent * es + double(P.lvl_rank_sum[l]) * sizeof(T) * NP,
+                   2.0 * ent * NP);
+    }
+    for (int l = 1; l <= P.L; ++l) {
+        if (P.bt_ns2[l] == 0 || P.lvl_blk[l + 1] <= P.lvl_blk[l])
+            continue;
+        hipEvent_t ev = P.prof.begin(s);
+        k_s2_mfma<DT><<<int(P.bt_ns2[l]), 64, 0, s>>>(
+            reinterpret_cast<const int2 *>(P.bt_s2[l]), P.bt_ns2[l], P.box_base[l], P.leaf_off,
+            3 * (P.L - l), P.tgt_begin, adjoint ? P.src_blk : nullptr,
+            adjoint ? P.blk_vptr : P.blk_uptr, P.blk_rank, P.blk_col0, Z, NP, Y);
+        H3D_LAUNCH_CHECK();
+        const double ent = double(adjoint ? P.lvl_entries_v[l] : P.lvl_entries_u[l]);
+        P.prof.end(s, ev, "k_s2_mfma",
+                   ent * es + double(P.lvl_rank_sum[l]) * sizeof(T) * NP + double(n) * 16.0 * NP,
+                   2.0 * ent * NP);
+    }
+    {
+        hipEvent_t ev = P.prof.begin(s);
+        dim3 blk(16, 16);
+        k_scatter_pm<<<grid_for(n, 16), blk, 0, s>>>(Y, n, nrhs, NP, P.perm, y, ldy, io_f32);
+        H3D_LAUNCH_CHECK();
+        P.prof.end(s, ev, "k_scatter_pm", double(n) * (4.0 + 8.0 * nrhs + (io_f32 ? 4 : 8) * nrhs), 0.0);
+    }
+}
+
+}  // namespace
+
+void matvec_batched(Plan &P, const void *x, void *y, int64_t nrhs, int64_t ldx, int64_t ldy,
+                    int io_dtype, bool adjoint, hipStream_t s) {
+    const int io_f32 = io_dtype == H3D_F32;
+    switch (P.factor_dtype) {
+    case H3D_F64:
+        batched_dt<H3D_F64>(P, x, y, int(nrhs), ldx, ldy, io_f32, adjoint, s);
+        break;
+    case H3D_F32:
+        batched_dt<H3D_F32>(P, x, y, int(nrhs), ldx, ldy, io_f32, adjoint, s);
+        break;
+    default:
+        batched_dt<H3D_BF16_SCALED>(P, x, y, int(nrhs), ldx, ldy, io_f32, adjoint, s);
+        break;
+    }
+}
+
+}  // namespace h3d

@@ -267,9 +267,24 @@ struct Plan {
     int64_t scratch_nrhs = 0;
     double *xp = nullptr, *yp = nullptr, *z = nullptr;
 
+    // many right-hand sides (matrix-core path): work items and point-major
+    // scratch, built on first use
+    bool bt_ready = false;
+    int32_t *bt_near = nullptr;
+    int64_t bt_nnear = 0;
+    int32_t *bt_s1[kMaxLevels + 1] = {};
+    int64_t bt_ns1[kMaxLevels + 1] = {};
+    int32_t *bt_s2[kMaxLevels + 1] = {};
+    int64_t bt_ns2[kMaxLevels + 1] = {};
+    void *bx = nullptr, *by = nullptr, *bz = nullptr;
+    size_t bx_bytes = 0, by_bytes = 0, bz_bytes = 0;
+
     Profiler prof;
     bool built = false;
 };
+
+// products with at least this many right-hand sides use the matrix cores
+constexpr int64_t kBatchedMinRhs = 8;
 
 // ---- building blocks implemented in the .hip files ----
 void tree_build(Plan &P, const double *points, hipStream_t s);
@@ -281,6 +296,8 @@ void export_factors(const Plan &P, int which, double *host_out);
 void set_level_shape(Plan &P, int cls, int l, const S1Shape &sh, hipStream_t s);
 S1Shape default_shape(const Plan &P, int l, int cls);
 void autotune(Plan &P, int64_t nrhs, hipStream_t s);
+void matvec_batched(Plan &P, const void *x, void *y, int64_t nrhs, int64_t ldx, int64_t ldy,
+                    int io_dtype, bool adjoint, hipStream_t s);
 
 // device-wide exclusive scan; out may alias in; returns the total
 int64_t scan_exclusive_i64(Plan &P, const int64_t *in, int64_t *out, int64_t n, hipStream_t s);

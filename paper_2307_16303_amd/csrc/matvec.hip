@@ -699,7 +699,7 @@ static void ensure_scratch(Plan &P, int64_t nrhs, hipStream_t s) {
 }
 
 void autotune(Plan &P, int64_t nrhs, hipStream_t s) {
-    if (P.nfar == 0)
+    if (P.nfar == 0 || nrhs >= kBatchedMinRhs)
         return;
     const int nr = nrhs == 1 ? 1 : int(std::min<int64_t>(nrhs, 4));
     ensure_scratch(P, std::max<int64_t>(nrhs, nr), s);
@@ -726,6 +726,10 @@ void autotune(Plan &P, int64_t nrhs, hipStream_t s) {
 
 void matvec_run(Plan &P, const void *x, void *y, int64_t nrhs, int64_t ldx, int64_t ldy,
                 int io_dtype, bool adjoint, hipStream_t s) {
+    if (nrhs >= kBatchedMinRhs) {
+        matvec_batched(P, x, y, nrhs, ldx, ldy, io_dtype, adjoint, s);
+        return;
+    }
     const int64_t n = P.n;
     ensure_scratch(P, nrhs, s);
     const int io_f32 = io_dtype == H3D_F32;

@@ -366,3 +366,45 @@ def test_autotune_changes_only_summation_order():
     assert rel(y1, y0) <= 1e-14 and rel(Y1, Y0) <= 1e-14 and rel(A1, A0) <= 1e-14
     np.testing.assert_array_equal(y1, gpu_apply(op, x))  # still reproducible
     op.close()
+
+
+# ---------------------------------------------------------------------------
+# many right-hand sides: the matrix-core (MFMA) path
+@pytest.fixture(scope="module")
+def rhs_cloud():
+    pts = inputs.uniform_points(12000, seed=30)
+    kw = dict(leaf_size=32, tol=1e-8, **CUBE)
+    return pts, kw
+
+
+@pytest.mark.parametrize("nrhs", [8, 16, 64, 70])
+def test_many_rhs_fp64_matrix_cores(rhs_cloud, nrhs):
+    pts, kw = rhs_cloud
+    op = gpu_build(pts, **kw)
+    X = inputs.normal_rhs(len(pts), seed=31, nrhs=nrhs)
+    Y = gpu_apply(op, X)
+    Ya = gpu_apply(op, X, adjoint=True)
+    ref = oracle.HODLR3D(pts, **oracle_kw(kw))
+    for c in (0, nrhs // 2, nrhs - 1):
+        assert rel(Y[:, c], ref.matvec(X[:, c])) <= 1e-13
+        assert rel(Ya[:, c], ref.rmatvec(X[:, c])) <= 1e-13
+    for c in range(nrhs):
+        assert rel(Y[:, c], gpu_apply(op, X[:, c])) <= 1e-13
+    np.testing.assert_array_equal(Y, gpu_apply(op, X))  # reproducible
+    op.close()
+
+
+@pytest.mark.parametrize("dtype,bound", [("fp32", 1e-6), ("bf16", 3e-2)])
+def test_many_rhs_low_precision(rhs_cloud, dtype, bound):
+    pts, kw = rhs_cloud
+    X = inputs.normal_rhs(len(pts), seed=32, nrhs=64)
+    op64 = gpu_build(pts, **kw)
+    op = gpu_build(pts, factor_dtype=dtype, **kw)
+    Y64, Y = gpu_apply(op64, X), gpu_apply(op, X)
+    Ya64, Ya = gpu_apply(op64, X, adjoint=True), gpu_apply(op, X, adjoint=True)
+    e = max(rel(Y[:, c], Y64[:, c]) for c in range(64))
+    ea = max(rel(Ya[:, c], Ya64[:, c]) for c in range(64))
+    print(f"[many rhs] {dtype}: worst column rel diff to FP64 {e:.3e} (adjoint {ea:.3e})")
+    assert e <= bound and ea <= bound
+    op.close()
+    op64.close()
