@@ -155,6 +155,24 @@ h3d_status h3d_matvec_adjoint(h3d_plan *plan, const void *x, void *y, int64_t nr
  */
 h3d_status h3d_autotune(h3d_plan *plan, int64_t nrhs, void *hip_stream);
 
+/*
+ * A product captured once into a HIP graph and replayed.  h3d_graph_create
+ * runs the product once eagerly on hip_stream (allocating the plan's scratch
+ * and tables), then captures the same launch sequence, with these x and y
+ * (device pointers, kept by the graph, owned by the caller) and sizes, on a
+ * private capture stream.  h3d_graph_launch replays it on hip_stream: same
+ * results, bitwise, as h3d_matvec / h3d_matvec_adjoint with the same
+ * arguments.  The graph shares the plan's scratch: replays and other
+ * products of the same plan must not overlap in time.  Destroy graphs
+ * before their plan.
+ */
+typedef struct h3d_graph h3d_graph;
+h3d_status h3d_graph_create(h3d_plan *plan, const void *x, void *y, int64_t nrhs, int64_t ldx,
+                            int64_t ldy, int32_t io_dtype, int32_t adjoint, void *hip_stream,
+                            h3d_graph **out);
+h3d_status h3d_graph_launch(h3d_graph *graph, void *hip_stream);
+h3d_status h3d_graph_destroy(h3d_graph *graph);
+
 h3d_status h3d_get_stats(const h3d_plan *plan, h3d_stats *out);
 
 /* What h3d_export copies to host memory. */

@@ -175,6 +175,7 @@ __global__ void __launch_bounds__(64)
         if (act) {
             for (int q = 0, j = r; j < n; ++q, j += SW) {
                 double v = entry(G, toff + i, soff + j);
+                #pragma unroll 4
                 for (int l = 0; l < k; ++l)
                     v -= U[int64_t(l) * m + i] * V[int64_t(l) * n + j];
                 V[int64_t(k) * n + j] = v;
@@ -219,6 +220,7 @@ __global__ void __launch_bounds__(64)
         if (act) {
             for (int ii = r; ii < m; ii += SW) {
                 double v = entry(G, toff + ii, soff + jp);
+                #pragma unroll 4
                 for (int l = 0; l < k; ++l)
                     v -= U[int64_t(l) * m + ii] * V[int64_t(l) * n + jp];
                 U[int64_t(k) * m + ii] = v;
@@ -234,16 +236,20 @@ __global__ void __launch_bounds__(64)
             // products (u_l . u_k)(v_l . v_k), one lane per l, sums in index order
             for (int l = r; l < k; l += SW) {
                 double a = 0.0, c = 0.0;
+                #pragma unroll 8
                 for (int ii = 0; ii < m; ++ii)
                     a += U[int64_t(l) * m + ii] * U[int64_t(k) * m + ii];
+                #pragma unroll 8
                 for (int j = 0; j < n; ++j)
                     c += V[int64_t(l) * n + j] * V[int64_t(k) * n + j];
                 P[l] = a * c;
             }
             if (r == 0)
+                #pragma unroll 8
                 for (int ii = 0; ii < m; ++ii)
                     uu += U[int64_t(k) * m + ii] * U[int64_t(k) * m + ii];
             if (r == (SW > 1 ? 1 : 0))
+                #pragma unroll 8
                 for (int j = 0; j < n; ++j)
                     vv += V[int64_t(k) * n + j] * V[int64_t(k) * n + j];
         }
@@ -334,6 +340,7 @@ __global__ void __launch_bounds__(kWG)
         Arg best{-1.0, kNone, 0.0};
         for (int j = tid; j < n; j += kWG) {
             double v = entry(G, toff + i, soff + j);
+            #pragma unroll 4
             for (int l = 0; l < k; ++l)
                 v -= U[int64_t(l) * m + i] * V[int64_t(l) * n + j];
             V[int64_t(k) * n + j] = v;
@@ -370,6 +377,7 @@ __global__ void __launch_bounds__(kWG)
         __syncthreads();
         for (int ii = tid; ii < m; ii += kWG) {
             double v = entry(G, toff + ii, soff + jp);
+            #pragma unroll 4
             for (int l = 0; l < k; ++l)
                 v -= U[int64_t(l) * m + ii] * V[int64_t(l) * n + jp];
             U[int64_t(k) * m + ii] = v;
@@ -384,20 +392,24 @@ __global__ void __launch_bounds__(kWG)
         __syncthreads();
         for (int l = tid; l < k; l += kWG) {
             double a = 0.0, c = 0.0;
+            #pragma unroll 8
             for (int ii = 0; ii < m; ++ii)
                 a += U[int64_t(l) * m + ii] * U[int64_t(k) * m + ii];
+            #pragma unroll 8
             for (int j = 0; j < n; ++j)
                 c += V[int64_t(l) * n + j] * V[int64_t(k) * n + j];
             P[l] = a * c;
         }
         if (tid == kWG - 1) {
             double uu = 0.0;
+            #pragma unroll 8
             for (int ii = 0; ii < m; ++ii)
                 uu += U[int64_t(k) * m + ii] * U[int64_t(k) * m + ii];
             sh_uv[0] = uu;
         }
         if (tid == kWG - 2) {
             double vv = 0.0;
+            #pragma unroll 8
             for (int j = 0; j < n; ++j)
                 vv += V[int64_t(k) * n + j] * V[int64_t(k) * n + j];
             sh_uv[1] = vv;

@@ -11,6 +11,12 @@ struct h3d_plan {
     h3d::Plan P;
 };
 
+struct h3d_graph {
+    h3d_plan *plan = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 namespace h3d {
 void near_pair_count(Plan &P, hipStream_t s);
 }
@@ -59,6 +65,27 @@ struct DeviceScope {
 };
 
 size_t io_size(int32_t dt) { return dt == H3D_F32 ? 4 : 8; }
+
+h3d_status matvec_check(h3d_plan *plan, const void *x, void *y, int64_t nrhs, int64_t ldx,
+                        int64_t ldy, int32_t io) {
+    if (!plan || !plan->P.built)
+        return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    h3d::Plan &P = plan->P;
+    if (!x || !y)
+        return invalid("x and y must be device pointers");
+    if (nrhs < 1)
+        return invalid("nrhs must be >= 1");
+    if (ldx < P.n || ldy < P.n)
+        return invalid("leading dimensions must be >= n");
+    if (io != H3D_F64 && io != H3D_F32)
+        return invalid("io_dtype must be H3D_F64 or H3D_F32");
+    const size_t es = io_size(io);
+    const uintptr_t xa = uintptr_t(x), xb = xa + size_t((nrhs - 1) * ldx + P.n) * es;
+    const uintptr_t ya = uintptr_t(y), yb = ya + size_t((nrhs - 1) * ldy + P.n) * es;
+    if (xa < yb && ya < xb)
+        return invalid("x and y overlap");
+    return H3D_OK;
+}
 
 h3d_status matvec_common(h3d_plan *plan, const void *x, void *y, int64_t nrhs, int64_t ldx,
                          int64_t ldy, int32_t io, void *stream, bool adjoint) {
@@ -190,6 +217,83 @@ h3d_status h3d_matvec(h3d_plan *plan, const void *x, void *y, int64_t nrhs, int6
 h3d_status h3d_matvec_adjoint(h3d_plan *plan, const void *x, void *y, int64_t nrhs, int64_t ldx,
                               int64_t ldy, int32_t io_dtype, void *hip_stream) {
     return matvec_common(plan, x, y, nrhs, ldx, ldy, io_dtype, hip_stream, true);
+}
+
+h3d_status h3d_graph_create(h3d_plan *plan, const void *x, void *y, int64_t nrhs, int64_t ldx,
+                            int64_t ldy, int32_t io_dtype, int32_t adjoint, void *hip_stream,
+                            h3d_graph **out) {
+    if (!out)
+        return invalid("out must not be NULL");
+    *out = nullptr;
+    h3d_status st = matvec_check(plan, x, y, nrhs, ldx, ldy, io_dtype);
+    if (st != H3D_OK)
+        return st;
+    h3d_graph *g = nullptr;
+    hipStream_t cs = nullptr;
+    st = guarded([&] {
+        h3d::Plan &P = plan->P;
+        DeviceScope ds(P.device);
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        // eager run: allocates scratch and tables outside the capture
+        h3d::matvec_run(P, x, y, nrhs, ldx, ldy, io_dtype, adjoint != 0, s);
+        H3D_HIP(hipStreamSynchronize(s));
+        g = new h3d_graph();
+        g->plan = plan;
+        const bool prof = P.prof.on;
+        P.prof.on = false;
+        H3D_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        H3D_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        try {
+            h3d::matvec_run(P, x, y, nrhs, ldx, ldy, io_dtype, adjoint != 0, cs);
+        } catch (...) {
+            hipGraph_t dead = nullptr;
+            (void)hipStreamEndCapture(cs, &dead);
+            if (dead)
+                (void)hipGraphDestroy(dead);
+            P.prof.on = prof;
+            throw;
+        }
+        H3D_HIP(hipStreamEndCapture(cs, &g->graph));
+        P.prof.on = prof;
+        H3D_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    });
+    if (cs)
+        (void)hipStreamDestroy(cs);
+    if (st != H3D_OK) {
+        if (g) {
+            if (g->exec)
+                (void)hipGraphExecDestroy(g->exec);
+            if (g->graph)
+                (void)hipGraphDestroy(g->graph);
+            delete g;
+        }
+        return st;
+    }
+    *out = g;
+    return H3D_OK;
+}
+
+h3d_status h3d_graph_launch(h3d_graph *graph, void *hip_stream) {
+    if (!graph || !graph->exec)
+        return invalid("graph is NULL");
+    return guarded([&] {
+        DeviceScope ds(graph->plan->P.device);
+        H3D_HIP(hipGraphLaunch(graph->exec, static_cast<hipStream_t>(hip_stream)));
+    });
+}
+
+h3d_status h3d_graph_destroy(h3d_graph *graph) {
+    if (!graph)
+        return H3D_OK;
+    return guarded([&] {
+        DeviceScope ds(graph->plan->P.device);
+        (void)hipDeviceSynchronize();
+        if (graph->exec)
+            (void)hipGraphExecDestroy(graph->exec);
+        if (graph->graph)
+            (void)hipGraphDestroy(graph->graph);
+        delete graph;
+    });
 }
 
 h3d_status h3d_autotune(h3d_plan *plan, int64_t nrhs, void *hip_stream) {

@@ -29,7 +29,8 @@ MAX_LEVELS = 11
 EXPORTED_SYMBOLS = (
     "h3d_config_init", "h3d_build", "h3d_matvec", "h3d_matvec_adjoint", "h3d_get_stats",
     "h3d_export", "h3d_destroy", "h3d_last_error", "h3d_profile_enable", "h3d_profile_read",
-    "h3d_profile_reset", "h3d_version", "h3d_autotune",
+    "h3d_profile_reset", "h3d_version", "h3d_autotune", "h3d_graph_create",
+    "h3d_graph_launch", "h3d_graph_destroy",
 )
 
 
@@ -144,6 +145,12 @@ def load_library():
     lib.h3d_profile_read.argtypes = [P, ctypes.POINTER(KernelProfile), I32,
                                      ctypes.POINTER(ctypes.c_int32)]
     lib.h3d_profile_read.restype = S
+    lib.h3d_graph_create.argtypes = [P, P, P, I64, I64, I64, I32, I32, P, ctypes.POINTER(P)]
+    lib.h3d_graph_create.restype = S
+    lib.h3d_graph_launch.argtypes = [P, P]
+    lib.h3d_graph_launch.restype = S
+    lib.h3d_graph_destroy.argtypes = [P]
+    lib.h3d_graph_destroy.restype = S
     lib.h3d_autotune.argtypes = [P, I64, P]
     lib.h3d_autotune.restype = S
     lib.h3d_version.argtypes = []
@@ -247,6 +254,10 @@ class Operator:
         return self.matvec(x)
 
     # -- introspection ----------------------------------------------------
+    def graph(self, x, adjoint: bool = False) -> "Graph":
+        """Captures the product with this x (kept alive) into a replayable HIP graph."""
+        return Graph(self, x, adjoint)
+
     def autotune(self, nrhs: int = 1) -> None:
         """Times the stream-kernel shapes for products with nrhs columns and keeps the fastest."""
         torch = _torch()
@@ -291,6 +302,51 @@ class Operator:
         return [dict(name=arr[i].name.decode(), launches=arr[i].launches,
                      total_ms=arr[i].total_ms, bytes_per_launch=arr[i].bytes_per_launch,
                      flops_per_launch=arr[i].flops_per_launch) for i in range(cnt.value)]
+
+
+class Graph:
+    """y = K~ x (or K~^T x) for a fixed x buffer, replayed from a captured HIP graph.
+    Write new values into ``x`` in place and call ``launch()``; the result is ``y``."""
+
+    def __init__(self, op: Operator, x, adjoint: bool = False):
+        torch = _torch()
+        if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype not in (torch.float64,
+                                                                                torch.float32):
+            raise TypeError("x must be a float64/float32 CUDA tensor")
+        self.op = op
+        self.vec = x.dim() == 1
+        self.nrhs = 1 if self.vec else x.shape[1]
+        # column-major buffers owned by the graph
+        self.x = torch.empty((self.nrhs, op.n), dtype=x.dtype, device=x.device)
+        self.x.copy_(x.reshape(op.n, -1).t())
+        self._y = torch.empty_like(self.x)
+        self._h = ctypes.c_void_p()
+        io = 0 if x.dtype == torch.float64 else 1
+        stream = torch.cuda.current_stream(x.device).cuda_stream
+        _check(load_library().h3d_graph_create(
+            op.handle, ctypes.c_void_p(self.x.data_ptr()), ctypes.c_void_p(self._y.data_ptr()),
+            self.nrhs, op.n, op.n, io, int(bool(adjoint)), ctypes.c_void_p(stream),
+            ctypes.byref(self._h)))
+
+    def set_x(self, x) -> None:
+        self.x.copy_(x.reshape(self.op.n, -1).t())
+
+    def launch(self):
+        torch = _torch()
+        stream = torch.cuda.current_stream(self.x.device).cuda_stream
+        _check(load_library().h3d_graph_launch(self._h, ctypes.c_void_p(stream)))
+        return self._y.reshape(-1) if self.vec else self._y.t()
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load_library().h3d_graph_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def build(points, kernel="laplace", kernel_param: float = 1.0, leaf_size: int = 64,

@@ -408,3 +408,27 @@ def test_many_rhs_low_precision(rhs_cloud, dtype, bound):
     assert e <= bound and ea <= bound
     op.close()
     op64.close()
+
+
+@pytest.mark.parametrize("nrhs,adjoint", [(1, False), (1, True), (3, False), (64, False), (64, True)])
+def test_graph_replay_equals_eager(nrhs, adjoint):
+    torch = torch_mod()
+    pts = inputs.uniform_points(15000, seed=40)
+    op = gpu_build(pts, leaf_size=32, tol=1e-8, **CUBE)
+    X = torch.as_tensor(inputs.normal_rhs(15000, seed=41, nrhs=None if nrhs == 1 else nrhs),
+                        device="cuda")
+    eager = (op.rmatvec(X) if adjoint else op.matvec(X)).cpu().numpy()
+    g = op.graph(X, adjoint=adjoint)
+    X2 = torch.as_tensor(inputs.normal_rhs(15000, seed=42, nrhs=None if nrhs == 1 else nrhs),
+                         device="cuda")
+    eager2 = (op.rmatvec(X2) if adjoint else op.matvec(X2)).cpu().numpy()
+    for rep in range(4):
+        # eager work of the program between replays
+        _ = op.matvec(X2)
+        torch.cuda.synchronize()
+        g.set_x(X if rep % 2 == 0 else X2)
+        out = g.launch().cpu().numpy()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out, eager if rep % 2 == 0 else eager2)
+    g.close()
+    op.close()
