@@ -13,6 +13,10 @@ by the library on the launch stream during the timed steps.
 The cpu_baseline object times the CPU oracle's exact dense direct sum on a
 bounded sample of target rows of the same workload (rows per second), and
 reports the GPU result's relative error on those rows.
+
+The variants object measures the same workload with FP32 and BF16 factors
+and with 64 right-hand sides (matrix-core path), each with its relative error
+on sampled rows of the exact product and its gain over the plain FP64 form.
 """
 from __future__ import annotations
 
@@ -44,7 +48,24 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the FP32 / BF16 / 64-RHS forms measured beside the headline")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="after the timed steps, fill and copy a 2 GiB buffer: the plain "
+                         "kernels that hardware byte counters are scaled by")
     return ap.parse_args()
+
+
+def time_products(op, x, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        y = op.matvec(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        y = op.matvec(x)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, y
 
 
 def main():
@@ -98,6 +119,42 @@ def main():
                 "kernel": dom["name"], "avg_launch_ms": round(avg_ms, 4),
                 "bytes_per_launch": dom["bytes_per_launch"]}
     kernels = {p["name"]: round(p["total_ms"] / max(p["launches"], 1), 4) for p in prof}
+    if args.calibration_copy:
+        # 2 GiB written by the fill, then 2 GiB read and 2 GiB written by the copy
+        a = torch.ones(2 ** 28, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    y_head = y.detach().cpu().numpy().reshape(n, -1)
+    op.close()
+    del op
+    torch.cuda.empty_cache()
+
+    # the same workload in the other storage forms and with 64 right-hand sides
+    variants = {}
+    var_y = {}
+    if not args.no_variants and args.factor_dtype == "fp64" and args.nrhs == 1:
+        x64_np = inputs.workload_rhs(args.workload, 64)
+        for name, dt, nr in (("fp32_1rhs", "fp32", 1), ("bf16_1rhs", "bf16", 1),
+                             ("fp64_64rhs", "fp64", 64), ("fp32_64rhs", "fp32", 64),
+                             ("bf16_64rhs", "bf16", 64)):
+            opv = hodlr3d.build(torch.as_tensor(pts, device=dev), kernel=w["kernel"],
+                                leaf_size=w["leaf_size"], tol=w["tol"], factor_dtype=dt,
+                                box_lo=inputs.CUBE_LO, box_side=inputs.CUBE_SIDE)
+            xv = torch.as_tensor(x_np if nr == 1 else x64_np, device=dev)
+            sec, yv = time_products(opv, xv, max(3, args.steps // (4 if nr > 1 else 1)),
+                                    max(1, args.warmup // 2))
+            var_y[name] = yv.detach().cpu().numpy().reshape(n, -1)
+            variants[name] = {"factor_dtype": dt, "nrhs": nr, "ms_per_step": round(1e3 * sec, 4),
+                              "value": round(n * nr / sec, 1),
+                              "gain_vs_fp64_1rhs": round(n * nr / sec / value, 2),
+                              "factor_bytes": opv.stats()["factor_bytes"]}
+            print(f"[bench] {name}: {1e3 * sec:.3f} ms, {n * nr / sec:.3e} {UNIT}", file=sys.stderr,
+                  flush=True)
+            opv.close()
+            del opv, xv, yv
+            torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -105,7 +162,7 @@ def main():
         oracle.build(force=False)
         threads = min(16, os.cpu_count() or 1)
         oracle.set_num_threads(threads)
-        y_np = y.detach().cpu().numpy().reshape(n, -1)
+        y_np = y_head
         xs = x_np.reshape(n, -1)
         probe = inputs.sample_rows(n, 64, seed=3)
         t0 = time.perf_counter()
@@ -117,6 +174,16 @@ def main():
         yd = oracle.dense_rows(pts, xs, rows, kernel=w["kernel"])
         cpu_s = time.perf_counter() - t0
         err = float(np.linalg.norm(y_np[rows] - yd) / np.linalg.norm(yd))
+        # accuracy of the other forms on sampled rows of the exact product
+        if var_y:
+            r64 = rows[:64]
+            yd64 = oracle.dense_rows(pts, inputs.workload_rhs(args.workload, 64), r64,
+                                     kernel=w["kernel"])
+            for name, yv in var_y.items():
+                ref = yd if yv.shape[1] == 1 else yd64
+                rr = rows if yv.shape[1] == 1 else r64
+                variants[name]["rel_err_on_sample"] = float(
+                    np.linalg.norm(yv[rr] - ref) / np.linalg.norm(ref))
         cpu = {"value": round(rows.size * args.nrhs / cpu_s, 1), "unit": UNIT,
                "cores": oracle.num_threads(), "kind": "oracle",
                "sample": f"exact FP64 direct sum for {rows.size} sampled target rows of the "
@@ -139,9 +206,9 @@ def main():
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "variants": variants or None,
     }
     print(json.dumps(out))
-    op.close()
 
 
 if __name__ == "__main__":

@@ -12,10 +12,10 @@
 // Stage 1 treats every factor column as one dot product: a sub-wave of S
 // lanes (S ~ the level's box size) walks one column, so 64/S consecutive
 // columns, which are consecutive in memory, are read per wave instruction.
-// Stage 2 gives every row its own lane: one wave per box of a chunk level
-// (boxes of roughly 64 points), looping over the levels; at each level the
-// lane streams the column slices of the factors of the box that contains its
-// row.  No atomics: every output row is written by exactly one lane, and the
+// Stage 2 gives every row its own lane (two rows for boxes of 65..128 points):
+// one workgroup per box of a chunk level (boxes of roughly 64 points), looping
+// over the levels; at each level the lane streams the column slices of the
+// factors of the box that contains its row.  No atomics: every output row is written by exactly one lane, and the
 // summation order is fixed, so results are bitwise reproducible.
 #include "h3d_internal.hpp"
 
@@ -23,21 +23,34 @@ namespace h3d {
 
 namespace {
 
+// Factor loads.  Plain loads keep the lines in L2: a column slice rarely
+// starts on a 128-byte line, and the part of a line that the next slice
+// needs is then still cached (with the non-temporal hint such lines were
+// fetched twice).  kS2NonTemporal selects the hint for the stage-2 stream.
+constexpr bool kS2NonTemporal = false;
+
 template <int DT> struct Fac;
 template <> struct Fac<H3D_F64> {
     using T = double;
-    static __device__ __forceinline__ double ld(const T *p) { return __builtin_nontemporal_load(p); }
+    static __device__ __forceinline__ double cvt(T v) { return v; }
 };
 template <> struct Fac<H3D_F32> {
     using T = float;
-    static __device__ __forceinline__ double ld(const T *p) { return double(__builtin_nontemporal_load(p)); }
+    static __device__ __forceinline__ double cvt(T v) { return double(v); }
 };
 template <> struct Fac<H3D_BF16_SCALED> {
     using T = uint16_t;
-    static __device__ __forceinline__ double ld(const T *p) {
-        return double(__uint_as_float(uint32_t(__builtin_nontemporal_load(p)) << 16));
+    static __device__ __forceinline__ double cvt(T v) {
+        return double(__uint_as_float(uint32_t(v) << 16));
     }
 };
+template <int DT, bool NT = false>
+__device__ __forceinline__ double fac_ld(const typename Fac<DT>::T *p) {
+    if constexpr (NT)
+        return Fac<DT>::cvt(__builtin_nontemporal_load(p));
+    else
+        return Fac<DT>::cvt(*p);
+}
 
 __device__ __forceinline__ double kernel_f(int kind, double kp, double r) {
     if (r == 0.0)
@@ -224,7 +237,7 @@ __global__ void __launch_bounds__(256) k_s1_wide(S1Args a) {
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int c = cb + sub + u * NS;
-                    v[u] = c < cend ? Fac<DT>::ld(p + int64_t(c) * len + j) : 0.0;
+                    v[u] = c < cend ? fac_ld<DT>(p + int64_t(c) * len + j) : 0.0;
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u)
@@ -294,7 +307,7 @@ __global__ void __launch_bounds__(256) k_s1_packed(S1Args a) {
                 double v[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    v[u] = cb + u < k ? Fac<DT>::ld(p + int64_t(cb + u) * len + j) : 0.0;
+                    v[u] = cb + u < k ? fac_ld<DT>(p + int64_t(cb + u) * len + j) : 0.0;
 #pragma unroll
                 for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -346,10 +359,11 @@ template <int DT, int NR> void launch_s1(const S1Shape &sh, S1Args a, hipStream_
 }
 
 // ---------------------------------------------------------------------------
-// stage 2: one wave per box of the chunk level, one lane per row.  At levels
-// up to the chunk level every lane of the wave lies in the same box, so the
-// block metadata and z are wave-uniform (scalar loads) and each lane streams
-// one column slice of U per load, U2 loads in flight.
+// stage 2: one workgroup per box of the chunk level, one lane per row (two
+// for boxes of 65..128 rows).  At levels up to the chunk level every lane of
+// the workgroup lies in the same box, so the block metadata and z are
+// wave-uniform (scalar loads) and each lane streams one column slice of U per
+// load, U2 loads in flight; the waves split the box's blocks.
 struct S2Tab {
     int64_t box_base[kMaxLevels + 1];
     int L, lc;
@@ -364,7 +378,7 @@ __device__ __forceinline__ void stage2_block(const typename Fac<DT>::T *__restri
         double v[U2];
 #pragma unroll
         for (int u = 0; u < U2; ++u)
-            v[u] = Fac<DT>::ld(p + int64_t(c + u) * bm);
+            v[u] = fac_ld<DT, kS2NonTemporal>(p + int64_t(c + u) * bm);
 #pragma unroll
         for (int u = 0; u < U2; ++u)
 #pragma unroll
@@ -373,11 +387,49 @@ __device__ __forceinline__ void stage2_block(const typename Fac<DT>::T *__restri
                     acc[q] += v[u] * zz[(rb + q) * ldz + c + u];
     }
     for (; c < k; ++c) {
-        const double v = Fac<DT>::ld(p + int64_t(c) * bm);
+        const double v = fac_ld<DT, kS2NonTemporal>(p + int64_t(c) * bm);
 #pragma unroll
         for (int q = 0; q < NR; ++q)
             if (NR == 1 || rb + q < nrhs)
                 acc[q] += v * zz[(rb + q) * ldz + c];
+    }
+}
+
+// The same for two rows per lane, d rows apart (d = 0 for a lane whose second
+// row lies past the box: it then repeats its first load and drops the sum).
+template <int DT, int NR, int U2>
+__device__ __forceinline__ void stage2_block2(const typename Fac<DT>::T *__restrict__ p, int d,
+                                              int bm, int k, const double *__restrict__ zz,
+                                              int64_t ldz, int rb, int nrhs, double (&a0)[NR],
+                                              double (&a1)[NR]) {
+    int c = 0;
+    for (; c + U2 <= k; c += U2) {
+        double v[U2], w[U2];
+#pragma unroll
+        for (int u = 0; u < U2; ++u) {
+            v[u] = fac_ld<DT, kS2NonTemporal>(p + int64_t(c + u) * bm);
+            w[u] = fac_ld<DT, kS2NonTemporal>(p + d + int64_t(c + u) * bm);
+        }
+#pragma unroll
+        for (int u = 0; u < U2; ++u)
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+                if (NR == 1 || rb + q < nrhs) {
+                    const double zq = zz[(rb + q) * ldz + c + u];
+                    a0[q] += v[u] * zq;
+                    a1[q] += w[u] * zq;
+                }
+    }
+    for (; c < k; ++c) {
+        const double v = fac_ld<DT, kS2NonTemporal>(p + int64_t(c) * bm);
+        const double w = fac_ld<DT, kS2NonTemporal>(p + d + int64_t(c) * bm);
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+            if (NR == 1 || rb + q < nrhs) {
+                const double zq = zz[(rb + q) * ldz + c];
+                a0[q] += v * zq;
+                a1[q] += w * zq;
+            }
     }
 }
 
@@ -392,21 +444,35 @@ __global__ void __launch_bounds__(512)
     using T = typename Fac<DT>::T;
     __shared__ double part[kS2Waves][NR][64];
     const int L = tab.L, lc = tab.lc;
-    const int64_t B = blockIdx.x;
+    // Neighbouring chunk boxes share the cache line at their common edge in
+    // every coarse column they read, and workgroups are dealt to the eight
+    // XCDs (each with its own L2) in turn: give each XCD a contiguous run of
+    // chunk boxes so that those lines are fetched once.
+    const int64_t nch = gridDim.x;
+    int64_t B = blockIdx.x;
+    if ((nch & 7) == 0)
+        B = (B & 7) * (nch >> 3) + (B >> 3);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int shc = 3 * (L - lc);
     const int32_t r0 = leaf_off[B << shc], r1 = leaf_off[(B + 1) << shc];
-    for (int32_t rowb = r0; rowb < r1; rowb += 64) {
-        const int32_t row = rowb + lane;
-        const bool act = row < r1;
-        const int32_t rr = act ? row : r0;
-        const int32_t leaf = leaf_of[rr];
+    // Passes of up to 128 rows: a box of 65..128 rows reads every coarse
+    // column slice in one pass, two rows per lane (rows rowb + lane and
+    // rowb + 64 + lane), instead of a second pass over the same columns.
+    for (int32_t rowb = r0; rowb < r1;) {
+        const bool two = r1 - rowb > 64;
+        const int32_t rowA = rowb + lane, rowB = rowb + 64 + lane;
+        const bool actA = rowA < r1, actB = two && rowB < r1;
+        const int32_t rrA = actA ? rowA : r0;
+        const int dB = actB ? 64 : 0;
         for (int rb = 0; rb < nrhs; rb += NR) {
-            double acc[NR];
+            double acc[2][NR];
 #pragma unroll
-            for (int c = 0; c < NR; ++c)
-                acc[c] = (wv == 0 && (NR == 1 || rb + c < nrhs)) ? yn[(rb + c) * n + rr] : 0.0;
+            for (int c = 0; c < NR; ++c) {
+                const bool ok = wv == 0 && (NR == 1 || rb + c < nrhs);
+                acc[0][c] = ok ? yn[(rb + c) * n + rrA] : 0.0;
+                acc[1][c] = (ok && two) ? yn[(rb + c) * n + rrA + dB] : 0.0;
+            }
             // levels whose boxes contain the whole chunk box: wave-uniform;
             // the waves of the workgroup take every kS2Waves-th block
             for (int l = lb; l <= min(lc, le); ++l) {
@@ -415,63 +481,80 @@ __global__ void __launch_bounds__(512)
                 const int64_t g = tab.box_base[l] + t;
                 const int32_t bs = leaf_off[t << sh];
                 const int32_t bm = leaf_off[(t + 1) << sh] - bs;
-                const int32_t loc = rr - bs;
+                const int32_t loc = rrA - bs;
                 const int64_t e0 = grp_begin[g], e1 = grp_begin[g + 1];
                 for (int64_t e = e0 + wv; e < e1; e += kS2Waves) {
                     const int64_t bi = grp_blk ? grp_blk[e] : e;
                     const T *p = static_cast<const T *>(fptr[bi]) + loc;
-                    stage2_block<DT, NR, 8>(p, bm, rank[bi], z + blk_col0[bi], ldz, rb, nrhs, acc);
+                    if (two)
+                        stage2_block2<DT, NR, 8>(p, dB, bm, rank[bi], z + blk_col0[bi], ldz, rb,
+                                                 nrhs, acc[0], acc[1]);
+                    else
+                        stage2_block<DT, NR, 8>(p, bm, rank[bi], z + blk_col0[bi], ldz, rb, nrhs,
+                                                acc[0]);
                 }
             }
-            // finer levels: every lane follows the box of its own row
-            for (int l = max(lc + 1, lb); l <= le; ++l) {
-                const int sh = 3 * (L - l);
-                const int64_t t = int64_t(leaf) >> sh;
-                const int64_t g = tab.box_base[l] + t;
-                const int32_t bs = leaf_off[t << sh];
-                const int32_t bm = leaf_off[(t + 1) << sh] - bs;
-                const int32_t loc = rr - bs;
-                const int64_t e0 = grp_begin[g], e1 = grp_begin[g + 1];
-                for (int64_t e = e0 + wv; e < e1; e += kS2Waves) {
-                    const int64_t bi = grp_blk ? grp_blk[e] : e;
-                    const T *p = static_cast<const T *>(fptr[bi]) + loc;
-                    stage2_block<DT, NR, 4>(p, bm, rank[bi], z + blk_col0[bi], ldz, rb, nrhs, acc);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (h == 1 && !two)
+                    break;
+                const int32_t row = h ? rowB : rowA;
+                const bool act = h ? actB : actA;
+                const int32_t rr = act ? row : r0;
+                const int32_t leaf = leaf_of[rr];
+                // finer levels: every lane follows the box of its own row
+                for (int l = max(lc + 1, lb); l <= le; ++l) {
+                    const int sh = 3 * (L - l);
+                    const int64_t t = int64_t(leaf) >> sh;
+                    const int64_t g = tab.box_base[l] + t;
+                    const int32_t bs = leaf_off[t << sh];
+                    const int32_t bm = leaf_off[(t + 1) << sh] - bs;
+                    const int32_t loc = rr - bs;
+                    const int64_t e0 = grp_begin[g], e1 = grp_begin[g + 1];
+                    for (int64_t e = e0 + wv; e < e1; e += kS2Waves) {
+                        const int64_t bi = grp_blk ? grp_blk[e] : e;
+                        const T *p = static_cast<const T *>(fptr[bi]) + loc;
+                        stage2_block<DT, NR, 4>(p, bm, rank[bi], z + blk_col0[bi], ldz, rb, nrhs,
+                                                acc[h]);
+                    }
                 }
+                // combine the waves' partial sums in a fixed order
+#pragma unroll
+                for (int q = 0; q < NR; ++q)
+                    part[wv][q][lane] = acc[h][q];
+                __syncthreads();
+                if (wv == 0) {
+                    double y[NR];
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) {
+                        double v = part[0][q][lane];
+#pragma unroll
+                        for (int w2 = 1; w2 < kS2Waves; ++w2)
+                            v += part[w2][q][lane];
+                        y[q] = v;
+                    }
+                    if (act && ypart) {
+                        // partial sums in sorted order (level-by-level profiling)
+#pragma unroll
+                        for (int q = 0; q < NR; ++q)
+                            if (NR == 1 || rb + q < nrhs)
+                                ypart[(rb + q) * n + row] = y[q];
+                    } else if (act) {
+                        const int64_t dst = perm[row];
+#pragma unroll
+                        for (int q = 0; q < NR; ++q)
+                            if (NR == 1 || rb + q < nrhs) {
+                                if (io_f32)
+                                    static_cast<float *>(yout)[(rb + q) * ldy + dst] = float(y[q]);
+                                else
+                                    static_cast<double *>(yout)[(rb + q) * ldy + dst] = y[q];
+                            }
+                    }
+                }
+                __syncthreads();
             }
-            // combine the waves' partial sums in a fixed order
-#pragma unroll
-            for (int q = 0; q < NR; ++q)
-                part[wv][q][lane] = acc[q];
-            __syncthreads();
-            if (wv == 0) {
-#pragma unroll
-                for (int q = 0; q < NR; ++q) {
-                    double v = part[0][q][lane];
-#pragma unroll
-                    for (int w2 = 1; w2 < kS2Waves; ++w2)
-                        v += part[w2][q][lane];
-                    acc[q] = v;
-                }
-                if (act && ypart) {
-                    // partial sums in sorted order (level-by-level profiling)
-#pragma unroll
-                    for (int q = 0; q < NR; ++q)
-                        if (NR == 1 || rb + q < nrhs)
-                            ypart[(rb + q) * n + row] = acc[q];
-                } else if (act) {
-                    const int64_t dst = perm[row];
-#pragma unroll
-                    for (int q = 0; q < NR; ++q)
-                        if (NR == 1 || rb + q < nrhs) {
-                            if (io_f32)
-                                static_cast<float *>(yout)[(rb + q) * ldy + dst] = float(acc[q]);
-                            else
-                                static_cast<double *>(yout)[(rb + q) * ldy + dst] = acc[q];
-                        }
-                }
-            }
-            __syncthreads();
         }
+        rowb += two ? 128 : 64;
     }
 }
 
