@@ -3,13 +3,12 @@
 // ABI; failures return an h3d_status and leave a message for h3d_last_error.
 #include <chrono>
 #include <cmath>
+#include <memory>
 #include <new>
 
 #include "h3d_internal.hpp"
 
-struct h3d_plan {
-    h3d::Plan P;
-};
+h3d_plan::~h3d_plan() { delete batch; }
 
 struct h3d_graph {
     h3d_plan *plan = nullptr;
@@ -19,6 +18,7 @@ struct h3d_graph {
 
 namespace h3d {
 void near_pair_count(Plan &P, hipStream_t s);
+bool batch_wait_failed(h3d_plan &bp, hipStream_t s);
 }
 
 namespace {
@@ -66,10 +66,16 @@ struct DeviceScope {
 
 size_t io_size(int32_t dt) { return dt == H3D_F32 ? 4 : 8; }
 
+h3d_status batch_plan_error() {
+    return invalid("a batch plan takes h3d_matvec_batch; h3d_batch_plan gives its problems");
+}
+
 h3d_status matvec_check(h3d_plan *plan, const void *x, void *y, int64_t nrhs, int64_t ldx,
                         int64_t ldy, int32_t io) {
     if (!plan || !plan->P.built)
         return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    if (plan->batch)
+        return batch_plan_error();
     h3d::Plan &P = plan->P;
     if (!x || !y)
         return invalid("x and y must be device pointers");
@@ -89,26 +95,79 @@ h3d_status matvec_check(h3d_plan *plan, const void *x, void *y, int64_t nrhs, in
 
 h3d_status matvec_common(h3d_plan *plan, const void *x, void *y, int64_t nrhs, int64_t ldx,
                          int64_t ldy, int32_t io, void *stream, bool adjoint) {
-    if (!plan || !plan->P.built)
-        return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    const h3d_status st = matvec_check(plan, x, y, nrhs, ldx, ldy, io);
+    if (st != H3D_OK)
+        return st;
     h3d::Plan &P = plan->P;
-    if (!x || !y)
-        return invalid("x and y must be device pointers");
-    if (nrhs < 1)
-        return invalid("nrhs must be >= 1");
-    if (ldx < P.n || ldy < P.n)
-        return invalid("leading dimensions must be >= n");
-    if (io != H3D_F64 && io != H3D_F32)
-        return invalid("io_dtype must be H3D_F64 or H3D_F32");
-    const size_t es = io_size(io);
-    const uintptr_t xa = uintptr_t(x), xb = xa + size_t((nrhs - 1) * ldx + P.n) * es;
-    const uintptr_t ya = uintptr_t(y), yb = ya + size_t((nrhs - 1) * ldy + P.n) * es;
-    if (xa < yb && ya < xb)
-        return invalid("x and y overlap");
     return guarded([&] {
         DeviceScope ds(P.device);
         h3d::matvec_run(P, x, y, nrhs, ldx, ldy, io, adjoint, static_cast<hipStream_t>(stream));
     });
+}
+
+h3d_status check_config(const h3d_config *cfg, const h3d_allocator *alloc) {
+    if (!cfg)
+        return invalid("cfg must not be NULL");
+    if (cfg->kernel < H3D_LAPLACE || cfg->kernel > H3D_COS_R)
+        return invalid("unknown kernel");
+    if (!std::isfinite(cfg->kernel_param))
+        return invalid("kernel_param must be finite");
+    if (cfg->leaf_size < 1)
+        return invalid("leaf_size must be >= 1");
+    if (!(cfg->tol > 0.0 && cfg->tol < 1.0))
+        return invalid("tol must lie in (0, 1)");
+    if (cfg->factor_dtype < H3D_F64 || cfg->factor_dtype > H3D_BF16_SCALED)
+        return invalid("unknown factor_dtype");
+    if (cfg->max_depth < 0 || cfg->max_depth > h3d::kMaxDepth)
+        return invalid("max_depth must lie in [0, 10]");
+    if (!std::isfinite(cfg->box_side))
+        return invalid("box_side must be finite");
+    if (cfg->box_side > 0.0)
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(cfg->box_lo[a]))
+                return invalid("box_lo must be finite");
+    if (alloc && ((alloc->alloc == nullptr) != (alloc->free == nullptr)))
+        return invalid("allocator needs both alloc and free");
+    return H3D_OK;
+}
+
+// Builds one operator (throws h3d::Error).  A member of a batch keeps the
+// default stage-1 shapes and one wave per stage-2 chunk box.
+h3d_plan *build_plan(const double *points, int64_t n, const h3d_config &cfg,
+                     const h3d_allocator *alloc, hipStream_t s, bool in_batch) {
+    const auto t0 = std::chrono::steady_clock::now();
+    std::unique_ptr<h3d_plan> plan(new h3d_plan());
+    h3d::Plan &P = plan->P;
+    P.cfg = cfg;
+    H3D_HIP(hipGetDevice(&P.device));
+    P.mem.configure(alloc, s);
+    P.n = n;
+    P.in_batch = in_batch;
+    h3d::tree_build(P, points, s);
+    h3d::lists_build(P, s);
+    h3d::factors_build(P, s);
+    h3d::near_pair_count(P, s);
+    if (in_batch) {
+        P.s2_waves[0] = P.s2_waves[1] = 1;
+    } else if (!(P.cfg.flags & H3D_FLAG_NO_AUTOTUNE)) {
+        h3d::autotune(P, 1, s);
+    }
+    H3D_HIP(hipStreamSynchronize(s));
+    h3d_stats &S = P.stats;
+    S.n = n;
+    S.depth = P.L;
+    S.factor_dtype = P.factor_dtype;
+    for (int a = 0; a < 3; ++a)
+        S.box_lo[a] = P.lo[a];
+    S.box_side = P.side;
+    S.n_far = P.nfar;
+    S.n_near = P.nnear;
+    for (int l = 0; l < H3D_MAX_LEVELS; ++l)
+        S.far_per_level[l] = (l >= 1 && l <= P.L) ? P.lvl_blk[l + 1] - P.lvl_blk[l] : 0;
+    S.device_bytes = int64_t(P.mem.total());
+    S.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    P.built = true;
+    return plan.release();
 }
 
 }  // namespace
@@ -140,65 +199,16 @@ h3d_status h3d_build(const double *points, int64_t n, const h3d_config *cfg,
     if (!out)
         return invalid("out must not be NULL");
     *out = nullptr;
-    if (!cfg)
-        return invalid("cfg must not be NULL");
+    h3d_status st = check_config(cfg, alloc);
+    if (st != H3D_OK)
+        return st;
     if (!points)
         return invalid("points must not be NULL");
     if (n < 1 || n > int64_t(0x7fffffff) - 1)
         return invalid("n must be in [1, 2^31 - 2]");
-    if (cfg->kernel < H3D_LAPLACE || cfg->kernel > H3D_COS_R)
-        return invalid("unknown kernel");
-    if (!std::isfinite(cfg->kernel_param))
-        return invalid("kernel_param must be finite");
-    if (cfg->leaf_size < 1)
-        return invalid("leaf_size must be >= 1");
-    if (!(cfg->tol > 0.0 && cfg->tol < 1.0))
-        return invalid("tol must lie in (0, 1)");
-    if (cfg->factor_dtype < H3D_F64 || cfg->factor_dtype > H3D_BF16_SCALED)
-        return invalid("unknown factor_dtype");
-    if (cfg->max_depth < 0 || cfg->max_depth > h3d::kMaxDepth)
-        return invalid("max_depth must lie in [0, 10]");
-    if (!std::isfinite(cfg->box_side))
-        return invalid("box_side must be finite");
-    if (cfg->box_side > 0.0)
-        for (int a = 0; a < 3; ++a)
-            if (!std::isfinite(cfg->box_lo[a]))
-                return invalid("box_lo must be finite");
-    if (alloc && ((alloc->alloc == nullptr) != (alloc->free == nullptr)))
-        return invalid("allocator needs both alloc and free");
-
-    h3d_plan *plan = nullptr;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    h3d_status st = guarded([&] {
-        const auto t0 = std::chrono::steady_clock::now();
-        plan = new h3d_plan();
-        h3d::Plan &P = plan->P;
-        P.cfg = *cfg;
-        H3D_HIP(hipGetDevice(&P.device));
-        P.mem.configure(alloc, s);
-        P.n = n;
-        h3d::tree_build(P, points, s);
-        h3d::lists_build(P, s);
-        h3d::factors_build(P, s);
-        h3d::near_pair_count(P, s);
-        if (!(P.cfg.flags & H3D_FLAG_NO_AUTOTUNE))
-            h3d::autotune(P, 1, s);
-        H3D_HIP(hipStreamSynchronize(s));
-        h3d_stats &S = P.stats;
-        S.n = n;
-        S.depth = P.L;
-        S.factor_dtype = P.factor_dtype;
-        for (int a = 0; a < 3; ++a)
-            S.box_lo[a] = P.lo[a];
-        S.box_side = P.side;
-        S.n_far = P.nfar;
-        S.n_near = P.nnear;
-        for (int l = 0; l < H3D_MAX_LEVELS; ++l)
-            S.far_per_level[l] = (l >= 1 && l <= P.L) ? P.lvl_blk[l + 1] - P.lvl_blk[l] : 0;
-        S.device_bytes = int64_t(P.mem.total());
-        S.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        P.built = true;
-    });
+    h3d_plan *plan = nullptr;
+    st = guarded([&] { plan = build_plan(points, n, *cfg, alloc, s, false); });
     if (st != H3D_OK) {
         (void)hipStreamSynchronize(s);
         (void)hipGetLastError();
@@ -206,6 +216,129 @@ h3d_status h3d_build(const double *points, int64_t n, const h3d_config *cfg,
         return st;
     }
     *out = plan;
+    return H3D_OK;
+}
+
+h3d_status h3d_build_batch(int32_t nprob, const double *const *points, const int64_t *n,
+                           const h3d_config *cfg, const h3d_allocator *alloc, void *hip_stream,
+                           h3d_plan **out) {
+    if (!out)
+        return invalid("out must not be NULL");
+    *out = nullptr;
+    if (nprob < 1)
+        return invalid("nprob must be >= 1");
+    if (!points || !n)
+        return invalid("points and n must not be NULL");
+    h3d_status st = check_config(cfg, alloc);
+    if (st != H3D_OK)
+        return st;
+    for (int32_t i = 0; i < nprob; ++i) {
+        if (!points[i])
+            return invalid("points[" + std::to_string(i) + "] is NULL");
+        if (n[i] < 1 || n[i] > int64_t(0x7fffffff) - 1)
+            return invalid("n[" + std::to_string(i) + "] must be in [1, 2^31 - 2]");
+    }
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    h3d_plan *bp = nullptr;
+    st = guarded([&] {
+        const auto t0 = std::chrono::steady_clock::now();
+        bp = new h3d_plan();
+        bp->batch = new h3d::BatchState();
+        h3d::Plan &P = bp->P;
+        P.cfg = *cfg;
+        H3D_HIP(hipGetDevice(&P.device));
+        P.mem.configure(alloc, s);
+        P.factor_dtype = cfg->factor_dtype;
+        h3d_stats &S = P.stats;
+        S.factor_dtype = cfg->factor_dtype;
+        for (int32_t i = 0; i < nprob; ++i) {
+            bp->batch->subs.push_back(nullptr);
+            h3d_plan *q = build_plan(points[i], n[i], *cfg, alloc, s, true);
+            bp->batch->subs.back() = q;
+            const h3d_stats &Q = q->P.stats;
+            S.n += Q.n;
+            S.depth = std::max(S.depth, Q.depth);
+            S.n_far += Q.n_far;
+            S.n_near += Q.n_near;
+            for (int l = 0; l < H3D_MAX_LEVELS; ++l) {
+                S.far_per_level[l] += Q.far_per_level[l];
+                S.factor_bytes_per_level[l] += Q.factor_bytes_per_level[l];
+            }
+            S.rank_sum += Q.rank_sum;
+            S.rank_max = std::max(S.rank_max, Q.rank_max);
+            S.n_rank_capped += Q.n_rank_capped;
+            S.factor_entries += Q.factor_entries;
+            S.factor_bytes += Q.factor_bytes;
+            S.near_pair_evals += Q.near_pair_evals;
+            S.aca_ms += Q.aca_ms;
+        }
+        h3d::batch_setup(*bp, s);
+        H3D_HIP(hipStreamSynchronize(s));
+        P.n = S.n;
+        S.build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        P.built = true;
+    });
+    if (st != H3D_OK) {
+        (void)hipStreamSynchronize(s);
+        (void)hipGetLastError();
+        delete bp;
+        return st;
+    }
+    *out = bp;
+    return H3D_OK;
+}
+
+h3d_status h3d_matvec_batch(h3d_plan *batch, const void *const *x, void *const *y, int64_t nrhs,
+                            int32_t io_dtype, void *hip_stream) {
+    if (!batch || !batch->P.built)
+        return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    if (!batch->batch)
+        return invalid("not a batch plan (built by h3d_build_batch)");
+    if (!x || !y)
+        return invalid("x and y must be host arrays of device pointers");
+    const auto &subs = batch->batch->subs;
+    for (size_t i = 0; i < subs.size(); ++i) {
+        const int64_t ni = subs[i]->P.n;
+        const h3d_status st = matvec_check(subs[i], x[i], y[i], nrhs, ni, ni, io_dtype);
+        if (st != H3D_OK) {
+            g_last_error = "problem " + std::to_string(i) + ": " + g_last_error;
+            return st;
+        }
+    }
+    return guarded([&] {
+        DeviceScope ds(batch->P.device);
+        h3d::batch_run(*batch, x, y, nrhs, io_dtype, static_cast<hipStream_t>(hip_stream));
+    });
+}
+
+h3d_status h3d_batch_plan(h3d_plan *batch, int32_t i, h3d_plan **out) {
+    if (!out)
+        return invalid("out must not be NULL");
+    *out = nullptr;
+    if (!batch || !batch->P.built)
+        return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    if (!batch->batch)
+        return invalid("not a batch plan (built by h3d_build_batch)");
+    if (i < 0 || size_t(i) >= batch->batch->subs.size())
+        return invalid("problem index out of range");
+    *out = batch->batch->subs[size_t(i)];
+    return H3D_OK;
+}
+
+h3d_status h3d_batch_check(h3d_plan *batch, void *hip_stream) {
+    if (!batch || !batch->P.built)
+        return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    if (!batch->batch)
+        return invalid("not a batch plan (built by h3d_build_batch)");
+    bool failed = false;
+    const h3d_status st = guarded([&] {
+        DeviceScope ds(batch->P.device);
+        failed = h3d::batch_wait_failed(*batch, static_cast<hipStream_t>(hip_stream));
+    });
+    if (st != H3D_OK)
+        return st;
+    if (failed)
+        return g_last_error = "a dependency wait of the batch product gave up", H3D_EDEVICE;
     return H3D_OK;
 }
 
@@ -299,6 +432,10 @@ h3d_status h3d_graph_destroy(h3d_graph *graph) {
 h3d_status h3d_autotune(h3d_plan *plan, int64_t nrhs, void *hip_stream) {
     if (!plan || !plan->P.built)
         return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    if (plan->batch)
+        return batch_plan_error();
+    if (plan->P.in_batch)
+        return invalid("the launch shapes of a batch member are fixed by its batch");
     if (nrhs < 1)
         return invalid("nrhs must be >= 1");
     return guarded([&] {
@@ -314,12 +451,17 @@ h3d_status h3d_get_stats(const h3d_plan *plan, h3d_stats *out) {
         return invalid("out must not be NULL");
     *out = plan->P.stats;
     out->device_bytes = int64_t(plan->P.mem.total());
+    if (plan->batch)
+        for (const h3d_plan *q : plan->batch->subs)
+            out->device_bytes += int64_t(q->P.mem.total());
     return H3D_OK;
 }
 
 h3d_status h3d_export(const h3d_plan *plan, int32_t what, void *host_buf, size_t *bytes) {
     if (!plan || !plan->P.built)
         return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    if (plan->batch)
+        return batch_plan_error();
     if (!bytes)
         return invalid("bytes must not be NULL");
     h3d::Plan &P = const_cast<h3d::Plan &>(plan->P);

@@ -281,10 +281,50 @@ struct Plan {
 
     Profiler prof;
     bool built = false;
+    bool in_batch = false;  // a problem of a batch: launch shapes fixed
 };
 
 // products with at least this many right-hand sides use the matrix cores
 constexpr int64_t kBatchedMinRhs = 8;
+
+struct BatchState;
+}  // namespace h3d
+
+// The opaque handle of the C ABI: one operator, or a batch of independent
+// operators (then P holds only the batch's own device tables and profiler).
+struct h3d_plan {
+    h3d::Plan P;
+    h3d::BatchState *batch = nullptr;
+    ~h3d_plan();
+};
+
+namespace h3d {
+
+struct BatchProb;  // device descriptor of one problem (batch.hip)
+struct BatchSeg;   // a run of queue items of one kind and problem (batch.hip)
+
+// A batch of independent operators multiplied in one persistent launch.
+struct BatchState {
+    std::vector<h3d_plan *> subs;  // owned
+    BatchProb *probs = nullptr;    // device [nprob]
+    BatchSeg *segs = nullptr;      // device [nseg]
+    int nseg = 0;
+    int64_t nitems = 0;            // queue length in units
+    std::vector<int64_t> n_gather, n_mid;  // per problem: units each phase waits for
+    unsigned *ctl = nullptr;       // device: ticket head, error flag, per-problem counters
+    const void **io = nullptr;     // device [2 nprob]: x pointers then y pointers
+    int64_t desc_nrhs = 0;         // right-hand sides the descriptors were written for
+    std::vector<const void *> desc_scratch;  // scratch pointers they hold
+    int grid = 0;                  // resident one-wave workgroups of the launch
+    ~BatchState() {
+        for (h3d_plan *p : subs)
+            delete p;
+    }
+};
+
+void batch_setup(h3d_plan &batch, hipStream_t s);
+void batch_run(h3d_plan &batch, const void *const *x, void *const *y, int64_t nrhs, int io_dtype,
+               hipStream_t s);
 
 // ---- building blocks implemented in the .hip files ----
 void tree_build(Plan &P, const double *points, hipStream_t s);
@@ -296,6 +336,8 @@ void export_factors(const Plan &P, int which, double *host_out);
 void set_level_shape(Plan &P, int cls, int l, const S1Shape &sh, hipStream_t s);
 S1Shape default_shape(const Plan &P, int l, int cls);
 void autotune(Plan &P, int64_t nrhs, hipStream_t s);
+// grows the plan's mat-vec scratch (xp, yp, z) to nrhs right-hand sides
+void ensure_scratch(Plan &P, int64_t nrhs, hipStream_t s);
 void matvec_batched(Plan &P, const void *x, void *y, int64_t nrhs, int64_t ldx, int64_t ldy,
                     int io_dtype, bool adjoint, hipStream_t s);
 

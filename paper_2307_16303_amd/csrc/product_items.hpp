@@ -1,0 +1,526 @@
+// Per-item device code of the mat-vec (Algorithm 2): the gather of one row,
+// the near field of one leaf, one stage-1 work item and stage 2 of one chunk
+// box.  The per-phase kernels of a single operator and the persistent kernel
+// of a batch of operators both call these functions, so a problem computes
+// the same sums in either form.
+#pragma once
+
+#include "h3d_internal.hpp"
+
+namespace h3d {
+namespace dev {
+
+// Factor loads.  Plain loads keep the lines in L2: a column slice rarely
+// starts on a 128-byte line, and the part of a line that the next slice
+// needs is then still cached (with the non-temporal hint such lines were
+// fetched twice).  kS2NonTemporal selects the hint for the stage-2 stream.
+constexpr bool kS2NonTemporal = false;
+
+template <int DT> struct Fac;
+template <> struct Fac<H3D_F64> {
+    using T = double;
+    static __device__ __forceinline__ double cvt(T v) { return v; }
+};
+template <> struct Fac<H3D_F32> {
+    using T = float;
+    static __device__ __forceinline__ double cvt(T v) { return double(v); }
+};
+template <> struct Fac<H3D_BF16_SCALED> {
+    using T = uint16_t;
+    static __device__ __forceinline__ double cvt(T v) {
+        return double(__uint_as_float(uint32_t(v) << 16));
+    }
+};
+template <int DT, bool NT = false>
+__device__ __forceinline__ double fac_ld(const typename Fac<DT>::T *p) {
+    if constexpr (NT)
+        return Fac<DT>::cvt(__builtin_nontemporal_load(p));
+    else
+        return Fac<DT>::cvt(*p);
+}
+
+// Reads of data that another wave of the same launch may have written (the
+// persistent multi-problem kernel: xp, the near-field sums, z).  A relaxed
+// atomic load is always a vector load, so the value comes through the caches
+// that the acquire fence of the waiting wave invalidated, never through the
+// scalar cache; outside that kernel (LIVE = false) plain loads let the
+// compiler use scalar loads for wave-uniform values.
+template <bool LIVE> __device__ __forceinline__ double rd(const double *p) {
+    if constexpr (LIVE)
+        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    else
+        return *p;
+}
+
+__device__ __forceinline__ double kernel_f(int kind, double kp, double r) {
+    if (r == 0.0)
+        return 0.0;
+    switch (kind) {
+    case H3D_LAPLACE:
+        return 1.0 / (4.0 * 3.14159265358979323846 * r);
+    case H3D_YUKAWA:
+        return exp(-kp * r) / r;
+    case H3D_INV_R4: {
+        double r2 = r * r;
+        return 1.0 / (r2 * r2);
+    }
+    case H3D_COS_R:
+        return cos(kp * r) / r;
+    default:
+        return 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// xp[:, p] = x[perm[p], :] for one sorted row p < n
+__device__ __forceinline__ void gather_row(const void *__restrict__ x, int io_f32, int64_t ldx,
+                                           int64_t n, int nrhs, const int32_t *__restrict__ perm,
+                                           double *__restrict__ xp, int64_t p) {
+    const int64_t src = perm[p];
+    for (int q = 0; q < nrhs; ++q) {
+        double v = io_f32 ? double(static_cast<const float *>(x)[q * ldx + src])
+                          : static_cast<const double *>(x)[q * ldx + src];
+        xp[q * n + p] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// near field: one wave per leaf; lane = (row within a pass of R rows, source
+// slice q of Q = 64/R); sources staged through LDS in chunks of kChunk points
+constexpr int kChunk = 256;
+
+template <int NR, bool LIVE = false>
+__device__ __forceinline__ void near_leaf(int64_t t, const int32_t *__restrict__ leaf_off,
+                                          const int32_t *__restrict__ near_ptr,
+                                          const int32_t *__restrict__ near_s,
+                                          const double *__restrict__ px,
+                                          const double *__restrict__ py,
+                                          const double *__restrict__ pz, int kind, double kp,
+                                          int nrhs, const double *__restrict__ xp, int64_t n,
+                                          double *__restrict__ yn) {
+    __shared__ double sx[kChunk], sy[kChunk], sz[kChunk];
+    __shared__ double sv[NR][kChunk];
+    const int lane = threadIdx.x;
+    const int32_t t0 = leaf_off[t];
+    const int m = leaf_off[t + 1] - t0;
+    if (m == 0)
+        return;
+    int R = 1;
+    while (R < m && R < 64)
+        R <<= 1;
+    const int Q = 64 / R;
+    const int e0 = near_ptr[t], e1 = near_ptr[t + 1];
+    for (int rowb = 0; rowb < m; rowb += R) {
+        const int i = rowb + (lane % R);
+        const int q = lane / R;
+        const bool ai = i < m;
+        const int64_t gi = t0 + (ai ? i : 0);
+        const double xi = px[gi], yi = py[gi], zi = pz[gi];
+        for (int rb = 0; rb < nrhs; rb += NR) {
+            double acc[NR];
+#pragma unroll
+            for (int c = 0; c < NR; ++c)
+                acc[c] = 0.0;
+            for (int e = e0; e < e1; ++e) {
+                const int32_t s = near_s[e];
+                const int32_t s0 = leaf_off[s];
+                const int ns = leaf_off[s + 1] - s0;
+                for (int cb = 0; cb < ns; cb += kChunk) {
+                    const int cn = min(kChunk, ns - cb);
+                    __syncthreads();
+                    for (int j = lane; j < cn; j += 64) {
+                        const int64_t gj = s0 + cb + j;
+                        sx[j] = px[gj];
+                        sy[j] = py[gj];
+                        sz[j] = pz[gj];
+#pragma unroll
+                        for (int c = 0; c < NR; ++c)
+                            sv[c][j] = (rb + c < nrhs) ? rd<LIVE>(xp + (rb + c) * n + gj) : 0.0;
+                    }
+                    __syncthreads();
+                    if (ai) {
+                        for (int j = q; j < cn; j += Q) {
+                            const int64_t gj = s0 + cb + j;
+                            if (gj == gi)
+                                continue;
+                            const double dx = xi - sx[j], dy = yi - sy[j], dz = zi - sz[j];
+                            const double f = kernel_f(kind, kp, sqrt(dx * dx + dy * dy + dz * dz));
+#pragma unroll
+                            for (int c = 0; c < NR; ++c)
+                                acc[c] += f * sv[c][j];
+                        }
+                    }
+                }
+            }
+            for (int off = R; off < 64; off <<= 1)
+#pragma unroll
+                for (int c = 0; c < NR; ++c)
+                    acc[c] += __shfl_xor(acc[c], off, 64);
+            if (ai && q == 0)
+#pragma unroll
+                for (int c = 0; c < NR; ++c)
+                    if (rb + c < nrhs)
+                        yn[(rb + c) * n + gi] = acc[c];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// stage 1: z[col] = dot(column col of its block's factor, x segment), one
+// launch per level with a shape chosen for that level's box size and rank.
+//
+//  wide   <S, U>: item = (block, first column); NS = 64/S columns side by side
+//                 (S lanes each, rows strided by S), U such groups per pass,
+//                 so each lane has U independent loads in flight; block
+//                 metadata is wave-uniform.
+//  packed <S, U>: item = (first block, count); one sub-wave of S lanes per
+//                 block, 64/S consecutive blocks per wave, U columns per pass;
+//                 the column loop runs to the wave's largest rank so the
+//                 shuffles stay in uniform control flow.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v)));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
+    return int64_t((uint64_t(hi) << 32) | lo);
+}
+
+struct S1Args {
+    const int2 *items;
+    int64_t nitems;
+    int span;
+    const int64_t *blk_col0;
+    const int32_t *rank;
+    const int32_t *seg_len;
+    const int32_t *seg_off;
+    void *const *seg_ptr;
+    const float *scale2;
+    int nrhs;
+    const double *xp;
+    int64_t n;
+    double *z;
+    int64_t ldz;
+};
+
+template <int S, int U, int DT, int NR, bool LIVE = false>
+__device__ __forceinline__ void s1_wide_item(const S1Args &a, int64_t w) {
+    using T = typename Fac<DT>::T;
+    constexpr int NS = 64 / S;
+    const int2 item = a.items[w];
+    const int lane = threadIdx.x & 63;
+    const int r = lane % S, sub = lane / S;
+    const int b = item.x;
+    const int len = a.seg_len[b];
+    const int64_t off = a.seg_off[b];
+    const int64_t col0 = a.blk_col0[b];
+    const int k = a.rank[b];
+    const T *__restrict__ p = static_cast<const T *>(a.seg_ptr[b]);
+    double sc = 1.0;
+    if (DT == H3D_BF16_SCALED)
+        sc = double(a.scale2[2 * b]) * double(a.scale2[2 * b + 1]);
+    const int cend = min(item.y + a.span, k);
+    const double *__restrict__ xp = a.xp;
+    for (int rb = 0; rb < a.nrhs; rb += NR) {
+        for (int cb = item.y; cb < cend; cb += NS * U) {
+            double acc[U][NR];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int q = 0; q < NR; ++q)
+                    acc[u][q] = 0.0;
+            for (int j = r; j < len; j += S) {
+                double xv[NR];
+#pragma unroll
+                for (int q = 0; q < NR; ++q)
+                    xv[q] = (NR == 1 || rb + q < a.nrhs) ? rd<LIVE>(xp + (rb + q) * a.n + off + j) : 0.0;
+                double v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int c = cb + sub + u * NS;
+                    v[u] = c < cend ? fac_ld<DT>(p + int64_t(c) * len + j) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int q = 0; q < NR; ++q)
+                        acc[u][q] += v[u] * xv[q];
+            }
+#pragma unroll
+            for (int o = S / 2; o > 0; o >>= 1)
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int q = 0; q < NR; ++q)
+                        acc[u][q] += __shfl_xor(acc[u][q], o, S);
+            if (r == 0) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int c = cb + sub + u * NS;
+                    if (c < cend)
+#pragma unroll
+                        for (int q = 0; q < NR; ++q)
+                            if (NR == 1 || rb + q < a.nrhs)
+                                a.z[(rb + q) * a.ldz + col0 + c] = acc[u][q] * sc;
+                }
+            }
+        }
+    }
+}
+
+template <int S, int U, int DT, int NR, bool LIVE = false>
+__device__ __forceinline__ void s1_packed_item(const S1Args &a, int64_t w) {
+    using T = typename Fac<DT>::T;
+    const int2 item = a.items[w];
+    const int lane = threadIdx.x & 63;
+    const int r = lane % S, sub = lane / S;
+    const bool valid = sub < item.y;
+    const int b = item.x + (valid ? sub : 0);
+    const int len = valid ? a.seg_len[b] : 0;
+    const int64_t off = a.seg_off[b];
+    const int64_t col0 = a.blk_col0[b];
+    const int k = valid ? a.rank[b] : 0;
+    const T *__restrict__ p = static_cast<const T *>(a.seg_ptr[b]);
+    double sc = 1.0;
+    if (DT == H3D_BF16_SCALED)
+        sc = double(a.scale2[2 * b]) * double(a.scale2[2 * b + 1]);
+    int kmax = k;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        kmax = max(kmax, __shfl_xor(kmax, o, 64));
+    const double *__restrict__ xp = a.xp;
+    for (int rb = 0; rb < a.nrhs; rb += NR) {
+        for (int cb = 0; cb < kmax; cb += U) {
+            double acc[U][NR];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int q = 0; q < NR; ++q)
+                    acc[u][q] = 0.0;
+            for (int j = r; j < len; j += S) {
+                double xv[NR];
+#pragma unroll
+                for (int q = 0; q < NR; ++q)
+                    xv[q] = (NR == 1 || rb + q < a.nrhs) ? rd<LIVE>(xp + (rb + q) * a.n + off + j) : 0.0;
+                double v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    v[u] = cb + u < k ? fac_ld<DT>(p + int64_t(cb + u) * len + j) : 0.0;
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int q = 0; q < NR; ++q)
+                        acc[u][q] += v[u] * xv[q];
+            }
+#pragma unroll
+            for (int o = S / 2; o > 0; o >>= 1)
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int q = 0; q < NR; ++q)
+                        acc[u][q] += __shfl_xor(acc[u][q], o, S);
+            if (r == 0) {
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (cb + u < k)
+#pragma unroll
+                        for (int q = 0; q < NR; ++q)
+                            if (NR == 1 || rb + q < a.nrhs)
+                                a.z[(rb + q) * a.ldz + col0 + cb + u] = acc[u][q] * sc;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// stage 2: one workgroup per box of the chunk level, one lane per row (two
+// for boxes of 65..128 rows).  At levels up to the chunk level every lane of
+// the workgroup lies in the same box, so the block metadata and z are
+// wave-uniform (scalar loads) and each lane streams one column slice of U per
+// load, U2 loads in flight; the waves split the box's blocks.
+struct S2Tab {
+    int64_t box_base[kMaxLevels + 1];
+    int L, lc;
+};
+
+template <int DT, int NR, int U2, bool LIVE = false>
+__device__ __forceinline__ void stage2_block(const typename Fac<DT>::T *__restrict__ p, int bm, int k,
+                                             const double *__restrict__ zz, int64_t ldz, int rb,
+                                             int nrhs, double (&acc)[NR]) {
+    int c = 0;
+    for (; c + U2 <= k; c += U2) {
+        double v[U2];
+#pragma unroll
+        for (int u = 0; u < U2; ++u)
+            v[u] = fac_ld<DT, kS2NonTemporal>(p + int64_t(c + u) * bm);
+#pragma unroll
+        for (int u = 0; u < U2; ++u)
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+                if (NR == 1 || rb + q < nrhs)
+                    acc[q] += v[u] * rd<LIVE>(zz + (rb + q) * ldz + c + u);
+    }
+    for (; c < k; ++c) {
+        const double v = fac_ld<DT, kS2NonTemporal>(p + int64_t(c) * bm);
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+            if (NR == 1 || rb + q < nrhs)
+                acc[q] += v * rd<LIVE>(zz + (rb + q) * ldz + c);
+    }
+}
+
+// The same for two rows per lane, d rows apart (d = 0 for a lane whose second
+// row lies past the box: it then repeats its first load and drops the sum).
+template <int DT, int NR, int U2, bool LIVE = false>
+__device__ __forceinline__ void stage2_block2(const typename Fac<DT>::T *__restrict__ p, int d,
+                                              int bm, int k, const double *__restrict__ zz,
+                                              int64_t ldz, int rb, int nrhs, double (&a0)[NR],
+                                              double (&a1)[NR]) {
+    int c = 0;
+    for (; c + U2 <= k; c += U2) {
+        double v[U2], w[U2];
+#pragma unroll
+        for (int u = 0; u < U2; ++u) {
+            v[u] = fac_ld<DT, kS2NonTemporal>(p + int64_t(c + u) * bm);
+            w[u] = fac_ld<DT, kS2NonTemporal>(p + d + int64_t(c + u) * bm);
+        }
+#pragma unroll
+        for (int u = 0; u < U2; ++u)
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+                if (NR == 1 || rb + q < nrhs) {
+                    const double zq = rd<LIVE>(zz + (rb + q) * ldz + c + u);
+                    a0[q] += v[u] * zq;
+                    a1[q] += w[u] * zq;
+                }
+    }
+    for (; c < k; ++c) {
+        const double v = fac_ld<DT, kS2NonTemporal>(p + int64_t(c) * bm);
+        const double w = fac_ld<DT, kS2NonTemporal>(p + d + int64_t(c) * bm);
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+            if (NR == 1 || rb + q < nrhs) {
+                const double zq = rd<LIVE>(zz + (rb + q) * ldz + c);
+                a0[q] += v * zq;
+                a1[q] += w * zq;
+            }
+    }
+}
+
+template <int DT, int NR, int kS2Waves, bool LIVE = false>
+__device__ __forceinline__ void
+    stage2_chunk(int64_t B, const S2Tab &tab, const int32_t *__restrict__ leaf_off,
+                 const int32_t *__restrict__ leaf_of, const int64_t *__restrict__ grp_begin,
+                 const int64_t *__restrict__ grp_blk, void *const *__restrict__ fptr,
+                 const int32_t *__restrict__ rank, const int64_t *__restrict__ blk_col0,
+                 const double *__restrict__ z, int64_t ldz, const double *yn, int64_t n, int nrhs,
+                 const int32_t *__restrict__ perm, void *__restrict__ yout, int64_t ldy, int io_f32,
+                 int lb, int le, double *ypart) {
+    using T = typename Fac<DT>::T;
+    __shared__ double part[kS2Waves][NR][64];
+    const int L = tab.L, lc = tab.lc;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int shc = 3 * (L - lc);
+    const int32_t r0 = leaf_off[B << shc], r1 = leaf_off[(B + 1) << shc];
+    // Passes of up to 128 rows: a box of 65..128 rows reads every coarse
+    // column slice in one pass, two rows per lane (rows rowb + lane and
+    // rowb + 64 + lane), instead of a second pass over the same columns.
+    for (int32_t rowb = r0; rowb < r1;) {
+        const bool two = r1 - rowb > 64;
+        const int32_t rowA = rowb + lane, rowB = rowb + 64 + lane;
+        const bool actA = rowA < r1, actB = two && rowB < r1;
+        const int32_t rrA = actA ? rowA : r0;
+        const int dB = actB ? 64 : 0;
+        for (int rb = 0; rb < nrhs; rb += NR) {
+            double acc[2][NR];
+#pragma unroll
+            for (int c = 0; c < NR; ++c) {
+                const bool ok = wv == 0 && (NR == 1 || rb + c < nrhs);
+                acc[0][c] = ok ? rd<LIVE>(yn + (rb + c) * n + rrA) : 0.0;
+                acc[1][c] = (ok && two) ? rd<LIVE>(yn + (rb + c) * n + rrA + dB) : 0.0;
+            }
+            // levels whose boxes contain the whole chunk box: wave-uniform;
+            // the waves of the workgroup take every kS2Waves-th block
+            for (int l = lb; l <= min(lc, le); ++l) {
+                const int sh = 3 * (L - l);
+                const int64_t t = B >> (3 * (lc - l));
+                const int64_t g = tab.box_base[l] + t;
+                const int32_t bs = leaf_off[t << sh];
+                const int32_t bm = leaf_off[(t + 1) << sh] - bs;
+                const int32_t loc = rrA - bs;
+                const int64_t e0 = grp_begin[g], e1 = grp_begin[g + 1];
+                for (int64_t e = e0 + wv; e < e1; e += kS2Waves) {
+                    const int64_t bi = grp_blk ? grp_blk[e] : e;
+                    const T *p = static_cast<const T *>(fptr[bi]) + loc;
+                    if (two)
+                        stage2_block2<DT, NR, 8, LIVE>(p, dB, bm, rank[bi], z + blk_col0[bi], ldz, rb,
+                                                 nrhs, acc[0], acc[1]);
+                    else
+                        stage2_block<DT, NR, 8, LIVE>(p, bm, rank[bi], z + blk_col0[bi], ldz, rb, nrhs,
+                                                acc[0]);
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (h == 1 && !two)
+                    break;
+                const int32_t row = h ? rowB : rowA;
+                const bool act = h ? actB : actA;
+                const int32_t rr = act ? row : r0;
+                const int32_t leaf = leaf_of[rr];
+                // finer levels: every lane follows the box of its own row
+                for (int l = max(lc + 1, lb); l <= le; ++l) {
+                    const int sh = 3 * (L - l);
+                    const int64_t t = int64_t(leaf) >> sh;
+                    const int64_t g = tab.box_base[l] + t;
+                    const int32_t bs = leaf_off[t << sh];
+                    const int32_t bm = leaf_off[(t + 1) << sh] - bs;
+                    const int32_t loc = rr - bs;
+                    const int64_t e0 = grp_begin[g], e1 = grp_begin[g + 1];
+                    for (int64_t e = e0 + wv; e < e1; e += kS2Waves) {
+                        const int64_t bi = grp_blk ? grp_blk[e] : e;
+                        const T *p = static_cast<const T *>(fptr[bi]) + loc;
+                        stage2_block<DT, NR, 4, LIVE>(p, bm, rank[bi], z + blk_col0[bi], ldz, rb, nrhs,
+                                                acc[h]);
+                    }
+                }
+                // combine the waves' partial sums in a fixed order
+#pragma unroll
+                for (int q = 0; q < NR; ++q)
+                    part[wv][q][lane] = acc[h][q];
+                __syncthreads();
+                if (wv == 0) {
+                    double y[NR];
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) {
+                        double v = part[0][q][lane];
+#pragma unroll
+                        for (int w2 = 1; w2 < kS2Waves; ++w2)
+                            v += part[w2][q][lane];
+                        y[q] = v;
+                    }
+                    if (act && ypart) {
+                        // partial sums in sorted order (level-by-level profiling)
+#pragma unroll
+                        for (int q = 0; q < NR; ++q)
+                            if (NR == 1 || rb + q < nrhs)
+                                ypart[(rb + q) * n + row] = y[q];
+                    } else if (act) {
+                        const int64_t dst = perm[row];
+#pragma unroll
+                        for (int q = 0; q < NR; ++q)
+                            if (NR == 1 || rb + q < nrhs) {
+                                if (io_f32)
+                                    static_cast<float *>(yout)[(rb + q) * ldy + dst] = float(y[q]);
+                                else
+                                    static_cast<double *>(yout)[(rb + q) * ldy + dst] = y[q];
+                            }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        rowb += two ? 128 : 64;
+    }
+}
+
+}  // namespace dev
+}  // namespace h3d

@@ -30,7 +30,8 @@ EXPORTED_SYMBOLS = (
     "h3d_config_init", "h3d_build", "h3d_matvec", "h3d_matvec_adjoint", "h3d_get_stats",
     "h3d_export", "h3d_destroy", "h3d_last_error", "h3d_profile_enable", "h3d_profile_read",
     "h3d_profile_reset", "h3d_version", "h3d_autotune", "h3d_graph_create",
-    "h3d_graph_launch", "h3d_graph_destroy",
+    "h3d_graph_launch", "h3d_graph_destroy", "h3d_build_batch", "h3d_matvec_batch",
+    "h3d_batch_plan", "h3d_batch_check",
 )
 
 
@@ -153,6 +154,16 @@ def load_library():
     lib.h3d_graph_destroy.restype = S
     lib.h3d_autotune.argtypes = [P, I64, P]
     lib.h3d_autotune.restype = S
+    lib.h3d_build_batch.argtypes = [I32, ctypes.POINTER(P), ctypes.POINTER(I64),
+                                    ctypes.POINTER(Config), ctypes.POINTER(Allocator), P,
+                                    ctypes.POINTER(P)]
+    lib.h3d_build_batch.restype = S
+    lib.h3d_matvec_batch.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), I64, I32, P]
+    lib.h3d_matvec_batch.restype = S
+    lib.h3d_batch_plan.argtypes = [P, I32, ctypes.POINTER(P)]
+    lib.h3d_batch_plan.restype = S
+    lib.h3d_batch_check.argtypes = [P, P]
+    lib.h3d_batch_check.restype = S
     lib.h3d_version.argtypes = []
     lib.h3d_version.restype = I32
     _lib = lib
@@ -200,15 +211,19 @@ class _TorchAllocator:
 class Operator:
     """The HODLR3D representation of K on one point cloud, resident on the GPU."""
 
-    def __init__(self, handle, n: int, device: int, allocator, config: Config):
+    def __init__(self, handle, n: int, device: int, allocator, config: Config, owner=None):
         self._h = handle
         self.n = int(n)
         self.device = device
         self._alloc = allocator
         self.config = config
+        self._owner = owner  # the batch a problem's plan belongs to (not destroyed here)
 
     # -- lifecycle --------------------------------------------------------
     def close(self) -> None:
+        if self._owner is not None:
+            self._h = None
+            return
         if getattr(self, "_h", None) is not None and self._h.value:
             _check(load_library().h3d_destroy(self._h))
             self._h = None
@@ -349,21 +364,8 @@ class Graph:
             pass
 
 
-def build(points, kernel="laplace", kernel_param: float = 1.0, leaf_size: int = 64,
-          tol: float = 1e-8, factor_dtype="fp64", max_rank: int = 0, max_depth: int = 10,
-          box_lo=None, box_side: float = 0.0, workspace_bytes: int = 0,
-          keep_pivots: bool = False, use_torch_allocator: bool = True,
-          autotune: bool = True) -> Operator:
-    """Builds the HODLR3D operator of the n x 3 FP64 point cloud (moved to the GPU)."""
-    torch = _torch()
-    lib = load_library()
-    if not isinstance(points, torch.Tensor):
-        points = torch.as_tensor(np.ascontiguousarray(points, dtype=np.float64))
-    if not points.is_cuda:
-        points = points.to("cuda")
-    points = points.to(torch.float64).contiguous()
-    if points.dim() != 2 or points.shape[1] != 3:
-        raise ValueError("points must have shape (n, 3)")
+def _make_config(kernel, kernel_param, leaf_size, tol, factor_dtype, max_rank, max_depth, box_lo,
+                 box_side, workspace_bytes, keep_pivots, autotune) -> Config:
     cfg = default_config()
     cfg.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     cfg.kernel_param = float(kernel_param)
@@ -378,6 +380,32 @@ def build(points, kernel="laplace", kernel_param: float = 1.0, leaf_size: int = 
     cfg.box_side = float(box_side)
     cfg.workspace_bytes = int(workspace_bytes)
     cfg.flags = (FLAG_KEEP_PIVOTS if keep_pivots else 0) | (0 if autotune else FLAG_NO_AUTOTUNE)
+    return cfg
+
+
+def _device_points(points):
+    torch = _torch()
+    if not isinstance(points, torch.Tensor):
+        points = torch.as_tensor(np.ascontiguousarray(points, dtype=np.float64))
+    if not points.is_cuda:
+        points = points.to("cuda")
+    points = points.to(torch.float64).contiguous()
+    if points.dim() != 2 or points.shape[1] != 3:
+        raise ValueError("points must have shape (n, 3)")
+    return points
+
+
+def build(points, kernel="laplace", kernel_param: float = 1.0, leaf_size: int = 64,
+          tol: float = 1e-8, factor_dtype="fp64", max_rank: int = 0, max_depth: int = 10,
+          box_lo=None, box_side: float = 0.0, workspace_bytes: int = 0,
+          keep_pivots: bool = False, use_torch_allocator: bool = True,
+          autotune: bool = True) -> Operator:
+    """Builds the HODLR3D operator of the n x 3 FP64 point cloud (moved to the GPU)."""
+    torch = _torch()
+    lib = load_library()
+    points = _device_points(points)
+    cfg = _make_config(kernel, kernel_param, leaf_size, tol, factor_dtype, max_rank, max_depth,
+                       box_lo, box_side, workspace_bytes, keep_pivots, autotune)
     device = points.device.index if points.device.index is not None else torch.cuda.current_device()
     alloc = _TorchAllocator(device) if use_torch_allocator else None
     handle = ctypes.c_void_p()
@@ -387,6 +415,108 @@ def build(points, kernel="laplace", kernel_param: float = 1.0, leaf_size: int = 
                              ctypes.byref(alloc.struct) if alloc else None,
                              ctypes.c_void_p(stream), ctypes.byref(handle)))
     return Operator(handle, points.shape[0], device, alloc, cfg)
+
+
+class BatchOperator:
+    """Independent HODLR3D operators (one per point cloud) whose products run together
+    in one persistent kernel launch.  ``plans[i]`` is problem i's own operator."""
+
+    def __init__(self, handle, ns, device: int, allocator, config: Config):
+        self._h = handle
+        self.ns = [int(v) for v in ns]
+        self.device = device
+        self._alloc = allocator
+        self.config = config
+        lib = load_library()
+        self.plans = []
+        for i, n in enumerate(self.ns):
+            sub = ctypes.c_void_p()
+            _check(lib.h3d_batch_plan(self._h, i, ctypes.byref(sub)))
+            self.plans.append(Operator(sub, n, device, None, config, owner=self))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            for p in self.plans:
+                p.close()
+            _check(load_library().h3d_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def matvec(self, xs, outs=None):
+        """[K~_i x_i] for a list of tensors x_i of shape (n_i,) or (n_i, nrhs), one launch."""
+        torch = _torch()
+        if len(xs) != len(self.ns):
+            raise ValueError(f"expected {len(self.ns)} inputs, got {len(xs)}")
+        cols, ys, shapes = [], [], []
+        nrhs, dtype = None, None
+        for x, n in zip(xs, self.ns):
+            if not isinstance(x, torch.Tensor) or not x.is_cuda:
+                raise TypeError("every x must be a CUDA (HIP) tensor")
+            x2 = x.reshape(n, -1)
+            if nrhs is None:
+                nrhs, dtype = x2.shape[1], x.dtype
+            if x2.shape[1] != nrhs or x.dtype != dtype:
+                raise ValueError("all inputs must share nrhs and dtype")
+            xc = x2.t().contiguous()
+            cols.append(xc)
+            ys.append(torch.empty_like(xc))
+            shapes.append(x.dim() == 1)
+        if dtype not in (torch.float64, torch.float32):
+            raise TypeError("inputs must be float64 or float32")
+        P = ctypes.c_void_p * len(self.ns)
+        xp = P(*[c.data_ptr() for c in cols])
+        yp = P(*[y.data_ptr() for y in ys])
+        io = 0 if dtype == torch.float64 else 1
+        stream = torch.cuda.current_stream(cols[0].device).cuda_stream
+        _check(load_library().h3d_matvec_batch(self._h, xp, yp, nrhs, io, ctypes.c_void_p(stream)))
+        return [y.reshape(-1) if vec else y.t() for y, vec in zip(ys, shapes)]
+
+    def check(self) -> None:
+        """Raises if a dependency wait of the last product gave up (synchronises)."""
+        torch = _torch()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        _check(load_library().h3d_batch_check(self._h, ctypes.c_void_p(stream)))
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(load_library().h3d_get_stats(self._h, ctypes.byref(s)))
+        return s.to_dict()
+
+    profile = Operator.profile
+    profile_reset = Operator.profile_reset
+    profile_read = Operator.profile_read
+
+
+def build_batch(points_list, kernel="laplace", kernel_param: float = 1.0, leaf_size: int = 64,
+                tol: float = 1e-8, factor_dtype="fp64", max_rank: int = 0, max_depth: int = 10,
+                box_lo=None, box_side: float = 0.0, workspace_bytes: int = 0,
+                use_torch_allocator: bool = True) -> BatchOperator:
+    """Builds one operator per point cloud for products in one persistent launch."""
+    torch = _torch()
+    lib = load_library()
+    pts = [_device_points(p) for p in points_list]
+    if not pts:
+        raise ValueError("points_list is empty")
+    cfg = _make_config(kernel, kernel_param, leaf_size, tol, factor_dtype, max_rank, max_depth,
+                       box_lo, box_side, workspace_bytes, False, False)
+    device = pts[0].device.index if pts[0].device.index is not None else torch.cuda.current_device()
+    alloc = _TorchAllocator(device) if use_torch_allocator else None
+    P = ctypes.c_void_p * len(pts)
+    N = ctypes.c_int64 * len(pts)
+    parr = P(*[p.data_ptr() for p in pts])
+    narr = N(*[p.shape[0] for p in pts])
+    handle = ctypes.c_void_p()
+    stream = torch.cuda.current_stream(pts[0].device).cuda_stream
+    with torch.cuda.device(device):
+        _check(lib.h3d_build_batch(len(pts), parr, narr, ctypes.byref(cfg),
+                                   ctypes.byref(alloc.struct) if alloc else None,
+                                   ctypes.c_void_p(stream), ctypes.byref(handle)))
+    return BatchOperator(handle, [p.shape[0] for p in pts], device, alloc, cfg)
 
 
 def _autograd_function():

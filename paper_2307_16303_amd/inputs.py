@@ -89,3 +89,15 @@ def workload_rhs(name: str, nrhs: int | None = None) -> np.ndarray:
 def batch_problem_sizes(count: int = 32, seed: int = 7, lo: int = 8192, hi: int = 131072):
     """Sizes of independent problems for the multi-problem form: uniform integers in [lo, hi]."""
     return np.random.default_rng(seed).integers(lo, hi, count, endpoint=True)
+
+
+# The multi-problem workload: 32 independent clouds, Laplace, leaf <= 64,
+# ACA tol 1e-7, FP32 factors, one RHS each.
+BATCH_WORKLOAD = dict(count=32, kernel="laplace", leaf_size=64, tol=1e-7, factor_dtype="fp32")
+
+
+def batch_workload(count: int = 32, seed: int = 7, lo: int = 8192, hi: int = 131072):
+    """[(points_i, rhs_i)]: sizes from batch_problem_sizes, points of problem i uniform in
+    [-1,1]^3 with seed 100 + i, right-hand side N(0,1) with seed 200 + i."""
+    ns = batch_problem_sizes(count, seed, lo, hi)
+    return [(uniform_points(int(v), 100 + i), normal_rhs(int(v), 200 + i)) for i, v in enumerate(ns)]

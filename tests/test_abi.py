@@ -27,7 +27,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
-    assert len(names) == 16, names
+    assert len(names) == 20, names
     out = subprocess.run(["nm", "-D", "--defined-only", hodlr3d.library_path()],
                          capture_output=True, text=True, check=True).stdout
     exported = set(re.findall(r" T (h3d_\w+)", out))
@@ -110,3 +110,34 @@ def test_calls_on_null_plan(lib):
     assert lib.h3d_destroy(None) == hodlr3d.H3D_OK
     cnt = ctypes.c_int32(0)
     assert lib.h3d_profile_read(None, None, 0, ctypes.byref(cnt)) == hodlr3d.H3D_ENOTBUILT
+
+
+def test_batch_calls_validate_before_device_work(lib):
+    cfg = hodlr3d.default_config()
+    out = ctypes.c_void_p()
+    P2 = (ctypes.c_void_p * 2)(0x1000, 0x2000)
+    N2 = (ctypes.c_int64 * 2)(100, 200)
+    assert lib.h3d_build_batch(0, P2, N2, ctypes.byref(cfg), None, None,
+                               ctypes.byref(out)) == hodlr3d.H3D_EINVAL
+    assert lib.h3d_build_batch(2, None, N2, ctypes.byref(cfg), None, None,
+                               ctypes.byref(out)) == hodlr3d.H3D_EINVAL
+    assert lib.h3d_build_batch(2, P2, None, ctypes.byref(cfg), None, None,
+                               ctypes.byref(out)) == hodlr3d.H3D_EINVAL
+    assert lib.h3d_build_batch(2, P2, N2, None, None, None, ctypes.byref(out)) == hodlr3d.H3D_EINVAL
+    assert lib.h3d_build_batch(2, P2, N2, ctypes.byref(cfg), None, None, None) == hodlr3d.H3D_EINVAL
+    bad = (ctypes.c_int64 * 2)(100, 0)
+    assert lib.h3d_build_batch(2, P2, bad, ctypes.byref(cfg), None, None,
+                               ctypes.byref(out)) == hodlr3d.H3D_EINVAL
+    assert b"n[1]" in lib.h3d_last_error()
+    nullp = (ctypes.c_void_p * 2)(0x1000, None)
+    assert lib.h3d_build_batch(2, nullp, N2, ctypes.byref(cfg), None, None,
+                               ctypes.byref(out)) == hodlr3d.H3D_EINVAL
+    cfg.tol = 2.0
+    assert lib.h3d_build_batch(2, P2, N2, ctypes.byref(cfg), None, None,
+                               ctypes.byref(out)) == hodlr3d.H3D_EINVAL
+    assert not out.value
+    assert lib.h3d_matvec_batch(None, P2, P2, 1, 0, None) == hodlr3d.H3D_ENOTBUILT
+    sub = ctypes.c_void_p()
+    assert lib.h3d_batch_plan(None, 0, ctypes.byref(sub)) == hodlr3d.H3D_ENOTBUILT
+    assert lib.h3d_batch_plan(None, 0, None) == hodlr3d.H3D_EINVAL
+    assert lib.h3d_batch_check(None, None) == hodlr3d.H3D_ENOTBUILT

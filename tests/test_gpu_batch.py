@@ -1,0 +1,203 @@
+"""Multi-problem batching: independent operators multiplied in one persistent
+launch (h3d_build_batch / h3d_matvec_batch), through the C ABI.
+
+Each problem of a batch is an ordinary operator (h3d_batch_plan): its product
+inside the persistent launch runs the same per-item arithmetic as its own
+per-phase kernels, so the two are compared bitwise; the batch output is also
+checked against the CPU oracle's HODLR3D (same ACA decisions, summation order
+only) and against exact dense rows (compression error).
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_16303_amd import hodlr3d, inputs
+
+pytestmark = pytest.mark.gpu
+
+CUBE = dict(box_lo=inputs.CUBE_LO, box_side=inputs.CUBE_SIDE)
+
+
+def torch_mod():
+    import torch
+    return torch
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b))
+
+
+def build_batch(clouds, **kw):
+    torch = torch_mod()
+    print(f"[build_batch] n={[len(c) for c in clouds]} {kw}", flush=True)
+    return hodlr3d.build_batch([torch.as_tensor(c, device="cuda") for c in clouds], **kw)
+
+
+def batch_apply(bop, xs, dtype="float64"):
+    torch = torch_mod()
+    ys = bop.matvec([torch.as_tensor(np.asarray(x), device="cuda").to(getattr(torch, dtype))
+                     for x in xs])
+    torch.cuda.synchronize()
+    bop.check()
+    return [y.double().cpu().numpy() for y in ys]
+
+
+def solo_apply(op, x, dtype="float64"):
+    torch = torch_mod()
+    y = op.matvec(torch.as_tensor(np.asarray(x), device="cuda").to(getattr(torch, dtype)))
+    torch.cuda.synchronize()
+    return y.double().cpu().numpy()
+
+
+# sizes chosen to give depths 1..3 and chunk boxes of one and two passes
+MIXED = [(3000, 11), (12000, 12), (20000, 13), (700, 14), (9000, 15), (64, 16), (20, 17)]
+
+
+@pytest.fixture(scope="module")
+def mixed():
+    clouds = [inputs.uniform_points(n, s) for n, s in MIXED]
+    kw = dict(leaf_size=32, tol=1e-8, **CUBE)
+    bop = build_batch(clouds, **kw)
+    yield clouds, kw, bop
+    bop.close()
+
+
+def test_batch_equals_solo_bitwise(mixed):
+    clouds, kw, bop = mixed
+    xs = [inputs.normal_rhs(len(c), seed=30 + i) for i, c in enumerate(clouds)]
+    ys = batch_apply(bop, xs)
+    for i, (x, y) in enumerate(zip(xs, ys)):
+        np.testing.assert_array_equal(y, solo_apply(bop.plans[i], x), err_msg=f"problem {i}")
+
+
+def test_batch_vs_oracle_and_dense(mixed):
+    clouds, kw, bop = mixed
+    xs = [inputs.normal_rhs(len(c), seed=40 + i) for i, c in enumerate(clouds)]
+    ys = batch_apply(bop, xs)
+    for i in (0, 2, 5):
+        ref = oracle.HODLR3D(clouds[i], kernel="laplace", leaf_size=kw["leaf_size"], tol=kw["tol"],
+                             box_lo=kw["box_lo"], box_side=kw["box_side"])
+        assert rel(ys[i], ref.matvec(xs[i])) <= 1e-13, i
+        yd = oracle.dense_matvec(clouds[i], xs[i])
+        assert rel(ys[i], yd) <= 10 * kw["tol"], i
+
+
+def test_consecutive_products_and_stats(mixed):
+    """Counters are reset per product: a second product with other inputs is right too."""
+    clouds, kw, bop = mixed
+    for seed in (50, 60):
+        xs = [inputs.normal_rhs(len(c), seed=seed + i) for i, c in enumerate(clouds)]
+        ys = batch_apply(bop, xs)
+        for i in (1, 4):
+            np.testing.assert_array_equal(ys[i], solo_apply(bop.plans[i], xs[i]))
+    st = bop.stats()
+    subs = [p.stats() for p in bop.plans]
+    assert st["n"] == sum(len(c) for c in clouds)
+    assert st["n_far"] == sum(s["n_far"] for s in subs)
+    assert st["factor_bytes"] == sum(s["factor_bytes"] for s in subs)
+    assert st["depth"] == max(s["depth"] for s in subs)
+
+
+def test_multiple_rhs_and_float32_io(mixed):
+    clouds, kw, bop = mixed
+    xs = [inputs.normal_rhs(len(c), seed=70 + i, nrhs=3) for i, c in enumerate(clouds)]
+    ys = batch_apply(bop, xs)
+    for i, (x, y) in enumerate(zip(xs, ys)):
+        np.testing.assert_array_equal(y, solo_apply(bop.plans[i], x), err_msg=f"problem {i}")
+    ys32 = batch_apply(bop, xs, dtype="float32")
+    for i, x in enumerate(xs):
+        np.testing.assert_array_equal(ys32[i], solo_apply(bop.plans[i], x, dtype="float32"))
+
+
+@pytest.mark.parametrize("dtype", ["fp32", "bf16"])
+def test_low_precision_batch(dtype):
+    clouds = [inputs.uniform_points(n, s) for n, s in [(15000, 21), (4000, 22), (30000, 23)]]
+    kw = dict(leaf_size=64, tol=1e-7, factor_dtype=dtype, **CUBE)
+    bop = build_batch(clouds, **kw)
+    xs = [inputs.normal_rhs(len(c), seed=80 + i) for i, c in enumerate(clouds)]
+    ys = batch_apply(bop, xs)
+    for i, (c, x, y) in enumerate(zip(clouds, xs, ys)):
+        np.testing.assert_array_equal(y, solo_apply(bop.plans[i], x))
+        rows = inputs.sample_rows(len(c), 256, seed=3)
+        yd = oracle.dense_rows(c, x, rows)
+        assert rel(y[rows], yd) <= (1e-6 if dtype == "fp32" else 1e-2), (i, rel(y[rows], yd))
+    bop.close()
+
+
+def test_single_problem_batch():
+    c = inputs.uniform_points(5000, 31)
+    bop = build_batch([c], leaf_size=64, tol=1e-8, **CUBE)
+    x = inputs.normal_rhs(5000, seed=32)
+    (y,) = batch_apply(bop, [x])
+    np.testing.assert_array_equal(y, solo_apply(bop.plans[0], x))
+    assert rel(y, oracle.dense_matvec(c, x)) <= 1e-7
+    bop.close()
+
+
+def test_batch_error_paths(mixed):
+    clouds, kw, bop = mixed
+    torch = torch_mod()
+    lib = hodlr3d.load_library()
+    # single-operator calls on a batch plan are refused
+    x = torch.zeros(len(clouds[0]), dtype=torch.float64, device="cuda")
+    y = torch.zeros_like(x)
+    st = lib.h3d_matvec(bop._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), 1,
+                        len(clouds[0]), len(clouds[0]), 0, None)
+    assert st == hodlr3d.H3D_EINVAL
+    # the launch shapes of a member are fixed by its batch
+    assert lib.h3d_autotune(bop.plans[0].handle, 1, None) == hodlr3d.H3D_EINVAL
+    sub = ctypes.c_void_p()
+    assert lib.h3d_batch_plan(bop._h, len(clouds), ctypes.byref(sub)) == hodlr3d.H3D_EINVAL
+    assert lib.h3d_batch_plan(bop._h, -1, ctypes.byref(sub)) == hodlr3d.H3D_EINVAL
+    # a single operator is not a batch
+    assert lib.h3d_batch_check(bop.plans[0].handle, None) == hodlr3d.H3D_EINVAL
+    # bad build arguments
+    h = ctypes.c_void_p()
+    cfg = hodlr3d.default_config()
+    assert lib.h3d_build_batch(0, None, None, ctypes.byref(cfg), None, None,
+                               ctypes.byref(h)) == hodlr3d.H3D_EINVAL
+    pts = torch.as_tensor(clouds[0], device="cuda")
+    P1 = (ctypes.c_void_p * 1)(pts.data_ptr())
+    N0 = (ctypes.c_int64 * 1)(0)
+    assert lib.h3d_build_batch(1, P1, N0, ctypes.byref(cfg), None, None,
+                               ctypes.byref(h)) == hodlr3d.H3D_EINVAL
+    assert not h.value
+    # a NULL input pointer and overlapping x / y of one problem
+    n = [len(c) for c in clouds]
+    bufs = [torch.zeros(v, dtype=torch.float64, device="cuda") for v in n]
+    xp = (ctypes.c_void_p * len(n))(*[b.data_ptr() for b in bufs])
+    yp = (ctypes.c_void_p * len(n))(*[b.data_ptr() for b in bufs])
+    assert lib.h3d_matvec_batch(bop._h, xp, yp, 1, 0, None) == hodlr3d.H3D_EINVAL
+    xp[2] = None
+    assert lib.h3d_matvec_batch(bop._h, xp, yp, 1, 0, None) == hodlr3d.H3D_EINVAL
+    with pytest.raises(ValueError):
+        bop.matvec([torch.zeros(v, dtype=torch.float64, device="cuda") for v in n[:-1]])
+    # the plan is still usable afterwards
+    xs = [inputs.normal_rhs(v, seed=90 + i) for i, v in enumerate(n)]
+    ys = batch_apply(bop, xs)
+    np.testing.assert_array_equal(ys[3], solo_apply(bop.plans[3], xs[3]))
+
+
+def test_multi_problem_workload_full_size():
+    """The 32-problem workload (N_i in [8192, 131072], FP32 factors, tol 1e-7):
+    every problem bitwise equal to its own product, and sampled dense rows of
+    four problems within the 1e-6 precision gate."""
+    work = inputs.batch_workload()
+    w = inputs.BATCH_WORKLOAD
+    bop = build_batch([p for p, _ in work], kernel=w["kernel"], leaf_size=w["leaf_size"],
+                      tol=w["tol"], factor_dtype=w["factor_dtype"], **CUBE)
+    st = bop.stats()
+    print(f"[batch32] N={st['n']} far={st['n_far']} factor GB={st['factor_bytes'] / 1e9:.2f} "
+          f"build {st['build_ms'] / 1e3:.1f} s", flush=True)
+    ys = batch_apply(bop, [x for _, x in work])
+    for i, (pts, x) in enumerate(work):
+        np.testing.assert_array_equal(ys[i], solo_apply(bop.plans[i], x), err_msg=f"problem {i}")
+    for i in (0, 9, 17, 31):
+        pts, x = work[i]
+        rows = inputs.sample_rows(len(pts), 256, seed=3)
+        e = rel(ys[i][rows], oracle.dense_rows(pts, x, rows))
+        print(f"[batch32] problem {i} n={len(pts)} sampled rel err {e:.3e}", flush=True)
+        assert e <= 1e-6
+    bop.close()
