@@ -315,6 +315,7 @@ static void write_descriptors(BatchState &B, int64_t nrhs) {
             D.tab.box_base[l] = Q.box_base[l];
         D.tab.L = Q.L;
         D.tab.lc = Q.chunk_level;
+        D.tab.panel = 1;
         D.grp_begin = Q.tgt_begin;
         D.uptr = Q.blk_uptr;
         D.rank = Q.blk_rank;

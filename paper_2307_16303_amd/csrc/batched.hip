@@ -210,7 +210,8 @@ __global__ void __launch_bounds__(64)
               const int32_t *__restrict__ seg_off, void *const *__restrict__ seg_ptr,
               const int32_t *__restrict__ rank, const int64_t *__restrict__ blk_col0,
               const float *__restrict__ scale2, const typename CT<DT>::T *__restrict__ Xs, int NP,
-              typename CT<DT>::T *__restrict__ Z) {
+              typename CT<DT>::T *__restrict__ Z, int panel, const int32_t *__restrict__ leaf_off,
+              const int32_t *__restrict__ leaf_of, int shc) {
     using C = CT<DT>;
     using T = typename C::T;
     using F = typename FacB<DT>::T;
@@ -249,7 +250,10 @@ __global__ void __launch_bounds__(64)
             for (int u = 0; u < KU; ++u) {
                 const int j = j0 + 4 * u + (lane >> 4);
                 const bool aj = j < len;
-                a[u] = (ac && aj) ? T(FacB<DT>::ld(p + int64_t(ca) * len + j)) : T(0);
+                int64_t ea = int64_t(ca) * len + j;
+                if (panel && ac && aj)  // U_b stored as row panels (adjoint above lc)
+                    ea = panel_off(leaf_off, leaf_of, shc, int32_t(off), k, j, ca);
+                a[u] = (ac && aj) ? T(FacB<DT>::ld(p + ea)) : T(0);
 #pragma unroll
                 for (int q = 0; q < kNT; ++q)
                     bv[u][q] = (aj && q < ntl) ? Xs[(off + j) * NP + nb + 16 * q + (lane & 15)] : T(0);
@@ -293,7 +297,8 @@ __global__ void __launch_bounds__(64)
               const int32_t *__restrict__ leaf_off, int sh, const int64_t *__restrict__ grp_begin,
               const int64_t *__restrict__ grp_blk, void *const *__restrict__ fptr,
               const int32_t *__restrict__ rank, const int64_t *__restrict__ blk_col0,
-              const typename CT<DT>::T *__restrict__ Z, int NP, double *__restrict__ Y) {
+              const typename CT<DT>::T *__restrict__ Z, int NP, double *__restrict__ Y, int panel,
+              const int32_t *__restrict__ leaf_of, int shc) {
     using C = CT<DT>;
     using T = typename C::T;
     using F = typename FacB<DT>::T;
@@ -307,6 +312,13 @@ __global__ void __launch_bounds__(64)
     const int r0 = it.y * 16;
     const int ia = r0 + (lane & 15);  // A row (box row) of this lane
     const bool ar = ia < bm;
+    // row panels (forward above the chunk level): this row's chunk box
+    int32_t pr0 = bs, pld = bm;
+    if (panel && ar) {
+        const int32_t ch = leaf_of[bs + ia] >> shc;
+        pr0 = leaf_off[ch << shc];
+        pld = leaf_off[(ch + 1) << shc] - pr0;
+    }
     const int64_t e0 = grp_begin[gbase + tb], e1 = grp_begin[gbase + tb + 1];
     for (int nb = 0; nb < NP; nb += 16 * kNT) {
         const int ntl = min(kNT, (NP - nb) / 16);
@@ -322,7 +334,8 @@ __global__ void __launch_bounds__(64)
             const int64_t bi = grp_blk ? grp_blk[e] : e;
             const int k = rank[bi];
             const int64_t col0 = blk_col0[bi];
-            const F *__restrict__ p = static_cast<const F *>(fptr[bi]);
+            const F *__restrict__ p = static_cast<const F *>(fptr[bi]) +
+                                      (int64_t(pr0 - bs) * k + (bs + ia - pr0));
             typename C::V4 acc[kNT];
 #pragma unroll
             for (int q = 0; q < kNT; ++q)
@@ -334,7 +347,7 @@ __global__ void __launch_bounds__(64)
                 for (int u = 0; u < KU; ++u) {
                     const int c = c0 + 4 * u + (lane >> 4);
                     const bool ak = c < k;
-                    a[u] = (ar && ak) ? T(FacB<DT>::ld(p + int64_t(c) * bm + ia)) : T(0);
+                    a[u] = (ar && ak) ? T(FacB<DT>::ld(p + int64_t(c) * pld)) : T(0);
 #pragma unroll
                     for (int q = 0; q < kNT; ++q)
                         bv[u][q] = (ak && q < ntl) ? Z[(col0 + c) * NP + nb + 16 * q + (lane & 15)] : T(0);
@@ -494,7 +507,8 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
         k_s1_mfma<DT><<<int(P.bt_ns1[l]), 64, 0, s>>>(
             reinterpret_cast<const int2 *>(P.bt_s1[l]), P.bt_ns1[l], adjoint ? P.blk_m : P.blk_n,
             adjoint ? P.blk_toff : P.blk_soff, adjoint ? P.blk_uptr : P.blk_vptr, P.blk_rank,
-            P.blk_col0, P.blk_scale, Xs, NP, Z);
+            P.blk_col0, P.blk_scale, Xs, NP, Z, int(adjoint && l < P.chunk_level), P.leaf_off,
+            P.leaf_of, 3 * (P.L - P.chunk_level));
         H3D_LAUNCH_CHECK();
         const double ent = double(adjoint ? P.lvl_entries_u[l] : P.lvl_entries_v[l]);
         P.prof.end(s, ev, "k_s1_mfma", ent * es + double(P.lvl_rank_sum[l]) * sizeof(T) * NP,
@@ -507,7 +521,8 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
         k_s2_mfma<DT><<<int(P.bt_ns2[l]), 64, 0, s>>>(
             reinterpret_cast<const int2 *>(P.bt_s2[l]), P.bt_ns2[l], P.box_base[l], P.leaf_off,
             3 * (P.L - l), P.tgt_begin, adjoint ? P.src_blk : nullptr,
-            adjoint ? P.blk_vptr : P.blk_uptr, P.blk_rank, P.blk_col0, Z, NP, Y);
+            adjoint ? P.blk_vptr : P.blk_uptr, P.blk_rank, P.blk_col0, Z, NP, Y,
+            int(!adjoint && l < P.chunk_level), P.leaf_of, 3 * (P.L - P.chunk_level));
         H3D_LAUNCH_CHECK();
         const double ent = double(adjoint ? P.lvl_entries_v[l] : P.lvl_entries_u[l]);
         P.prof.end(s, ev, "k_s2_mfma",

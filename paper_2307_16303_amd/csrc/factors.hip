@@ -75,7 +75,9 @@ __global__ void __launch_bounds__(256)
            const int32_t *__restrict__ n, const int32_t *__restrict__ rank, int max_rank, int kws,
            const double *__restrict__ ws, const int64_t *__restrict__ ws_off, int64_t ws_base,
            const int64_t *__restrict__ uoff, const int64_t *__restrict__ voff, char *cu, char *cv,
-           void **uptr, void **vptr, float *scale2) {
+           void **uptr, void **vptr, float *scale2, int64_t panel_end,
+           const int32_t *__restrict__ toff, const int32_t *__restrict__ leaf_off,
+           const int32_t *__restrict__ leaf_of, int shc) {
     const int64_t q = q0 + ((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6);
     const int lane = threadIdx.x & 63;
     if (q >= q1)
@@ -90,11 +92,21 @@ __global__ void __launch_bounds__(256)
     const double *V = U + int64_t(mb) * kcap;
     const int64_t nu = int64_t(mb) * k, nv = int64_t(nb) * k;
     const int64_t ou = uoff[q - q0], ov = voff[q - q0];
+    // destination of element e (column-major index) of U_b: row panels above
+    // the chunk level, column-major otherwise
+    const bool panel = b < panel_end;
+    const int32_t bs = toff[b];
+    auto udst = [&](int64_t e) -> int64_t {
+        if (!panel)
+            return e;
+        const int c = int(e / mb);
+        return panel_off(leaf_off, leaf_of, shc, bs, k, int32_t(e - int64_t(c) * mb), c);
+    };
     if (DT == H3D_F64) {
         double *du = reinterpret_cast<double *>(cu) + ou;
         double *dv = reinterpret_cast<double *>(cv) + ov;
         for (int64_t e = lane; e < nu; e += 64)
-            du[e] = U[e];
+            du[udst(e)] = U[e];
         for (int64_t e = lane; e < nv; e += 64)
             dv[e] = V[e];
         if (lane == 0) {
@@ -105,7 +117,7 @@ __global__ void __launch_bounds__(256)
         float *du = reinterpret_cast<float *>(cu) + ou;
         float *dv = reinterpret_cast<float *>(cv) + ov;
         for (int64_t e = lane; e < nu; e += 64)
-            du[e] = float(U[e]);
+            du[udst(e)] = float(U[e]);
         for (int64_t e = lane; e < nv; e += 64)
             dv[e] = float(V[e]);
         if (lane == 0) {
@@ -126,7 +138,7 @@ __global__ void __launch_bounds__(256)
         su = su > 0.0 ? exp2(ceil(log2(su))) : 1.0;
         sv = sv > 0.0 ? exp2(ceil(log2(sv))) : 1.0;
         for (int64_t e = lane; e < nu; e += 64)
-            du[e] = f32_to_bf16(float(U[e] / su));
+            du[udst(e)] = f32_to_bf16(float(U[e] / su));
         for (int64_t e = lane; e < nv; e += 64)
             dv[e] = f32_to_bf16(float(V[e] / sv));
         if (lane == 0) {
@@ -235,26 +247,38 @@ template <int DT>
 __global__ void __launch_bounds__(256)
     k_export(int64_t nfar, int which, const int32_t *__restrict__ len, const int32_t *__restrict__ rank,
              void *const *__restrict__ ptr, const float *__restrict__ scale2,
-             const int64_t *__restrict__ off, double *__restrict__ out) {
+             const int64_t *__restrict__ off, double *__restrict__ out, int64_t panel_end,
+             const int32_t *__restrict__ toff, const int32_t *__restrict__ leaf_off,
+             const int32_t *__restrict__ leaf_of, int shc) {
     const int64_t b = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (b >= nfar)
         return;
-    const int64_t cnt = int64_t(len[b]) * rank[b];
+    const int mb = len[b], k = rank[b];
+    const int64_t cnt = int64_t(mb) * k;
     double *o = out + off[b];
+    // source of element e (column-major index): row panels for U above the chunk level
+    const bool panel = which == 0 && b < panel_end;
+    const int32_t bs = toff[b];
+    auto src = [&](int64_t e) -> int64_t {
+        if (!panel)
+            return e;
+        const int c = int(e / mb);
+        return panel_off(leaf_off, leaf_of, shc, bs, k, int32_t(e - int64_t(c) * mb), c);
+    };
     if (DT == H3D_F64) {
         const double *p = reinterpret_cast<const double *>(ptr[b]);
         for (int64_t e = lane; e < cnt; e += 64)
-            o[e] = p[e];
+            o[e] = p[src(e)];
     } else if (DT == H3D_F32) {
         const float *p = reinterpret_cast<const float *>(ptr[b]);
         for (int64_t e = lane; e < cnt; e += 64)
-            o[e] = double(p[e]);
+            o[e] = double(p[src(e)]);
     } else {
         const uint16_t *p = reinterpret_cast<const uint16_t *>(ptr[b]);
         const double sc = double(scale2[2 * b + which]);
         for (int64_t e = lane; e < cnt; e += 64)
-            o[e] = double(bf16_to_f32(p[e])) * sc;
+            o[e] = double(bf16_to_f32(p[src(e)])) * sc;
     }
 }
 
@@ -266,6 +290,14 @@ void factors_build(Plan &P, hipStream_t s) {
     const int64_t nf = P.nfar;
     const int dt = P.cfg.factor_dtype;
     P.factor_dtype = dt;
+    // stage-2 chunk level: the deepest level whose boxes hold about 48 or
+    // more points on average; U_b above it is stored as row panels
+    int lc = P.L;
+    while (lc > 0 && P.mean_box[lc] < 48)
+        --lc;
+    P.chunk_level = lc;
+    P.panel_end = lc >= 1 ? P.lvl_blk[lc] : 0;
+    const int shc = 3 * (P.L - lc);
     P.blk_rank = P.mem.alloc_n<int32_t>(nf);
     P.blk_uptr = P.mem.alloc_n<void *>(nf);
     P.blk_vptr = P.mem.alloc_n<void *>(nf);
@@ -364,17 +396,22 @@ void factors_build(Plan &P, hipStream_t s) {
                 case H3D_F64:
                     k_pack<H3D_F64><<<grid, 256, 0, s>>>(q0, q1, list, P.blk_m, P.blk_n, P.blk_rank, mr,
                                                          kws, ws, ws_off, base, mk, nk, cu, cv,
-                                                         P.blk_uptr, P.blk_vptr, P.blk_scale);
+                                                         P.blk_uptr, P.blk_vptr, P.blk_scale,
+                                                         P.panel_end, P.blk_toff, P.leaf_off,
+                                                         P.leaf_of, shc);
                     break;
                 case H3D_F32:
                     k_pack<H3D_F32><<<grid, 256, 0, s>>>(q0, q1, list, P.blk_m, P.blk_n, P.blk_rank, mr,
                                                          kws, ws, ws_off, base, mk, nk, cu, cv,
-                                                         P.blk_uptr, P.blk_vptr, P.blk_scale);
+                                                         P.blk_uptr, P.blk_vptr, P.blk_scale,
+                                                         P.panel_end, P.blk_toff, P.leaf_off,
+                                                         P.leaf_of, shc);
                     break;
                 default:
                     k_pack<H3D_BF16_SCALED><<<grid, 256, 0, s>>>(
                         q0, q1, list, P.blk_m, P.blk_n, P.blk_rank, mr, kws, ws, ws_off, base, mk,
-                        nk, cu, cv, P.blk_uptr, P.blk_vptr, P.blk_scale);
+                        nk, cu, cv, P.blk_uptr, P.blk_vptr, P.blk_scale, P.panel_end, P.blk_toff,
+                        P.leaf_off, P.leaf_of, shc);
                     break;
                 }
                 H3D_LAUNCH_CHECK();
@@ -451,14 +488,30 @@ void factors_build(Plan &P, hipStream_t s) {
     P.stats.rank_sum = P.ncols;
     P.stats.rank_max = rmax;
 
+    // adjoint stage-1 items of the panelled levels
+    for (int l = 1; l < P.chunk_level; ++l) {
+        const int64_t b0 = P.lvl_blk[l], b1 = P.lvl_blk[l + 1];
+        if (b1 <= b0)
+            continue;
+        const int64_t nb = b1 - b0;
+        int64_t *cnt = P.mem.alloc_n<int64_t>(nb + 1);
+        H3D_HIP(hipMemsetAsync(cnt + nb, 0, sizeof(int64_t), s));
+        k_item_count<<<grid_for(nb, 256), 256, 0, s>>>(b0, b1, 8, P.blk_rank, cnt);
+        H3D_LAUNCH_CHECK();
+        const int64_t ni = scan_exclusive_i64(P, cnt, cnt, nb + 1, s);
+        int32_t *items = P.mem.alloc_n<int32_t>(2 * std::max<int64_t>(ni, 1));
+        k_item_fill<<<grid_for(nb, 256), 256, 0, s>>>(b0, b1, 8, P.blk_rank, cnt, items);
+        H3D_LAUNCH_CHECK();
+        H3D_HIP(hipStreamSynchronize(s));
+        P.mem.release(cnt);
+        P.s1a_items[l] = items;
+        P.s1a_nitems[l] = ni;
+    }
+
     // stage-1 shapes and work items (defaults; the autotuner may replace them)
     for (int cls = 0; cls < 2; ++cls)
         for (int l = 1; l <= P.L; ++l)
             set_level_shape(P, cls, l, default_shape(P, l, cls), s);
-    int lc = P.L;
-    while (lc > 0 && P.mean_box[lc] < 48)
-        --lc;
-    P.chunk_level = lc;
 }
 
 // Default stage-1 shape of level l: about four rows per lane, several tiny
@@ -538,14 +591,20 @@ void export_factors(const Plan &Pc, int which, double *host_out) {
     const int grid = grid_for(nf * 64, 256);
     switch (P.factor_dtype) {
     case H3D_F64:
-        k_export<H3D_F64><<<grid, 256, 0, s>>>(nf, which, len, P.blk_rank, ptr, P.blk_scale, off, out);
+        k_export<H3D_F64><<<grid, 256, 0, s>>>(nf, which, len, P.blk_rank, ptr, P.blk_scale, off, out,
+                                               P.panel_end, P.blk_toff, P.leaf_off, P.leaf_of,
+                                               3 * (P.L - P.chunk_level));
         break;
     case H3D_F32:
-        k_export<H3D_F32><<<grid, 256, 0, s>>>(nf, which, len, P.blk_rank, ptr, P.blk_scale, off, out);
+        k_export<H3D_F32><<<grid, 256, 0, s>>>(nf, which, len, P.blk_rank, ptr, P.blk_scale, off, out,
+                                               P.panel_end, P.blk_toff, P.leaf_off, P.leaf_of,
+                                               3 * (P.L - P.chunk_level));
         break;
     default:
         k_export<H3D_BF16_SCALED><<<grid, 256, 0, s>>>(nf, which, len, P.blk_rank, ptr, P.blk_scale,
-                                                       off, out);
+                                                       off, out, P.panel_end, P.blk_toff,
+                                                       P.leaf_off, P.leaf_of,
+                                                       3 * (P.L - P.chunk_level));
         break;
     }
     H3D_LAUNCH_CHECK();

@@ -249,6 +249,10 @@ struct Plan {
     bool tuned[2] = {false, false};
     int64_t lvl_rank_sum[kMaxLevels + 1] = {0};
     int chunk_level = 0;           // stage-2 boxes: about 64 rows per wave
+    int64_t panel_end = 0;         // blocks [0, panel_end) store U_b as row panels
+    // adjoint stage-1 items of the panelled levels: (block, first of 8 columns)
+    int32_t *s1a_items[kMaxLevels + 1] = {};
+    int64_t s1a_nitems[kMaxLevels + 1] = {};
     int mean_box[kMaxLevels + 1] = {0};  // mean size of non-empty boxes per level
     int max_box[kMaxLevels + 1] = {0};
 
@@ -286,6 +290,24 @@ struct Plan {
 
 // products with at least this many right-hand sides use the matrix cores
 constexpr int64_t kBatchedMinRhs = 8;
+
+// Row panels.  Stage 2 gives one workgroup to each box of the chunk level lc
+// and streams, for every coarser level, the rows of U_b that fall in that
+// box.  So the U_b of a block whose level lies above lc is stored as one
+// panel per chunk box of its target box, in row order; a panel holds the
+// chunk box's rows of all k columns, column-major (leading dimension = the
+// chunk box's row count), so each workgroup reads one contiguous range.
+// Blocks at or below lc keep U_b column-major (one panel).  V_b is always
+// column-major.  Offset of element (i, c) of a panelled U_b whose target box
+// starts at sorted row bs; shc = 3 (L - lc).
+__device__ __forceinline__ int64_t panel_off(const int32_t *__restrict__ leaf_off,
+                                             const int32_t *__restrict__ leaf_of, int shc,
+                                             int32_t bs, int k, int32_t i, int c) {
+    const int32_t row = bs + i;
+    const int32_t ch = leaf_of[row] >> shc;
+    const int32_t r0 = leaf_off[ch << shc], r1 = leaf_off[(ch + 1) << shc];
+    return int64_t(r0 - bs) * k + (row - r0) + int64_t(c) * (r1 - r0);
+}
 
 struct BatchState;
 }  // namespace h3d

@@ -84,6 +84,16 @@ template <int DT, int NR> void launch_s1(const S1Shape &sh, S1Args a, hipStream_
     fail(H3D_EDEVICE, "internal: no stage-1 kernel for this shape");
 }
 
+// adjoint stage 1 of a panelled level: one work item per wave
+template <int DT, int NR>
+__global__ void __launch_bounds__(256)
+    k_s1_panel(S1Args a, const int32_t *__restrict__ leaf_off, const int32_t *__restrict__ box,
+               int shc, int shl) {
+    const int64_t w = uniform64((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6);
+    if (w < a.nitems)
+        s1_panel_item<DT, NR>(a, leaf_off, box, shc, shl, w);
+}
+
 // stage 2: one workgroup per chunk box.  Neighbouring chunk boxes share the
 // cache line at their common edge in every coarse column they read, and
 // workgroups are dealt to the eight XCDs (each with its own L2) in turn: each
@@ -162,14 +172,26 @@ void launch_far(Plan &P, bool adjoint, int nrhs, const double *xp, double *z, co
         const double ent = double(adjoint ? P.lvl_entries_u[l] : P.lvl_entries_v[l]);
         const double cols = double(P.lvl_rank_sum[l]);
         const double bytes = ent * es + cols * 8.0 * nrhs + double(n) * 8.0 * nrhs;
+        // the adjoint reads U_b, stored as row panels above the chunk level
+        const bool pan = adjoint && l < P.chunk_level;
         hipEvent_t ev = P.prof.begin(s);
-        launch_s1<DT, NR>(sh, a, s);
+        if (pan) {
+            S1Args ap = a;
+            ap.items = reinterpret_cast<const int2 *>(P.s1a_items[l]);
+            ap.nitems = P.s1a_nitems[l];
+            ap.span = kPanelCols;
+            k_s1_panel<DT, NR><<<grid_for(ap.nitems * 64, 256), 256, 0, s>>>(
+                ap, P.leaf_off, P.blk_t, 3 * (L - P.chunk_level), 3 * (P.chunk_level - l));
+        } else {
+            launch_s1<DT, NR>(sh, a, s);
+        }
         H3D_LAUNCH_CHECK();
+        const char *kname = pan ? "k_s1_panel" : (sh.packed ? "k_s1_packed" : "k_s1_wide");
         char name[48];
         if (P.prof.levels)
-            snprintf(name, sizeof(name), "%s_L%d", sh.packed ? "k_s1_packed" : "k_s1_wide", l);
+            snprintf(name, sizeof(name), "%s_L%d", kname, l);
         else
-            snprintf(name, sizeof(name), "%s", sh.packed ? "k_s1_packed" : "k_s1_wide");
+            snprintf(name, sizeof(name), "%s", kname);
         P.prof.end(s, ev, name, bytes, 2.0 * ent * nrhs);
     }
     // stage 2 (always: it also writes y); level by level when profiling
@@ -179,6 +201,7 @@ void launch_far(Plan &P, bool adjoint, int nrhs, const double *xp, double *z, co
         tab.box_base[l] = P.box_base[l];
     tab.L = L;
     tab.lc = P.chunk_level;
+    tab.panel = adjoint ? 0 : 1;
     const int64_t nchunk = pow8(P.chunk_level);
     const int parts = (P.prof.levels && L > 1) ? L : 1;
     for (int part = 1; part <= parts; ++part) {
@@ -283,6 +306,7 @@ void autotune_dt(Plan &P, int nrhs, hipStream_t s) {
         tab.box_base[l] = P.box_base[l];
     tab.L = P.L;
     tab.lc = P.chunk_level;
+    tab.panel = 1;
     const int64_t nchunk = pow8(P.chunk_level);
     float best_ms = 1e30f;
     int best_w = P.s2_waves[cls];

@@ -329,6 +329,78 @@ __device__ __forceinline__ void s1_packed_item(const S1Args &a, int64_t w) {
     }
 }
 
+// Adjoint stage 1 above the chunk level: z_c = (column c of U_b) . x_t with
+// U_b stored as row panels.  Item = (block, first column); a wave takes
+// kPanelCols columns side by side over 64 lanes per column and walks the
+// panels of the target box in row order.
+constexpr int kPanelCols = 8;
+
+template <int DT, int NR, bool LIVE = false>
+__device__ __forceinline__ void s1_panel_item(const S1Args &a, const int32_t *__restrict__ leaf_off,
+                                              const int32_t *__restrict__ box, int shc, int shl,
+                                              int64_t w) {
+    using T = typename Fac<DT>::T;
+    constexpr int U = kPanelCols;
+    const int2 item = a.items[w];
+    const int lane = threadIdx.x & 63;
+    const int b = item.x;
+    const int32_t bs = a.seg_off[b];
+    const int64_t col0 = a.blk_col0[b];
+    const int k = a.rank[b];
+    const T *__restrict__ p = static_cast<const T *>(a.seg_ptr[b]);
+    double sc = 1.0;
+    if (DT == H3D_BF16_SCALED)
+        sc = double(a.scale2[2 * b]) * double(a.scale2[2 * b + 1]);
+    const int cb = item.y;
+    const int64_t ch0 = int64_t(box[b]) << shl, nch = int64_t(1) << shl;
+    const double *__restrict__ xp = a.xp;
+    for (int rb = 0; rb < a.nrhs; rb += NR) {
+        double acc[U][NR];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+                acc[u][q] = 0.0;
+        for (int64_t ch = ch0; ch < ch0 + nch; ++ch) {
+            const int32_t r0 = leaf_off[ch << shc], r1 = leaf_off[(ch + 1) << shc];
+            const int mj = r1 - r0;
+            const T *__restrict__ pj = p + int64_t(r0 - bs) * k;
+            for (int j = lane; j < mj; j += 64) {
+                double xv[NR];
+#pragma unroll
+                for (int q = 0; q < NR; ++q)
+                    xv[q] = (NR == 1 || rb + q < a.nrhs) ? rd<LIVE>(xp + (rb + q) * a.n + r0 + j)
+                                                         : 0.0;
+                double v[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    v[u] = cb + u < k ? fac_ld<DT>(pj + int64_t(cb + u) * mj + j) : 0.0;
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int q = 0; q < NR; ++q)
+                        acc[u][q] += v[u] * xv[q];
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int q = 0; q < NR; ++q)
+                    acc[u][q] += __shfl_xor(acc[u][q], o, 64);
+        if (lane == 0) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (cb + u < k)
+#pragma unroll
+                    for (int q = 0; q < NR; ++q)
+                        if (NR == 1 || rb + q < a.nrhs)
+                            a.z[(rb + q) * a.ldz + col0 + cb + u] = acc[u][q] * sc;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // stage 2: one workgroup per box of the chunk level, one lane per row (two
 // for boxes of 65..128 rows).  At levels up to the chunk level every lane of
@@ -338,6 +410,7 @@ __device__ __forceinline__ void s1_packed_item(const S1Args &a, int64_t w) {
 struct S2Tab {
     int64_t box_base[kMaxLevels + 1];
     int L, lc;
+    int panel;  // the factors streamed are U_b stored as row panels above lc
 };
 
 template <int DT, int NR, int U2, bool LIVE = false>
@@ -445,17 +518,21 @@ __device__ __forceinline__ void
                 const int64_t g = tab.box_base[l] + t;
                 const int32_t bs = leaf_off[t << sh];
                 const int32_t bm = leaf_off[(t + 1) << sh] - bs;
-                const int32_t loc = rrA - bs;
+                // this chunk box's panel of U_b: rows r0..r1, leading dimension r1 - r0
+                const bool pan = tab.panel && l < lc;
+                const int32_t ld = pan ? r1 - r0 : bm;
                 const int64_t e0 = grp_begin[g], e1 = grp_begin[g + 1];
                 for (int64_t e = e0 + wv; e < e1; e += kS2Waves) {
                     const int64_t bi = grp_blk ? grp_blk[e] : e;
-                    const T *p = static_cast<const T *>(fptr[bi]) + loc;
+                    const int kb = rank[bi];
+                    const T *p = static_cast<const T *>(fptr[bi]) +
+                                 (pan ? int64_t(r0 - bs) * kb + (rrA - r0) : int64_t(rrA - bs));
                     if (two)
-                        stage2_block2<DT, NR, 8, LIVE>(p, dB, bm, rank[bi], z + blk_col0[bi], ldz, rb,
-                                                 nrhs, acc[0], acc[1]);
+                        stage2_block2<DT, NR, 8, LIVE>(p, dB, ld, kb, z + blk_col0[bi], ldz, rb,
+                                                       nrhs, acc[0], acc[1]);
                     else
-                        stage2_block<DT, NR, 8, LIVE>(p, bm, rank[bi], z + blk_col0[bi], ldz, rb, nrhs,
-                                                acc[0]);
+                        stage2_block<DT, NR, 8, LIVE>(p, ld, kb, z + blk_col0[bi], ldz, rb, nrhs,
+                                                      acc[0]);
                 }
             }
 #pragma unroll
