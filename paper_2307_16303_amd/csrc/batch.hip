@@ -66,6 +66,8 @@ constexpr int64_t kSpinLimit = int64_t(1) << 20;  // polls: about a second
 
 // stage-1 shapes the persistent kernel carries (the default shapes)
 int shape_id(const S1Shape &sh) {
+    if (sh.rows > 0)
+        return -1;
     if (sh.packed && sh.S == 4 && sh.U == 4)
         return 0;
     if (sh.packed && sh.S == 8 && sh.U == 4)

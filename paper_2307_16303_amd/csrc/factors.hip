@@ -175,6 +175,45 @@ __global__ void k_item_count(int64_t b0, int64_t b1, int span, const int32_t *__
     cnt[b - b0] = (rank[b] + span - 1) / span;
 }
 
+// split items: every column group of span columns is cut into parts of
+// `rows` rows (enough parts for the longer of the two sides of the block);
+// one reduction group per column group
+__global__ void k_item_count_split(int64_t b0, int64_t b1, int span, int rows,
+                                   const int32_t *__restrict__ m, const int32_t *__restrict__ n,
+                                   const int32_t *__restrict__ rank, int64_t *__restrict__ cnt,
+                                   int64_t *__restrict__ gcnt) {
+    int64_t b = b0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= b1)
+        return;
+    const int ncg = (rank[b] + span - 1) / span;
+    const int np = max(1, (max(m[b], n[b]) + rows - 1) / rows);
+    cnt[b - b0] = int64_t(ncg) * np;
+    gcnt[b - b0] = ncg;
+}
+
+__global__ void k_item_fill_split(int64_t b0, int64_t b1, int span, int rows,
+                                  const int32_t *__restrict__ m, const int32_t *__restrict__ n,
+                                  const int32_t *__restrict__ rank, const int64_t *__restrict__ off,
+                                  const int64_t *__restrict__ goff, int32_t *__restrict__ items,
+                                  int32_t *__restrict__ part, int32_t *__restrict__ grp) {
+    int64_t b = b0 + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= b1)
+        return;
+    const int ncg = (rank[b] + span - 1) / span;
+    const int np = max(1, (max(m[b], n[b]) + rows - 1) / rows);
+    const int64_t o = off[b - b0], g = goff[b - b0];
+    for (int q = 0; q < ncg; ++q) {
+        grp[2 * (g + q)] = int32_t(o + int64_t(q) * np);
+        grp[2 * (g + q) + 1] = np;
+        for (int pp = 0; pp < np; ++pp) {
+            const int64_t i = o + int64_t(q) * np + pp;
+            items[2 * i] = int32_t(b);
+            items[2 * i + 1] = q * span;
+            part[i] = pp;
+        }
+    }
+}
+
 // packed items: the first block of every group of g consecutive blocks
 // carries one item (first block, number of blocks)
 __global__ void k_item_count_packed(int64_t b0, int64_t b1, int g, int64_t *__restrict__ cnt) {
@@ -546,9 +585,50 @@ void set_level_shape(Plan &P, int cls, int l, const S1Shape &sh, hipStream_t s) 
     P.mem.release(P.s1_items[cls][l]);
     P.s1_items[cls][l] = nullptr;
     P.s1_nitems[cls][l] = 0;
+    if (cls == 0) {
+        P.mem.release(P.s1_part[l]);
+        P.mem.release(P.s1_grp[l]);
+        P.mem.release(P.s1_zp[l]);
+        P.s1_part[l] = P.s1_grp[l] = nullptr;
+        P.s1_zp[l] = nullptr;
+        P.s1_ngrp[l] = 0;
+    }
     if (b1 <= b0)
         return;
     const int64_t nb = b1 - b0;
+    if (!sh.packed && sh.rows > 0) {
+        if (cls != 0)
+            fail(H3D_EINVAL, "internal: split stage-1 shapes serve one right-hand side");
+        const int span = (64 / sh.S) * sh.U;
+        int64_t *cnt = P.mem.alloc_n<int64_t>(nb + 1);
+        int64_t *gcnt = P.mem.alloc_n<int64_t>(nb + 1);
+        H3D_HIP(hipMemsetAsync(cnt + nb, 0, sizeof(int64_t), s));
+        H3D_HIP(hipMemsetAsync(gcnt + nb, 0, sizeof(int64_t), s));
+        k_item_count_split<<<grid_for(nb, 256), 256, 0, s>>>(b0, b1, span, sh.rows, P.blk_m,
+                                                             P.blk_n, P.blk_rank, cnt, gcnt);
+        H3D_LAUNCH_CHECK();
+        const int64_t ni = scan_exclusive_i64(P, cnt, cnt, nb + 1, s);
+        const int64_t ng = scan_exclusive_i64(P, gcnt, gcnt, nb + 1, s);
+        if (ni >= int64_t(0x7fffffff))
+            fail(H3D_EINVAL, "too many stage-1 work items");
+        int32_t *items = P.mem.alloc_n<int32_t>(2 * std::max<int64_t>(ni, 1));
+        int32_t *part = P.mem.alloc_n<int32_t>(std::max<int64_t>(ni, 1));
+        int32_t *grp = P.mem.alloc_n<int32_t>(2 * std::max<int64_t>(ng, 1));
+        k_item_fill_split<<<grid_for(nb, 256), 256, 0, s>>>(b0, b1, span, sh.rows, P.blk_m, P.blk_n,
+                                                            P.blk_rank, cnt, gcnt, items, part, grp);
+        H3D_LAUNCH_CHECK();
+        H3D_HIP(hipStreamSynchronize(s));
+        P.mem.release(cnt);
+        P.mem.release(gcnt);
+        P.s1_items[0][l] = items;
+        P.s1_nitems[0][l] = ni;
+        P.s1_span[0][l] = span;
+        P.s1_part[l] = part;
+        P.s1_grp[l] = grp;
+        P.s1_ngrp[l] = ng;
+        P.s1_zp[l] = P.mem.alloc_n<double>(std::max<int64_t>(ni, 1) * span);
+        return;
+    }
     int64_t *cnt = P.mem.alloc_n<int64_t>(nb + 1);
     H3D_HIP(hipMemsetAsync(cnt + nb, 0, sizeof(int64_t), s));
     int span = 0;

@@ -195,6 +195,8 @@ struct S1Shape {
     int S = 64;      // lanes per factor column
     int U = 8;       // columns in flight per lane and pass
     int reps = 1;    // wide form: passes per work item
+    int rows = 0;    // wide form, one RHS: > 0 splits each column into parts of this
+                     // many rows (partial sums, then a fixed-order reduction)
 };
 
 // Everything one HODLR3D operator owns.  Rows are numbered in sorted (Morton)
@@ -245,6 +247,12 @@ struct Plan {
     int32_t *s1_items[2][kMaxLevels + 1] = {};  // [2 count]: (block, c0) or (first, count)
     int64_t s1_nitems[2][kMaxLevels + 1] = {};
     int s1_span[2][kMaxLevels + 1] = {};        // wide form: columns per item
+    // split levels (class 0): part index of every item, reduction groups
+    // (first item, parts) of every (block, column group), partial sums
+    int32_t *s1_part[kMaxLevels + 1] = {};
+    int32_t *s1_grp[kMaxLevels + 1] = {};
+    int64_t s1_ngrp[kMaxLevels + 1] = {};
+    double *s1_zp[kMaxLevels + 1] = {};
     int s2_waves[2] = {4, 4};                    // waves per stage-2 chunk box
     bool tuned[2] = {false, false};
     int64_t lvl_rank_sum[kMaxLevels + 1] = {0};

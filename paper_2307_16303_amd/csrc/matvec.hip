@@ -60,6 +60,27 @@ __global__ void __launch_bounds__(256) k_s1_packed(S1Args a) {
         s1_packed_item<S, U, DT, NR>(a, w);
 }
 
+// split columns: z of every column group = its parts' partial sums, added in
+// part order (one thread per column of a group)
+__global__ void k_s1_reduce(int64_t ngrp, const int32_t *__restrict__ grp,
+                            const int2 *__restrict__ items, int span,
+                            const int32_t *__restrict__ rank, const int64_t *__restrict__ col0,
+                            const double *__restrict__ zp, double *__restrict__ z) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t g = t / span;
+    const int u = int(t - g * span);
+    if (g >= ngrp)
+        return;
+    const int32_t first = grp[2 * g], np = grp[2 * g + 1];
+    const int2 it = items[first];
+    if (it.y + u >= rank[it.x])
+        return;
+    double v = 0.0;
+    for (int32_t pp = 0; pp < np; ++pp)
+        v += zp[int64_t(first + pp) * span + u];
+    z[col0[it.x] + it.y + u] = v;
+}
+
 // one launch of level l's stage 1 with its current shape
 template <int DT, int NR> void launch_s1(const S1Shape &sh, S1Args a, hipStream_t s) {
     const int grid = grid_for(a.nitems * 64, 256);
@@ -70,6 +91,10 @@ template <int DT, int NR> void launch_s1(const S1Shape &sh, S1Args a, hipStream_
         return;                                                                           \
     }
         H3D_S1P(4, 2) H3D_S1P(4, 4) H3D_S1P(8, 2) H3D_S1P(8, 4) H3D_S1P(16, 2) H3D_S1P(16, 4)
+        // narrow factors, one right-hand side: twice the loads in flight
+        if constexpr (NR == 1 && DT != H3D_F64) {
+            H3D_S1P(4, 8) H3D_S1P(8, 8) H3D_S1P(16, 8)
+        }
 #undef H3D_S1P
     } else {
 #define H3D_S1W(SS, UU)                                                                   \
@@ -79,9 +104,25 @@ template <int DT, int NR> void launch_s1(const S1Shape &sh, S1Args a, hipStream_
     }
         H3D_S1W(8, 4) H3D_S1W(8, 8) H3D_S1W(16, 4) H3D_S1W(16, 8) H3D_S1W(32, 4) H3D_S1W(32, 8)
         H3D_S1W(64, 2) H3D_S1W(64, 4) H3D_S1W(64, 8)
+        if constexpr (NR == 1 && DT != H3D_F64) {
+            H3D_S1W(16, 16) H3D_S1W(32, 16) H3D_S1W(64, 16)
+        }
 #undef H3D_S1W
     }
     fail(H3D_EDEVICE, "internal: no stage-1 kernel for this shape");
+}
+
+// level l's stage 1 with its current shape, including the reduction of split
+// columns
+template <int DT, int NR>
+void launch_s1_level(const Plan &P, int l, const S1Shape &sh, const S1Args &a, hipStream_t s) {
+    launch_s1<DT, NR>(sh, a, s);
+    if (a.part) {
+        H3D_LAUNCH_CHECK();
+        const int64_t nt = P.s1_ngrp[l] * a.span;
+        k_s1_reduce<<<grid_for(nt, 256), 256, 0, s>>>(
+            P.s1_ngrp[l], P.s1_grp[l], a.items, a.span, a.rank, a.blk_col0, a.zp, a.z);
+    }
 }
 
 // adjoint stage 1 of a panelled level: one work item per wave
@@ -138,7 +179,7 @@ void launch_s2_kernel(int waves, int64_t nchunk, hipStream_t s, const S2Tab &tab
 template <int DT, int NR>
 S1Args stage1_args(const Plan &P, int cls, int l, bool adjoint, int nrhs, const double *xp,
                    double *z) {
-    S1Args a;
+    S1Args a{};
     a.items = reinterpret_cast<const int2 *>(P.s1_items[cls][l]);
     a.nitems = P.s1_nitems[cls][l];
     a.span = P.s1_span[cls][l];
@@ -153,6 +194,11 @@ S1Args stage1_args(const Plan &P, int cls, int l, bool adjoint, int nrhs, const 
     a.n = P.n;
     a.z = z;
     a.ldz = P.ncols;
+    if (cls == 0 && P.s1_part[l]) {
+        a.part = P.s1_part[l];
+        a.rows = P.s1_shape[0][l].rows;
+        a.zp = P.s1_zp[l];
+    }
     return a;
 }
 
@@ -183,7 +229,7 @@ void launch_far(Plan &P, bool adjoint, int nrhs, const double *xp, double *z, co
             k_s1_panel<DT, NR><<<grid_for(ap.nitems * 64, 256), 256, 0, s>>>(
                 ap, P.leaf_off, P.blk_t, 3 * (L - P.chunk_level), 3 * (P.chunk_level - l));
         } else {
-            launch_s1<DT, NR>(sh, a, s);
+            launch_s1_level<DT, NR>(P, l, sh, a, s);
         }
         H3D_LAUNCH_CHECK();
         const char *kname = pan ? "k_s1_panel" : (sh.packed ? "k_s1_packed" : "k_s1_wide");
@@ -231,7 +277,7 @@ void launch_far(Plan &P, bool adjoint, int nrhs, const double *xp, double *z, co
 // ---------------------------------------------------------------------------
 // Autotuner: times candidate stage-1 shapes level by level and stage-2 wave
 // counts on the plan's own factor streams, keeps the fastest of each.
-std::vector<S1Shape> s1_candidates(const Plan &P, int l) {
+std::vector<S1Shape> s1_candidates(const Plan &P, int l, bool narrow, bool split) {
     std::vector<S1Shape> c;
     const int m = std::max(1, P.mean_box[l]);
     auto add = [&](int packed, int S, int U, int reps) {
@@ -247,10 +293,16 @@ std::vector<S1Shape> s1_candidates(const Plan &P, int l) {
         add(1, 4, 4, 1);
         add(1, 8, 2, 1);
         add(1, 8, 4, 1);
+        if (narrow) {
+            add(1, 4, 8, 1);
+            add(1, 8, 8, 1);
+        }
     }
     if (m >= 8 && m <= 128) {
         add(1, 16, 2, 1);
         add(1, 16, 4, 1);
+        if (narrow)
+            add(1, 16, 8, 1);
     }
     for (int S : {8, 16, 32, 64}) {
         if (S > std::max(8, 2 * m) || 16 * S < m)
@@ -261,7 +313,20 @@ std::vector<S1Shape> s1_candidates(const Plan &P, int l) {
         }
         if (S == 64)
             add(0, 64, 2, 1);
+        if (narrow && S >= 16) {
+            add(0, S, 16, 1);
+            add(0, S, 16, 64);
+        }
     }
+    // long columns, one right-hand side: split into parts of `rows` rows
+    if (split && m > 512)
+        for (int rows : {512, 2048})
+            for (int U : {4, 8, 16}) {
+                if (U == 16 && !narrow)
+                    continue;
+                add(0, 64, U, 1);
+                c.back().rows = rows;
+            }
     return c;
 }
 
@@ -290,10 +355,10 @@ void autotune_dt(Plan &P, int nrhs, hipStream_t s) {
             continue;
         S1Shape best_sh = P.s1_shape[cls][l];
         float best_ms = 1e30f;
-        for (const S1Shape &sh : s1_candidates(P, l)) {
+        for (const S1Shape &sh : s1_candidates(P, l, NR == 1 && DT != H3D_F64, NR == 1)) {
             set_level_shape(P, cls, l, sh, s);
             const S1Args a = stage1_args<DT, NR>(P, cls, l, false, nrhs, P.xp, P.z);
-            const float ms = time_it([&] { launch_s1<DT, NR>(sh, a, s); });
+            const float ms = time_it([&] { launch_s1_level<DT, NR>(P, l, sh, a, s); });
             if (ms < best_ms) {
                 best_ms = ms;
                 best_sh = sh;

@@ -198,6 +198,11 @@ struct S1Args {
     int64_t n;
     double *z;
     int64_t ldz;
+    // split columns (wide form, one RHS): part of each item, rows per part,
+    // and the partial sums (span per item)
+    const int32_t *part;
+    int rows;
+    double *zp;
 };
 
 template <int S, int U, int DT, int NR, bool LIVE = false>
@@ -218,6 +223,12 @@ __device__ __forceinline__ void s1_wide_item(const S1Args &a, int64_t w) {
         sc = double(a.scale2[2 * b]) * double(a.scale2[2 * b + 1]);
     const int cend = min(item.y + a.span, k);
     const double *__restrict__ xp = a.xp;
+    // rows of this item: a part of the column when columns are split
+    int j0 = 0, j1 = len;
+    if (a.part) {
+        j0 = a.part[w] * a.rows;
+        j1 = min(len, j0 + a.rows);
+    }
     for (int rb = 0; rb < a.nrhs; rb += NR) {
         for (int cb = item.y; cb < cend; cb += NS * U) {
             double acc[U][NR];
@@ -226,7 +237,7 @@ __device__ __forceinline__ void s1_wide_item(const S1Args &a, int64_t w) {
 #pragma unroll
                 for (int q = 0; q < NR; ++q)
                     acc[u][q] = 0.0;
-            for (int j = r; j < len; j += S) {
+            for (int j = j0 + r; j < j1; j += S) {
                 double xv[NR];
 #pragma unroll
                 for (int q = 0; q < NR; ++q)
@@ -254,7 +265,9 @@ __device__ __forceinline__ void s1_wide_item(const S1Args &a, int64_t w) {
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int c = cb + sub + u * NS;
-                    if (c < cend)
+                    if (a.part)  // one pass of span columns per item
+                        a.zp[w * int64_t(a.span) + (c - item.y)] = acc[u][0] * sc;
+                    else if (c < cend)
 #pragma unroll
                         for (int q = 0; q < NR; ++q)
                             if (NR == 1 || rb + q < a.nrhs)
