@@ -16,11 +16,23 @@ reports the GPU result's relative error on those rows.
 
 The variants object measures the same workload with FP32 and BF16 factors
 and with 64 right-hand sides (matrix-core path), each with its relative error
-on sampled rows of the exact product and its gain over the plain FP64 form.
+on sampled rows of the exact product and its gain over the plain FP64 form,
+and the multi-problem form: 32 independent clouds (N_i in [8192, 131072],
+FP32 factors, tol 1e-7) multiplied in one persistent launch, beside the same
+problems' own products run one after another.
+
+roofline.traffic is the dominant kernel's HBM traffic per launch from the
+hardware counters FETCH_SIZE and WRITE_SIZE (rocprofv3 --pmc, one counter per
+run, on this workload), each divided by what the same counter reads for a
+plain 2 GiB device copy (--calibration-copy).  Those figures hold for the
+sources they were taken on: if any file under csrc/ or include/ has changed
+since, traffic is null.
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -35,6 +47,38 @@ METRIC = "HODLR3D matvec points·RHS/s vs plain FP64 GPU at rel err ≤1e-6; HBM
 UNIT = "points·RHS/s"
 HBM_PEAK_GBS = 8000.0
 DTYPE_NAMES = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
+
+# Counter readings of the dominant kernel on uniform262k (FP64 factors, one
+# RHS), KiB per dispatch, with the copy-kernel scale of each counter.  The
+# runs that produced them are listed in profiles/; sources_sha256 identifies
+# the library sources they were taken on (see sources_digest).
+TRAFFIC = {
+    "kernel": "k_stage2", "workload": "uniform262k",
+    "fetch_kib": 11637912.9583, "fetch_scale": 0.500016,
+    "write_kib": 8200.7396, "write_scale": 1.000000,
+    "sources_sha256": "9f1081179b4d0ca668ecbffe8d9c89bbe86c3b70f19175ef8e87233946c54b50",
+}
+
+
+def sources_digest() -> str:
+    """sha256 over the library's kernel sources and public header, in name order."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2307_16303_amd", "csrc", "*")))
+    files.append(os.path.join(ROOT, "include", "hodlr3d.h"))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_bytes(kernel: str, workload: str, factor_dtype: str, nrhs: int):
+    """HBM bytes per launch from the stored counter readings, or None."""
+    t = TRAFFIC
+    if (t is None or t["kernel"] != kernel or t["workload"] != workload
+            or factor_dtype != "fp64" or nrhs != 1 or t["sources_sha256"] != sources_digest()):
+        return None
+    return t["fetch_kib"] * 1024.0 / t["fetch_scale"] + t["write_kib"] * 1024.0 / t["write_scale"]
 
 
 def parse():
@@ -114,8 +158,10 @@ def main():
     dom = max(prof, key=lambda p: p["total_ms"])
     avg_ms = dom["total_ms"] / max(dom["launches"], 1)
     achieved = dom["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
+    traffic = traffic_bytes(dom["name"], args.workload, args.factor_dtype, args.nrhs)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic, 0),
                 "kernel": dom["name"], "avg_launch_ms": round(avg_ms, 4),
                 "bytes_per_launch": dom["bytes_per_launch"]}
     kernels = {p["name"]: round(p["total_ms"] / max(p["launches"], 1), 4) for p in prof}
@@ -156,6 +202,53 @@ def main():
             del opv, xv, yv
             torch.cuda.empty_cache()
 
+    # many uneven problems in one persistent launch
+    batch_ys = None
+    if not args.no_variants and args.factor_dtype == "fp64" and args.nrhs == 1:
+        bw = inputs.BATCH_WORKLOAD
+        work = inputs.batch_workload(bw["count"])
+        t0 = time.perf_counter()
+        bop = hodlr3d.build_batch([torch.as_tensor(p, device=dev) for p, _ in work],
+                                  kernel=bw["kernel"], leaf_size=bw["leaf_size"], tol=bw["tol"],
+                                  factor_dtype=bw["factor_dtype"], box_lo=inputs.CUBE_LO,
+                                  box_side=inputs.CUBE_SIDE)
+        torch.cuda.synchronize()
+        bbuild = time.perf_counter() - t0
+        xs = [torch.as_tensor(x, device=dev) for _, x in work]
+        nb = max(3, args.steps // 2)
+        for _ in range(max(1, args.warmup // 2)):
+            ys = bop.matvec(xs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nb):
+            ys = bop.matvec(xs)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / nb
+        bop.check()
+        for p, x in zip(bop.plans, xs):
+            p.matvec(x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nb):
+            for p, x in zip(bop.plans, xs):
+                p.matvec(x)
+        torch.cuda.synchronize()
+        ts = (time.perf_counter() - t0) / nb
+        ntot = sum(len(p) for p, _ in work)
+        bst = bop.stats()
+        variants["batch32_fp32"] = {
+            "factor_dtype": bw["factor_dtype"], "nrhs": 1, "problems": len(work), "n_total": ntot,
+            "ms_per_step": round(1e3 * tb, 4), "value": round(ntot / tb, 1),
+            "own_products_in_sequence_ms": round(1e3 * ts, 4),
+            "gain_vs_own_products": round(ts / tb, 2),
+            "factor_bytes": bst["factor_bytes"], "build_s": round(bbuild, 2)}
+        print(f"[bench] batch32: {1e3 * tb:.3f} ms ({1e3 * ts:.3f} ms as own products)",
+              file=sys.stderr, flush=True)
+        batch_ys = [(work[i][0], work[i][1], ys[i].detach().cpu().numpy()) for i in (0, 17)]
+        bop.close()
+        del bop, xs, ys
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -184,6 +277,13 @@ def main():
                 rr = rows if yv.shape[1] == 1 else r64
                 variants[name]["rel_err_on_sample"] = float(
                     np.linalg.norm(yv[rr] - ref) / np.linalg.norm(ref))
+        if batch_ys:
+            errs = []
+            for pts_i, x_i, y_i in batch_ys:
+                r_i = inputs.sample_rows(len(pts_i), 64, seed=3)
+                ref = oracle.dense_rows(pts_i, x_i, r_i, kernel=inputs.BATCH_WORKLOAD["kernel"])
+                errs.append(float(np.linalg.norm(y_i[r_i] - ref) / np.linalg.norm(ref)))
+            variants["batch32_fp32"]["rel_err_on_sample"] = max(errs)
         cpu = {"value": round(rows.size * args.nrhs / cpu_s, 1), "unit": UNIT,
                "cores": oracle.num_threads(), "kind": "oracle",
                "sample": f"exact FP64 direct sum for {rows.size} sampled target rows of the "
