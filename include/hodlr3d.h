@@ -72,7 +72,12 @@ typedef struct {
 
 enum {
     H3D_FLAG_KEEP_PIVOTS = 1, /* keep ACA pivots for h3d_export(H3D_EXPORT_PIVOTS) */
-    H3D_FLAG_NO_AUTOTUNE = 2  /* keep the default launch shapes (no timing at build) */
+    H3D_FLAG_NO_AUTOTUNE = 2, /* keep the default launch shapes (no timing at build) */
+    /* recompress every block's ACA factors in FP64 to the smallest rank r with
+     * ||(s_{r+1}, ..., s_k)||_2 <= tol ||s||_2, s the singular values of U V^T
+     * (QR of U and V, SVD of the small core); blocks of rank above 256 and
+     * boxes of more than 4096 points are kept.  Excludes H3D_FLAG_KEEP_PIVOTS. */
+    H3D_FLAG_TRUNCATE = 4
 };
 
 typedef struct {

@@ -7,7 +7,9 @@ with the GPU library in ``paper_2307_16303_amd/`` and never imports it.
 The arithmetic lives in ``h3d_oracle.c`` (plain C, FP64, ``-ffp-contract=off``,
 sums in index order); this module only compiles it with gcc and marshals numpy
 arrays through ctypes.  See the header of ``h3d_oracle.c`` for the paper
-passage each function follows.
+passage each function follows.  The one exception is ``truncate_factors``
+(rank truncation of given factors), written here with numpy's LAPACK QR and
+SVD as the steps of its definition.
 """
 from __future__ import annotations
 
@@ -161,6 +163,37 @@ def aca_dense(A, tol: float, max_rank: int = 0, return_norm: bool = False):
                                  _ptr(cp), ctypes.byref(capped), ctypes.byref(norm2))
     out = (U[:, :k].copy(), V[:, :k].copy(), rp[:k].copy(), cp[:k].copy())
     return out + (norm2.value,) if return_norm else out
+
+
+def truncate_factors(U, V, tol: float):
+    """Recompression of low-rank factors to their optimal rank (the step that
+    follows ACA in the recompression the references of Sec. 4.1 describe).
+
+    With U = Q_U R_U and V = Q_V R_V (QR) and R_U R_V^T = W diag(s) Z^T (SVD),
+    r is the smallest rank with ||(s_{r+1}, ..., s_k)||_2 <= tol ||s||_2, and
+    U' = Q_U W_r diag(s_r)^(1/2), V' = Q_V Z_r diag(s_r)^(1/2).  Blocks of rank
+    below 2, zero blocks and blocks whose rank does not drop come back as
+    given.  Returns (U', V', r).
+    """
+    U = np.asarray(U, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    k = U.shape[1]
+    if k < 2:
+        return U.copy(), V.copy(), k
+    qu, ru = np.linalg.qr(U)
+    qv, rv = np.linalg.qr(V)
+    w, sv, zt = np.linalg.svd(ru @ rv.T)
+    s2 = sv * sv
+    total = float(np.sum(s2))
+    if total == 0.0:
+        return U.copy(), V.copy(), k
+    tail = np.zeros(k + 1)
+    tail[:k] = np.cumsum(s2[::-1])[::-1]  # tail[r] = sum of s_i^2 for i >= r (0-based)
+    r = next(j for j in range(1, k + 1) if tail[j] <= tol * tol * total)
+    if r >= k:
+        return U.copy(), V.copy(), k
+    root = np.sqrt(sv[:r])
+    return qu @ (w[:, :r] * root), qv @ (zt[:r].T * root), r
 
 
 def relation(a, b) -> str:

@@ -128,6 +128,9 @@ h3d_status check_config(const h3d_config *cfg, const h3d_allocator *alloc) {
                 return invalid("box_lo must be finite");
     if (alloc && ((alloc->alloc == nullptr) != (alloc->free == nullptr)))
         return invalid("allocator needs both alloc and free");
+    if ((cfg->flags & H3D_FLAG_TRUNCATE) && (cfg->flags & H3D_FLAG_KEEP_PIVOTS))
+        return invalid("truncated factors have no ACA pivots: H3D_FLAG_TRUNCATE excludes "
+                       "H3D_FLAG_KEEP_PIVOTS");
     return H3D_OK;
 }
 

@@ -17,6 +17,9 @@ void aca_level_batch(Plan &P, int level, const int32_t *list, int64_t q0, int64_
 void aca_workspace_sizes(Plan &P, const int32_t *list, int64_t cnt, int kws, int64_t *ws,
                          hipStream_t s);
 void aca_pivot_sizes(Plan &P, int64_t *kc2, hipStream_t s);
+void truncate_batch(Plan &P, const int32_t *list, int64_t q0, int64_t q1, int kws, double *ws,
+                    const int64_t *ws_off, int64_t ws_base, const int32_t *overflow,
+                    hipStream_t s);
 
 namespace {
 
@@ -415,6 +418,9 @@ void factors_build(Plan &P, hipStream_t s) {
             float ms = 0.f;
             H3D_HIP(hipEventElapsedTime(&ms, ev0, ev1));
             aca_ms += ms;
+            // optional FP64 recompression to the optimal rank at tol
+            if (P.cfg.flags & H3D_FLAG_TRUNCATE)
+                truncate_batch(P, list, q0, q1, kws, ws, ws_off, base, overflow, s);
             // pack the finished blocks of the batch into their own chunk
             const int64_t nb = q1 - q0;
             k_pack_sizes<<<grid_for(nb, 256), 256, 0, s>>>(q0, q1, list, P.blk_m, P.blk_n,

@@ -24,6 +24,7 @@ EXPORTS = {"perm": 0, "leaf_off": 1, "far": 2, "near": 3, "factors_u": 4, "facto
            "pivots": 6}
 FLAG_KEEP_PIVOTS = 1
 FLAG_NO_AUTOTUNE = 2
+FLAG_TRUNCATE = 4
 MAX_LEVELS = 11
 
 EXPORTED_SYMBOLS = (
@@ -365,7 +366,7 @@ class Graph:
 
 
 def _make_config(kernel, kernel_param, leaf_size, tol, factor_dtype, max_rank, max_depth, box_lo,
-                 box_side, workspace_bytes, keep_pivots, autotune) -> Config:
+                 box_side, workspace_bytes, keep_pivots, autotune, truncate=False) -> Config:
     cfg = default_config()
     cfg.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     cfg.kernel_param = float(kernel_param)
@@ -379,7 +380,8 @@ def _make_config(kernel, kernel_param, leaf_size, tol, factor_dtype, max_rank, m
             cfg.box_lo[a] = float(box_lo[a])
     cfg.box_side = float(box_side)
     cfg.workspace_bytes = int(workspace_bytes)
-    cfg.flags = (FLAG_KEEP_PIVOTS if keep_pivots else 0) | (0 if autotune else FLAG_NO_AUTOTUNE)
+    cfg.flags = ((FLAG_KEEP_PIVOTS if keep_pivots else 0) | (0 if autotune else FLAG_NO_AUTOTUNE)
+                 | (FLAG_TRUNCATE if truncate else 0))
     return cfg
 
 
@@ -399,13 +401,14 @@ def build(points, kernel="laplace", kernel_param: float = 1.0, leaf_size: int = 
           tol: float = 1e-8, factor_dtype="fp64", max_rank: int = 0, max_depth: int = 10,
           box_lo=None, box_side: float = 0.0, workspace_bytes: int = 0,
           keep_pivots: bool = False, use_torch_allocator: bool = True,
-          autotune: bool = True) -> Operator:
-    """Builds the HODLR3D operator of the n x 3 FP64 point cloud (moved to the GPU)."""
+          autotune: bool = True, truncate: bool = False) -> Operator:
+    """Builds the HODLR3D operator of the n x 3 FP64 point cloud (moved to the GPU).
+    truncate=True recompresses every block's ACA factors to its optimal rank at tol."""
     torch = _torch()
     lib = load_library()
     points = _device_points(points)
     cfg = _make_config(kernel, kernel_param, leaf_size, tol, factor_dtype, max_rank, max_depth,
-                       box_lo, box_side, workspace_bytes, keep_pivots, autotune)
+                       box_lo, box_side, workspace_bytes, keep_pivots, autotune, truncate)
     device = points.device.index if points.device.index is not None else torch.cuda.current_device()
     alloc = _TorchAllocator(device) if use_torch_allocator else None
     handle = ctypes.c_void_p()
