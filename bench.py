@@ -14,8 +14,9 @@ The cpu_baseline object times the CPU oracle's exact dense direct sum on a
 bounded sample of target rows of the same workload (rows per second), and
 reports the GPU result's relative error on those rows.
 
-The variants object measures the same workload with FP32 and BF16 factors
-and with 64 right-hand sides (matrix-core path), each with its relative error
+The variants object measures the same workload with FP32 and BF16 factors,
+with FP32 factors recompressed to their optimal ranks (rank truncation), and
+with 64 right-hand sides (matrix-core path), each with its relative error
 on sampled rows of the exact product and its gain over the plain FP64 form,
 and the multi-problem form: 32 independent clouds (N_i in [8192, 131072],
 FP32 factors, tol 1e-7) multiplied in one persistent launch, beside the same
@@ -201,6 +202,25 @@ def main():
             opv.close()
             del opv, xv, yv
             torch.cuda.empty_cache()
+        # FP32 factors recompressed in FP64 to their optimal ranks at tol
+        opv = hodlr3d.build(torch.as_tensor(pts, device=dev), kernel=w["kernel"],
+                            leaf_size=w["leaf_size"], tol=w["tol"], factor_dtype="fp32",
+                            box_lo=inputs.CUBE_LO, box_side=inputs.CUBE_SIDE, truncate=True)
+        for name, nr in (("fp32_trunc_1rhs", 1), ("fp32_trunc_64rhs", 64)):
+            xv = torch.as_tensor(x_np if nr == 1 else x64_np, device=dev)
+            sec, yv = time_products(opv, xv, max(3, args.steps // (4 if nr > 1 else 1)),
+                                    max(1, args.warmup // 2))
+            var_y[name] = yv.detach().cpu().numpy().reshape(n, -1)
+            variants[name] = {"factor_dtype": "fp32", "truncated": True, "nrhs": nr,
+                              "ms_per_step": round(1e3 * sec, 4), "value": round(n * nr / sec, 1),
+                              "gain_vs_fp64_1rhs": round(n * nr / sec / value, 2),
+                              "factor_bytes": opv.stats()["factor_bytes"]}
+            print(f"[bench] {name}: {1e3 * sec:.3f} ms, {n * nr / sec:.3e} {UNIT}", file=sys.stderr,
+                  flush=True)
+            del xv, yv
+        opv.close()
+        del opv
+        torch.cuda.empty_cache()
 
     # many uneven problems in one persistent launch
     batch_ys = None
