@@ -9,8 +9,9 @@
 // for FP32 and BF16 factors).  Right-hand sides are held point-major (a row of
 // NP = 16 ceil(nrhs/16) values per point) so that every B fragment is four
 // 64-byte segments.  FP32 tiles are flushed into FP64 registers every 64
-// K-steps (and after every block in stage 2), so long dot products and the
-// sums over blocks and levels carry FP64 accumulation.  The adjoint swaps
+// K-steps (in stage 2 the K loop runs over the columns of all blocks of a
+// box), so long dot products and the sums over blocks and levels carry FP64
+// accumulation.  The adjoint swaps
 // U and V and walks the blocks by source box, as in the one-column kernels.
 #include "h3d_internal.hpp"
 
@@ -203,6 +204,8 @@ __global__ void __launch_bounds__(64)
 }
 
 // ---------------------------------------------------------------------------
+// Single-tile forms (one 16-column or 16-row tile per wave; the faster form
+// when the level's work items are many and its blocks narrow).
 // stage 1: one wave per (block, 16-column tile of its factor)
 template <int DT>
 __global__ void __launch_bounds__(64)
@@ -378,12 +381,312 @@ __global__ void __launch_bounds__(64)
 }
 
 // ---------------------------------------------------------------------------
+// Wide forms.  A wave holds MT 16-row (stage 2) or 16-column (stage 1) tiles
+// against the kNT 16-wide RHS tiles, so every B fragment loaded (a row of Z
+// or X, shared by all rows or columns of the block) feeds MT MFMAs; FP32
+// tiles are flushed into FP64 every 64 K-steps.
+
+// stage 2 of one level: one wave per (box, 16 MT-row tile); the K loop runs
+// over the columns of all blocks of the box; Y updated in place
+template <int DT, int MT>
+__global__ void __launch_bounds__(64)
+    k_s2_mfma_w(const int2 *__restrict__ items, int64_t nitems, int64_t gbase,
+                const int32_t *__restrict__ leaf_off, int sh, const int64_t *__restrict__ grp_begin,
+                const int64_t *__restrict__ grp_blk, void *const *__restrict__ fptr,
+                const int32_t *__restrict__ rank, const int64_t *__restrict__ blk_col0,
+                const typename CT<DT>::T *__restrict__ Z, int NP, double *__restrict__ Y, int panel,
+                const int32_t *__restrict__ leaf_of, int shc) {
+    using C = CT<DT>;
+    using T = typename C::T;
+    using F = typename FacB<DT>::T;
+    const int64_t w = blockIdx.x;
+    if (w >= nitems)
+        return;
+    const int lane = threadIdx.x;
+    const int2 it = items[w];
+    const int64_t tb = it.x;
+    const int32_t bs = leaf_off[tb << sh], bm = leaf_off[(tb + 1) << sh] - bs;
+    const int r0 = it.y * 16 * MT;
+    int ia[MT];
+    bool ar[MT];
+    int32_t pr0[MT], pld[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+        ia[t] = r0 + 16 * t + (lane & 15);
+        ar[t] = ia[t] < bm;
+        pr0[t] = bs;
+        pld[t] = bm;
+        if (panel && ar[t]) {  // row panels: this row's chunk box
+            const int32_t ch = leaf_of[bs + ia[t]] >> shc;
+            pr0[t] = leaf_off[ch << shc];
+            pld[t] = leaf_off[(ch + 1) << shc] - pr0[t];
+        }
+    }
+    const int64_t e0 = grp_begin[gbase + tb], e1 = grp_begin[gbase + tb + 1];
+    for (int nb = 0; nb < NP; nb += 16 * kNT) {
+        const int ntl = min(kNT, (NP - nb) / 16);
+        // FP64 tiles accumulate in place from Y; FP32 tiles are flushed into acc64
+        constexpr int A64 = DT == H3D_F64 ? 1 : MT;
+        double acc64[A64][kNT][4];
+        typename C::V4 acc[MT][kNT];
+#pragma unroll
+        for (int t = 0; t < MT; ++t)
+#pragma unroll
+            for (int q = 0; q < kNT; ++q)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int r = r0 + 16 * t + C::row(lane, jj);
+                    const double y0 = (q < ntl && r < bm)
+                                          ? Y[(bs + r) * int64_t(NP) + nb + 16 * q + (lane & 15)]
+                                          : 0.0;
+                    if constexpr (DT == H3D_F64) {
+                        acc[t][q][jj] = y0;
+                    } else {
+                        acc[t][q][jj] = 0.0f;
+                        acc64[t][q][jj] = y0;
+                    }
+                }
+        int steps = 0;
+        for (int64_t e = e0; e < e1; ++e) {
+            const int64_t bi = grp_blk ? grp_blk[e] : e;
+            const int k = rank[bi];
+            const int64_t col0 = blk_col0[bi];
+            const F *__restrict__ base = static_cast<const F *>(fptr[bi]);
+            const F *p[MT];
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+                p[t] = base + (int64_t(pr0[t] - bs) * k + (bs + ia[t] - pr0[t]));
+            for (int c0 = 0; c0 < k; c0 += 4) {
+                const int c = c0 + (lane >> 4);
+                const bool ak = c < k;
+                T a[MT], bv[kNT];
+#pragma unroll
+                for (int t = 0; t < MT; ++t)
+                    a[t] = (ar[t] && ak) ? T(FacB<DT>::ld(p[t] + int64_t(c) * pld[t])) : T(0);
+#pragma unroll
+                for (int q = 0; q < kNT; ++q)
+                    bv[q] = (ak && q < ntl) ? Z[(col0 + c) * NP + nb + 16 * q + (lane & 15)] : T(0);
+#pragma unroll
+                for (int t = 0; t < MT; ++t)
+#pragma unroll
+                    for (int q = 0; q < kNT; ++q)
+                        if (q < ntl)
+                            acc[t][q] = C::mfma(a[t], bv[q], acc[t][q]);
+                if constexpr (DT != H3D_F64) {
+                    if (++steps == 64) {
+                        steps = 0;
+#pragma unroll
+                        for (int t = 0; t < MT; ++t)
+#pragma unroll
+                            for (int q = 0; q < kNT; ++q) {
+#pragma unroll
+                                for (int jj = 0; jj < 4; ++jj)
+                                    acc64[t][q][jj] += double(acc[t][q][jj]);
+                                acc[t][q] = typename C::V4{0, 0, 0, 0};
+                            }
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < MT; ++t)
+#pragma unroll
+            for (int q = 0; q < kNT; ++q)
+                if (q < ntl)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const int r = r0 + 16 * t + C::row(lane, jj);
+                        double v = double(acc[t][q][jj]);
+                        if constexpr (DT != H3D_F64)
+                            v += acc64[t][q][jj];
+                        if (r < bm)
+                            Y[(bs + r) * int64_t(NP) + nb + 16 * q + (lane & 15)] = v;
+                    }
+    }
+}
+
+// stage 1: one wave per (block, 16 MT-column tile of its factor)
+template <int DT, int MT>
+__global__ void __launch_bounds__(64)
+    k_s1_mfma_w(const int2 *__restrict__ items, int64_t nitems, const int32_t *__restrict__ seg_len,
+                const int32_t *__restrict__ seg_off, void *const *__restrict__ seg_ptr,
+                const int32_t *__restrict__ rank, const int64_t *__restrict__ blk_col0,
+                const float *__restrict__ scale2, const typename CT<DT>::T *__restrict__ Xs, int NP,
+                typename CT<DT>::T *__restrict__ Z, int panel, const int32_t *__restrict__ leaf_off,
+                const int32_t *__restrict__ leaf_of, int shc, int rows,
+                typename CT<DT>::T *__restrict__ Zp) {
+    using C = CT<DT>;
+    using T = typename C::T;
+    using F = typename FacB<DT>::T;
+    const int64_t w = blockIdx.x;
+    if (w >= nitems)
+        return;
+    const int lane = threadIdx.x;
+    const int2 it = items[w];
+    // split columns: item.y = tile + 256 part; the part's partial tile goes to Zp
+    const int tile = rows > 0 ? (it.y & 255) : it.y;
+    const int b = it.x, c0 = tile * 16 * MT;
+    const int len = seg_len[b], k = rank[b];
+    int jb = 0, je = len;
+    if (rows > 0) {
+        jb = min(len, (it.y >> 8) * rows);
+        je = min(len, jb + rows);
+    }
+    const int64_t off = seg_off[b], col0 = blk_col0[b];
+    const F *__restrict__ p = static_cast<const F *>(seg_ptr[b]);
+    double sc = 1.0;
+    if (DT == H3D_BF16_SCALED)
+        sc = double(scale2[2 * b]) * double(scale2[2 * b + 1]);
+    int ca[MT];
+    bool ac[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+        ca[t] = c0 + 16 * t + (lane & 15);
+        ac[t] = ca[t] < k;
+    }
+    for (int nb = 0; nb < NP; nb += 16 * kNT) {
+        const int ntl = min(kNT, (NP - nb) / 16);
+        constexpr int A64 = DT == H3D_F64 ? 1 : MT;
+        typename C::V4 acc[MT][kNT];
+        double acc64[A64][kNT][4];
+#pragma unroll
+        for (int t = 0; t < MT; ++t)
+#pragma unroll
+            for (int q = 0; q < kNT; ++q)
+                acc[t][q] = typename C::V4{0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < A64; ++t)
+#pragma unroll
+            for (int q = 0; q < kNT; ++q)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+                    acc64[t][q][jj] = 0.0;
+        int steps = 0;
+        for (int j0 = jb; j0 < je; j0 += 4) {
+            const int j = j0 + (lane >> 4);
+            const bool aj = j < je;
+            T a[MT], bv[kNT];
+#pragma unroll
+            for (int t = 0; t < MT; ++t) {
+                int64_t ea = int64_t(ca[t]) * len + j;
+                if (panel && ac[t] && aj)  // U_b stored as row panels (adjoint above lc)
+                    ea = panel_off(leaf_off, leaf_of, shc, int32_t(off), k, j, ca[t]);
+                a[t] = (ac[t] && aj) ? T(FacB<DT>::ld(p + ea)) : T(0);
+            }
+#pragma unroll
+            for (int q = 0; q < kNT; ++q)
+                bv[q] = (aj && q < ntl) ? Xs[(off + j) * NP + nb + 16 * q + (lane & 15)] : T(0);
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+#pragma unroll
+                for (int q = 0; q < kNT; ++q)
+                    if (q < ntl)
+                        acc[t][q] = C::mfma(a[t], bv[q], acc[t][q]);
+            if constexpr (DT != H3D_F64) {
+                if (++steps == 64) {
+                    steps = 0;
+#pragma unroll
+                    for (int t = 0; t < MT; ++t)
+#pragma unroll
+                        for (int q = 0; q < kNT; ++q) {
+#pragma unroll
+                            for (int jj = 0; jj < 4; ++jj)
+                                acc64[t][q][jj] += double(acc[t][q][jj]);
+                            acc[t][q] = typename C::V4{0, 0, 0, 0};
+                        }
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < MT; ++t)
+#pragma unroll
+            for (int q = 0; q < kNT; ++q)
+                if (q < ntl)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const int c = c0 + 16 * t + C::row(lane, jj);
+                        double v = double(acc[t][q][jj]);
+                        if constexpr (DT != H3D_F64)
+                            v += acc64[t][q][jj];
+                        if (rows > 0)  // every slot of the partial tile, in item order
+                            Zp[(w * 16 * MT + 16 * t + C::row(lane, jj)) * int64_t(NP) + nb + 16 * q +
+                               (lane & 15)] = T(v * sc);
+                        else if (c < k)
+                            Z[(col0 + c) * NP + nb + 16 * q + (lane & 15)] = T(v * sc);
+                    }
+    }
+}
+
+// split stage-1 columns: Z of every (block, column tile) = its parts' partial
+// tiles added in part order; one thread per (group, column, RHS)
+template <typename T>
+__global__ void k_s1_mfma_reduce(int64_t ngrp, const int32_t *__restrict__ grp,
+                                 const int2 *__restrict__ items, int cols,
+                                 const int32_t *__restrict__ rank,
+                                 const int64_t *__restrict__ blk_col0, const T *__restrict__ Zp,
+                                 int NP, T *__restrict__ Z) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t per = int64_t(cols) * NP;
+    const int64_t g = t / per;
+    if (g >= ngrp)
+        return;
+    const int64_t rem = t - g * per;
+    const int u = int(rem / NP), rhs = int(rem - int64_t(u) * NP);
+    const int32_t first = grp[2 * g], np = grp[2 * g + 1];
+    const int2 it = items[first];
+    const int c = (it.y & 255) * cols + u;
+    if (c >= rank[it.x])
+        return;
+    double v = 0.0;
+    for (int32_t pp = 0; pp < np; ++pp)
+        v += double(Zp[((int64_t(first) + pp) * cols + u) * NP + rhs]);
+    Z[(blk_col0[it.x] + c) * int64_t(NP) + rhs] = T(v);
+}
+
+// split items of the blocks [b0, b0 + nb): (block, tile + 256 part) with the
+// parts of a tile consecutive; one reduction group (first item, parts) per tile
+__global__ void k_cnt_split(int64_t b0, int64_t nb, const int32_t *__restrict__ rank,
+                            const int32_t *__restrict__ m, const int32_t *__restrict__ n, int cols,
+                            int rows, int64_t *__restrict__ cnt, int64_t *__restrict__ gcnt) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= nb)
+        return;
+    const int64_t b = b0 + i;
+    const int nt = (rank[b] + cols - 1) / cols;
+    const int np = max(1, (max(m[b], n[b]) + rows - 1) / rows);
+    cnt[i] = int64_t(nt) * np;
+    gcnt[i] = nt;
+}
+
+__global__ void k_fill_split(int64_t b0, int64_t nb, const int32_t *__restrict__ rank,
+                             const int32_t *__restrict__ m, const int32_t *__restrict__ n, int cols,
+                             int rows, const int64_t *__restrict__ off,
+                             const int64_t *__restrict__ goff, int32_t *__restrict__ items,
+                             int32_t *__restrict__ grp) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= nb)
+        return;
+    const int64_t b = b0 + i;
+    const int nt = (rank[b] + cols - 1) / cols;
+    const int np = max(1, (max(m[b], n[b]) + rows - 1) / rows);
+    for (int t = 0; t < nt; ++t) {
+        const int64_t f = off[i] + int64_t(t) * np;
+        grp[2 * (goff[i] + t)] = int32_t(f);
+        grp[2 * (goff[i] + t) + 1] = np;
+        for (int pp = 0; pp < np; ++pp) {
+            items[2 * (f + pp)] = int32_t(b);
+            items[2 * (f + pp) + 1] = t + 256 * pp;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // work items: (leaf, row tile), (block, column tile), (box, row tile)
 __global__ void k_cnt_rowtiles(int64_t nb, int sh, const int32_t *__restrict__ leaf_off,
-                               int64_t *__restrict__ cnt) {
+                               int tile, int64_t *__restrict__ cnt) {
     const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (b < nb)
-        cnt[b] = (leaf_off[(b + 1) << sh] - leaf_off[b << sh] + 15) / 16;
+        cnt[b] = (leaf_off[(b + 1) << sh] - leaf_off[b << sh] + tile - 1) / tile;
 }
 
 __global__ void k_fill_tiles(int64_t nb, const int64_t *__restrict__ cnt_scan,
@@ -400,10 +703,10 @@ __global__ void k_fill_tiles(int64_t nb, const int64_t *__restrict__ cnt_scan,
 }
 
 __global__ void k_cnt_coltiles(int64_t b0, int64_t nb, const int32_t *__restrict__ rank,
-                               int64_t *__restrict__ cnt) {
+                               int tile, int64_t *__restrict__ cnt) {
     const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (b < nb)
-        cnt[b] = (rank[b0 + b] + 15) / 16;
+        cnt[b] = (rank[b0 + b] + tile - 1) / tile;
 }
 
 // builds items for nb consecutive units whose tile counts are in cnt[0..nb)
@@ -421,15 +724,42 @@ int32_t *make_items(Plan &P, int64_t nb, int64_t id0, int64_t *cnt, int64_t *cou
     return items;
 }
 
+// 16-column tiles per stage-1 wave (by the level's mean rank) and 16-row
+// tiles per stage-2 wave (by the level's mean box size)
+// (measured: wider tiles pay off for FP64 tiles only; FP32 tiles carry FP64
+// flush registers as well and lose more to occupancy than they gain)
+int tiles_for(int v, int dt) {
+    if (dt != H3D_F64)
+        return 1;
+    return v >= 48 ? 4 : (v >= 24 ? 2 : 1);
+}
+
+// stage-1 columns of boxes above this size are split into parts of this many rows
+constexpr int kMfmaSplitBox = 2048;
+constexpr int kMfmaSplitRows = 1024;
+
 void ensure_batched_tables(Plan &P, hipStream_t s) {
     if (P.bt_ready)
         return;
     const int L = P.L;
+    for (int l = 1; l <= L; ++l) {
+        const int64_t nbl = P.lvl_blk[l + 1] - P.lvl_blk[l];
+        const int mean_rank = nbl > 0 ? int(P.lvl_rank_sum[l] / nbl) : 0;
+        P.bt_mt2[l] = tiles_for(P.mean_box[l], P.factor_dtype);
+        // (split items keep the tile index in 8 bits)
+        P.bt_split[l] =
+            (P.mean_box[l] > kMfmaSplitBox && P.stats.rank_max < 255 * 16) ? kMfmaSplitRows : 0;
+        // wide stage-1 tiles for wide blocks only, where they still leave
+        // enough waves (measured: four tiles help at mean rank >= 48, two do not)
+        const int t1 = tiles_for(mean_rank, P.factor_dtype) == 4 ? 4 : 1;
+        P.bt_mt1[l] = (P.bt_split[l] == 0 && nbl * ((mean_rank + 16 * t1 - 1) / (16 * t1)) >= 8192)
+                          ? t1 : 1;
+    }
     // near: (leaf, row tile)
     {
         const int64_t nl = pow8(L);
         int64_t *cnt = P.mem.alloc_n<int64_t>(nl + 1);
-        k_cnt_rowtiles<<<grid_for(nl, 256), 256, 0, s>>>(nl, 0, P.leaf_off, cnt);
+        k_cnt_rowtiles<<<grid_for(nl, 256), 256, 0, s>>>(nl, 0, P.leaf_off, 16, cnt);
         H3D_LAUNCH_CHECK();
         P.bt_near = make_items(P, nl, 0, cnt, &P.bt_nnear, s);
         P.mem.release(cnt);
@@ -439,9 +769,34 @@ void ensure_batched_tables(Plan &P, hipStream_t s) {
         const int64_t b0 = P.lvl_blk[l], nb = P.lvl_blk[l + 1] - b0;
         P.bt_s1[l] = nullptr;
         P.bt_ns1[l] = 0;
-        if (nb > 0) {
+        if (nb > 0 && P.bt_split[l] > 0) {
+            const int cols = 16 * P.bt_mt1[l];
             int64_t *cnt = P.mem.alloc_n<int64_t>(nb + 1);
-            k_cnt_coltiles<<<grid_for(nb, 256), 256, 0, s>>>(b0, nb, P.blk_rank, cnt);
+            int64_t *gcnt = P.mem.alloc_n<int64_t>(nb + 1);
+            H3D_HIP(hipMemsetAsync(cnt + nb, 0, sizeof(int64_t), s));
+            H3D_HIP(hipMemsetAsync(gcnt + nb, 0, sizeof(int64_t), s));
+            k_cnt_split<<<grid_for(nb, 256), 256, 0, s>>>(b0, nb, P.blk_rank, P.blk_m, P.blk_n,
+                                                          cols, P.bt_split[l], cnt, gcnt);
+            H3D_LAUNCH_CHECK();
+            const int64_t ni = scan_exclusive_i64(P, cnt, cnt, nb + 1, s);
+            const int64_t ng = scan_exclusive_i64(P, gcnt, gcnt, nb + 1, s);
+            int32_t *items = P.mem.alloc_n<int32_t>(2 * std::max<int64_t>(ni, 1));
+            int32_t *grp = P.mem.alloc_n<int32_t>(2 * std::max<int64_t>(ng, 1));
+            k_fill_split<<<grid_for(nb, 256), 256, 0, s>>>(b0, nb, P.blk_rank, P.blk_m, P.blk_n,
+                                                           cols, P.bt_split[l], cnt, gcnt, items,
+                                                           grp);
+            H3D_LAUNCH_CHECK();
+            H3D_HIP(hipStreamSynchronize(s));
+            P.mem.release(cnt);
+            P.mem.release(gcnt);
+            P.bt_s1[l] = items;
+            P.bt_ns1[l] = ni;
+            P.bt_grp[l] = grp;
+            P.bt_ngrp[l] = ng;
+        } else if (nb > 0) {
+            int64_t *cnt = P.mem.alloc_n<int64_t>(nb + 1);
+            k_cnt_coltiles<<<grid_for(nb, 256), 256, 0, s>>>(b0, nb, P.blk_rank,
+                                                            16 * P.bt_mt1[l], cnt);
             H3D_LAUNCH_CHECK();
             P.bt_s1[l] = make_items(P, nb, b0, cnt, &P.bt_ns1[l], s);
             P.mem.release(cnt);
@@ -449,7 +804,8 @@ void ensure_batched_tables(Plan &P, hipStream_t s) {
         // stage 2: (box, row tile) for the boxes of level l
         const int64_t nbox = pow8(l);
         int64_t *cnt = P.mem.alloc_n<int64_t>(nbox + 1);
-        k_cnt_rowtiles<<<grid_for(nbox, 256), 256, 0, s>>>(nbox, 3 * (L - l), P.leaf_off, cnt);
+        k_cnt_rowtiles<<<grid_for(nbox, 256), 256, 0, s>>>(nbox, 3 * (L - l), P.leaf_off,
+                                                          16 * P.bt_mt2[l], cnt);
         H3D_LAUNCH_CHECK();
         P.bt_s2[l] = make_items(P, nbox, 0, cnt, &P.bt_ns2[l], s);
         P.mem.release(cnt);
@@ -504,28 +860,78 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
         if (P.bt_ns1[l] == 0)
             continue;
         hipEvent_t ev = P.prof.begin(s);
-        k_s1_mfma<DT><<<int(P.bt_ns1[l]), 64, 0, s>>>(
-            reinterpret_cast<const int2 *>(P.bt_s1[l]), P.bt_ns1[l], adjoint ? P.blk_m : P.blk_n,
-            adjoint ? P.blk_toff : P.blk_soff, adjoint ? P.blk_uptr : P.blk_vptr, P.blk_rank,
-            P.blk_col0, P.blk_scale, Xs, NP, Z, int(adjoint && l < P.chunk_level), P.leaf_off,
-            P.leaf_of, 3 * (P.L - P.chunk_level));
+        // split levels: partial tiles of every row part, then their sum
+        T *Zp = nullptr;
+        if (P.bt_split[l] > 0) {
+            const size_t need = size_t(P.bt_ns1[l]) * 16 * P.bt_mt1[l] * NP * sizeof(T);
+            if (need > P.bzp_bytes) {
+                P.mem.release(P.bzp);
+                P.bzp = P.mem.alloc(need);
+                P.bzp_bytes = need;
+            }
+            Zp = static_cast<T *>(P.bzp);
+        }
+#define H3D_S1M(MT)                                                                         \
+    k_s1_mfma_w<DT, MT><<<int(P.bt_ns1[l]), 64, 0, s>>>(                                    \
+        reinterpret_cast<const int2 *>(P.bt_s1[l]), P.bt_ns1[l], adjoint ? P.blk_m : P.blk_n, \
+        adjoint ? P.blk_toff : P.blk_soff, adjoint ? P.blk_uptr : P.blk_vptr, P.blk_rank,     \
+        P.blk_col0, P.blk_scale, Xs, NP, Z, int(adjoint && l < P.chunk_level), P.leaf_off,    \
+        P.leaf_of, 3 * (P.L - P.chunk_level), P.bt_split[l], Zp)
+        if (P.bt_mt1[l] == 4)
+            H3D_S1M(4);
+        else if (P.bt_mt1[l] == 2)
+            H3D_S1M(2);
+        else if (P.bt_split[l] > 0)
+            H3D_S1M(1);
+        else
+            k_s1_mfma<DT><<<int(P.bt_ns1[l]), 64, 0, s>>>(
+                reinterpret_cast<const int2 *>(P.bt_s1[l]), P.bt_ns1[l],
+                adjoint ? P.blk_m : P.blk_n, adjoint ? P.blk_toff : P.blk_soff,
+                adjoint ? P.blk_uptr : P.blk_vptr, P.blk_rank, P.blk_col0, P.blk_scale, Xs, NP, Z,
+                int(adjoint && l < P.chunk_level), P.leaf_off, P.leaf_of,
+                3 * (P.L - P.chunk_level));
+#undef H3D_S1M
+        if (P.bt_split[l] > 0) {
+            H3D_LAUNCH_CHECK();
+            const int cols = 16 * P.bt_mt1[l];
+            const int64_t nt = P.bt_ngrp[l] * cols * NP;
+            k_s1_mfma_reduce<T><<<grid_for(nt, 256), 256, 0, s>>>(
+                P.bt_ngrp[l], P.bt_grp[l], reinterpret_cast<const int2 *>(P.bt_s1[l]), cols,
+                P.blk_rank, P.blk_col0, Zp, NP, Z);
+        }
         H3D_LAUNCH_CHECK();
         const double ent = double(adjoint ? P.lvl_entries_u[l] : P.lvl_entries_v[l]);
-        P.prof.end(s, ev, "k_s1_mfma", ent * es + double(P.lvl_rank_sum[l]) * sizeof(T) * NP,
+        char name[48];
+        snprintf(name, sizeof(name), P.prof.levels ? "k_s1_mfma_L%d" : "k_s1_mfma", l);
+        P.prof.end(s, ev, name, ent * es + double(P.lvl_rank_sum[l]) * sizeof(T) * NP,
                    2.0 * ent * NP);
     }
     for (int l = 1; l <= P.L; ++l) {
         if (P.bt_ns2[l] == 0 || P.lvl_blk[l + 1] <= P.lvl_blk[l])
             continue;
         hipEvent_t ev = P.prof.begin(s);
-        k_s2_mfma<DT><<<int(P.bt_ns2[l]), 64, 0, s>>>(
-            reinterpret_cast<const int2 *>(P.bt_s2[l]), P.bt_ns2[l], P.box_base[l], P.leaf_off,
-            3 * (P.L - l), P.tgt_begin, adjoint ? P.src_blk : nullptr,
-            adjoint ? P.blk_vptr : P.blk_uptr, P.blk_rank, P.blk_col0, Z, NP, Y,
-            int(!adjoint && l < P.chunk_level), P.leaf_of, 3 * (P.L - P.chunk_level));
+#define H3D_S2M(MT)                                                                         \
+    k_s2_mfma_w<DT, MT><<<int(P.bt_ns2[l]), 64, 0, s>>>(                                    \
+        reinterpret_cast<const int2 *>(P.bt_s2[l]), P.bt_ns2[l], P.box_base[l], P.leaf_off,   \
+        3 * (P.L - l), P.tgt_begin, adjoint ? P.src_blk : nullptr,                           \
+        adjoint ? P.blk_vptr : P.blk_uptr, P.blk_rank, P.blk_col0, Z, NP, Y,                 \
+        int(!adjoint && l < P.chunk_level), P.leaf_of, 3 * (P.L - P.chunk_level))
+        if (P.bt_mt2[l] == 4)
+            H3D_S2M(4);
+        else if (P.bt_mt2[l] == 2)
+            H3D_S2M(2);
+        else
+            k_s2_mfma<DT><<<int(P.bt_ns2[l]), 64, 0, s>>>(
+                reinterpret_cast<const int2 *>(P.bt_s2[l]), P.bt_ns2[l], P.box_base[l],
+                P.leaf_off, 3 * (P.L - l), P.tgt_begin, adjoint ? P.src_blk : nullptr,
+                adjoint ? P.blk_vptr : P.blk_uptr, P.blk_rank, P.blk_col0, Z, NP, Y,
+                int(!adjoint && l < P.chunk_level), P.leaf_of, 3 * (P.L - P.chunk_level));
+#undef H3D_S2M
         H3D_LAUNCH_CHECK();
         const double ent = double(adjoint ? P.lvl_entries_v[l] : P.lvl_entries_u[l]);
-        P.prof.end(s, ev, "k_s2_mfma",
+        char name2[48];
+        snprintf(name2, sizeof(name2), P.prof.levels ? "k_s2_mfma_L%d" : "k_s2_mfma", l);
+        P.prof.end(s, ev, name2,
                    ent * es + double(P.lvl_rank_sum[l]) * sizeof(T) * NP + double(n) * 16.0 * NP,
                    2.0 * ent * NP);
     }

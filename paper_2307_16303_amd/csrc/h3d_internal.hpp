@@ -288,6 +288,13 @@ struct Plan {
     int64_t bt_ns1[kMaxLevels + 1] = {};
     int32_t *bt_s2[kMaxLevels + 1] = {};
     int64_t bt_ns2[kMaxLevels + 1] = {};
+    int bt_mt1[kMaxLevels + 1] = {};  // 16-column tiles per stage-1 wave
+    int bt_mt2[kMaxLevels + 1] = {};  // 16-row tiles per stage-2 wave
+    int bt_split[kMaxLevels + 1] = {};  // stage-1 rows per part (0: columns not split)
+    int32_t *bt_grp[kMaxLevels + 1] = {};  // split levels: (first item, parts) per tile
+    int64_t bt_ngrp[kMaxLevels + 1] = {};
+    void *bzp = nullptr;  // partial stage-1 tiles of the split levels
+    size_t bzp_bytes = 0;
     void *bx = nullptr, *by = nullptr, *bz = nullptr;
     size_t bx_bytes = 0, by_bytes = 0, bz_bytes = 0;
 
