@@ -26,8 +26,8 @@ roofline.traffic is the dominant kernel's HBM traffic per launch from the
 hardware counters FETCH_SIZE and WRITE_SIZE (rocprofv3 --pmc, one counter per
 run, on this workload), each divided by what the same counter reads for a
 plain 2 GiB device copy (--calibration-copy).  Those figures hold for the
-sources they were taken on: if any file under csrc/ or include/ has changed
-since, traffic is null.
+sources they were taken on: if any library source that the build and the
+one-RHS product depend on has changed since, traffic is null.
 """
 from __future__ import annotations
 
@@ -55,16 +55,23 @@ DTYPE_NAMES = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
 # the library sources they were taken on (see sources_digest).
 TRAFFIC = {
     "kernel": "k_stage2", "workload": "uniform262k",
-    "fetch_kib": 11637912.9583, "fetch_scale": 0.500016,
-    "write_kib": 8200.7396, "write_scale": 1.000000,
-    "sources_sha256": "9f1081179b4d0ca668ecbffe8d9c89bbe86c3b70f19175ef8e87233946c54b50",
+    "fetch_kib": 11639801.8125, "fetch_scale": 0.500016,
+    "write_kib": 8198.5521, "write_scale": 1.000000,
+    "sources_sha256": "8d59384fb0bc6ee159a4158d8bb33bde7b8db42410ff9b550b3242389cd6c49f",
 }
 
 
+# library sources the one-RHS product does not depend on (many right-hand
+# sides, many problems, optional rank truncation)
+OTHER_PATHS = ("batched.hip", "batch.hip", "truncate.hip")
+
+
 def sources_digest() -> str:
-    """sha256 over the library's kernel sources and public header, in name order."""
+    """sha256, in name order, over the library sources and header that the build
+    and the one-RHS product of a plan depend on."""
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_2307_16303_amd", "csrc", "*")))
+    files = sorted(f for f in glob.glob(os.path.join(ROOT, "paper_2307_16303_amd", "csrc", "*"))
+                   if os.path.basename(f) not in OTHER_PATHS)
     files.append(os.path.join(ROOT, "include", "hodlr3d.h"))
     for f in files:
         h.update(os.path.basename(f).encode())
@@ -166,12 +173,22 @@ def main():
                 "kernel": dom["name"], "avg_launch_ms": round(avg_ms, 4),
                 "bytes_per_launch": dom["bytes_per_launch"]}
     kernels = {p["name"]: round(p["total_ms"] / max(p["launches"], 1), 4) for p in prof}
+    copy_gbs = None
     if args.calibration_copy:
         # 2 GiB written by the fill, then 2 GiB read and 2 GiB written by the copy
         a = torch.ones(2 ** 28, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 5 * 2 * 2 ** 31 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        print(f"[bench] device copy: {copy_gbs:.1f} GB/s (read + write)", file=sys.stderr,
+              flush=True)
         del a, b
     y_head = y.detach().cpu().numpy().reshape(n, -1)
     op.close()
@@ -326,6 +343,7 @@ def main():
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "device_copy_gbs": None if copy_gbs is None else round(copy_gbs, 1),
         "variants": variants or None,
     }
     print(json.dumps(out))
