@@ -5,6 +5,8 @@
 //                                   on the fly straight into the A operand
 //   stage1 Z_b  = V_b^T X_s         (k x n) (n x nrhs)
 //   stage2 Y_t += U_b Z_b           (m x k) (k x nrhs), level by level
+// (forward products with FP32/BF16 factors fuse both stages at the finest
+// level: k_leaf_mfma)
 // All three run on 16x16x4 MFMA tiles (FP64 MFMA for FP64 factors, FP32 MFMA
 // for FP32 and BF16 factors).  Right-hand sides are held point-major (a row of
 // NP = 16 ceil(nrhs/16) values per point) so that every B fragment is four
@@ -617,6 +619,131 @@ __global__ void __launch_bounds__(64)
     }
 }
 
+// Finest level, forward product: both stages per block in one pass, Z kept on
+// chip.  One wave per (target leaf, 16-row tile); for every block of the leaf
+// and every 16-column tile of its factors: Z (16 columns x 64 RHS) =
+// V_b^T X_s on the matrix cores, handed through wave-private LDS into the B
+// layout, then Y_t += U_b Z.  At the leaf level Z (ranks x RHS values) is
+// several times the factor bytes, and it never reaches HBM here.  FP32 tiles
+// are flushed into FP64 after every block.
+template <int DT>
+__global__ void __launch_bounds__(64)
+    k_leaf_mfma(const int2 *__restrict__ items, int64_t nitems, int64_t gbase,
+                const int32_t *__restrict__ leaf_off, const int64_t *__restrict__ grp_begin,
+                void *const *__restrict__ uptr, void *const *__restrict__ vptr,
+                const int32_t *__restrict__ rank, const int32_t *__restrict__ soff,
+                const int32_t *__restrict__ slen, const float *__restrict__ scale2,
+                const typename CT<DT>::T *__restrict__ Xs, int NP, double *__restrict__ Y) {
+    using C = CT<DT>;
+    using T = typename C::T;
+    using F = typename FacB<DT>::T;
+    __shared__ T zl[16][16 * kNT + 1];  // one Z tile: [column][RHS]
+    const int64_t w = blockIdx.x;
+    if (w >= nitems)
+        return;
+    const int lane = threadIdx.x;
+    const int2 it = items[w];
+    const int64_t t = it.x;
+    const int32_t bs = leaf_off[t], bm = leaf_off[t + 1] - bs;
+    const int r0 = it.y * 16;
+    const int ia = r0 + (lane & 15);
+    const bool ar = ia < bm;
+    const int64_t e0 = grp_begin[gbase + t], e1 = grp_begin[gbase + t + 1];
+    for (int nb = 0; nb < NP; nb += 16 * kNT) {
+        const int ntl = min(kNT, (NP - nb) / 16);
+        double acc64[kNT][4];
+        typename C::V4 acc[kNT];
+#pragma unroll
+        for (int q = 0; q < kNT; ++q) {
+            acc[q] = typename C::V4{0, 0, 0, 0};
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const int r = r0 + C::row(lane, jj);
+                acc64[q][jj] = (q < ntl && r < bm)
+                                   ? Y[(bs + r) * int64_t(NP) + nb + 16 * q + (lane & 15)]
+                                   : 0.0;
+            }
+        }
+        for (int64_t b = e0; b < e1; ++b) {
+            const int k = rank[b];
+            const int n = slen[b];
+            const int64_t so = soff[b];
+            const F *__restrict__ V = static_cast<const F *>(vptr[b]);
+            const F *__restrict__ U = static_cast<const F *>(uptr[b]);
+            T sc = T(1);
+            if (DT == H3D_BF16_SCALED)
+                sc = T(double(scale2[2 * b]) * double(scale2[2 * b + 1]));
+            for (int c0 = 0; c0 < k; c0 += 16) {
+                // stage 1: Z tile = V^T X over the source rows
+                const int ca = c0 + (lane & 15);
+                const bool ac = ca < k;
+                typename C::V4 zt[kNT];
+#pragma unroll
+                for (int q = 0; q < kNT; ++q)
+                    zt[q] = typename C::V4{0, 0, 0, 0};
+                for (int j0 = 0; j0 < n; j0 += 4) {
+                    const int j = j0 + (lane >> 4);
+                    const bool aj = j < n;
+                    const T a = (ac && aj) ? T(FacB<DT>::ld(V + int64_t(ca) * n + j)) : T(0);
+#pragma unroll
+                    for (int q = 0; q < kNT; ++q) {
+                        const T bv = (aj && q < ntl) ? Xs[(so + j) * NP + nb + 16 * q + (lane & 15)]
+                                                     : T(0);
+                        if (q < ntl)
+                            zt[q] = C::mfma(a, bv, zt[q]);
+                    }
+                }
+                // output layout -> [column][RHS] in LDS
+#pragma unroll
+                for (int q = 0; q < kNT; ++q)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj)
+                        zl[C::row(lane, jj)][16 * q + (lane & 15)] = zt[q][jj] * sc;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                // stage 2: Y tile += U Z over the tile's columns
+                const int kc = min(16, k - c0);
+                for (int s4 = 0; s4 < kc; s4 += 4) {
+                    const int c = s4 + (lane >> 4);
+                    const bool ak = c < kc;
+                    const T a = (ar && ak) ? T(FacB<DT>::ld(U + int64_t(c0 + c) * bm + ia)) : T(0);
+#pragma unroll
+                    for (int q = 0; q < kNT; ++q) {
+                        const T bv = (ak && q < ntl) ? zl[c][16 * q + (lane & 15)] : T(0);
+                        if (q < ntl)
+                            acc[q] = C::mfma(a, bv, acc[q]);
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            if constexpr (DT != H3D_F64) {
+#pragma unroll
+                for (int q = 0; q < kNT; ++q) {
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj)
+                        acc64[q][jj] += double(acc[q][jj]);
+                    acc[q] = typename C::V4{0, 0, 0, 0};
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kNT; ++q)
+            if (q < ntl)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int r = r0 + C::row(lane, jj);
+                    double v = acc64[q][jj];
+                    if constexpr (DT == H3D_F64)
+                        v += acc[q][jj];
+                    if (r < bm)
+                        Y[(bs + r) * int64_t(NP) + nb + 16 * q + (lane & 15)] = v;
+                }
+    }
+}
+
 // split stage-1 columns: Z of every (block, column tile) = its parts' partial
 // tiles added in part order; one thread per (group, column, RHS)
 template <typename T>
@@ -856,8 +983,12 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
         P.prof.end(s, ev, "k_near_mfma", double(n) * (32.0 + 16.0 * NP),
                    double(P.stats.near_pair_evals) * (10.0 + 2.0 * NP));
     }
+    // forward products with FP32/BF16 factors run both stages of the finest
+    // level in k_leaf_mfma (measured: the fused chain is latency-bound, which
+    // FP64 tiles make slower than two launches)
+    const int lfuse = (adjoint || DT == H3D_F64) ? 0 : P.L;
     for (int l = 1; l <= P.L; ++l) {
-        if (P.bt_ns1[l] == 0)
+        if (P.bt_ns1[l] == 0 || l == lfuse)
             continue;
         hipEvent_t ev = P.prof.begin(s);
         // split levels: partial tiles of every row part, then their sum
@@ -907,7 +1038,7 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
                    2.0 * ent * NP);
     }
     for (int l = 1; l <= P.L; ++l) {
-        if (P.bt_ns2[l] == 0 || P.lvl_blk[l + 1] <= P.lvl_blk[l])
+        if (P.bt_ns2[l] == 0 || P.lvl_blk[l + 1] <= P.lvl_blk[l] || l == lfuse)
             continue;
         hipEvent_t ev = P.prof.begin(s);
 #define H3D_S2M(MT)                                                                         \
@@ -934,6 +1065,19 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
         P.prof.end(s, ev, name2,
                    ent * es + double(P.lvl_rank_sum[l]) * sizeof(T) * NP + double(n) * 16.0 * NP,
                    2.0 * ent * NP);
+    }
+    if (lfuse >= 1 && P.lvl_blk[lfuse + 1] > P.lvl_blk[lfuse] && P.bt_nnear > 0) {
+        const int l = lfuse;
+        hipEvent_t ev = P.prof.begin(s);
+        k_leaf_mfma<DT><<<int(P.bt_nnear), 64, 0, s>>>(
+            reinterpret_cast<const int2 *>(P.bt_near), P.bt_nnear, P.box_base[l], P.leaf_off,
+            P.tgt_begin, P.blk_uptr, P.blk_vptr, P.blk_rank, P.blk_soff, P.blk_n, P.blk_scale, Xs,
+            NP, Y);
+        H3D_LAUNCH_CHECK();
+        const double ent = double(P.lvl_entries_u[l] + P.lvl_entries_v[l]);
+        char name[48];
+        snprintf(name, sizeof(name), P.prof.levels ? "k_leaf_mfma_L%d" : "k_leaf_mfma", l);
+        P.prof.end(s, ev, name, ent * es + double(n) * 16.0 * NP, 4.0 * ent * NP / 2.0);
     }
     {
         hipEvent_t ev = P.prof.begin(s);
