@@ -565,11 +565,41 @@ __device__ __forceinline__ void
                     const int32_t bm = leaf_off[(t + 1) << sh] - bs;
                     const int32_t loc = rr - bs;
                     const int64_t e0 = grp_begin[g], e1 = grp_begin[g + 1];
-                    for (int64_t e = e0 + wv; e < e1; e += kS2Waves) {
-                        const int64_t bi = grp_blk ? grp_blk[e] : e;
-                        const T *p = static_cast<const T *>(fptr[bi]) + loc;
-                        stage2_block<DT, NR, 4, LIVE>(p, bm, rank[bi], z + blk_col0[bi], ldz, rb, nrhs,
-                                                acc[h]);
+                    if (grp_blk) {
+                        for (int64_t e = e0 + wv; e < e1; e += kS2Waves) {
+                            const int64_t bi = grp_blk[e];
+                            const T *p = static_cast<const T *>(fptr[bi]) + loc;
+                            stage2_block<DT, NR, 4, LIVE>(p, bm, rank[bi], z + blk_col0[bi], ldz, rb,
+                                                          nrhs, acc[h]);
+                        }
+                    } else if (e1 > e0) {
+                        // The blocks of a target box are consecutive, and so are their
+                        // z columns: wave wv takes columns [cb, ce) of the box's K.
+                        // When the U_b also lie back to back (one ACA batch), they form
+                        // one bm x K matrix, streamed as such; otherwise the same column
+                        // range is walked block by block, so that the sums, and their
+                        // order, do not depend on how the factors were batched.
+                        const int64_t zc0 = blk_col0[e0];
+                        const int kt = int(blk_col0[e1] - zc0);
+                        const int cb = (kt * wv) / kS2Waves, ce = (kt * (wv + 1)) / kS2Waves;
+                        const T *pf = static_cast<const T *>(fptr[e0]);
+                        const T *pl = static_cast<const T *>(fptr[e1 - 1]);
+                        if (pl + int64_t(bm) * rank[e1 - 1] == pf + int64_t(bm) * kt) {
+                            stage2_block<DT, NR, 8, LIVE>(pf + loc + int64_t(cb) * bm, bm, ce - cb,
+                                                          z + zc0 + cb, ldz, rb, nrhs, acc[h]);
+                        } else {
+                            for (int64_t e = e0; e < e1; ++e) {
+                                const int c0 = int(blk_col0[e] - zc0);
+                                if (c0 >= ce)
+                                    break;
+                                const int lo = max(cb, c0), hi = min(ce, c0 + rank[e]);
+                                if (lo < hi)
+                                    stage2_block<DT, NR, 8, LIVE>(
+                                        static_cast<const T *>(fptr[e]) + loc +
+                                            int64_t(lo - c0) * bm,
+                                        bm, hi - lo, z + zc0 + lo, ldz, rb, nrhs, acc[h]);
+                            }
+                        }
                     }
                 }
                 // combine the waves' partial sums in a fixed order
