@@ -254,6 +254,8 @@ struct Plan {
     int64_t s1_ngrp[kMaxLevels + 1] = {};
     double *s1_zp[kMaxLevels + 1] = {};
     int s2_waves[2] = {4, 4};                    // waves per stage-2 chunk box
+    int leaf_fuse = -1;  // one RHS: lanes per column of the fused finest level
+                         // (0: not fused, -1: chosen from the leaf size)
     bool tuned[2] = {false, false};
     int64_t lvl_rank_sum[kMaxLevels + 1] = {0};
     int chunk_level = 0;           // stage-2 boxes: about 64 rows per wave

@@ -29,6 +29,18 @@ def uniform_points(n: int, seed: int = 0) -> np.ndarray:
     return np.ascontiguousarray(np.random.default_rng(seed).uniform(-1.0, 1.0, (n, 3)))
 
 
+def clustered_points(n_uniform: int, n_ball: int, radius: float = 0.05,
+                     centre=(0.3, -0.2, 0.1), seed: int = 0) -> np.ndarray:
+    """n_uniform points uniform in [-1,1]^3 followed by n_ball points uniform in a ball
+    (a dense cluster: the tree then mixes nearly empty leaves with full ones)."""
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(-1.0, 1.0, (n_uniform, 3))
+    d = rng.standard_normal((n_ball, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    b = np.asarray(centre) + radius * np.cbrt(rng.uniform(0.0, 1.0, (n_ball, 1))) * d
+    return np.ascontiguousarray(np.concatenate([u, b], axis=0))
+
+
 def uniform_rhs(n: int, seed: int = 0, nrhs: int | None = None) -> np.ndarray:
     shape = (n,) if nrhs is None else (n, nrhs)
     return np.random.default_rng(seed).uniform(-1.0, 1.0, shape)

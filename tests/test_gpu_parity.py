@@ -58,6 +58,10 @@ CASES = {
                                 dict(leaf_size=8, tol=1e-7)),
     "uniform3000_leaf100": (lambda: inputs.uniform_points(3000, 3),
                             dict(leaf_size=100, tol=1e-9, **CUBE)),
+    # mostly tiny leaves with a cluster of full ones: the finest level in one
+    # fused pass, with leaves of more than 16 rows taken in several row passes
+    "clustered8k_leaf64": (lambda: inputs.clustered_points(6000, 2000, seed=4),
+                           dict(leaf_size=64, tol=1e-8, **CUBE)),
 }
 
 
