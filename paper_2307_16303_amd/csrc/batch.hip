@@ -157,8 +157,9 @@ __global__ void __launch_bounds__(64)
             }
             if (kind == kSegNear) {
                 for (int64_t i = i0; i < i1; ++i)
-                    near_leaf<1, true>(i, D.leaf_off, D.near_ptr, D.near_s, D.px, D.py, D.pz,
-                                       D.kind, D.kp, nrhs, D.xp, D.n, D.yn);
+                    near_leaf<1, true, DT != H3D_F64>(i, D.leaf_off, D.near_ptr, D.near_s, D.px,
+                                                      D.py, D.pz, D.kind, D.kp, nrhs, D.xp,
+                                                      D.n, D.yn);
             } else {
                 const S1Args &a = D.s1[sg.level];
                 switch (sg.shape) {

@@ -15,7 +15,7 @@
 // box), so long dot products and the sums over blocks and levels carry FP64
 // accumulation.  The adjoint swaps
 // U and V and walks the blocks by source box, as in the one-column kernels.
-#include "h3d_internal.hpp"
+#include "product_items.hpp"
 
 namespace h3d {
 
@@ -58,43 +58,6 @@ template <> struct CT<H3D_F64> {
     }
     static __device__ __forceinline__ int row(int lane, int j) { return 4 * j + (lane >> 4); }
 };
-
-__device__ __forceinline__ double kernel_f(int kind, double kp, double r) {
-    if (r == 0.0)
-        return 0.0;
-    switch (kind) {
-    case H3D_LAPLACE:
-        return 1.0 / (4.0 * 3.14159265358979323846 * r);
-    case H3D_YUKAWA:
-        return exp(-kp * r) / r;
-    case H3D_INV_R4: {
-        double r2 = r * r;
-        return 1.0 / (r2 * r2);
-    }
-    case H3D_COS_R:
-        return cos(kp * r) / r;
-    default:
-        return 0.0;
-    }
-}
-
-__device__ __forceinline__ float kernel_f32(int kind, float kp, float r2) {
-    if (r2 == 0.0f)
-        return 0.0f;
-    const float ir = __frsqrt_rn(r2);
-    switch (kind) {
-    case H3D_LAPLACE:
-        return ir * 0.0795774715459476679f;  // 1/(4 pi)
-    case H3D_YUKAWA:
-        return __expf(-kp * r2 * ir) * ir;
-    case H3D_INV_R4:
-        return ir * ir * ir * ir;
-    case H3D_COS_R:
-        return __cosf(kp * r2 * ir) * ir;
-    default:
-        return 0.0f;
-    }
-}
 
 constexpr int kNT = 4;  // 16-wide RHS tiles per pass (64 columns)
 
@@ -177,9 +140,9 @@ __global__ void __launch_bounds__(64)
                     if (ai && j < ns && gj != gi) {
                         const double dx = xi - px[gj], dy = yi - py[gj], dz = zi - pz[gj];
                         if (DT == H3D_F64)
-                            a[u] = T(kernel_f(kind, kp, sqrt(dx * dx + dy * dy + dz * dz)));
+                            a[u] = T(dev::kernel_f(kind, kp, sqrt(dx * dx + dy * dy + dz * dz)));
                         else
-                            a[u] = T(kernel_f32(kind, float(kp), float(dx * dx + dy * dy + dz * dz)));
+                            a[u] = T(dev::kernel_f32(kind, float(kp), float(dx * dx + dy * dy + dz * dz)));
                     }
 #pragma unroll
                     for (int q = 0; q < kNT; ++q)

@@ -36,13 +36,14 @@ __global__ void k_gather(const void *__restrict__ x, int io_f32, int64_t ldx, in
 }
 
 // near field: one wave per leaf
-template <int NR>
+template <int NR, bool E32>
 __global__ void __launch_bounds__(64)
     k_near(const int32_t *__restrict__ leaf_off, const int32_t *__restrict__ near_ptr,
            const int32_t *__restrict__ near_s, const double *__restrict__ px,
            const double *__restrict__ py, const double *__restrict__ pz, int kind, double kp,
            int nrhs, const double *__restrict__ xp, int64_t n, double *__restrict__ yn) {
-    near_leaf<NR>(blockIdx.x, leaf_off, near_ptr, near_s, px, py, pz, kind, kp, nrhs, xp, n, yn);
+    near_leaf<NR, false, E32>(blockIdx.x, leaf_off, near_ptr, near_s, px, py, pz, kind, kp, nrhs,
+                              xp, n, yn);
 }
 
 // stage 1: one work item per wave
@@ -632,8 +633,15 @@ void autotune_dt(Plan &P, int nrhs, hipStream_t s) {
 template <int NR>
 void launch_near(Plan &P, int nrhs, const double *xp, double *yn, hipStream_t s) {
     hipEvent_t ev = P.prof.begin(s);
-    k_near<NR><<<int(pow8(P.L)), 64, 0, s>>>(P.leaf_off, P.near_ptr, P.near_s, P.px, P.py, P.pz,
-                                              P.cfg.kernel, P.cfg.kernel_param, nrhs, xp, P.n, yn);
+    // the FP32 and BF16 forms evaluate the near-field entries in FP32
+    if (P.factor_dtype == H3D_F64)
+        k_near<NR, false><<<int(pow8(P.L)), 64, 0, s>>>(P.leaf_off, P.near_ptr, P.near_s, P.px,
+                                                         P.py, P.pz, P.cfg.kernel,
+                                                         P.cfg.kernel_param, nrhs, xp, P.n, yn);
+    else
+        k_near<NR, true><<<int(pow8(P.L)), 64, 0, s>>>(P.leaf_off, P.near_ptr, P.near_s, P.px,
+                                                        P.py, P.pz, P.cfg.kernel,
+                                                        P.cfg.kernel_param, nrhs, xp, P.n, yn);
     H3D_LAUNCH_CHECK();
     P.prof.end(s, ev, "k_near", double(P.n) * (32.0 + 8.0 * nrhs),
                double(P.stats.near_pair_evals) * (10.0 + 2.0 * nrhs));

@@ -71,6 +71,27 @@ __device__ __forceinline__ double kernel_f(int kind, double kp, double r) {
     }
 }
 
+// Kernel entry in FP32 from the squared distance (the FP32 and BF16 forms):
+// one reciprocal square root; 0 at r = 0.  The squared distance comes from
+// FP64 coordinate differences, so it is symmetric in the two points.
+__device__ __forceinline__ float kernel_f32(int kind, float kp, float r2) {
+    if (r2 == 0.0f)
+        return 0.0f;
+    const float ir = __frsqrt_rn(r2);
+    switch (kind) {
+    case H3D_LAPLACE:
+        return ir * 0.0795774715459476679f;  // 1/(4 pi)
+    case H3D_YUKAWA:
+        return __expf(-kp * r2 * ir) * ir;
+    case H3D_INV_R4:
+        return ir * ir * ir * ir;
+    case H3D_COS_R:
+        return __cosf(kp * r2 * ir) * ir;
+    default:
+        return 0.0f;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // xp[:, p] = x[perm[p], :] for one sorted row p < n
 __device__ __forceinline__ void gather_row(const void *__restrict__ x, int io_f32, int64_t ldx,
@@ -89,7 +110,9 @@ __device__ __forceinline__ void gather_row(const void *__restrict__ x, int io_f3
 // slice q of Q = 64/R); sources staged through LDS in chunks of kChunk points
 constexpr int kChunk = 256;
 
-template <int NR, bool LIVE = false>
+// E32: kernel entries evaluated in FP32 (forms with FP32 or BF16 factors),
+// accumulated in FP64
+template <int NR, bool LIVE = false, bool E32 = false>
 __device__ __forceinline__ void near_leaf(int64_t t, const int32_t *__restrict__ leaf_off,
                                           const int32_t *__restrict__ near_ptr,
                                           const int32_t *__restrict__ near_s,
@@ -144,7 +167,9 @@ __device__ __forceinline__ void near_leaf(int64_t t, const int32_t *__restrict__
                             if (gj == gi)
                                 continue;
                             const double dx = xi - sx[j], dy = yi - sy[j], dz = zi - sz[j];
-                            const double f = kernel_f(kind, kp, sqrt(dx * dx + dy * dy + dz * dz));
+                            const double r2 = dx * dx + dy * dy + dz * dz;
+                            const double f = E32 ? double(kernel_f32(kind, float(kp), float(r2)))
+                                                 : kernel_f(kind, kp, sqrt(r2));
 #pragma unroll
                             for (int c = 0; c < NR; ++c)
                                 acc[c] += f * sv[c][j];
