@@ -191,13 +191,6 @@ struct LeafArgs {
 // Global-memory load of a factor entry through a pointer that the compiler
 // cannot place itself (it was read from LDS): without the address space the
 // load would be a flat one, which also waits on the LDS counter.
-// Raw global-memory load of a factor entry through a pointer that the
-// compiler cannot place itself (it was read from LDS): without the address
-// space the load would be a flat one, which also waits on the LDS counter.
-template <class T> __device__ __forceinline__ T ld_global(const T *p) {
-    return *(const __attribute__((address_space(1))) T *)p;
-}
-
 // v + the value of the lane given by a DPP row permutation (CTRL), on both
 // halves of a double
 template <int CTRL> __device__ __forceinline__ double dpp_add(double v) {
@@ -273,11 +266,11 @@ __global__ void __launch_bounds__(256) k_leaf(LeafArgs a) {
 #pragma unroll
                     for (int t = 0; t < UR; ++t) {
                         const int64_t cc = min(c + t, k - 1);
-                        vr[t] = ld_global(bp + cc * len + rv);
+                        vr[t] = fac_raw<DT>(bp + cc * len + rv);
 #pragma unroll
                         for (int h = 0; h < RM; ++h)
                             if (ro + h * S < mo)  // wave-uniform
-                                ur[t][h] = ld_global(ap + cc * mo + min(ro + h * S + r, mo - 1));
+                                ur[t][h] = fac_raw<DT>(ap + cc * mo + min(ro + h * S + r, mo - 1));
                     }
 #pragma unroll
                     for (int t = 0; t < UR; ++t) {
@@ -285,7 +278,7 @@ __global__ void __launch_bounds__(256) k_leaf(LeafArgs a) {
                         double zs = on ? Fac<DT>::cvt(vr[t]) * x0 : 0.0;
                         if (len > S && on)
                             for (int jr = r + S; jr < len; jr += S)
-                                zs += Fac<DT>::cvt(ld_global(bp + int64_t(c + t) * len + jr)) * xq[jr];
+                                zs += fac_ld<DT>(bp + int64_t(c + t) * len + jr) * xq[jr];
                         zs = group_sum<S>(zs);
                         if (DT == H3D_BF16_SCALED)
                             zs *= double(s_sc[wv][jb]);

@@ -31,12 +31,20 @@ template <> struct Fac<H3D_BF16_SCALED> {
         return double(__uint_as_float(uint32_t(v) << 16));
     }
 };
+// Factor pointers come from tables in memory, where the compiler cannot see
+// that they address global memory: without the address space every factor
+// load would be a flat load, which also waits on the LDS/scalar counter.
+template <int DT, bool NT = false>
+__device__ __forceinline__ typename Fac<DT>::T fac_raw(const typename Fac<DT>::T *p) {
+    using G = const __attribute__((address_space(1))) typename Fac<DT>::T;
+    if constexpr (NT)
+        return __builtin_nontemporal_load((G *)p);
+    else
+        return *(G *)p;
+}
 template <int DT, bool NT = false>
 __device__ __forceinline__ double fac_ld(const typename Fac<DT>::T *p) {
-    if constexpr (NT)
-        return Fac<DT>::cvt(__builtin_nontemporal_load(p));
-    else
-        return Fac<DT>::cvt(*p);
+    return Fac<DT>::cvt(fac_raw<DT, NT>(p));
 }
 
 // Reads of data that another wave of the same launch may have written (the
@@ -267,12 +275,16 @@ __device__ __forceinline__ void s1_wide_item(const S1Args &a, int64_t w) {
 #pragma unroll
                 for (int q = 0; q < NR; ++q)
                     xv[q] = (NR == 1 || rb + q < a.nrhs) ? rd<LIVE>(xp + (rb + q) * a.n + off + j) : 0.0;
+                // every load is issued, from a column clamped into the item
+                // (cend > cb here); columns past the item drop the value
+                T vr[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    vr[u] = fac_raw<DT>(p + int64_t(min(cb + sub + u * NS, cend - 1)) * len + j);
                 double v[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int c = cb + sub + u * NS;
-                    v[u] = c < cend ? fac_ld<DT>(p + int64_t(c) * len + j) : 0.0;
-                }
+                for (int u = 0; u < U; ++u)
+                    v[u] = cb + sub + u * NS < cend ? Fac<DT>::cvt(vr[u]) : 0.0;
 #pragma unroll
                 for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -311,10 +323,10 @@ __device__ __forceinline__ void s1_packed_item(const S1Args &a, int64_t w) {
     const int r = lane % S, sub = lane / S;
     const bool valid = sub < item.y;
     const int b = item.x + (valid ? sub : 0);
-    const int len = valid ? a.seg_len[b] : 0;
+    const int k = valid ? a.rank[b] : 0;
+    const int len = k > 0 ? a.seg_len[b] : 0;  // no rows, so no loads, without columns
     const int64_t off = a.seg_off[b];
     const int64_t col0 = a.blk_col0[b];
-    const int k = valid ? a.rank[b] : 0;
     const T *__restrict__ p = static_cast<const T *>(a.seg_ptr[b]);
     double sc = 1.0;
     if (DT == H3D_BF16_SCALED)
@@ -332,15 +344,21 @@ __device__ __forceinline__ void s1_packed_item(const S1Args &a, int64_t w) {
 #pragma unroll
                 for (int q = 0; q < NR; ++q)
                     acc[u][q] = 0.0;
-            for (int j = r; j < len; j += S) {
+            const int jend = cb < k ? len : 0;  // this block's columns are done
+            for (int j = r; j < jend; j += S) {
                 double xv[NR];
 #pragma unroll
                 for (int q = 0; q < NR; ++q)
                     xv[q] = (NR == 1 || rb + q < a.nrhs) ? rd<LIVE>(xp + (rb + q) * a.n + off + j) : 0.0;
+                // k > cb here: columns clamped into the block, every load issued
+                T vr[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    vr[u] = fac_raw<DT>(p + int64_t(min(cb + u, k - 1)) * len + j);
                 double v[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    v[u] = cb + u < k ? fac_ld<DT>(p + int64_t(cb + u) * len + j) : 0.0;
+                    v[u] = cb + u < k ? Fac<DT>::cvt(vr[u]) : 0.0;
 #pragma unroll
                 for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -409,10 +427,15 @@ __device__ __forceinline__ void s1_panel_item(const S1Args &a, const int32_t *__
                 for (int q = 0; q < NR; ++q)
                     xv[q] = (NR == 1 || rb + q < a.nrhs) ? rd<LIVE>(xp + (rb + q) * a.n + r0 + j)
                                                          : 0.0;
+                // cb < k: columns clamped into the block, every load issued
+                T vr[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    vr[u] = fac_raw<DT>(pj + int64_t(min(cb + u, k - 1)) * mj + j);
                 double v[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    v[u] = cb + u < k ? fac_ld<DT>(pj + int64_t(cb + u) * mj + j) : 0.0;
+                    v[u] = cb + u < k ? Fac<DT>::cvt(vr[u]) : 0.0;
 #pragma unroll
                 for (int u = 0; u < U; ++u)
 #pragma unroll
