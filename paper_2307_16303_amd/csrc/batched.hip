@@ -24,19 +24,20 @@ namespace {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// factor loads (global-address loads: the pointers come from block tables)
 template <int DT> struct FacB;
 template <> struct FacB<H3D_F64> {
     using T = double;
-    static __device__ __forceinline__ double ld(const T *p) { return *p; }
+    static __device__ __forceinline__ double ld(const T *p) { return dev::fac_raw<H3D_F64>(p); }
 };
 template <> struct FacB<H3D_F32> {
     using T = float;
-    static __device__ __forceinline__ float ld(const T *p) { return *p; }
+    static __device__ __forceinline__ float ld(const T *p) { return dev::fac_raw<H3D_F32>(p); }
 };
 template <> struct FacB<H3D_BF16_SCALED> {
     using T = uint16_t;
     static __device__ __forceinline__ float ld(const T *p) {
-        return __uint_as_float(uint32_t(*p) << 16);
+        return __uint_as_float(uint32_t(dev::fac_raw<H3D_BF16_SCALED>(p)) << 16);
     }
 };
 
