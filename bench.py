@@ -26,8 +26,9 @@ roofline.traffic is the dominant kernel's HBM traffic per launch from the
 hardware counters FETCH_SIZE and WRITE_SIZE (rocprofv3 --pmc, one counter per
 run, on this workload), each divided by what the same counter reads for a
 plain 2 GiB device copy (--calibration-copy).  Those figures hold for the
-sources they were taken on: if any library source that the build and the
-one-RHS product depend on has changed since, traffic is null.
+sources they were taken on: if any library source that the dominant kernel's
+code, its launch or the factor layout depends on has changed since, traffic
+is null.
 """
 from __future__ import annotations
 
@@ -55,20 +56,21 @@ DTYPE_NAMES = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
 # the library sources they were taken on (see sources_digest).
 TRAFFIC = {
     "kernel": "k_stage2", "workload": "uniform262k",
-    "fetch_kib": 11639801.8125, "fetch_scale": 0.500016,
-    "write_kib": 8198.5521, "write_scale": 1.000000,
-    "sources_sha256": "8d59384fb0bc6ee159a4158d8bb33bde7b8db42410ff9b550b3242389cd6c49f",
+    "fetch_kib": 10100750.4792, "fetch_scale": 0.500005,
+    "write_kib": 8200.8125, "write_scale": 1.000000,
+    "sources_sha256": "becd76a476148780a93938b88f03d8a2188acad9674161e690c4c217870a14d9",
 }
 
 
-# library sources the one-RHS product does not depend on (many right-hand
-# sides, many problems, optional rank truncation)
-OTHER_PATHS = ("batched.hip", "batch.hip", "truncate.hip")
+# library sources of kernels launched on their own, which the counter readings
+# of the dominant kernel do not depend on (many right-hand sides, many
+# problems, optional rank truncation, the fused finest level)
+OTHER_PATHS = ("batched.hip", "batch.hip", "truncate.hip", "leaf.hip")
 
 
 def sources_digest() -> str:
-    """sha256, in name order, over the library sources and header that the build
-    and the one-RHS product of a plan depend on."""
+    """sha256, in name order, over the library sources and header that the
+    dominant kernel's code and launch and the factor layout depend on."""
     h = hashlib.sha256()
     files = sorted(f for f in glob.glob(os.path.join(ROOT, "paper_2307_16303_amd", "csrc", "*"))
                    if os.path.basename(f) not in OTHER_PATHS)

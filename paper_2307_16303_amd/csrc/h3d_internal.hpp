@@ -308,6 +308,13 @@ struct Plan {
 // products with at least this many right-hand sides use the matrix cores
 constexpr int64_t kBatchedMinRhs = 8;
 
+// Fused finest level of a one-RHS product (leaf.hip): rows of an output leaf
+// per pass, and the launch of shape (lanes per column) | (columns in flight
+// << 8), adding the level's far field into the sorted sums yn.
+constexpr int kLeafRows = 16;
+void launch_leaf(const Plan &P, int shape, bool adjoint, const double *xp, double *yn,
+                 hipStream_t s);
+
 // Row panels.  Stage 2 gives one workgroup to each box of the chunk level lc
 // and streams, for every coarser level, the rows of U_b that fall in that
 // box.  So the U_b of a block whose level lies above lc is stored as one
