@@ -108,14 +108,23 @@ __global__ void __launch_bounds__(256) k_leaf(LeafArgs a) {
                 // Every block has m, n >= 1, and k >= 1 inside the column loop:
                 // indexes are clamped into the block, so every load is issued
                 // unconditionally, and lanes off the block then drop the value.
-                const int rv = min(r, len - 1);
-                const double x0 = r < len ? xq[rv] : 0.0;
+                // A lane takes the input rows r + h S (h < RM) of each column,
+                // and any further rows of a taller leaf in a loop.
+                int rv[RM];
+                double x0[RM];
+#pragma unroll
+                for (int h = 0; h < RM; ++h) {
+                    rv[h] = min(r + h * S, len - 1);
+                    x0[h] = r + h * S < len ? xq[rv[h]] : 0.0;
+                }
                 for (int c = 0; c < k; c += UR) {
-                    T vr[UR], ur[UR][RM];
+                    T vr[UR][RM], ur[UR][RM];
 #pragma unroll
                     for (int t = 0; t < UR; ++t) {
                         const int64_t cc = min(c + t, k - 1);
-                        vr[t] = fac_raw<DT>(bp + cc * len + rv);
+#pragma unroll
+                        for (int h = 0; h < RM; ++h)
+                            vr[t][h] = fac_raw<DT>(bp + cc * len + rv[h]);
 #pragma unroll
                         for (int h = 0; h < RM; ++h)
                             if (ro + h * S < mo)  // wave-uniform
@@ -124,9 +133,12 @@ __global__ void __launch_bounds__(256) k_leaf(LeafArgs a) {
 #pragma unroll
                     for (int t = 0; t < UR; ++t) {
                         const bool on = c + t < k;
-                        double zs = on ? Fac<DT>::cvt(vr[t]) * x0 : 0.0;
-                        if (len > S && on)
-                            for (int jr = r + S; jr < len; jr += S)
+                        double zs = 0.0;
+#pragma unroll
+                        for (int h = 0; h < RM; ++h)
+                            zs += on ? Fac<DT>::cvt(vr[t][h]) * x0[h] : 0.0;
+                        if (len > kLeafRows && on)
+                            for (int jr = r + kLeafRows; jr < len; jr += S)
                                 zs += fac_ld<DT>(bp + int64_t(c + t) * len + jr) * xq[jr];
                         zs = group_sum<S>(zs);
                         if (DT == H3D_BF16_SCALED)
@@ -182,7 +194,8 @@ void launch_leaf_dt(const Plan &P, int shape, bool adjoint, const double *xp, do
     case (S_) | ((U_) << 8):                                                                \
         k_leaf<DT, S_, U_><<<grid, 256, 0, s>>>(a);                                         \
         break;
-        H3D_LEAF(8, 4)
+        H3D_LEAF(8, 2)
+        H3D_LEAF(8, 3)
         H3D_LEAF(16, 2)
         H3D_LEAF(16, 3)
 #undef H3D_LEAF

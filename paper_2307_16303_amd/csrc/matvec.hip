@@ -164,7 +164,7 @@ int leaf_shape(const Plan &P) {
         return 0;
     if (P.leaf_fuse >= 0)
         return P.leaf_fuse;
-    return P.mean_box[P.L] <= kLeafRows ? (16 | (3 << 8)) : 0;
+    return P.mean_box[P.L] <= kLeafRows ? (8 | (3 << 8)) : 0;
 }
 
 template <int DT, int NR>
@@ -418,7 +418,7 @@ void autotune_dt(Plan &P, int nrhs, hipStream_t s) {
     if (NR == 1 && !P.in_batch && P.lvl_blk[P.L + 1] > P.lvl_blk[P.L]) {
         int best_s = 0;
         float best_f = 1e30f;
-        for (int S : {0, 8 | (4 << 8), 16 | (2 << 8), 16 | (3 << 8)}) {
+        for (int S : {0, 8 | (2 << 8), 8 | (3 << 8), 16 | (2 << 8), 16 | (3 << 8)}) {
             P.leaf_fuse = S;
             const float ms = time_it([&] {
                 launch_far<DT, 1>(P, false, 1, P.xp, P.z, P.yp, P.yp + P.n, P.n, 0, s);
