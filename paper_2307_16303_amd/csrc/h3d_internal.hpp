@@ -314,6 +314,10 @@ constexpr int64_t kBatchedMinRhs = 8;
 constexpr int kLeafRows = 16;
 void launch_leaf(const Plan &P, int shape, bool adjoint, const double *xp, double *yn,
                  hipStream_t s);
+// the shape a one-RHS product of P uses (0: the finest level runs in the two
+// stages), and the shapes the autotuner tries (0 among them)
+int leaf_shape(const Plan &P);
+std::vector<int> leaf_candidates();
 
 // Row panels.  Stage 2 gives one workgroup to each box of the chunk level lc
 // and streams, for every coarser level, the rows of U_b that fall in that

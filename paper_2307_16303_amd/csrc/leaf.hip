@@ -208,6 +208,18 @@ void launch_leaf_dt(const Plan &P, int shape, bool adjoint, const double *xp, do
 
 }  // namespace
 
+int leaf_shape(const Plan &P) {
+    if (P.in_batch || P.L < 1 || P.lvl_blk[P.L + 1] <= P.lvl_blk[P.L])
+        return 0;
+    if (P.leaf_fuse >= 0)
+        return P.leaf_fuse;
+    return P.mean_box[P.L] <= kLeafRows ? (8 | (3 << 8)) : 0;
+}
+
+std::vector<int> leaf_candidates() {
+    return {0, 8 | (2 << 8), 8 | (3 << 8), 16 | (2 << 8), 16 | (3 << 8)};
+}
+
 void launch_leaf(const Plan &P, int shape, bool adjoint, const double *xp, double *yn,
                  hipStream_t s) {
     switch (P.factor_dtype) {

@@ -157,16 +157,6 @@ __global__ void __launch_bounds__(512)
                                    ypart);
 }
 
-// Launch shape of the fused finest level for one right-hand side (0: the
-// finest level runs through the two stages like the others).
-int leaf_shape(const Plan &P) {
-    if (P.in_batch || P.L < 1 || P.lvl_blk[P.L + 1] <= P.lvl_blk[P.L])
-        return 0;
-    if (P.leaf_fuse >= 0)
-        return P.leaf_fuse;
-    return P.mean_box[P.L] <= kLeafRows ? (8 | (3 << 8)) : 0;
-}
-
 template <int DT, int NR>
 void launch_s2_kernel(int waves, int64_t nchunk, hipStream_t s, const S2Tab &tab, const Plan &P,
                       const int64_t *grp_blk, void *const *fptr, const double *z, const double *yn,
@@ -418,7 +408,7 @@ void autotune_dt(Plan &P, int nrhs, hipStream_t s) {
     if (NR == 1 && !P.in_batch && P.lvl_blk[P.L + 1] > P.lvl_blk[P.L]) {
         int best_s = 0;
         float best_f = 1e30f;
-        for (int S : {0, 8 | (2 << 8), 8 | (3 << 8), 16 | (2 << 8), 16 | (3 << 8)}) {
+        for (int S : leaf_candidates()) {
             P.leaf_fuse = S;
             const float ms = time_it([&] {
                 launch_far<DT, 1>(P, false, 1, P.xp, P.z, P.yp, P.yp + P.n, P.n, 0, s);
