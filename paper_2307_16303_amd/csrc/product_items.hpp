@@ -478,18 +478,20 @@ template <int DT, int NR, int U2, bool LIVE = false>
 __device__ __forceinline__ void stage2_block(const typename Fac<DT>::T *__restrict__ p, int bm, int k,
                                              const double *__restrict__ zz, int64_t ldz, int rb,
                                              int nrhs, double (&acc)[NR]) {
+    // raw values in flight (one register each for FP32/BF16), converted at use
+    using T = typename Fac<DT>::T;
     int c = 0;
     for (; c + U2 <= k; c += U2) {
-        double v[U2];
+        T v[U2];
 #pragma unroll
         for (int u = 0; u < U2; ++u)
-            v[u] = fac_ld<DT, kS2NonTemporal>(p + int64_t(c + u) * bm);
+            v[u] = fac_raw<DT, kS2NonTemporal>(p + int64_t(c + u) * bm);
 #pragma unroll
         for (int u = 0; u < U2; ++u)
 #pragma unroll
             for (int q = 0; q < NR; ++q)
                 if (NR == 1 || rb + q < nrhs)
-                    acc[q] += v[u] * rd<LIVE>(zz + (rb + q) * ldz + c + u);
+                    acc[q] += Fac<DT>::cvt(v[u]) * rd<LIVE>(zz + (rb + q) * ldz + c + u);
     }
     for (; c < k; ++c) {
         const double v = fac_ld<DT, kS2NonTemporal>(p + int64_t(c) * bm);
@@ -507,13 +509,14 @@ __device__ __forceinline__ void stage2_block2(const typename Fac<DT>::T *__restr
                                               int bm, int k, const double *__restrict__ zz,
                                               int64_t ldz, int rb, int nrhs, double (&a0)[NR],
                                               double (&a1)[NR]) {
+    using T = typename Fac<DT>::T;
     int c = 0;
     for (; c + U2 <= k; c += U2) {
-        double v[U2], w[U2];
+        T v[U2], w[U2];
 #pragma unroll
         for (int u = 0; u < U2; ++u) {
-            v[u] = fac_ld<DT, kS2NonTemporal>(p + int64_t(c + u) * bm);
-            w[u] = fac_ld<DT, kS2NonTemporal>(p + d + int64_t(c + u) * bm);
+            v[u] = fac_raw<DT, kS2NonTemporal>(p + int64_t(c + u) * bm);
+            w[u] = fac_raw<DT, kS2NonTemporal>(p + d + int64_t(c + u) * bm);
         }
 #pragma unroll
         for (int u = 0; u < U2; ++u)
@@ -521,8 +524,8 @@ __device__ __forceinline__ void stage2_block2(const typename Fac<DT>::T *__restr
             for (int q = 0; q < NR; ++q)
                 if (NR == 1 || rb + q < nrhs) {
                     const double zq = rd<LIVE>(zz + (rb + q) * ldz + c + u);
-                    a0[q] += v[u] * zq;
-                    a1[q] += w[u] * zq;
+                    a0[q] += Fac<DT>::cvt(v[u]) * zq;
+                    a1[q] += Fac<DT>::cvt(w[u]) * zq;
                 }
     }
     for (; c < k; ++c) {
@@ -589,17 +592,16 @@ __device__ __forceinline__ void
                     const T *p = static_cast<const T *>(fptr[bi]) +
                                  (pan ? int64_t(r0 - bs) * kb + (rrA - r0) : int64_t(rrA - bs));
                     if (two)
-                        stage2_block2<DT, NR, 8, LIVE>(p, dB, ld, kb, z + blk_col0[bi], ldz, rb,
-                                                       nrhs, acc[0], acc[1]);
+                        stage2_block2<DT, NR, 8, LIVE>(p, dB, ld, kb, z + blk_col0[bi],
+                                                                  ldz, rb, nrhs, acc[0], acc[1]);
                     else
-                        stage2_block<DT, NR, 8, LIVE>(p, ld, kb, z + blk_col0[bi], ldz, rb, nrhs,
-                                                      acc[0]);
+                        stage2_block<DT, NR, 8, LIVE>(p, ld, kb, z + blk_col0[bi], ldz,
+                                                                 rb, nrhs, acc[0]);
                 }
             }
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                if (h == 1 && !two)
-                    break;
+            // finer levels and the output, per row of the lane: a constant row
+            // slot, so that the accumulators stay in registers
+            auto finish = [&](const int h, double (&ah)[NR]) {
                 const int32_t row = h ? rowB : rowA;
                 const bool act = h ? actB : actA;
                 const int32_t rr = act ? row : r0;
@@ -618,7 +620,7 @@ __device__ __forceinline__ void
                             const int64_t bi = grp_blk[e];
                             const T *p = static_cast<const T *>(fptr[bi]) + loc;
                             stage2_block<DT, NR, 4, LIVE>(p, bm, rank[bi], z + blk_col0[bi], ldz, rb,
-                                                          nrhs, acc[h]);
+                                                          nrhs, ah);
                         }
                     } else if (e1 > e0) {
                         // The blocks of a target box are consecutive, and so are their
@@ -634,7 +636,7 @@ __device__ __forceinline__ void
                         const T *pl = static_cast<const T *>(fptr[e1 - 1]);
                         if (pl + int64_t(bm) * rank[e1 - 1] == pf + int64_t(bm) * kt) {
                             stage2_block<DT, NR, 8, LIVE>(pf + loc + int64_t(cb) * bm, bm, ce - cb,
-                                                          z + zc0 + cb, ldz, rb, nrhs, acc[h]);
+                                                          z + zc0 + cb, ldz, rb, nrhs, ah);
                         } else {
                             for (int64_t e = e0; e < e1; ++e) {
                                 const int c0 = int(blk_col0[e] - zc0);
@@ -645,7 +647,7 @@ __device__ __forceinline__ void
                                     stage2_block<DT, NR, 8, LIVE>(
                                         static_cast<const T *>(fptr[e]) + loc +
                                             int64_t(lo - c0) * bm,
-                                        bm, hi - lo, z + zc0 + lo, ldz, rb, nrhs, acc[h]);
+                                        bm, hi - lo, z + zc0 + lo, ldz, rb, nrhs, ah);
                             }
                         }
                     }
@@ -653,7 +655,7 @@ __device__ __forceinline__ void
                 // combine the waves' partial sums in a fixed order
 #pragma unroll
                 for (int q = 0; q < NR; ++q)
-                    part[wv][q][lane] = acc[h][q];
+                    part[wv][q][lane] = ah[q];
                 __syncthreads();
                 if (wv == 0) {
                     double y[NR];
@@ -684,7 +686,10 @@ __device__ __forceinline__ void
                     }
                 }
                 __syncthreads();
-            }
+            };
+            finish(0, acc[0]);
+            if (two)
+                finish(1, acc[1]);
         }
         rowb += two ? 128 : 64;
     }
