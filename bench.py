@@ -64,8 +64,8 @@ TRAFFIC = {
 
 # library sources of kernels launched on their own, which the counter readings
 # of the dominant kernel do not depend on (many right-hand sides, many
-# problems, optional rank truncation, the fused finest level)
-OTHER_PATHS = ("batched.hip", "batch.hip", "truncate.hip", "leaf.hip")
+# problems, optional rank truncation, the fused finest level, stage-1 items)
+OTHER_PATHS = ("batched.hip", "batch.hip", "truncate.hip", "leaf.hip", "stage1_items.hpp")
 
 
 def sources_digest() -> str:

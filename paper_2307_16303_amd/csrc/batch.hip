@@ -24,7 +24,7 @@
 // (product_items.hpp) with one wave per stage-2 chunk box: a problem's plan
 // configured that way (the batch sets it so) gives bitwise the same product
 // through h3d_matvec.
-#include "product_items.hpp"
+#include "stage1_items.hpp"
 
 namespace h3d {
 

@@ -18,7 +18,7 @@
 // factors of the box that contains its row.  No atomics: every output row is
 // written by exactly one lane, and the summation order is fixed, so results
 // are bitwise reproducible.
-#include "product_items.hpp"
+#include "stage1_items.hpp"
 
 namespace h3d {
 
