@@ -1,6 +1,6 @@
 // Finest level of a one-right-hand-side product with both stages of
 // Algorithm 2 fused (k_leaf); the product driver decides when it runs.
-#include "product_items.hpp"
+#include "stage1_items.hpp"
 
 namespace h3d {
 
@@ -40,30 +40,6 @@ struct LeafArgs {
 // Global-memory load of a factor entry through a pointer that the compiler
 // cannot place itself (it was read from LDS): without the address space the
 // load would be a flat one, which also waits on the LDS counter.
-// v + the value of the lane given by a DPP row permutation (CTRL), on both
-// halves of a double
-template <int CTRL> __device__ __forceinline__ double dpp_add(double v) {
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
-    return v + __hiloint2double(hi, lo);
-}
-
-// Sum over aligned groups of S <= 16 lanes, the same value in every lane of
-// the group: swap neighbours, swap pairs (quad permutations), then mirror the
-// half row and the row, each step adding a partial sum of the other half.
-template <int S> __device__ __forceinline__ double group_sum(double v) {
-    if constexpr (S >= 2)
-        v = dpp_add<0xB1>(v);   // quad_perm [1,0,3,2]
-    if constexpr (S >= 4)
-        v = dpp_add<0x4E>(v);   // quad_perm [2,3,0,1]
-    if constexpr (S >= 8)
-        v = dpp_add<0x141>(v);  // row_half_mirror
-    if constexpr (S >= 16)
-        v = dpp_add<0x140>(v);  // row_mirror
-    static_assert(S <= 16, "DPP row permutations cover 16 lanes");
-    return v;
-}
-
 template <int DT, int S, int UR>
 __global__ void __launch_bounds__(256) k_leaf(LeafArgs a) {
     using T = typename Fac<DT>::T;

@@ -140,10 +140,11 @@ __global__ void __launch_bounds__(256)
 // cache line at their common edge in every coarse column they read, and
 // workgroups are dealt to the eight XCDs (each with its own L2) in turn: each
 // XCD gets a contiguous run of chunk boxes so that those lines are fetched once.
-// (FP64 factors: at most 128 registers, four waves per SIMD, which the
-// compiler reaches without spilling)
+// (FP64 factors, one RHS: at most 128 registers, four waves per SIMD, which
+// the compiler reaches without spilling)
 template <int DT, int NR, int kS2Waves>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(DT == H3D_F64 ? 4 : 1)))
+__global__ void __launch_bounds__(512)
+    __attribute__((amdgpu_waves_per_eu(DT == H3D_F64 && NR == 1 ? 4 : 1)))
     k_stage2(S2Tab tab, const int32_t *__restrict__ leaf_off, const int32_t *__restrict__ leaf_of,
              const int64_t *__restrict__ grp_begin, const int64_t *__restrict__ grp_blk,
              void *const *__restrict__ fptr, const int32_t *__restrict__ rank,

@@ -9,6 +9,40 @@
 namespace h3d {
 namespace dev {
 
+// v + the value of the lane given by a DPP row permutation (CTRL), on both
+// halves of a double
+template <int CTRL> __device__ __forceinline__ double dpp_add(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return v + __hiloint2double(hi, lo);
+}
+
+// Sum over aligned groups of S <= 16 lanes, the same value in every lane of
+// the group: swap neighbours, swap pairs (quad permutations), then mirror the
+// half row and the row, each step adding a partial sum of the other half.
+template <int S> __device__ __forceinline__ double group_sum(double v) {
+    if constexpr (S >= 2)
+        v = dpp_add<0xB1>(v);   // quad_perm [1,0,3,2]
+    if constexpr (S >= 4)
+        v = dpp_add<0x4E>(v);   // quad_perm [2,3,0,1]
+    if constexpr (S >= 8)
+        v = dpp_add<0x141>(v);  // row_half_mirror
+    if constexpr (S >= 16)
+        v = dpp_add<0x140>(v);  // row_mirror
+    static_assert(S <= 16, "DPP row permutations cover 16 lanes");
+    return v;
+}
+
+// Sum over aligned sub-waves of S lanes, the same value in every lane: DPP
+// row permutations within rows of 16 lanes, shuffles for the wider strides.
+template <int S> __device__ __forceinline__ double sub_sum(double v) {
+    v = group_sum<(S < 16 ? S : 16)>(v);
+#pragma unroll
+    for (int o = 16; o < S; o <<= 1)
+        v += __shfl_xor(v, o, S);
+    return v;
+}
+
 // ---------------------------------------------------------------------------
 // stage 1: z[col] = dot(column col of its block's factor, x segment), one
 // launch per level with a shape chosen for that level's box size and rank.
@@ -81,34 +115,45 @@ __device__ __forceinline__ void s1_wide_item(const S1Args &a, int64_t w) {
 #pragma unroll
                 for (int q = 0; q < NR; ++q)
                     acc[u][q] = 0.0;
-            for (int j = j0 + r; j < j1; j += S) {
-                double xv[NR];
+            // JU rows per round (one right-hand side, FP32/BF16 factors, whose
+            // loads are narrow), so that one round keeps about 16 loads in
+            // flight (measured slower for FP64): every load is issued, from a row of the
+            // item and a column clamped into the item (cend > cb here); rows
+            // past the item's end take x = 0, columns past it drop the value
+            constexpr int JU = NR == 1 && DT != H3D_F64 && U < 16 ? 16 / U : 1;
+            for (int jb = j0 + r; jb < j1; jb += S * JU) {
+                double xv[JU][NR];
+                T vr[JU][U];
 #pragma unroll
-                for (int q = 0; q < NR; ++q)
-                    xv[q] = (NR == 1 || rb + q < a.nrhs) ? rd<LIVE>(xp + (rb + q) * a.n + off + j) : 0.0;
-                // every load is issued, from a column clamped into the item
-                // (cend > cb here); columns past the item drop the value
-                T vr[U];
+                for (int i = 0; i < JU; ++i) {
+                    const int j = jb + i * S, jc = min(j, j1 - 1);
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-                    vr[u] = fac_raw<DT>(p + int64_t(min(cb + sub + u * NS, cend - 1)) * len + j);
-                double v[U];
+                    for (int q = 0; q < NR; ++q) {
+                        const double xr = (NR == 1 || rb + q < a.nrhs)
+                                              ? rd<LIVE>(xp + (rb + q) * a.n + off + jc)
+                                              : 0.0;
+                        xv[i][q] = j < j1 ? xr : 0.0;
+                    }
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-                    v[u] = cb + sub + u * NS < cend ? Fac<DT>::cvt(vr[u]) : 0.0;
+                    for (int u = 0; u < U; ++u)
+                        vr[i][u] =
+                            fac_raw<DT>(p + int64_t(min(cb + sub + u * NS, cend - 1)) * len + jc);
+                }
 #pragma unroll
-                for (int u = 0; u < U; ++u)
+                for (int i = 0; i < JU; ++i)
 #pragma unroll
-                    for (int q = 0; q < NR; ++q)
-                        acc[u][q] += v[u] * xv[q];
+                    for (int u = 0; u < U; ++u) {
+                        const double v = cb + sub + u * NS < cend ? Fac<DT>::cvt(vr[i][u]) : 0.0;
+#pragma unroll
+                        for (int q = 0; q < NR; ++q)
+                            acc[u][q] += v * xv[i][q];
+                    }
             }
 #pragma unroll
-            for (int o = S / 2; o > 0; o >>= 1)
+            for (int u = 0; u < U; ++u)
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-#pragma unroll
-                    for (int q = 0; q < NR; ++q)
-                        acc[u][q] += __shfl_xor(acc[u][q], o, S);
+                for (int q = 0; q < NR; ++q)
+                    acc[u][q] = sub_sum<S>(acc[u][q]);
             if (r == 0) {
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
@@ -156,33 +201,41 @@ __device__ __forceinline__ void s1_packed_item(const S1Args &a, int64_t w) {
                 for (int q = 0; q < NR; ++q)
                     acc[u][q] = 0.0;
             const int jend = cb < k ? len : 0;  // this block's columns are done
-            for (int j = r; j < jend; j += S) {
-                double xv[NR];
+            // JU rows per round as in the wide form; k > cb here, so columns
+            // are clamped into the block and every load is issued
+            constexpr int JU = NR == 1 && DT != H3D_F64 && U < 16 ? 16 / U : 1;
+            for (int jb = r; jb < jend; jb += S * JU) {
+                double xv[JU][NR];
+                T vr[JU][U];
 #pragma unroll
-                for (int q = 0; q < NR; ++q)
-                    xv[q] = (NR == 1 || rb + q < a.nrhs) ? rd<LIVE>(xp + (rb + q) * a.n + off + j) : 0.0;
-                // k > cb here: columns clamped into the block, every load issued
-                T vr[U];
+                for (int i = 0; i < JU; ++i) {
+                    const int j = jb + i * S, jc = min(j, jend - 1);
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-                    vr[u] = fac_raw<DT>(p + int64_t(min(cb + u, k - 1)) * len + j);
-                double v[U];
+                    for (int q = 0; q < NR; ++q) {
+                        const double xr = (NR == 1 || rb + q < a.nrhs)
+                                              ? rd<LIVE>(xp + (rb + q) * a.n + off + jc)
+                                              : 0.0;
+                        xv[i][q] = j < jend ? xr : 0.0;
+                    }
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-                    v[u] = cb + u < k ? Fac<DT>::cvt(vr[u]) : 0.0;
+                    for (int u = 0; u < U; ++u)
+                        vr[i][u] = fac_raw<DT>(p + int64_t(min(cb + u, k - 1)) * len + jc);
+                }
 #pragma unroll
-                for (int u = 0; u < U; ++u)
+                for (int i = 0; i < JU; ++i)
 #pragma unroll
-                    for (int q = 0; q < NR; ++q)
-                        acc[u][q] += v[u] * xv[q];
+                    for (int u = 0; u < U; ++u) {
+                        const double v = cb + u < k ? Fac<DT>::cvt(vr[i][u]) : 0.0;
+#pragma unroll
+                        for (int q = 0; q < NR; ++q)
+                            acc[u][q] += v * xv[i][q];
+                    }
             }
 #pragma unroll
-            for (int o = S / 2; o > 0; o >>= 1)
+            for (int u = 0; u < U; ++u)
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-#pragma unroll
-                    for (int q = 0; q < NR; ++q)
-                        acc[u][q] += __shfl_xor(acc[u][q], o, S);
+                for (int q = 0; q < NR; ++q)
+                    acc[u][q] = sub_sum<S>(acc[u][q]);
             if (r == 0) {
 #pragma unroll
                 for (int u = 0; u < U; ++u)
