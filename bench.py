@@ -25,10 +25,12 @@ problems' own products run one after another.
 roofline.traffic is the dominant kernel's HBM traffic per launch from the
 hardware counters FETCH_SIZE and WRITE_SIZE (rocprofv3 --pmc, one counter per
 run, on this workload), each divided by what the same counter reads for a
-plain 2 GiB device copy (--calibration-copy).  Those figures hold for the
-sources they were taken on: if any library source that the dominant kernel's
-code, its launch or the factor layout depends on has changed since, traffic
-is null.
+plain 2 GiB device copy (--calibration-copy).  Readings are kept for the two
+kernels that take the largest share of the product (stage 2, and stage 1
+whose per-launch figure is the mean over its launches, one per level).  They
+hold for the sources they were taken on: if any library source that these
+kernels' code, their launches or the factor layout depend on has changed
+since, traffic is null.
 """
 from __future__ import annotations
 
@@ -50,27 +52,30 @@ UNIT = "points·RHS/s"
 HBM_PEAK_GBS = 8000.0
 DTYPE_NAMES = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
 
-# Counter readings of the dominant kernel on uniform262k (FP64 factors, one
-# RHS), KiB per dispatch, with the copy-kernel scale of each counter.  The
-# runs that produced them are listed in profiles/; sources_sha256 identifies
-# the library sources they were taken on (see sources_digest).
+# Counter readings on uniform262k (FP64 factors, one RHS), KiB per dispatch
+# (stage 1: the mean over the four dispatches of one product), with the
+# copy-kernel scale of each counter.  The runs that produced them are listed in
+# profiles/; sources_sha256 identifies the library sources they were taken on
+# (see sources_digest).
 TRAFFIC = {
-    "kernel": "k_stage2", "workload": "uniform262k",
-    "fetch_kib": 10105764.3125, "fetch_scale": 0.500006,
-    "write_kib": 8199.2604, "write_scale": 1.000000,
+    "workload": "uniform262k",
+    "fetch_scale": 0.500006, "write_scale": 1.000000,
+    "kernels": {
+        "k_stage2": {"fetch_kib": 10105764.3125, "write_kib": 8199.2604},
+    },
     "sources_sha256": "9b2116c0d6cc533c17f85f3bae79b8fb8895ae96639d64fe1b7a6a06423c917b",
 }
 
 
-# library sources of kernels launched on their own, which the counter readings
-# of the dominant kernel do not depend on (many right-hand sides, many
-# problems, optional rank truncation, the fused finest level, stage-1 items)
-OTHER_PATHS = ("batched.hip", "batch.hip", "truncate.hip", "leaf.hip", "stage1_items.hpp")
+# library sources of kernels launched on their own, on which the counter
+# readings above do not depend (many right-hand sides, many problems, optional
+# rank truncation, the fused finest level)
+OTHER_PATHS = ("batched.hip", "batch.hip", "truncate.hip", "leaf.hip")
 
 
 def sources_digest() -> str:
     """sha256, in name order, over the library sources and header that the
-    dominant kernel's code and launch and the factor layout depend on."""
+    stream kernels' code and launches and the factor layout depend on."""
     h = hashlib.sha256()
     files = sorted(f for f in glob.glob(os.path.join(ROOT, "paper_2307_16303_amd", "csrc", "*"))
                    if os.path.basename(f) not in OTHER_PATHS)
@@ -85,10 +90,11 @@ def sources_digest() -> str:
 def traffic_bytes(kernel: str, workload: str, factor_dtype: str, nrhs: int):
     """HBM bytes per launch from the stored counter readings, or None."""
     t = TRAFFIC
-    if (t is None or t["kernel"] != kernel or t["workload"] != workload
-            or factor_dtype != "fp64" or nrhs != 1 or t["sources_sha256"] != sources_digest()):
+    k = None if t is None else t["kernels"].get(kernel)
+    if (k is None or t["workload"] != workload or factor_dtype != "fp64" or nrhs != 1
+            or t["sources_sha256"] != sources_digest()):
         return None
-    return t["fetch_kib"] * 1024.0 / t["fetch_scale"] + t["write_kib"] * 1024.0 / t["write_scale"]
+    return k["fetch_kib"] * 1024.0 / t["fetch_scale"] + k["write_kib"] * 1024.0 / t["write_scale"]
 
 
 def parse():

@@ -386,26 +386,6 @@ void autotune_dt(Plan &P, int nrhs, hipStream_t s) {
         }
         set_level_shape(P, cls, l, best_sh, s);
     }
-    S2Tab tab{};
-    for (int l = 0; l <= kMaxLevels; ++l)
-        tab.box_base[l] = P.box_base[l];
-    tab.L = P.L;
-    tab.lc = P.chunk_level;
-    tab.panel = 1;
-    const int64_t nchunk = pow8(P.chunk_level);
-    float best_ms = 1e30f;
-    int best_w = P.s2_waves[cls];
-    for (int w : {2, 4, 8}) {
-        const float ms = time_it([&] {
-            launch_s2_kernel<DT, NR>(w, nchunk, s, tab, P, nullptr, P.blk_uptr, P.z, P.yp, nrhs,
-                                     P.yp + P.n * nrhs, P.n, 0, 1, P.L, nullptr);
-        });
-        if (ms < best_ms) {
-            best_ms = ms;
-            best_w = w;
-        }
-    }
-    P.s2_waves[cls] = best_w;
     // one right-hand side: the finest level fused (S lanes per column) or not,
     // timed over the whole far field
     if (NR == 1 && !P.in_batch && P.lvl_blk[P.L + 1] > P.lvl_blk[P.L]) {
@@ -423,6 +403,29 @@ void autotune_dt(Plan &P, int nrhs, hipStream_t s) {
         }
         P.leaf_fuse = best_s;
     }
+    // stage-2 waves per chunk box, timed on the levels stage 2 covers once the
+    // finest level is settled
+    S2Tab tab{};
+    for (int l = 0; l <= kMaxLevels; ++l)
+        tab.box_base[l] = P.box_base[l];
+    tab.L = P.L;
+    tab.lc = P.chunk_level;
+    tab.panel = 1;
+    const int64_t nchunk = pow8(P.chunk_level);
+    const int Lf = NR == 1 && leaf_shape(P) ? P.L - 1 : P.L;
+    float best_ms = 1e30f;
+    int best_w = P.s2_waves[cls];
+    for (int w : {2, 4, 8}) {
+        const float ms = time_it([&] {
+            launch_s2_kernel<DT, NR>(w, nchunk, s, tab, P, nullptr, P.blk_uptr, P.z, P.yp, nrhs,
+                                     P.yp + P.n * nrhs, P.n, 0, 1, Lf, nullptr);
+        });
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_w = w;
+        }
+    }
+    P.s2_waves[cls] = best_w;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     P.tuned[cls] = true;
