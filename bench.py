@@ -59,11 +59,12 @@ DTYPE_NAMES = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
 # (see sources_digest).
 TRAFFIC = {
     "workload": "uniform262k",
-    "fetch_scale": 0.500006, "write_scale": 1.000000,
+    "fetch_scale": 0.500016, "write_scale": 1.000000,
     "kernels": {
-        "k_stage2": {"fetch_kib": 10105764.3125, "write_kib": 8199.2604},
+        "k_stage2": {"fetch_kib": 10107054.5000, "write_kib": 8199.0729},
+        "k_s1_wide": {"fetch_kib": 2669879.4792, "write_kib": 37590.4922},
     },
-    "sources_sha256": "9b2116c0d6cc533c17f85f3bae79b8fb8895ae96639d64fe1b7a6a06423c917b",
+    "sources_sha256": "55124773feb4b845c4d59de80c186cc57607212204b91631bc6dc269580c8b84",
 }
 
 
