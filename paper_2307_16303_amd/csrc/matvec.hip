@@ -46,17 +46,28 @@ __global__ void __launch_bounds__(64)
                               xp, n, yn);
 }
 
+// Workgroups are dealt to the eight XCDs in turn (each XCD with its own L2).
+// Workgroup b is renumbered so that every XCD takes a contiguous run of the
+// grid: consecutive work items, whose factors lie back to back and share the
+// cache line at their common end, then meet in one L2.
+__device__ __forceinline__ int64_t xcd_contiguous(int64_t b, int64_t nwg) {
+    const int64_t q = nwg >> 3, r = nwg & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
 // stage 1: one work item per wave
 template <int S, int U, int DT, int NR>
 __global__ void __launch_bounds__(256) k_s1_wide(S1Args a) {
-    const int64_t w = uniform64((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6);
+    const int64_t b = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int64_t w = uniform64((b * blockDim.x + threadIdx.x) >> 6);
     if (w < a.nitems)
         s1_wide_item<S, U, DT, NR>(a, w);
 }
 
 template <int S, int U, int DT, int NR>
 __global__ void __launch_bounds__(256) k_s1_packed(S1Args a) {
-    const int64_t w = uniform64((int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6);
+    const int64_t b = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int64_t w = uniform64((b * blockDim.x + threadIdx.x) >> 6);
     if (w < a.nitems)
         s1_packed_item<S, U, DT, NR>(a, w);
 }
