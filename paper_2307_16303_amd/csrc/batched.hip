@@ -209,40 +209,70 @@ __global__ void __launch_bounds__(64)
             for (int jj = 0; jj < 4; ++jj)
                 acc64[q][jj] = 0.0;
         }
-        // KU K-steps per round: all their fragments are loaded before the
-        // MFMAs of the round are issued
-        constexpr int KU = 1;
-        int steps = 0;
-        for (int j0 = 0; j0 < len; j0 += 4 * KU) {
-            T a[KU], bv[KU][kNT];
-#pragma unroll
-            for (int u = 0; u < KU; ++u) {
-                const int j = j0 + 4 * u + (lane >> 4);
+        if constexpr (DT == H3D_F64) {
+            for (int j0 = 0; j0 < len; j0 += 4) {
+                const int j = j0 + (lane >> 4);
                 const bool aj = j < len;
                 int64_t ea = int64_t(ca) * len + j;
                 if (panel && ac && aj)  // U_b stored as row panels (adjoint above lc)
                     ea = panel_off(leaf_off, leaf_of, shc, int32_t(off), k, j, ca);
-                a[u] = (ac && aj) ? T(FacB<DT>::ld(p + ea)) : T(0);
+                const T a = (ac && aj) ? T(FacB<DT>::ld(p + ea)) : T(0);
+                T bv[kNT];
 #pragma unroll
                 for (int q = 0; q < kNT; ++q)
-                    bv[u][q] = (aj && q < ntl) ? Xs[(off + j) * NP + nb + 16 * q + (lane & 15)] : T(0);
-            }
-#pragma unroll
-            for (int u = 0; u < KU; ++u)
+                    bv[q] = (aj && q < ntl) ? Xs[(off + j) * NP + nb + 16 * q + (lane & 15)] : T(0);
 #pragma unroll
                 for (int q = 0; q < kNT; ++q)
                     if (q < ntl)
-                        acc[q] = C::mfma(a[u], bv[u][q], acc[q]);
-            steps += KU;
-            if (DT != H3D_F64 && steps >= 64) {
-                steps = 0;
+                        acc[q] = C::mfma(a, bv[q], acc[q]);
+            }
+        } else {
+            // FP32/BF16 tiles (measured: slower with FP64 tiles, whose fragments
+            // take twice the registers).  Every load is issued, from a row and
+            // column clamped into the block and a tile clamped into the RHS, so
+            // that the loads of the next K-step stay countable; the raw values
+            // are masked where they are used, and two fragment buffers let the
+            // next K-step load while the MFMAs of the current one run.
+            const int cc = min(ca, k - 1);
+            auto frag = [&](int j0, T &a, T (&bv)[kNT]) {
+                const int jc = min(j0 + (lane >> 4), len - 1);
+                int64_t ea = int64_t(cc) * len + jc;
+                if (panel)  // U_b stored as row panels (adjoint above lc)
+                    ea = panel_off(leaf_off, leaf_of, shc, int32_t(off), k, jc, cc);
+                a = T(FacB<DT>::ld(p + ea));
 #pragma unroll
-                for (int q = 0; q < kNT; ++q) {
+                for (int q = 0; q < kNT; ++q)
+                    bv[q] = Xs[(off + jc) * NP + nb + 16 * min(q, ntl - 1) + (lane & 15)];
+            };
+            int steps = 0;
+            auto step = [&](int j0, const T ar, const T (&br)[kNT]) {
+                const bool aj = j0 + (lane >> 4) < len;
+                const T a = (ac && aj) ? ar : T(0);
 #pragma unroll
-                    for (int jj = 0; jj < 4; ++jj)
-                        acc64[q][jj] += double(acc[q][jj]);
-                    acc[q] = typename C::V4{0, 0, 0, 0};
+                for (int q = 0; q < kNT; ++q)  // rows past the block, tiles past the RHS: 0
+                    acc[q] = C::mfma(a, (aj && q < ntl) ? br[q] : T(0), acc[q]);
+                if (++steps == 64) {
+                    steps = 0;
+#pragma unroll
+                    for (int q = 0; q < kNT; ++q) {
+#pragma unroll
+                        for (int jj = 0; jj < 4; ++jj)
+                            acc64[q][jj] += double(acc[q][jj]);
+                        acc[q] = typename C::V4{0, 0, 0, 0};
+                    }
                 }
+            };
+            T a0, b0[kNT], a1, b1[kNT];
+            frag(0, a0, b0);
+            for (int j0 = 0; j0 < len; j0 += 8) {
+                if (j0 + 4 < len)
+                    frag(j0 + 4, a1, b1);
+                step(j0, a0, b0);
+                if (j0 + 4 >= len)
+                    break;
+                if (j0 + 8 < len)
+                    frag(j0 + 8, a0, b0);
+                step(j0 + 4, a1, b1);
             }
         }
 #pragma unroll
@@ -281,10 +311,11 @@ __global__ void __launch_bounds__(64)
     const int r0 = it.y * 16;
     const int ia = r0 + (lane & 15);  // A row (box row) of this lane
     const bool ar = ia < bm;
+    const int iac = min(ia, bm - 1);  // a row of the box, for unmasked loads
     // row panels (forward above the chunk level): this row's chunk box
     int32_t pr0 = bs, pld = bm;
-    if (panel && ar) {
-        const int32_t ch = leaf_of[bs + ia] >> shc;
+    if (panel) {
+        const int32_t ch = leaf_of[bs + iac] >> shc;
         pr0 = leaf_off[ch << shc];
         pld = leaf_off[(ch + 1) << shc] - pr0;
     }
@@ -303,30 +334,60 @@ __global__ void __launch_bounds__(64)
             const int64_t bi = grp_blk ? grp_blk[e] : e;
             const int k = rank[bi];
             const int64_t col0 = blk_col0[bi];
-            const F *__restrict__ p = static_cast<const F *>(fptr[bi]) +
-                                      (int64_t(pr0 - bs) * k + (bs + ia - pr0));
             typename C::V4 acc[kNT];
 #pragma unroll
             for (int q = 0; q < kNT; ++q)
                 acc[q] = typename C::V4{0, 0, 0, 0};
-            constexpr int KU = 1;
-            for (int c0 = 0; c0 < k; c0 += 4 * KU) {
-                T a[KU], bv[KU][kNT];
-#pragma unroll
-                for (int u = 0; u < KU; ++u) {
-                    const int c = c0 + 4 * u + (lane >> 4);
+            if constexpr (DT == H3D_F64) {
+                const F *__restrict__ p = static_cast<const F *>(fptr[bi]) +
+                                          (int64_t(pr0 - bs) * k + (bs + ia - pr0));
+                for (int c0 = 0; c0 < k; c0 += 4) {
+                    const int c = c0 + (lane >> 4);
                     const bool ak = c < k;
-                    a[u] = (ar && ak) ? T(FacB<DT>::ld(p + int64_t(c) * pld)) : T(0);
+                    const T a = (ar && ak) ? T(FacB<DT>::ld(p + int64_t(c) * pld)) : T(0);
+                    T bv[kNT];
 #pragma unroll
                     for (int q = 0; q < kNT; ++q)
-                        bv[u][q] = (ak && q < ntl) ? Z[(col0 + c) * NP + nb + 16 * q + (lane & 15)] : T(0);
-                }
-#pragma unroll
-                for (int u = 0; u < KU; ++u)
+                        bv[q] = (ak && q < ntl) ? Z[(col0 + c) * NP + nb + 16 * q + (lane & 15)] : T(0);
 #pragma unroll
                     for (int q = 0; q < kNT; ++q)
                         if (q < ntl)
-                            acc[q] = C::mfma(a[u], bv[u][q], acc[q]);
+                            acc[q] = C::mfma(a, bv[q], acc[q]);
+                }
+            } else if (k > 0) {
+                // FP32/BF16 tiles (measured: slower with FP64 tiles, whose
+                // fragments take twice the registers): every load from a column
+                // of the block and a tile of the RHS, raw values masked where
+                // they are used, and the fragments of the next K-step loaded
+                // while the current one runs
+                const F *__restrict__ p = static_cast<const F *>(fptr[bi]) +
+                                          (int64_t(pr0 - bs) * k + (bs + iac - pr0));
+                auto frag = [&](int c0, T &a, T (&bv)[kNT]) {
+                    const int cc = min(c0 + (lane >> 4), k - 1);
+                    a = T(FacB<DT>::ld(p + int64_t(cc) * pld));
+#pragma unroll
+                    for (int q = 0; q < kNT; ++q)
+                        bv[q] = Z[(col0 + cc) * NP + nb + 16 * min(q, ntl - 1) + (lane & 15)];
+                };
+                auto step = [&](int c0, const T ra, const T (&rb)[kNT]) {
+                    const bool ak = c0 + (lane >> 4) < k;
+                    const T a = (ar && ak) ? ra : T(0);
+#pragma unroll
+                    for (int q = 0; q < kNT; ++q)
+                        acc[q] = C::mfma(a, (ak && q < ntl) ? rb[q] : T(0), acc[q]);
+                };
+                T a0, b0[kNT], a1, b1[kNT];
+                frag(0, a0, b0);
+                for (int c0 = 0; c0 < k; c0 += 8) {
+                    if (c0 + 4 < k)
+                        frag(c0 + 4, a1, b1);
+                    step(c0, a0, b0);
+                    if (c0 + 4 >= k)
+                        break;
+                    if (c0 + 8 < k)
+                        frag(c0 + 8, a0, b0);
+                    step(c0 + 4, a1, b1);
+                }
             }
 #pragma unroll
             for (int q = 0; q < kNT; ++q)
