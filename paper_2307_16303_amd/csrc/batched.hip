@@ -698,6 +698,58 @@ __global__ void __launch_bounds__(64)
             T sc = T(1);
             if (DT == H3D_BF16_SCALED)
                 sc = T(double(scale2[2 * b]) * double(scale2[2 * b + 1]));
+            if (k > 0 && k <= 16 && n <= 16) {
+                // one column tile, at most four K-steps in each stage (almost
+                // every block at this level): all loads of the block are issued
+                // at once, from rows and columns clamped into the block, and
+                // masked where they are used
+                const int cc = min(lane & 15, k - 1), iac = min(ia, bm - 1);
+                T av[4], xv[4][kNT], uv[4];
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    const int jc = min(4 * st + (lane >> 4), n - 1);
+                    av[st] = T(FacB<DT>::ld(V + int64_t(cc) * n + jc));
+#pragma unroll
+                    for (int q = 0; q < kNT; ++q)
+                        xv[st][q] = Xs[(so + jc) * NP + nb + 16 * min(q, ntl - 1) + (lane & 15)];
+                    uv[st] = T(FacB<DT>::ld(U + int64_t(min(4 * st + (lane >> 4), k - 1)) * bm + iac));
+                }
+                typename C::V4 zt[kNT];
+#pragma unroll
+                for (int q = 0; q < kNT; ++q)
+                    zt[q] = typename C::V4{0, 0, 0, 0};
+#pragma unroll
+                for (int st = 0; st < 4; ++st)
+                    if (4 * st < n) {
+                        const bool aj = 4 * st + (lane >> 4) < n;
+                        const T a = ((lane & 15) < k && aj) ? av[st] : T(0);
+#pragma unroll
+                        for (int q = 0; q < kNT; ++q)
+                            zt[q] = C::mfma(a, (aj && q < ntl) ? xv[st][q] : T(0), zt[q]);
+                    }
+#pragma unroll
+                for (int q = 0; q < kNT; ++q)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj)
+                        zl[C::row(lane, jj)][16 * q + (lane & 15)] = zt[q][jj] * sc;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+                for (int st = 0; st < 4; ++st)
+                    if (4 * st < k) {
+                        const int c = 4 * st + (lane >> 4);
+                        const bool ak = c < k;
+                        const T a = (ar && ak) ? uv[st] : T(0);
+#pragma unroll
+                        for (int q = 0; q < kNT; ++q)
+                            acc[q] = C::mfma(a, (ak && q < ntl) ? zl[c][16 * q + (lane & 15)] : T(0),
+                                             acc[q]);
+                    }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            } else
             for (int c0 = 0; c0 < k; c0 += 16) {
                 // stage 1: Z tile = V^T X over the source rows
                 const int ca = c0 + (lane & 15);
