@@ -5,8 +5,8 @@
 //                                   on the fly straight into the A operand
 //   stage1 Z_b  = V_b^T X_s         (k x n) (n x nrhs)
 //   stage2 Y_t += U_b Z_b           (m x k) (k x nrhs), level by level
-// (forward products with FP32/BF16 factors and leaves of at most 16 points on
-// average fuse both stages at the finest level: k_leaf_mfma)
+// (forward products with leaves of at most 16 points on average fuse both
+// stages at the finest level: k_leaf_mfma)
 // All three run on 16x16x4 MFMA tiles (FP64 MFMA for FP64 factors, FP32 MFMA
 // for FP32 and BF16 factors).  Right-hand sides are held point-major (a row of
 // NP = 16 ceil(nrhs/16) values per point) so that every B fragment is four
@@ -1060,13 +1060,12 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
         P.prof.end(s, ev, "k_near_mfma", double(n) * (32.0 + 16.0 * NP),
                    double(P.stats.near_pair_evals) * (10.0 + 2.0 * NP));
     }
-    // forward products with FP32/BF16 factors and small leaves run both
-    // stages of the finest level in k_leaf_mfma.  Measured: the fused chain
-    // is latency-bound, which FP64 tiles make slower than two launches, and
-    // so do leaves of about 32 points (1,048,576 uniform points: 62 ms fused
-    // against 27 ms in two launches; 262,144 points, leaves of 8: 5.5 vs 6.0)
-    const int lfuse =
-        (adjoint || DT == H3D_F64 || P.mean_box[P.L] > kLeafRows) ? 0 : P.L;
+    // forward products with small leaves run both stages of the finest level
+    // in k_leaf_mfma.  Measured on 262,144 points (leaves of 8): FP32 3.7 ms
+    // fused against 6.0 ms in two launches, FP64 5.7 against 8.1; with leaves
+    // of about 32 points (1,048,576 points) the fused chain was slower (62
+    // against 27 ms, FP32)
+    const int lfuse = (adjoint || P.mean_box[P.L] > kLeafRows) ? 0 : P.L;
     for (int l = 1; l <= P.L; ++l) {
         if (P.bt_ns1[l] == 0 || l == lfuse)
             continue;
