@@ -61,10 +61,10 @@ TRAFFIC = {
     "workload": "uniform262k",
     "fetch_scale": 0.500016, "write_scale": 1.000000,
     "kernels": {
-        "k_stage2": {"fetch_kib": 10107054.5000, "write_kib": 8199.0729},
-        "k_s1_wide": {"fetch_kib": 2669879.4792, "write_kib": 37590.4922},
+        "k_stage2": {"fetch_kib": 10106678.5833, "write_kib": 8198.8958},
+        "k_s1_wide": {"fetch_kib": 2559453.0781, "write_kib": 34831.4323},
     },
-    "sources_sha256": "55124773feb4b845c4d59de80c186cc57607212204b91631bc6dc269580c8b84",
+    "sources_sha256": "f33970800215d821173e4abe65f9537ac398dfe545884fc9cf2e471ad9e45eb0",
 }
 
 
