@@ -8,6 +8,9 @@
 //   stage 2  y_t = yn_t + sum_levels sum_{b of t} U_b z_b, written straight
 //            to y[perm] (in the adjoint V_b z_b summed over the blocks whose
 //            source is the box)
+//   with one right-hand side the finest level may instead run both stages at
+//   once (leaf.hip), adding its far field into yn before stage 2 runs over
+//   the coarser levels
 //
 // Stage 1 treats every factor column as one dot product: a sub-wave of S
 // lanes (S ~ the level's box size) walks one column, so 64/S consecutive
