@@ -113,7 +113,8 @@ def parse():
                     help="skip the FP32 / BF16 / 64-RHS forms measured beside the headline")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="after the timed steps, fill and copy a 2 GiB buffer: the plain "
-                         "kernels that hardware byte counters are scaled by")
+                         "kernels that hardware byte counters are scaled by; then time "
+                         "torch's sum over it, a plain read stream")
     return ap.parse_args()
 
 
@@ -182,7 +183,7 @@ def main():
                 "kernel": dom["name"], "avg_launch_ms": round(avg_ms, 4),
                 "bytes_per_launch": dom["bytes_per_launch"]}
     kernels = {p["name"]: round(p["total_ms"] / max(p["launches"], 1), 4) for p in prof}
-    copy_gbs = None
+    copy_gbs = read_gbs = None
     if args.calibration_copy:
         # 2 GiB written by the fill, then 2 GiB read and 2 GiB written by the copy
         a = torch.ones(2 ** 28, dtype=torch.float64, device=dev)
@@ -198,7 +199,17 @@ def main():
         copy_gbs = 5 * 2 * 2 ** 31 / (e0.elapsed_time(e1) * 1e-3) / 1e9
         print(f"[bench] device copy: {copy_gbs:.1f} GB/s (read + write)", file=sys.stderr,
               flush=True)
-        del a, b
+        # a plain read stream: torch's sum over the same 2 GiB
+        s = a.sum()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(5):
+            s = a.sum()
+        e1.record()
+        torch.cuda.synchronize()
+        read_gbs = 5 * 2 ** 31 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        print(f"[bench] device read (sum): {read_gbs:.1f} GB/s", file=sys.stderr, flush=True)
+        del a, b, s
     y_head = y.detach().cpu().numpy().reshape(n, -1)
     op.close()
     del op
@@ -353,6 +364,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "device_copy_gbs": None if copy_gbs is None else round(copy_gbs, 1),
+        "device_read_gbs": None if read_gbs is None else round(read_gbs, 1),
         "variants": variants or None,
     }
     print(json.dumps(out))
