@@ -38,15 +38,15 @@ __global__ void k_gather(const void *__restrict__ x, int io_f32, int64_t ldx, in
         gather_row(x, io_f32, ldx, n, nrhs, perm, xp, p);
 }
 
-// near field: one wave per leaf
-template <int NR, bool E32>
+// near field: one wave per leaf (KIND: the kernel fixed at compile time, or -1)
+template <int NR, bool E32, int KIND>
 __global__ void __launch_bounds__(64)
     k_near(const int32_t *__restrict__ leaf_off, const int32_t *__restrict__ near_ptr,
            const int32_t *__restrict__ near_s, const double *__restrict__ px,
            const double *__restrict__ py, const double *__restrict__ pz, int kind, double kp,
            int nrhs, const double *__restrict__ xp, int64_t n, double *__restrict__ yn) {
-    near_leaf<NR, false, E32>(blockIdx.x, leaf_off, near_ptr, near_s, px, py, pz, kind, kp, nrhs,
-                              xp, n, yn);
+    near_leaf<NR, false, E32, KIND>(blockIdx.x, leaf_off, near_ptr, near_s, px, py, pz, kind, kp,
+                                    nrhs, xp, n, yn);
 }
 
 // Workgroups are dealt to the eight XCDs in turn (each XCD with its own L2).
@@ -448,15 +448,26 @@ void autotune_dt(Plan &P, int nrhs, hipStream_t s) {
 template <int NR>
 void launch_near(Plan &P, int nrhs, const double *xp, double *yn, hipStream_t s) {
     hipEvent_t ev = P.prof.begin(s);
-    // the FP32 and BF16 forms evaluate the near-field entries in FP32
-    if (P.factor_dtype == H3D_F64)
-        k_near<NR, false><<<int(pow8(P.L)), 64, 0, s>>>(P.leaf_off, P.near_ptr, P.near_s, P.px,
-                                                         P.py, P.pz, P.cfg.kernel,
-                                                         P.cfg.kernel_param, nrhs, xp, P.n, yn);
-    else
-        k_near<NR, true><<<int(pow8(P.L)), 64, 0, s>>>(P.leaf_off, P.near_ptr, P.near_s, P.px,
-                                                        P.py, P.pz, P.cfg.kernel,
-                                                        P.cfg.kernel_param, nrhs, xp, P.n, yn);
+    // the FP32 and BF16 forms evaluate the near-field entries in FP32; the
+    // Laplace kernel has launches of its own (the general ones inline every
+    // kernel's formula)
+    const int g = int(pow8(P.L));
+    const bool e32 = P.factor_dtype != H3D_F64, lap = P.cfg.kernel == H3D_LAPLACE;
+#define H3D_NEAR(E, K)                                                                      \
+    k_near<NR, E, K><<<g, 64, 0, s>>>(P.leaf_off, P.near_ptr, P.near_s, P.px, P.py, P.pz,   \
+                                      P.cfg.kernel, P.cfg.kernel_param, nrhs, xp, P.n, yn)
+    if (e32) {
+        if (lap)
+            H3D_NEAR(true, H3D_LAPLACE);
+        else
+            H3D_NEAR(true, -1);
+    } else {
+        if (lap)
+            H3D_NEAR(false, H3D_LAPLACE);
+        else
+            H3D_NEAR(false, -1);
+    }
+#undef H3D_NEAR
     H3D_LAUNCH_CHECK();
     P.prof.end(s, ev, "k_near", double(P.n) * (32.0 + 8.0 * nrhs),
                double(P.stats.near_pair_evals) * (10.0 + 2.0 * nrhs));

@@ -115,12 +115,17 @@ __device__ __forceinline__ void gather_row(const void *__restrict__ x, int io_f3
 
 // ---------------------------------------------------------------------------
 // near field: one wave per leaf; lane = (row within a pass of R rows, source
-// slice q of Q = 64/R); sources staged through LDS in chunks of kChunk points
-constexpr int kChunk = 256;
+// slice q of Q = 64/R).  The sources of the whole near list, concatenated in
+// list order, are staged through LDS in chunks of kChunk points: one pass of
+// loads per chunk (a leaf's near list of up to 19 leaves of a few points is
+// one chunk), every lane finding the list entry of each point it stages by a
+// binary search over the entries' first positions.
+constexpr int kChunk = 128;
 
 // E32: kernel entries evaluated in FP32 (forms with FP32 or BF16 factors),
-// accumulated in FP64
-template <int NR, bool LIVE = false, bool E32 = false>
+// accumulated in FP64.  KIND >= 0 fixes the kernel at compile time (only its
+// formula is inlined into the loop); -1 takes `kind`.
+template <int NR, bool LIVE = false, bool E32 = false, int KIND = -1>
 __device__ __forceinline__ void near_leaf(int64_t t, const int32_t *__restrict__ leaf_off,
                                           const int32_t *__restrict__ near_ptr,
                                           const int32_t *__restrict__ near_s,
@@ -131,7 +136,10 @@ __device__ __forceinline__ void near_leaf(int64_t t, const int32_t *__restrict__
                                           double *__restrict__ yn) {
     __shared__ double sx[kChunk], sy[kChunk], sz[kChunk];
     __shared__ double sv[NR][kChunk];
+    __shared__ int32_t sg[kChunk];        // sorted index of each staged source
+    __shared__ int32_t s_beg[64], s_row[64];  // per list entry: first position, first row
     const int lane = threadIdx.x;
+    const int kd = KIND >= 0 ? KIND : kind;
     const int32_t t0 = leaf_off[t];
     const int m = leaf_off[t + 1] - t0;
     if (m == 0)
@@ -152,32 +160,65 @@ __device__ __forceinline__ void near_leaf(int64_t t, const int32_t *__restrict__
 #pragma unroll
             for (int c = 0; c < NR; ++c)
                 acc[c] = 0.0;
-            for (int e = e0; e < e1; ++e) {
-                const int32_t s = near_s[e];
-                const int32_t s0 = leaf_off[s];
-                const int ns = leaf_off[s + 1] - s0;
-                for (int cb = 0; cb < ns; cb += kChunk) {
-                    const int cn = min(kChunk, ns - cb);
-                    __syncthreads();
-                    for (int j = lane; j < cn; j += 64) {
-                        const int64_t gj = s0 + cb + j;
-                        sx[j] = px[gj];
-                        sy[j] = py[gj];
-                        sz[j] = pz[gj];
+            // the list, 64 entries at a time
+            for (int ea = e0; ea < e1; ea += 64) {
+                const int ne = min(64, e1 - ea);
+                int row0 = 0, ns = 0;
+                if (lane < ne) {
+                    const int32_t s = near_s[ea + lane];
+                    row0 = leaf_off[s];
+                    ns = leaf_off[s + 1] - row0;
+                }
+                int incl = ns;  // inclusive prefix sum of the sizes over the lanes
 #pragma unroll
-                        for (int c = 0; c < NR; ++c)
-                            sv[c][j] = (rb + c < nrhs) ? rd<LIVE>(xp + (rb + c) * n + gj) : 0.0;
+                for (int d = 1; d < 64; d <<= 1) {
+                    const int v = __shfl_up(incl, d, 64);
+                    if (lane >= d)
+                        incl += v;
+                }
+                const int total = __shfl(incl, ne - 1, 64);
+                __syncthreads();  // the previous chunk's readers are done
+                if (lane < ne) {
+                    s_beg[lane] = incl - ns;
+                    s_row[lane] = row0;
+                }
+                for (int cb = 0; cb < total; cb += kChunk) {
+                    const int cn = min(kChunk, total - cb);
+                    __syncthreads();
+#pragma unroll
+                    for (int u = 0; u < kChunk / 64; ++u) {
+                        const int f = cb + u * 64 + lane;
+                        if (f < cb + cn) {
+                            // last entry whose first position is <= f (entries
+                            // of empty leaves share the next entry's position)
+                            int lo = 0, hi = ne;
+                            while (hi - lo > 1) {
+                                const int mid = (lo + hi) >> 1;
+                                if (s_beg[mid] <= f)
+                                    lo = mid;
+                                else
+                                    hi = mid;
+                            }
+                            const int32_t gj = s_row[lo] + (f - s_beg[lo]);
+                            const int jj = f - cb;
+                            sg[jj] = gj;
+                            sx[jj] = px[gj];
+                            sy[jj] = py[gj];
+                            sz[jj] = pz[gj];
+#pragma unroll
+                            for (int c = 0; c < NR; ++c)
+                                sv[c][jj] = (rb + c < nrhs) ? rd<LIVE>(xp + (rb + c) * n + gj) : 0.0;
+                        }
                     }
                     __syncthreads();
                     if (ai) {
                         for (int j = q; j < cn; j += Q) {
-                            const int64_t gj = s0 + cb + j;
-                            if (gj == gi)
+                            if (sg[j] == gi)
                                 continue;
                             const double dx = xi - sx[j], dy = yi - sy[j], dz = zi - sz[j];
                             const double r2 = dx * dx + dy * dy + dz * dz;
-                            const double f = E32 ? double(kernel_f32(kind, float(kp), float(r2)))
-                                                 : kernel_f(kind, kp, sqrt(r2));
+                            const double f = E32 ? double(kernel_f32(kd, float(kp), float(r2)))
+                                                 : kernel_f(kd, kp, sqrt(r2));
 #pragma unroll
                             for (int c = 0; c < NR; ++c)
                                 acc[c] += f * sv[c][j];
