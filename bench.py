@@ -59,12 +59,13 @@ DTYPE_NAMES = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
 # (see sources_digest).
 TRAFFIC = {
     "workload": "uniform262k",
-    "fetch_scale": 0.500016, "write_scale": 1.000000,
+    "fetch_scale": 0.500016,
+    "write_scale": 1.000000,
     "kernels": {
-        "k_stage2": {"fetch_kib": 10106678.5833, "write_kib": 8198.8958},
-        "k_s1_wide": {"fetch_kib": 2559453.0781, "write_kib": 34831.4323},
+        "k_stage2": {"fetch_kib": 10105475.4375, "write_kib": 8198.3229},
+        "k_s1_wide": {"fetch_kib": 2551872.3438, "write_kib": 35194.4089},
     },
-    "sources_sha256": "f33970800215d821173e4abe65f9537ac398dfe545884fc9cf2e471ad9e45eb0",
+    "sources_sha256": "56043d14438b5b9a3065bde2e48fb7b01c5bfe4361b96bf4191d5524db659a6a",
 }
 
 
