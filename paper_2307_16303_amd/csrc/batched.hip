@@ -232,7 +232,8 @@ __global__ void __launch_bounds__(64)
             // column clamped into the block and a tile clamped into the RHS, so
             // that the loads of the next K-step stay countable; the raw values
             // are masked where they are used, and two fragment buffers let the
-            // next K-step load while the MFMAs of the current one run.
+            // next K-step load while the MFMAs of the current one run (a ring
+            // of four K-steps cost a wave per SIMD and was slower).
             const int cc = min(ca, k - 1);
             auto frag = [&](int j0, T &a, T (&bv)[kNT]) {
                 const int jc = min(j0 + (lane >> 4), len - 1);
@@ -588,28 +589,62 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj)
                     acc64[t][q][jj] = 0.0;
-        int steps = 0;
-        for (int j0 = jb; j0 < je; j0 += 4) {
-            const int j = j0 + (lane >> 4);
-            const bool aj = j < je;
-            T a[MT], bv[kNT];
+        if constexpr (DT == H3D_F64) {
+            for (int j0 = jb; j0 < je; j0 += 4) {
+                const int j = j0 + (lane >> 4);
+                const bool aj = j < je;
+                T a[MT], bv[kNT];
 #pragma unroll
-            for (int t = 0; t < MT; ++t) {
-                int64_t ea = int64_t(ca[t]) * len + j;
-                if (panel && ac[t] && aj)  // U_b stored as row panels (adjoint above lc)
-                    ea = panel_off(leaf_off, leaf_of, shc, int32_t(off), k, j, ca[t]);
-                a[t] = (ac[t] && aj) ? T(FacB<DT>::ld(p + ea)) : T(0);
-            }
-#pragma unroll
-            for (int q = 0; q < kNT; ++q)
-                bv[q] = (aj && q < ntl) ? Xs[(off + j) * NP + nb + 16 * q + (lane & 15)] : T(0);
-#pragma unroll
-            for (int t = 0; t < MT; ++t)
+                for (int t = 0; t < MT; ++t) {
+                    int64_t ea = int64_t(ca[t]) * len + j;
+                    if (panel && ac[t] && aj)  // U_b stored as row panels (adjoint above lc)
+                        ea = panel_off(leaf_off, leaf_of, shc, int32_t(off), k, j, ca[t]);
+                    a[t] = (ac[t] && aj) ? T(FacB<DT>::ld(p + ea)) : T(0);
+                }
 #pragma unroll
                 for (int q = 0; q < kNT; ++q)
-                    if (q < ntl)
-                        acc[t][q] = C::mfma(a[t], bv[q], acc[t][q]);
-            if constexpr (DT != H3D_F64) {
+                    bv[q] = (aj && q < ntl) ? Xs[(off + j) * NP + nb + 16 * q + (lane & 15)] : T(0);
+#pragma unroll
+                for (int t = 0; t < MT; ++t)
+#pragma unroll
+                    for (int q = 0; q < kNT; ++q)
+                        if (q < ntl)
+                            acc[t][q] = C::mfma(a[t], bv[q], acc[t][q]);
+            }
+        } else if (je > jb && k > 0) {
+            // FP32/BF16 tiles: a ring of D K-steps of fragments in flight.
+            // Every load is issued from a row clamped into the item, a column
+            // clamped into the block and a tile clamped into the RHS; the raw
+            // values are masked where the MFMA uses them, so the sums are
+            // those of the plain loop, in the same order.
+            constexpr int D = MT >= 4 ? 2 : 4;
+            int cc[MT];
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+                cc[t] = min(ca[t], k - 1);
+            auto frag = [&](int j0, T (&a)[MT], T (&bv)[kNT]) {
+                const int jc = min(j0 + (lane >> 4), je - 1);
+#pragma unroll
+                for (int t = 0; t < MT; ++t) {
+                    int64_t ea = int64_t(cc[t]) * len + jc;
+                    if (panel)  // U_b stored as row panels (adjoint above lc)
+                        ea = panel_off(leaf_off, leaf_of, shc, int32_t(off), k, jc, cc[t]);
+                    a[t] = T(FacB<DT>::ld(p + ea));
+                }
+#pragma unroll
+                for (int q = 0; q < kNT; ++q)
+                    bv[q] = Xs[(off + jc) * NP + nb + 16 * min(q, ntl - 1) + (lane & 15)];
+            };
+            int steps = 0;
+            auto step = [&](int j0, const T (&ar)[MT], const T (&br)[kNT]) {
+                const bool aj = j0 + (lane >> 4) < je;
+#pragma unroll
+                for (int t = 0; t < MT; ++t) {
+                    const T a = (ac[t] && aj) ? ar[t] : T(0);
+#pragma unroll
+                    for (int q = 0; q < kNT; ++q)  // tiles past the RHS: 0
+                        acc[t][q] = C::mfma(a, (aj && q < ntl) ? br[q] : T(0), acc[t][q]);
+                }
                 if (++steps == 64) {
                     steps = 0;
 #pragma unroll
@@ -621,6 +656,21 @@ __global__ void __launch_bounds__(64)
                                 acc64[t][q][jj] += double(acc[t][q][jj]);
                             acc[t][q] = typename C::V4{0, 0, 0, 0};
                         }
+                }
+            };
+            T ab[D][MT], bb[D][kNT];
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+                frag(jb + 4 * d, ab[d], bb[d]);
+            for (int j0 = jb; j0 < je; j0 += 4 * D) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const int js = j0 + 4 * d;
+                    if (js < je) {
+                        step(js, ab[d], bb[d]);
+                        if (js + 4 * D < je)
+                            frag(js + 4 * D, ab[d], bb[d]);
+                    }
                 }
             }
         }
