@@ -988,6 +988,14 @@ int tiles_for(int v, int dt) {
     return v >= 48 ? 4 : (v >= 24 ? 2 : 1);
 }
 
+// stage 2, FP64 tiles: two 16-row tiles per wave for boxes of 24 or more
+// points (measured on 262,144 points, 64 RHS, levels 2-4: 2.16 / 4.10 /
+// 4.54 ms with two tiles, 2.44 / 4.41 / 5.17 with four, 2.95 / 5.22 / 6.53
+// with one)
+int tiles_s2(int box, int dt) {
+    return tiles_for(box, dt) > 1 ? 2 : 1;
+}
+
 // stage-1 columns of boxes above this size are split into parts of this many rows
 constexpr int kMfmaSplitBox = 2048;
 constexpr int kMfmaSplitRows = 1024;
@@ -999,7 +1007,7 @@ void ensure_batched_tables(Plan &P, hipStream_t s) {
     for (int l = 1; l <= L; ++l) {
         const int64_t nbl = P.lvl_blk[l + 1] - P.lvl_blk[l];
         const int mean_rank = nbl > 0 ? int(P.lvl_rank_sum[l] / nbl) : 0;
-        P.bt_mt2[l] = tiles_for(P.mean_box[l], P.factor_dtype);
+        P.bt_mt2[l] = tiles_s2(P.mean_box[l], P.factor_dtype);
         // (split items keep the tile index in 8 bits)
         P.bt_split[l] =
             (P.mean_box[l] > kMfmaSplitBox && P.stats.rank_max < 255 * 16) ? kMfmaSplitRows : 0;
@@ -1176,9 +1184,7 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
         3 * (P.L - l), P.tgt_begin, adjoint ? P.src_blk : nullptr,                           \
         adjoint ? P.blk_vptr : P.blk_uptr, P.blk_rank, P.blk_col0, Z, NP, Y,                 \
         int(!adjoint && l < P.chunk_level), P.leaf_of, 3 * (P.L - P.chunk_level))
-        if (P.bt_mt2[l] == 4)
-            H3D_S2M(4);
-        else if (P.bt_mt2[l] == 2)
+        if (P.bt_mt2[l] == 2)
             H3D_S2M(2);
         else
             k_s2_mfma<DT><<<int(P.bt_ns2[l]), 64, 0, s>>>(
