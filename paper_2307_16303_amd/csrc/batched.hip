@@ -589,7 +589,7 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj)
                     acc64[t][q][jj] = 0.0;
-        if constexpr (DT == H3D_F64) {
+        if constexpr (DT == H3D_F64 && MT > 1) {
             for (int j0 = jb; j0 < je; j0 += 4) {
                 const int j = j0 + (lane >> 4);
                 const bool aj = j < je;
@@ -612,7 +612,8 @@ __global__ void __launch_bounds__(64)
                             acc[t][q] = C::mfma(a[t], bv[q], acc[t][q]);
             }
         } else if (je > jb && k > 0) {
-            // FP32/BF16 tiles: a ring of D K-steps of fragments in flight.
+            // FP32/BF16 tiles, and single FP64 tiles: a ring of D K-steps of
+            // fragments in flight.
             // Every load is issued from a row clamped into the item, a column
             // clamped into the block and a tile clamped into the RHS; the raw
             // values are masked where the MFMA uses them, so the sums are
@@ -645,7 +646,7 @@ __global__ void __launch_bounds__(64)
                     for (int q = 0; q < kNT; ++q)  // tiles past the RHS: 0
                         acc[t][q] = C::mfma(a, (aj && q < ntl) ? br[q] : T(0), acc[t][q]);
                 }
-                if (++steps == 64) {
+                if (DT != H3D_F64 && ++steps == 64) {
                     steps = 0;
 #pragma unroll
                     for (int t = 0; t < MT; ++t)
