@@ -435,17 +435,20 @@ __global__ void __launch_bounds__(64)
     const int64_t tb = it.x;
     const int32_t bs = leaf_off[tb << sh], bm = leaf_off[(tb + 1) << sh] - bs;
     const int r0 = it.y * 16 * MT;
-    int ia[MT];
+    // ia: the lane's row of tile t; iac: that row clamped into the box, which
+    // every load addresses (rows past the box are masked where used)
+    int ia[MT], iac[MT];
     bool ar[MT];
     int32_t pr0[MT], pld[MT];
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
         ia[t] = r0 + 16 * t + (lane & 15);
         ar[t] = ia[t] < bm;
+        iac[t] = min(ia[t], bm - 1);
         pr0[t] = bs;
         pld[t] = bm;
-        if (panel && ar[t]) {  // row panels: this row's chunk box
-            const int32_t ch = leaf_of[bs + ia[t]] >> shc;
+        if (panel) {  // row panels: this row's chunk box
+            const int32_t ch = leaf_of[bs + iac[t]] >> shc;
             pr0[t] = leaf_off[ch << shc];
             pld[t] = leaf_off[(ch + 1) << shc] - pr0[t];
         }
@@ -480,38 +483,59 @@ __global__ void __launch_bounds__(64)
             const int k = rank[bi];
             const int64_t col0 = blk_col0[bi];
             const F *__restrict__ base = static_cast<const F *>(fptr[bi]);
+            if (k <= 0)
+                continue;
             const F *p[MT];
 #pragma unroll
             for (int t = 0; t < MT; ++t)
-                p[t] = base + (int64_t(pr0[t] - bs) * k + (bs + ia[t] - pr0[t]));
-            for (int c0 = 0; c0 < k; c0 += 4) {
-                const int c = c0 + (lane >> 4);
-                const bool ak = c < k;
-                T a[MT], bv[kNT];
+                p[t] = base + (int64_t(pr0[t] - bs) * k + (bs + iac[t] - pr0[t]));
+            // a ring of D K-steps of the block's fragments in flight: every
+            // load from a row clamped into the box, a column clamped into the
+            // block and a tile clamped into the RHS, masked where the MFMA
+            // uses it, so the sums are those of one K-step at a time
+            constexpr int D = 2;
+            auto frag = [&](int cs, T (&a)[MT], T (&bv)[kNT]) {
+                const int cc = min(cs + (lane >> 4), k - 1);
 #pragma unroll
                 for (int t = 0; t < MT; ++t)
-                    a[t] = (ar[t] && ak) ? T(FacB<DT>::ld(p[t] + int64_t(c) * pld[t])) : T(0);
+                    a[t] = T(FacB<DT>::ld(p[t] + int64_t(cc) * pld[t]));
 #pragma unroll
                 for (int q = 0; q < kNT; ++q)
-                    bv[q] = (ak && q < ntl) ? Z[(col0 + c) * NP + nb + 16 * q + (lane & 15)] : T(0);
+                    bv[q] = Z[(col0 + cc) * NP + nb + 16 * min(q, ntl - 1) + (lane & 15)];
+            };
+            T ab[D][MT], bb[D][kNT];
 #pragma unroll
-                for (int t = 0; t < MT; ++t)
+            for (int d = 0; d < D; ++d)
+                frag(4 * d, ab[d], bb[d]);
+            for (int c0 = 0; c0 < k; c0 += 4 * D) {
 #pragma unroll
-                    for (int q = 0; q < kNT; ++q)
-                        if (q < ntl)
-                            acc[t][q] = C::mfma(a[t], bv[q], acc[t][q]);
-                if constexpr (DT != H3D_F64) {
-                    if (++steps == 64) {
-                        steps = 0;
+                for (int d = 0; d < D; ++d) {
+                    const int cs = c0 + 4 * d;
+                    if (cs >= k)
+                        break;
+                    const bool ak = cs + (lane >> 4) < k;
 #pragma unroll
-                        for (int t = 0; t < MT; ++t)
+                    for (int t = 0; t < MT; ++t) {
+                        const T a = (ar[t] && ak) ? ab[d][t] : T(0);
 #pragma unroll
-                            for (int q = 0; q < kNT; ++q) {
+                        for (int q = 0; q < kNT; ++q)  // tiles past the RHS: 0
+                            acc[t][q] = C::mfma(a, (ak && q < ntl) ? bb[d][q] : T(0), acc[t][q]);
+                    }
+                    if (cs + 4 * D < k)
+                        frag(cs + 4 * D, ab[d], bb[d]);
+                    if constexpr (DT != H3D_F64) {
+                        if (++steps == 64) {
+                            steps = 0;
 #pragma unroll
-                                for (int jj = 0; jj < 4; ++jj)
-                                    acc64[t][q][jj] += double(acc[t][q][jj]);
-                                acc[t][q] = typename C::V4{0, 0, 0, 0};
-                            }
+                            for (int t = 0; t < MT; ++t)
+#pragma unroll
+                                for (int q = 0; q < kNT; ++q) {
+#pragma unroll
+                                    for (int jj = 0; jj < 4; ++jj)
+                                        acc64[t][q][jj] += double(acc[t][q][jj]);
+                                    acc[t][q] = typename C::V4{0, 0, 0, 0};
+                                }
+                        }
                     }
                 }
             }
