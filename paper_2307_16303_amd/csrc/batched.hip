@@ -738,6 +738,12 @@ __global__ void __launch_bounds__(64)
     using T = typename C::T;
     using F = typename FacB<DT>::T;
     __shared__ T zl[16][16 * kNT + 1];  // one Z tile: [column][RHS]
+    // metadata of the leaf's next 64 blocks
+    __shared__ int32_t s_k[64], s_n[64];
+    __shared__ int64_t s_so[64];
+    __shared__ const F *s_v[64];
+    __shared__ const F *s_u[64];
+    __shared__ T s_sc[64];
     const int64_t w = blockIdx.x;
     if (w >= nitems)
         return;
@@ -764,22 +770,40 @@ __global__ void __launch_bounds__(64)
                                    : 0.0;
             }
         }
-        for (int64_t b = e0; b < e1; ++b) {
-            const int k = rank[b];
-            const int n = slen[b];
-            const int64_t so = soff[b];
-            const F *__restrict__ V = static_cast<const F *>(vptr[b]);
-            const F *__restrict__ U = static_cast<const F *>(uptr[b]);
-            T sc = T(1);
-            if (DT == H3D_BF16_SCALED)
-                sc = T(double(scale2[2 * b]) * double(scale2[2 * b + 1]));
-            if (k > 0 && k <= 16 && n <= 16) {
-                // one column tile, at most four K-steps in each stage (almost
-                // every block at this level): all loads of the block are issued
-                // at once, from rows and columns clamped into the block, and
-                // masked where they are used
-                const int cc = min(lane & 15, k - 1), iac = min(ia, bm - 1);
-                T av[4], xv[4][kNT], uv[4];
+        // The blocks 64 at a time: their metadata staged in LDS, and (FP32
+        // and BF16 fragments) the loads of block i + 1 issued before block
+        // i's MFMAs run (two named register sets, used alternately).  The
+        // loads are issued for every
+        // block, from rows and columns clamped into it (a block of rank 0
+        // reads at most 16 entries from its V pointer, which stay inside the
+        // padding that follows every chunk of factors), so that the waits for
+        // them stay countable; only blocks with k, n <= 16 use the values.
+        for (int64_t q0 = e0; q0 < e1; q0 += 64) {
+            const int nbk = int(min<int64_t>(64, e1 - q0));
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (lane < nbk) {
+                const int64_t b = q0 + lane;
+                s_k[lane] = rank[b];
+                s_n[lane] = slen[b];
+                s_so[lane] = soff[b];
+                s_v[lane] = static_cast<const F *>(vptr[b]);
+                s_u[lane] = static_cast<const F *>(uptr[b]);
+                s_sc[lane] = DT == H3D_BF16_SCALED ? T(double(scale2[2 * b]) * double(scale2[2 * b + 1]))
+                                                   : T(1);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            auto load = [&](int i, T (&av)[4], T (&xv)[4][kNT], T (&uv)[4]) {
+                const int k = s_k[i], n = s_n[i];
+                const int64_t so = s_so[i];
+                const F *__restrict__ V = s_v[i];
+                // rank 0: both reads go to V, at most 16 entries in
+                const F *__restrict__ U = k > 0 ? s_u[i] : V;
+                const int cc = min(lane & 15, max(k, 1) - 1);
+                const int iu = k > 0 ? min(ia, bm - 1) : min(min(ia, bm - 1), 15);
 #pragma unroll
                 for (int st = 0; st < 4; ++st) {
                     const int jc = min(4 * st + (lane >> 4), n - 1);
@@ -787,97 +811,129 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
                     for (int q = 0; q < kNT; ++q)
                         xv[st][q] = Xs[(so + jc) * NP + nb + 16 * min(q, ntl - 1) + (lane & 15)];
-                    uv[st] = T(FacB<DT>::ld(U + int64_t(min(4 * st + (lane >> 4), k - 1)) * bm + iac));
+                    uv[st] = T(FacB<DT>::ld(U + int64_t(min(4 * st + (lane >> 4), max(k, 1) - 1)) * bm + iu));
                 }
-                typename C::V4 zt[kNT];
+            };
+            auto run = [&](int i, const T (&av)[4], const T (&xv)[4][kNT], const T (&uv)[4]) {
+                const int k = s_k[i], n = s_n[i];
+                const int64_t so = s_so[i];
+                const F *__restrict__ V = s_v[i];
+                const F *__restrict__ U = s_u[i];
+                const T sc = s_sc[i];
+                if (k > 0 && k <= 16 && n <= 16) {
+                    // one column tile, at most four K-steps in each stage
+                    // (almost every block at this level), loaded in advance
+                    typename C::V4 zt[kNT];
 #pragma unroll
-                for (int q = 0; q < kNT; ++q)
-                    zt[q] = typename C::V4{0, 0, 0, 0};
+                    for (int q = 0; q < kNT; ++q)
+                        zt[q] = typename C::V4{0, 0, 0, 0};
 #pragma unroll
-                for (int st = 0; st < 4; ++st)
-                    if (4 * st < n) {
-                        const bool aj = 4 * st + (lane >> 4) < n;
-                        const T a = ((lane & 15) < k && aj) ? av[st] : T(0);
+                    for (int st = 0; st < 4; ++st)
+                        if (4 * st < n) {
+                            const bool aj = 4 * st + (lane >> 4) < n;
+                            const T a = ((lane & 15) < k && aj) ? av[st] : T(0);
+#pragma unroll
+                            for (int q = 0; q < kNT; ++q)
+                                zt[q] = C::mfma(a, (aj && q < ntl) ? xv[st][q] : T(0), zt[q]);
+                        }
+#pragma unroll
+                    for (int q = 0; q < kNT; ++q)
+#pragma unroll
+                        for (int jj = 0; jj < 4; ++jj)
+                            zl[C::row(lane, jj)][16 * q + (lane & 15)] = zt[q][jj] * sc;
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+                    for (int st = 0; st < 4; ++st)
+                        if (4 * st < k) {
+                            const int c = 4 * st + (lane >> 4);
+                            const bool ak = c < k;
+                            const T a = (ar && ak) ? uv[st] : T(0);
+#pragma unroll
+                            for (int q = 0; q < kNT; ++q)
+                                acc[q] = C::mfma(a, (ak && q < ntl) ? zl[c][16 * q + (lane & 15)] : T(0),
+                                                 acc[q]);
+                        }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                } else {
+                    for (int c0 = 0; c0 < k; c0 += 16) {
+                        // stage 1: Z tile = V^T X over the source rows
+                        const int ca = c0 + (lane & 15);
+                        const bool ac = ca < k;
+                        typename C::V4 zt[kNT];
 #pragma unroll
                         for (int q = 0; q < kNT; ++q)
-                            zt[q] = C::mfma(a, (aj && q < ntl) ? xv[st][q] : T(0), zt[q]);
-                    }
+                            zt[q] = typename C::V4{0, 0, 0, 0};
+                        for (int j0 = 0; j0 < n; j0 += 4) {
+                            const int j = j0 + (lane >> 4);
+                            const bool aj = j < n;
+                            const T a = (ac && aj) ? T(FacB<DT>::ld(V + int64_t(ca) * n + j)) : T(0);
 #pragma unroll
-                for (int q = 0; q < kNT; ++q)
-#pragma unroll
-                    for (int jj = 0; jj < 4; ++jj)
-                        zl[C::row(lane, jj)][16 * q + (lane & 15)] = zt[q][jj] * sc;
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-                for (int st = 0; st < 4; ++st)
-                    if (4 * st < k) {
-                        const int c = 4 * st + (lane >> 4);
-                        const bool ak = c < k;
-                        const T a = (ar && ak) ? uv[st] : T(0);
+                            for (int q = 0; q < kNT; ++q) {
+                                const T bv = (aj && q < ntl) ? Xs[(so + j) * NP + nb + 16 * q + (lane & 15)]
+                                                             : T(0);
+                                if (q < ntl)
+                                    zt[q] = C::mfma(a, bv, zt[q]);
+                            }
+                        }
+                        // output layout -> [column][RHS] in LDS
 #pragma unroll
                         for (int q = 0; q < kNT; ++q)
-                            acc[q] = C::mfma(a, (ak && q < ntl) ? zl[c][16 * q + (lane & 15)] : T(0),
-                                             acc[q]);
-                    }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            } else
-            for (int c0 = 0; c0 < k; c0 += 16) {
-                // stage 1: Z tile = V^T X over the source rows
-                const int ca = c0 + (lane & 15);
-                const bool ac = ca < k;
-                typename C::V4 zt[kNT];
 #pragma unroll
-                for (int q = 0; q < kNT; ++q)
-                    zt[q] = typename C::V4{0, 0, 0, 0};
-                for (int j0 = 0; j0 < n; j0 += 4) {
-                    const int j = j0 + (lane >> 4);
-                    const bool aj = j < n;
-                    const T a = (ac && aj) ? T(FacB<DT>::ld(V + int64_t(ca) * n + j)) : T(0);
+                            for (int jj = 0; jj < 4; ++jj)
+                                zl[C::row(lane, jj)][16 * q + (lane & 15)] = zt[q][jj] * sc;
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        // stage 2: Y tile += U Z over the tile's columns
+                        const int kc = min(16, k - c0);
+                        for (int s4 = 0; s4 < kc; s4 += 4) {
+                            const int c = s4 + (lane >> 4);
+                            const bool ak = c < kc;
+                            const T a = (ar && ak) ? T(FacB<DT>::ld(U + int64_t(c0 + c) * bm + ia)) : T(0);
 #pragma unroll
-                    for (int q = 0; q < kNT; ++q) {
-                        const T bv = (aj && q < ntl) ? Xs[(so + j) * NP + nb + 16 * q + (lane & 15)]
-                                                     : T(0);
-                        if (q < ntl)
-                            zt[q] = C::mfma(a, bv, zt[q]);
+                            for (int q = 0; q < kNT; ++q) {
+                                const T bv = (ak && q < ntl) ? zl[c][16 * q + (lane & 15)] : T(0);
+                                if (q < ntl)
+                                    acc[q] = C::mfma(a, bv, acc[q]);
+                            }
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                     }
                 }
-                // output layout -> [column][RHS] in LDS
-#pragma unroll
-                for (int q = 0; q < kNT; ++q)
-#pragma unroll
-                    for (int jj = 0; jj < 4; ++jj)
-                        zl[C::row(lane, jj)][16 * q + (lane & 15)] = zt[q][jj] * sc;
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                // stage 2: Y tile += U Z over the tile's columns
-                const int kc = min(16, k - c0);
-                for (int s4 = 0; s4 < kc; s4 += 4) {
-                    const int c = s4 + (lane >> 4);
-                    const bool ak = c < kc;
-                    const T a = (ar && ak) ? T(FacB<DT>::ld(U + int64_t(c0 + c) * bm + ia)) : T(0);
+                if constexpr (DT != H3D_F64) {
 #pragma unroll
                     for (int q = 0; q < kNT; ++q) {
-                        const T bv = (ak && q < ntl) ? zl[c][16 * q + (lane & 15)] : T(0);
-                        if (q < ntl)
-                            acc[q] = C::mfma(a, bv, acc[q]);
+#pragma unroll
+                        for (int jj = 0; jj < 4; ++jj)
+                            acc64[q][jj] += double(acc[q][jj]);
+                        acc[q] = typename C::V4{0, 0, 0, 0};
                     }
                 }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            }
-            if constexpr (DT != H3D_F64) {
-#pragma unroll
-                for (int q = 0; q < kNT; ++q) {
-#pragma unroll
-                    for (int jj = 0; jj < 4; ++jj)
-                        acc64[q][jj] += double(acc[q][jj]);
-                    acc[q] = typename C::V4{0, 0, 0, 0};
+            };
+            T av0[4], xv0[4][kNT], uv0[4], av1[4], xv1[4][kNT], uv1[4];
+            if constexpr (DT == H3D_F64) {
+                // FP64 fragments: a second register set costs occupancy
+                // (measured slower); each block loads just before it runs
+                for (int i = 0; i < nbk; ++i) {
+                    load(i, av0, xv0, uv0);
+                    run(i, av0, xv0, uv0);
+                }
+            } else {
+                // (past the last block the loads repeat it, unused)
+                load(0, av0, xv0, uv0);
+                for (int i = 0; i < nbk; i += 2) {
+                    load(min(i + 1, nbk - 1), av1, xv1, uv1);
+                    run(i, av0, xv0, uv0);
+                    if (i + 1 >= nbk)
+                        break;
+                    load(min(i + 2, nbk - 1), av0, xv0, uv0);
+                    run(i + 1, av1, xv1, uv1);
                 }
             }
         }
