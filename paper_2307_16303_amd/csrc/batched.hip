@@ -302,6 +302,9 @@ __global__ void __launch_bounds__(64)
     using C = CT<DT>;
     using T = typename C::T;
     using F = typename FacB<DT>::T;
+    __shared__ int32_t s_bk[64];
+    __shared__ int64_t s_bc[64];
+    __shared__ const F *s_bp[64];
     const int64_t w = blockIdx.x;
     if (w >= nitems)
         return;
@@ -331,70 +334,84 @@ __global__ void __launch_bounds__(64)
                 const int r = r0 + C::row(lane, jj);
                 acc64[q][jj] = (q < ntl && r < bm) ? Y[(bs + r) * int64_t(NP) + nb + 16 * q + (lane & 15)] : 0.0;
             }
-        for (int64_t e = e0; e < e1; ++e) {
-            const int64_t bi = grp_blk ? grp_blk[e] : e;
-            const int k = rank[bi];
-            const int64_t col0 = blk_col0[bi];
-            typename C::V4 acc[kNT];
-#pragma unroll
-            for (int q = 0; q < kNT; ++q)
-                acc[q] = typename C::V4{0, 0, 0, 0};
-            if constexpr (DT == H3D_F64) {
-                const F *__restrict__ p = static_cast<const F *>(fptr[bi]) +
-                                          (int64_t(pr0 - bs) * k + (bs + ia - pr0));
-                for (int c0 = 0; c0 < k; c0 += 4) {
-                    const int c = c0 + (lane >> 4);
-                    const bool ak = c < k;
-                    const T a = (ar && ak) ? T(FacB<DT>::ld(p + int64_t(c) * pld)) : T(0);
-                    T bv[kNT];
-#pragma unroll
-                    for (int q = 0; q < kNT; ++q)
-                        bv[q] = (ak && q < ntl) ? Z[(col0 + c) * NP + nb + 16 * q + (lane & 15)] : T(0);
-#pragma unroll
-                    for (int q = 0; q < kNT; ++q)
-                        if (q < ntl)
-                            acc[q] = C::mfma(a, bv[q], acc[q]);
-                }
-            } else if (k > 0) {
-                // FP32/BF16 tiles (measured: slower with FP64 tiles, whose
-                // fragments take twice the registers): every load from a column
-                // of the block and a tile of the RHS, raw values masked where
-                // they are used, and the fragments of the next K-step loaded
-                // while the current one runs
-                const F *__restrict__ p = static_cast<const F *>(fptr[bi]) +
-                                          (int64_t(pr0 - bs) * k + (bs + iac - pr0));
-                auto frag = [&](int c0, T &a, T (&bv)[kNT]) {
-                    const int cc = min(c0 + (lane >> 4), k - 1);
-                    a = T(FacB<DT>::ld(p + int64_t(cc) * pld));
-#pragma unroll
-                    for (int q = 0; q < kNT; ++q)
-                        bv[q] = Z[(col0 + cc) * NP + nb + 16 * min(q, ntl - 1) + (lane & 15)];
-                };
-                auto step = [&](int c0, const T ra, const T (&rb)[kNT]) {
-                    const bool ak = c0 + (lane >> 4) < k;
-                    const T a = (ar && ak) ? ra : T(0);
-#pragma unroll
-                    for (int q = 0; q < kNT; ++q)
-                        acc[q] = C::mfma(a, (ak && q < ntl) ? rb[q] : T(0), acc[q]);
-                };
-                T a0, b0[kNT], a1, b1[kNT];
-                frag(0, a0, b0);
-                for (int c0 = 0; c0 < k; c0 += 8) {
-                    if (c0 + 4 < k)
-                        frag(c0 + 4, a1, b1);
-                    step(c0, a0, b0);
-                    if (c0 + 4 >= k)
-                        break;
-                    if (c0 + 8 < k)
-                        frag(c0 + 8, a0, b0);
-                    step(c0 + 4, a1, b1);
-                }
+        for (int64_t q0 = e0; q0 < e1; q0 += 64) {
+            // metadata of the box's next 64 blocks, staged in LDS
+            const int nbk = int(min<int64_t>(64, e1 - q0));
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (lane < nbk) {
+                const int64_t bj = grp_blk ? grp_blk[q0 + lane] : q0 + lane;
+                s_bk[lane] = rank[bj];
+                s_bc[lane] = blk_col0[bj];
+                s_bp[lane] = static_cast<const F *>(fptr[bj]);
             }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int ib = 0; ib < nbk; ++ib) {
+                const int k = s_bk[ib];
+                const int64_t col0 = s_bc[ib];
+                typename C::V4 acc[kNT];
 #pragma unroll
-            for (int q = 0; q < kNT; ++q)
+                for (int q = 0; q < kNT; ++q)
+                    acc[q] = typename C::V4{0, 0, 0, 0};
+                if constexpr (DT == H3D_F64) {
+                    const F *__restrict__ p = s_bp[ib] + (int64_t(pr0 - bs) * k + (bs + ia - pr0));
+                    for (int c0 = 0; c0 < k; c0 += 4) {
+                        const int c = c0 + (lane >> 4);
+                        const bool ak = c < k;
+                        const T a = (ar && ak) ? T(FacB<DT>::ld(p + int64_t(c) * pld)) : T(0);
+                        T bv[kNT];
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj)
-                    acc64[q][jj] += double(acc[q][jj]);
+                        for (int q = 0; q < kNT; ++q)
+                            bv[q] = (ak && q < ntl) ? Z[(col0 + c) * NP + nb + 16 * q + (lane & 15)] : T(0);
+#pragma unroll
+                        for (int q = 0; q < kNT; ++q)
+                            if (q < ntl)
+                                acc[q] = C::mfma(a, bv[q], acc[q]);
+                    }
+                } else if (k > 0) {
+                    // FP32/BF16 tiles (measured: slower with FP64 tiles, whose
+                    // fragments take twice the registers): every load from a column
+                    // of the block and a tile of the RHS, raw values masked where
+                    // they are used, and the fragments of the next K-step loaded
+                    // while the current one runs
+                    const F *__restrict__ p = s_bp[ib] + (int64_t(pr0 - bs) * k + (bs + iac - pr0));
+                    auto frag = [&](int c0, T &a, T (&bv)[kNT]) {
+                        const int cc = min(c0 + (lane >> 4), k - 1);
+                        a = T(FacB<DT>::ld(p + int64_t(cc) * pld));
+#pragma unroll
+                        for (int q = 0; q < kNT; ++q)
+                            bv[q] = Z[(col0 + cc) * NP + nb + 16 * min(q, ntl - 1) + (lane & 15)];
+                    };
+                    auto step = [&](int c0, const T ra, const T (&rb)[kNT]) {
+                        const bool ak = c0 + (lane >> 4) < k;
+                        const T a = (ar && ak) ? ra : T(0);
+#pragma unroll
+                        for (int q = 0; q < kNT; ++q)
+                            acc[q] = C::mfma(a, (ak && q < ntl) ? rb[q] : T(0), acc[q]);
+                    };
+                    T a0, b0[kNT], a1, b1[kNT];
+                    frag(0, a0, b0);
+                    for (int c0 = 0; c0 < k; c0 += 8) {
+                        if (c0 + 4 < k)
+                            frag(c0 + 4, a1, b1);
+                        step(c0, a0, b0);
+                        if (c0 + 4 >= k)
+                            break;
+                        if (c0 + 8 < k)
+                            frag(c0 + 8, a0, b0);
+                        step(c0 + 4, a1, b1);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < kNT; ++q)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj)
+                        acc64[q][jj] += double(acc[q][jj]);
+        
+            }
         }
 #pragma unroll
         for (int q = 0; q < kNT; ++q)
@@ -427,6 +444,9 @@ __global__ void __launch_bounds__(64)
     using C = CT<DT>;
     using T = typename C::T;
     using F = typename FacB<DT>::T;
+    __shared__ int32_t s_bk[64];
+    __shared__ int64_t s_bc[64];
+    __shared__ const F *s_bp[64];
     const int64_t w = blockIdx.x;
     if (w >= nitems)
         return;
@@ -478,66 +498,82 @@ __global__ void __launch_bounds__(64)
                     }
                 }
         int steps = 0;
-        for (int64_t e = e0; e < e1; ++e) {
-            const int64_t bi = grp_blk ? grp_blk[e] : e;
-            const int k = rank[bi];
-            const int64_t col0 = blk_col0[bi];
-            const F *__restrict__ base = static_cast<const F *>(fptr[bi]);
-            if (k <= 0)
-                continue;
-            const F *p[MT];
-#pragma unroll
-            for (int t = 0; t < MT; ++t)
-                p[t] = base + (int64_t(pr0[t] - bs) * k + (bs + iac[t] - pr0[t]));
-            // a ring of D K-steps of the block's fragments in flight: every
-            // load from a row clamped into the box, a column clamped into the
-            // block and a tile clamped into the RHS, masked where the MFMA
-            // uses it, so the sums are those of one K-step at a time
-            constexpr int D = 2;
-            auto frag = [&](int cs, T (&a)[MT], T (&bv)[kNT]) {
-                const int cc = min(cs + (lane >> 4), k - 1);
+        for (int64_t q0 = e0; q0 < e1; q0 += 64) {
+            // metadata of the box's next 64 blocks, staged in LDS
+            const int nbk = int(min<int64_t>(64, e1 - q0));
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (lane < nbk) {
+                const int64_t bj = grp_blk ? grp_blk[q0 + lane] : q0 + lane;
+                s_bk[lane] = rank[bj];
+                s_bc[lane] = blk_col0[bj];
+                s_bp[lane] = static_cast<const F *>(fptr[bj]);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int ib = 0; ib < nbk; ++ib) {
+                const int k = s_bk[ib];
+                const int64_t col0 = s_bc[ib];
+                const F *__restrict__ base = s_bp[ib];
+                if (k <= 0)
+                    continue;
+                const F *p[MT];
 #pragma unroll
                 for (int t = 0; t < MT; ++t)
-                    a[t] = T(FacB<DT>::ld(p[t] + int64_t(cc) * pld[t]));
+                    p[t] = base + (int64_t(pr0[t] - bs) * k + (bs + iac[t] - pr0[t]));
+                // a ring of D K-steps of the block's fragments in flight: every
+                // load from a row clamped into the box, a column clamped into the
+                // block and a tile clamped into the RHS, masked where the MFMA
+                // uses it, so the sums are those of one K-step at a time
+                constexpr int D = 2;
+                auto frag = [&](int cs, T (&a)[MT], T (&bv)[kNT]) {
+                    const int cc = min(cs + (lane >> 4), k - 1);
 #pragma unroll
-                for (int q = 0; q < kNT; ++q)
-                    bv[q] = Z[(col0 + cc) * NP + nb + 16 * min(q, ntl - 1) + (lane & 15)];
-            };
-            T ab[D][MT], bb[D][kNT];
+                    for (int t = 0; t < MT; ++t)
+                        a[t] = T(FacB<DT>::ld(p[t] + int64_t(cc) * pld[t]));
 #pragma unroll
-            for (int d = 0; d < D; ++d)
-                frag(4 * d, ab[d], bb[d]);
-            for (int c0 = 0; c0 < k; c0 += 4 * D) {
+                    for (int q = 0; q < kNT; ++q)
+                        bv[q] = Z[(col0 + cc) * NP + nb + 16 * min(q, ntl - 1) + (lane & 15)];
+                };
+                T ab[D][MT], bb[D][kNT];
 #pragma unroll
-                for (int d = 0; d < D; ++d) {
-                    const int cs = c0 + 4 * d;
-                    if (cs >= k)
-                        break;
-                    const bool ak = cs + (lane >> 4) < k;
+                for (int d = 0; d < D; ++d)
+                    frag(4 * d, ab[d], bb[d]);
+                for (int c0 = 0; c0 < k; c0 += 4 * D) {
 #pragma unroll
-                    for (int t = 0; t < MT; ++t) {
-                        const T a = (ar[t] && ak) ? ab[d][t] : T(0);
+                    for (int d = 0; d < D; ++d) {
+                        const int cs = c0 + 4 * d;
+                        if (cs >= k)
+                            break;
+                        const bool ak = cs + (lane >> 4) < k;
 #pragma unroll
-                        for (int q = 0; q < kNT; ++q)  // tiles past the RHS: 0
-                            acc[t][q] = C::mfma(a, (ak && q < ntl) ? bb[d][q] : T(0), acc[t][q]);
-                    }
-                    if (cs + 4 * D < k)
-                        frag(cs + 4 * D, ab[d], bb[d]);
-                    if constexpr (DT != H3D_F64) {
-                        if (++steps == 64) {
-                            steps = 0;
+                        for (int t = 0; t < MT; ++t) {
+                            const T a = (ar[t] && ak) ? ab[d][t] : T(0);
 #pragma unroll
-                            for (int t = 0; t < MT; ++t)
+                            for (int q = 0; q < kNT; ++q)  // tiles past the RHS: 0
+                                acc[t][q] = C::mfma(a, (ak && q < ntl) ? bb[d][q] : T(0), acc[t][q]);
+                        }
+                        if (cs + 4 * D < k)
+                            frag(cs + 4 * D, ab[d], bb[d]);
+                        if constexpr (DT != H3D_F64) {
+                            if (++steps == 64) {
+                                steps = 0;
 #pragma unroll
-                                for (int q = 0; q < kNT; ++q) {
+                                for (int t = 0; t < MT; ++t)
 #pragma unroll
-                                    for (int jj = 0; jj < 4; ++jj)
-                                        acc64[t][q][jj] += double(acc[t][q][jj]);
-                                    acc[t][q] = typename C::V4{0, 0, 0, 0};
-                                }
+                                    for (int q = 0; q < kNT; ++q) {
+#pragma unroll
+                                        for (int jj = 0; jj < 4; ++jj)
+                                            acc64[t][q][jj] += double(acc[t][q][jj]);
+                                        acc[t][q] = typename C::V4{0, 0, 0, 0};
+                                    }
+                            }
                         }
                     }
                 }
+        
             }
         }
 #pragma unroll
