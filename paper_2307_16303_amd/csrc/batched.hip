@@ -10,10 +10,13 @@
 // All three run on 16x16x4 MFMA tiles (FP64 MFMA for FP64 factors, FP32 MFMA
 // for FP32 and BF16 factors).  Right-hand sides are held point-major (a row of
 // NP = 16 ceil(nrhs/16) values per point) so that every B fragment is four
-// 64-byte segments.  FP32 tiles are flushed into FP64 registers every 64
-// K-steps (in stage 2 the K loop runs over the columns of all blocks of a
-// box), so long dot products and the sums over blocks and levels carry FP64
-// accumulation.  The adjoint swaps
+// 64-byte segments.  FP32 tiles are flushed into FP64 registers at least
+// every 64 K-steps (the single-tile stage-2 and finest-level kernels after
+// every block), so long dot products and the sums over blocks and levels
+// carry FP64 accumulation.  Fragment loads are issued from indices clamped
+// into the block and masked where the MFMA uses them, so that the loads of
+// the next K-steps (or the next block) can be in flight while the current
+// MFMAs run.  The adjoint swaps
 // U and V and walks the blocks by source box, as in the one-column kernels.
 #include "product_items.hpp"
 
