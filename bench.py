@@ -315,7 +315,9 @@ def main():
         oracle.set_num_threads(threads)
         y_np = y_head
         xs = x_np.reshape(n, -1)
-        probe = inputs.sample_rows(n, 64, seed=3)
+        # a probe large enough for every thread to stay busy: the rate of a
+        # few dozen rows understates what the threads sustain several times
+        probe = inputs.sample_rows(n, min(n, 2048), seed=3)
         t0 = time.perf_counter()
         oracle.dense_rows(pts, xs, probe, kernel=w["kernel"])
         per_row = (time.perf_counter() - t0) / probe.size
