@@ -167,9 +167,15 @@ h3d_status h3d_autotune(h3d_plan *plan, int64_t nrhs, void *hip_stream);
  * (device pointers, kept by the graph, owned by the caller) and sizes, on a
  * private capture stream.  h3d_graph_launch replays it on hip_stream: same
  * results, bitwise, as h3d_matvec / h3d_matvec_adjoint with the same
- * arguments.  The graph shares the plan's scratch: replays and other
- * products of the same plan must not overlap in time.  Destroy graphs
- * before their plan.
+ * arguments.  The graph shares the plan's scratch and work tables: replays
+ * and other products of the same plan must not overlap in time.  While a
+ * graph of a plan exists, nothing it holds may move, so every call that would
+ * reallocate them returns H3D_EINVAL and changes nothing: h3d_matvec,
+ * h3d_matvec_adjoint, h3d_graph_create or h3d_matvec_batch (for a batch
+ * member) with more right-hand sides than the plan's scratch was sized for,
+ * h3d_autotune, and h3d_destroy of the plan (or of its batch).  Destroy the
+ * graphs first.  h3d_graph_launch and h3d_graph_destroy on a destroyed graph
+ * return H3D_EINVAL.
  */
 typedef struct h3d_graph h3d_graph;
 h3d_status h3d_graph_create(h3d_plan *plan, const void *x, void *y, int64_t nrhs, int64_t ldx,
@@ -243,7 +249,10 @@ typedef enum {
  * receives the bytes written.  Factors are returned in FP64 (scales applied). */
 h3d_status h3d_export(const h3d_plan *plan, int32_t what, void *host_buf, size_t *bytes);
 
-/* Releases the plan (NULL is accepted). */
+/* Releases the plan (NULL is accepted).  H3D_EINVAL, with nothing released,
+ * for a handle that is not a live plan (already destroyed), for a problem of
+ * a batch (destroy the batch) and for a plan with live graphs.  Every other
+ * entry point returns H3D_ENOTBUILT for a destroyed plan. */
 h3d_status h3d_destroy(h3d_plan *plan);
 
 /* Message of the last failure on the calling thread ("" if none). */

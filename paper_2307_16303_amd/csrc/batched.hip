@@ -1204,18 +1204,38 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
     const size_t need_x = size_t(n) * NP * sizeof(T);
     const size_t need_y = size_t(n) * NP * sizeof(double);
     const size_t need_z = size_t(std::max<int64_t>(P.ncols, 1)) * NP * sizeof(T);
-    if (need_x > P.bx_bytes || need_y > P.by_bytes || need_z > P.bz_bytes) {
-        P.mem.release(P.bx);
-        P.mem.release(P.by);
-        P.mem.release(P.bz);
-        P.bx = P.mem.alloc(need_x);
-        P.by = P.mem.alloc(need_y);
-        P.bz = P.mem.alloc(need_z);
-        P.bx_bytes = need_x;
-        P.by_bytes = need_y;
-        P.bz_bytes = need_z;
-    }
     ensure_batched_tables(P, s);
+    // partial tiles of the split stage-1 levels (sized for both directions)
+    size_t need_zp = 0;
+    for (int l = 1; l <= P.L; ++l)
+        if (P.bt_split[l] > 0 && P.bt_ns1[l] > 0)
+            need_zp = std::max(need_zp, size_t(P.bt_ns1[l]) * 16 * P.bt_mt1[l] * NP * sizeof(T));
+    // every buffer is grown before the first launch of the product
+    if (need_x > P.bx_bytes || need_y > P.by_bytes || need_z > P.bz_bytes ||
+        need_zp > P.bzp_bytes) {
+        if (P.bx || P.bzp)
+            before_release(P, "a product with more right-hand sides");
+        if (need_x > P.bx_bytes || need_y > P.by_bytes || need_z > P.bz_bytes) {
+            P.mem.release(P.bx);
+            P.mem.release(P.by);
+            P.mem.release(P.bz);
+            P.bx = P.by = P.bz = nullptr;
+            P.bx_bytes = P.by_bytes = P.bz_bytes = 0;
+            P.bx = P.mem.alloc(need_x);
+            P.by = P.mem.alloc(need_y);
+            P.bz = P.mem.alloc(need_z);
+            P.bx_bytes = need_x;
+            P.by_bytes = need_y;
+            P.bz_bytes = need_z;
+        }
+        if (need_zp > P.bzp_bytes) {
+            P.mem.release(P.bzp);
+            P.bzp = nullptr;
+            P.bzp_bytes = 0;
+            P.bzp = P.mem.alloc(need_zp);
+            P.bzp_bytes = need_zp;
+        }
+    }
     T *Xs = static_cast<T *>(P.bx);
     double *Y = static_cast<double *>(P.by);
     T *Z = static_cast<T *>(P.bz);
@@ -1249,16 +1269,7 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
             continue;
         hipEvent_t ev = P.prof.begin(s);
         // split levels: partial tiles of every row part, then their sum
-        T *Zp = nullptr;
-        if (P.bt_split[l] > 0) {
-            const size_t need = size_t(P.bt_ns1[l]) * 16 * P.bt_mt1[l] * NP * sizeof(T);
-            if (need > P.bzp_bytes) {
-                P.mem.release(P.bzp);
-                P.bzp = P.mem.alloc(need);
-                P.bzp_bytes = need;
-            }
-            Zp = static_cast<T *>(P.bzp);
-        }
+        T *Zp = P.bt_split[l] > 0 ? static_cast<T *>(P.bzp) : nullptr;
 #define H3D_S1M(MT)                                                                         \
     k_s1_mfma_w<DT, MT><<<int(P.bt_ns1[l]), 64, 0, s>>>(                                    \
         reinterpret_cast<const int2 *>(P.bt_s1[l]), P.bt_ns1[l], adjoint ? P.blk_m : P.blk_n, \

@@ -4,7 +4,9 @@
 #include <chrono>
 #include <cmath>
 #include <memory>
+#include <mutex>
 #include <new>
+#include <unordered_map>
 
 #include "h3d_internal.hpp"
 
@@ -24,6 +26,40 @@ bool batch_wait_failed(h3d_plan &bp, hipStream_t s);
 namespace {
 
 thread_local std::string g_last_error;
+
+// Handles the library has handed out and not yet released.  Every entry point
+// looks its handle up here first, so a destroyed (or never created) handle
+// gives an error instead of a use of freed memory.
+enum HandleKind { kOwnPlan = 1, kMemberPlan = 2, kGraph = 3 };
+std::mutex g_reg_mu;
+std::unordered_map<const void *, int> g_reg;
+
+void reg_add(const void *h, int kind) {
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    g_reg[h] = kind;
+}
+void reg_del(const void *h) {
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    g_reg.erase(h);
+}
+int reg_kind(const void *h) {
+    std::lock_guard<std::mutex> lk(g_reg_mu);
+    auto it = g_reg.find(h);
+    return it == g_reg.end() ? 0 : it->second;
+}
+
+// H3D_OK for a live, built plan (own or batch member); H3D_ENOTBUILT otherwise.
+h3d_status plan_status(const h3d_plan *plan) {
+    if (!plan)
+        return g_last_error = "plan is NULL", H3D_ENOTBUILT;
+    const int k = reg_kind(plan);
+    if (k != kOwnPlan && k != kMemberPlan)
+        return g_last_error = "not a live plan (destroyed, or never returned by a build call)",
+               H3D_ENOTBUILT;
+    if (!plan->P.built)
+        return g_last_error = "plan is not built", H3D_ENOTBUILT;
+    return H3D_OK;
+}
 
 template <class F> h3d_status guarded(F &&f) {
     try {
@@ -72,8 +108,8 @@ h3d_status batch_plan_error() {
 
 h3d_status matvec_check(h3d_plan *plan, const void *x, void *y, int64_t nrhs, int64_t ldx,
                         int64_t ldy, int32_t io) {
-    if (!plan || !plan->P.built)
-        return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    if (const h3d_status ps = plan_status(plan); ps != H3D_OK)
+        return ps;
     if (plan->batch)
         return batch_plan_error();
     h3d::Plan &P = plan->P;
@@ -146,14 +182,21 @@ h3d_plan *build_plan(const double *points, int64_t n, const h3d_config &cfg,
     P.mem.configure(alloc, s);
     P.n = n;
     P.in_batch = in_batch;
-    h3d::tree_build(P, points, s);
-    h3d::lists_build(P, s);
-    h3d::factors_build(P, s);
-    h3d::near_pair_count(P, s);
-    if (in_batch) {
-        P.s2_waves[0] = P.s2_waves[1] = 1;
-    } else if (!(P.cfg.flags & H3D_FLAG_NO_AUTOTUNE)) {
-        h3d::autotune(P, 1, s);
+    try {
+        h3d::tree_build(P, points, s);
+        h3d::lists_build(P, s);
+        h3d::factors_build(P, s);
+        h3d::near_pair_count(P, s);
+        if (in_batch) {
+            P.s2_waves[0] = P.s2_waves[1] = 1;
+        } else if (!(P.cfg.flags & H3D_FLAG_NO_AUTOTUNE)) {
+            h3d::autotune(P, 1, s);
+        }
+    } catch (...) {
+        // kernels queued before the failure finish before the plan's memory
+        // goes back to the allocator
+        (void)hipStreamSynchronize(s);
+        throw;
     }
     H3D_HIP(hipStreamSynchronize(s));
     h3d_stats &S = P.stats;
@@ -218,6 +261,7 @@ h3d_status h3d_build(const double *points, int64_t n, const h3d_config *cfg,
         delete plan;
         return st;
     }
+    reg_add(plan, kOwnPlan);
     *out = plan;
     return H3D_OK;
 }
@@ -287,14 +331,17 @@ h3d_status h3d_build_batch(int32_t nprob, const double *const *points, const int
         delete bp;
         return st;
     }
+    reg_add(bp, kOwnPlan);
+    for (h3d_plan *q : bp->batch->subs)
+        reg_add(q, kMemberPlan);
     *out = bp;
     return H3D_OK;
 }
 
 h3d_status h3d_matvec_batch(h3d_plan *batch, const void *const *x, void *const *y, int64_t nrhs,
                             int32_t io_dtype, void *hip_stream) {
-    if (!batch || !batch->P.built)
-        return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    if (const h3d_status ps = plan_status(batch); ps != H3D_OK)
+        return ps;
     if (!batch->batch)
         return invalid("not a batch plan (built by h3d_build_batch)");
     if (!x || !y)
@@ -318,8 +365,8 @@ h3d_status h3d_batch_plan(h3d_plan *batch, int32_t i, h3d_plan **out) {
     if (!out)
         return invalid("out must not be NULL");
     *out = nullptr;
-    if (!batch || !batch->P.built)
-        return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    if (const h3d_status ps = plan_status(batch); ps != H3D_OK)
+        return ps;
     if (!batch->batch)
         return invalid("not a batch plan (built by h3d_build_batch)");
     if (i < 0 || size_t(i) >= batch->batch->subs.size())
@@ -329,8 +376,8 @@ h3d_status h3d_batch_plan(h3d_plan *batch, int32_t i, h3d_plan **out) {
 }
 
 h3d_status h3d_batch_check(h3d_plan *batch, void *hip_stream) {
-    if (!batch || !batch->P.built)
-        return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    if (const h3d_status ps = plan_status(batch); ps != H3D_OK)
+        return ps;
     if (!batch->batch)
         return invalid("not a batch plan (built by h3d_build_batch)");
     bool failed = false;
@@ -392,6 +439,7 @@ h3d_status h3d_graph_create(h3d_plan *plan, const void *x, void *y, int64_t nrhs
         H3D_HIP(hipStreamEndCapture(cs, &g->graph));
         P.prof.on = prof;
         H3D_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+        P.live_graphs += 1;
     });
     if (cs)
         (void)hipStreamDestroy(cs);
@@ -405,13 +453,14 @@ h3d_status h3d_graph_create(h3d_plan *plan, const void *x, void *y, int64_t nrhs
         }
         return st;
     }
+    reg_add(g, kGraph);
     *out = g;
     return H3D_OK;
 }
 
 h3d_status h3d_graph_launch(h3d_graph *graph, void *hip_stream) {
-    if (!graph || !graph->exec)
-        return invalid("graph is NULL");
+    if (!graph || reg_kind(graph) != kGraph || !graph->exec)
+        return invalid("not a live graph (NULL or destroyed)");
     return guarded([&] {
         DeviceScope ds(graph->plan->P.device);
         H3D_HIP(hipGraphLaunch(graph->exec, static_cast<hipStream_t>(hip_stream)));
@@ -421,7 +470,12 @@ h3d_status h3d_graph_launch(h3d_graph *graph, void *hip_stream) {
 h3d_status h3d_graph_destroy(h3d_graph *graph) {
     if (!graph)
         return H3D_OK;
+    if (reg_kind(graph) != kGraph)
+        return invalid("not a live graph (already destroyed?)");
+    reg_del(graph);
     return guarded([&] {
+        // the plan outlives its graphs: h3d_destroy refuses a plan with live graphs
+        graph->plan->P.live_graphs -= 1;
         DeviceScope ds(graph->plan->P.device);
         (void)hipDeviceSynchronize();
         if (graph->exec)
@@ -433,14 +487,17 @@ h3d_status h3d_graph_destroy(h3d_graph *graph) {
 }
 
 h3d_status h3d_autotune(h3d_plan *plan, int64_t nrhs, void *hip_stream) {
-    if (!plan || !plan->P.built)
-        return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    if (const h3d_status ps = plan_status(plan); ps != H3D_OK)
+        return ps;
     if (plan->batch)
         return batch_plan_error();
     if (plan->P.in_batch)
         return invalid("the launch shapes of a batch member are fixed by its batch");
     if (nrhs < 1)
         return invalid("nrhs must be >= 1");
+    if (plan->P.live_graphs > 0)
+        return invalid("autotuning rebuilds work tables that captured graphs of this plan use: "
+                       "destroy them first");
     return guarded([&] {
         DeviceScope ds(plan->P.device);
         h3d::autotune(plan->P, nrhs, static_cast<hipStream_t>(hip_stream));
@@ -448,8 +505,8 @@ h3d_status h3d_autotune(h3d_plan *plan, int64_t nrhs, void *hip_stream) {
 }
 
 h3d_status h3d_get_stats(const h3d_plan *plan, h3d_stats *out) {
-    if (!plan || !plan->P.built)
-        return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    if (const h3d_status ps = plan_status(plan); ps != H3D_OK)
+        return ps;
     if (!out)
         return invalid("out must not be NULL");
     *out = plan->P.stats;
@@ -461,8 +518,8 @@ h3d_status h3d_get_stats(const h3d_plan *plan, h3d_stats *out) {
 }
 
 h3d_status h3d_export(const h3d_plan *plan, int32_t what, void *host_buf, size_t *bytes) {
-    if (!plan || !plan->P.built)
-        return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    if (const h3d_status ps = plan_status(plan); ps != H3D_OK)
+        return ps;
     if (plan->batch)
         return batch_plan_error();
     if (!bytes)
@@ -580,6 +637,22 @@ h3d_status h3d_export(const h3d_plan *plan, int32_t what, void *host_buf, size_t
 h3d_status h3d_destroy(h3d_plan *plan) {
     if (!plan)
         return H3D_OK;
+    const int kind = reg_kind(plan);
+    if (kind == kMemberPlan)
+        return invalid("a problem of a batch belongs to its batch: destroy the batch");
+    if (kind != kOwnPlan)
+        return invalid("not a live plan (already destroyed?)");
+    int graphs = plan->P.live_graphs;
+    if (plan->batch)
+        for (const h3d_plan *q : plan->batch->subs)
+            graphs += q->P.live_graphs;
+    if (graphs > 0)
+        return invalid("the plan has " + std::to_string(graphs) +
+                       " live graph(s): destroy them first");
+    reg_del(plan);
+    if (plan->batch)
+        for (const h3d_plan *q : plan->batch->subs)
+            reg_del(q);
     return guarded([&] {
         {
             DeviceScope ds(plan->P.device);
@@ -590,8 +663,8 @@ h3d_status h3d_destroy(h3d_plan *plan) {
 }
 
 h3d_status h3d_profile_enable(h3d_plan *plan, int32_t enable) {
-    if (!plan || !plan->P.built)
-        return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    if (const h3d_status ps = plan_status(plan); ps != H3D_OK)
+        return ps;
     return guarded([&] {
         plan->P.prof.collect();
         plan->P.prof.on = enable != 0;
@@ -600,15 +673,15 @@ h3d_status h3d_profile_enable(h3d_plan *plan, int32_t enable) {
 }
 
 h3d_status h3d_profile_reset(h3d_plan *plan) {
-    if (!plan || !plan->P.built)
-        return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    if (const h3d_status ps = plan_status(plan); ps != H3D_OK)
+        return ps;
     return guarded([&] { plan->P.prof.reset(); });
 }
 
 h3d_status h3d_profile_read(h3d_plan *plan, h3d_kernel_profile *out, int32_t capacity,
                             int32_t *count) {
-    if (!plan || !plan->P.built)
-        return g_last_error = "plan is NULL or not built", H3D_ENOTBUILT;
+    if (const h3d_status ps = plan_status(plan); ps != H3D_OK)
+        return ps;
     if (!count || (capacity > 0 && !out))
         return invalid("count (and out when capacity > 0) must not be NULL");
     return guarded([&] {

@@ -303,7 +303,24 @@ struct Plan {
     Profiler prof;
     bool built = false;
     bool in_batch = false;  // a problem of a batch: launch shapes fixed
+    // HIP graphs captured from this plan's products: they hold the device
+    // addresses of the scratch and of the work tables, so while any exists
+    // nothing that a product uses may be freed or reallocated
+    int live_graphs = 0;
 };
+
+// Called before scratch or work tables that earlier products used are
+// released to grow or rebuild them: refuses while a captured graph holds
+// their addresses, then drains the device, so that no kernel of an earlier
+// product on any stream still uses the memory when the allocator takes it
+// back.
+inline void before_release(Plan &P, const char *what) {
+    if (P.live_graphs > 0)
+        fail(H3D_EINVAL, std::string(what) + " would reallocate memory that " +
+                             std::to_string(P.live_graphs) +
+                             " captured graph(s) of this plan use: destroy them first");
+    H3D_HIP(hipDeviceSynchronize());
+}
 
 // products with at least this many right-hand sides use the matrix cores
 constexpr int64_t kBatchedMinRhs = 8;
@@ -382,6 +399,12 @@ void lists_build(Plan &P, hipStream_t s);
 void factors_build(Plan &P, hipStream_t s);
 void matvec_run(Plan &P, const void *x, void *y, int64_t nrhs, int64_t ldx, int64_t ldy,
                 int io_dtype, bool adjoint, hipStream_t s);
+// The product for nrhs < kBatchedMinRhs with caller-given scratch: xp and yn
+// hold n nrhs doubles each, z vector_z_entries(P, nrhs).  Every value of the
+// three is written before it is read, so none needs clearing.
+void matvec_vector(Plan &P, const void *x, void *y, int64_t nrhs, int64_t ldx, int64_t ldy,
+                   int io_dtype, bool adjoint, double *xp, double *yn, double *z, hipStream_t s);
+int64_t vector_z_entries(const Plan &P, int64_t nrhs);
 void export_factors(const Plan &P, int which, double *host_out);
 void set_level_shape(Plan &P, int cls, int l, const S1Shape &sh, hipStream_t s);
 S1Shape default_shape(const Plan &P, int l, int cls);

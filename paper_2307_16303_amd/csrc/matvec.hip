@@ -479,6 +479,8 @@ void ensure_scratch(Plan &P, int64_t nrhs, hipStream_t s) {
     if (nrhs <= P.scratch_nrhs)
         return;
     const int64_t n = P.n;
+    if (P.xp)
+        before_release(P, "a product with more right-hand sides");
     P.mem.release(P.xp);
     P.mem.release(P.yp);
     P.mem.release(P.z);
@@ -493,6 +495,9 @@ void ensure_scratch(Plan &P, int64_t nrhs, hipStream_t s) {
 void autotune(Plan &P, int64_t nrhs, hipStream_t s) {
     if (P.nfar == 0 || nrhs >= kBatchedMinRhs)
         return;
+    // the tuner rebuilds the stage-1 work tables that earlier products used
+    if (P.built)
+        before_release(P, "autotuning");
     const int nr = nrhs == 1 ? 1 : int(std::min<int64_t>(nrhs, 4));
     ensure_scratch(P, std::max<int64_t>(nrhs, nr), s);
     auto go = [&](auto dt_tag) {
@@ -516,18 +521,21 @@ void autotune(Plan &P, int64_t nrhs, hipStream_t s) {
     H3D_HIP(hipStreamSynchronize(s));
 }
 
-void matvec_run(Plan &P, const void *x, void *y, int64_t nrhs, int64_t ldx, int64_t ldy,
-                int io_dtype, bool adjoint, hipStream_t s) {
-    if (nrhs >= kBatchedMinRhs) {
-        matvec_batched(P, x, y, nrhs, ldx, ldy, io_dtype, adjoint, s);
-        return;
-    }
+int64_t vector_z_entries(const Plan &P, int64_t nrhs) {
+    // one right-hand side with the finest level fused: z of that level (the
+    // last columns) is never stored
+    if (nrhs == 1 && P.L >= 1 && leaf_shape(P))
+        return std::max<int64_t>(P.lvl_col[P.L], 1);
+    return std::max<int64_t>(P.ncols, 1) * nrhs;
+}
+
+void matvec_vector(Plan &P, const void *x, void *y, int64_t nrhs, int64_t ldx, int64_t ldy,
+                   int io_dtype, bool adjoint, double *xp, double *yn, double *z, hipStream_t s) {
     const int64_t n = P.n;
-    ensure_scratch(P, nrhs, s);
     const int io_f32 = io_dtype == H3D_F32;
     {
         hipEvent_t ev = P.prof.begin(s);
-        k_gather<<<grid_for(n, 256), 256, 0, s>>>(x, io_f32, ldx, n, int(nrhs), P.perm, P.xp);
+        k_gather<<<grid_for(n, 256), 256, 0, s>>>(x, io_f32, ldx, n, int(nrhs), P.perm, xp);
         H3D_LAUNCH_CHECK();
         P.prof.end(s, ev, "k_gather", double(n) * (4.0 + (io_f32 ? 4.0 : 8.0) * nrhs + 8.0 * nrhs), 0.0);
     }
@@ -535,15 +543,15 @@ void matvec_run(Plan &P, const void *x, void *y, int64_t nrhs, int64_t ldx, int6
     // kernels are radial, so K(t,s)^T = K(s,t): the adjoint near field walks
     // the same list with the roles of row and column exchanged.
     if (nrhs == 1)
-        launch_near<1>(P, 1, P.xp, P.yp, s);
+        launch_near<1>(P, 1, xp, yn, s);
     else
-        launch_near<4>(P, int(nrhs), P.xp, P.yp, s);
+        launch_near<4>(P, int(nrhs), xp, yn, s);
     auto far = [&](auto dt_tag) {
         constexpr int DT = decltype(dt_tag)::value;
         if (nrhs == 1)
-            launch_far<DT, 1>(P, adjoint, 1, P.xp, P.z, P.yp, y, ldy, io_f32, s);
+            launch_far<DT, 1>(P, adjoint, 1, xp, z, yn, y, ldy, io_f32, s);
         else
-            launch_far<DT, 4>(P, adjoint, int(nrhs), P.xp, P.z, P.yp, y, ldy, io_f32, s);
+            launch_far<DT, 4>(P, adjoint, int(nrhs), xp, z, yn, y, ldy, io_f32, s);
     };
     switch (P.factor_dtype) {
     case H3D_F64:
@@ -556,6 +564,16 @@ void matvec_run(Plan &P, const void *x, void *y, int64_t nrhs, int64_t ldx, int6
         far(std::integral_constant<int, H3D_BF16_SCALED>{});
         break;
     }
+}
+
+void matvec_run(Plan &P, const void *x, void *y, int64_t nrhs, int64_t ldx, int64_t ldy,
+                int io_dtype, bool adjoint, hipStream_t s) {
+    if (nrhs >= kBatchedMinRhs) {
+        matvec_batched(P, x, y, nrhs, ldx, ldy, io_dtype, adjoint, s);
+        return;
+    }
+    ensure_scratch(P, nrhs, s);
+    matvec_vector(P, x, y, nrhs, ldx, ldy, io_dtype, adjoint, P.xp, P.yp, P.z, s);
 }
 
 }  // namespace h3d

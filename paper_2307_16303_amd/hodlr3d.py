@@ -209,6 +209,14 @@ class _TorchAllocator:
         self.struct = Allocator(self._a, self._f, None)
 
 
+def _check_rhs(x, n: int, device: int) -> None:
+    """x must be (n,) or (n, nrhs) with nrhs >= 1, on the operator's GPU."""
+    if x.dim() not in (1, 2) or x.shape[0] != n or (x.dim() == 2 and x.shape[1] < 1):
+        raise ValueError(f"x must have shape ({n},) or ({n}, nrhs); got {tuple(x.shape)}")
+    if x.device.index is not None and x.device.index != device:
+        raise ValueError(f"x is on cuda:{x.device.index}, the operator on cuda:{device}")
+
+
 class Operator:
     """The HODLR3D representation of K on one point cloud, resident on the GPU."""
 
@@ -246,6 +254,7 @@ class Operator:
             raise TypeError("x must be a CUDA (HIP) tensor")
         if x.dtype not in (torch.float64, torch.float32):
             raise TypeError("x must be float64 or float32")
+        _check_rhs(x, self.n, self.device)
         vec = x.dim() == 1
         x2 = x.reshape(self.n, -1)
         nrhs = x2.shape[1]
@@ -329,6 +338,7 @@ class Graph:
         if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype not in (torch.float64,
                                                                                 torch.float32):
             raise TypeError("x must be a float64/float32 CUDA tensor")
+        _check_rhs(x, op.n, op.device)
         self.op = op
         self.vec = x.dim() == 1
         self.nrhs = 1 if self.vec else x.shape[1]
@@ -460,6 +470,7 @@ class BatchOperator:
         for x, n in zip(xs, self.ns):
             if not isinstance(x, torch.Tensor) or not x.is_cuda:
                 raise TypeError("every x must be a CUDA (HIP) tensor")
+            _check_rhs(x, n, self.device)
             x2 = x.reshape(n, -1)
             if nrhs is None:
                 nrhs, dtype = x2.shape[1], x.dtype

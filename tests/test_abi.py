@@ -112,6 +112,24 @@ def test_calls_on_null_plan(lib):
     assert lib.h3d_profile_read(None, None, 0, ctypes.byref(cnt)) == hodlr3d.H3D_ENOTBUILT
 
 
+def test_handles_the_library_never_returned(lib):
+    """Handles are looked up in the library's registry before use: a pointer it
+    never handed out (or has released) is refused without being dereferenced."""
+    buf = np.zeros(8)
+    p = buf.ctypes.data_as(ctypes.c_void_p)
+    fake = ctypes.c_void_p(buf.ctypes.data + 16)
+    assert lib.h3d_matvec(fake, p, p, 1, 4, 4, 0, None) == hodlr3d.H3D_ENOTBUILT
+    assert b"not a live plan" in lib.h3d_last_error()
+    assert lib.h3d_matvec_adjoint(fake, p, p, 1, 4, 4, 0, None) == hodlr3d.H3D_ENOTBUILT
+    assert lib.h3d_autotune(fake, 1, None) == hodlr3d.H3D_ENOTBUILT
+    s = hodlr3d.Stats()
+    assert lib.h3d_get_stats(fake, ctypes.byref(s)) == hodlr3d.H3D_ENOTBUILT
+    assert lib.h3d_destroy(fake) == hodlr3d.H3D_EINVAL
+    assert lib.h3d_graph_launch(fake, None) == hodlr3d.H3D_EINVAL
+    assert lib.h3d_graph_destroy(fake) == hodlr3d.H3D_EINVAL
+    assert lib.h3d_matvec_batch(fake, p, p, 1, 0, None) == hodlr3d.H3D_ENOTBUILT
+
+
 def test_batch_calls_validate_before_device_work(lib):
     cfg = hodlr3d.default_config()
     out = ctypes.c_void_p()

@@ -111,6 +111,26 @@ def test_multiple_rhs_and_float32_io(mixed):
         np.testing.assert_array_equal(ys32[i], solo_apply(bop.plans[i], x, dtype="float32"))
 
 
+def test_many_rhs_batch(mixed):
+    """nrhs = 8 (the width from which a single operator's product uses the
+    matrix cores): every column of every problem against the problem's own
+    h3d_matvec (same factors, another summation order) and the oracle."""
+    clouds, kw, bop = mixed
+    xs = [inputs.normal_rhs(len(c), seed=90 + i, nrhs=8) for i, c in enumerate(clouds)]
+    ys = batch_apply(bop, xs)
+    for i, (x, y) in enumerate(zip(xs, ys)):
+        ys_solo = solo_apply(bop.plans[i], x)
+        for c in range(8):
+            assert rel(y[:, c], ys_solo[:, c]) <= 1e-13, (i, c)
+    for i in (0, 2):
+        ref = oracle.HODLR3D(clouds[i], kernel="laplace", leaf_size=kw["leaf_size"], tol=kw["tol"],
+                             box_lo=kw["box_lo"], box_side=kw["box_side"])
+        yo = ref.matvec(xs[i])
+        for c in range(8):
+            assert rel(ys[i][:, c], yo[:, c]) <= 1e-13, (i, c)
+    np.testing.assert_array_equal(batch_apply(bop, xs)[2], ys[2])  # reproducible
+
+
 @pytest.mark.parametrize("dtype", ["fp32", "bf16"])
 def test_low_precision_batch(dtype):
     clouds = [inputs.uniform_points(n, s) for n, s in [(15000, 21), (4000, 22), (30000, 23)]]

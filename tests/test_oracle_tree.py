@@ -237,3 +237,41 @@ def test_grid4096_exact_structure(oracle_mod):
     dense_entries = 784 * 64 * 64
     assert dense_entries == 3_211_264
     assert dense_entries + 8 * 512 * 512 + 2800 * 64 * 64 == 4096 ** 2
+
+
+def test_smallest_enclosing_cube(oracle_mod):
+    """Box rule for general inputs (Sec. 2.1 encloses the points in one cube B):
+    lower corner = componentwise minimum, side = the largest extent over the
+    three axes; the point on the upper face of that axis falls into the last
+    box (half-open boxes, upper face clamped)."""
+    pts = np.array([[-0.3, 0.10, -1.00],
+                     [0.5, 0.20, -0.50],
+                     [0.1, 0.15, -0.75],
+                     [0.2, 0.12, -0.90],
+                     [-0.1, 0.18, -0.60]])
+    h = oracle_mod.HODLR3D(pts, leaf_size=1, tol=1e-8, compress=False)
+    lo, side = h.box()
+    np.testing.assert_array_equal(lo, [-0.3, 0.10, -1.00])
+    assert side == 0.8  # x extent 0.5 - (-0.3) is the largest (y 0.1, z 0.5)
+    # the cube is the smallest one: a point on the face x = lo + side exists, and
+    # it is placed in the last box along x at every level
+    perm, leaf_off = h.tree()
+    L = h.depth
+    assert L >= 1
+    leaf_of = np.empty(len(pts), dtype=np.int64)
+    for b in range(8 ** L):
+        leaf_of[perm[leaf_off[b]:leaf_off[b + 1]]] = b
+    qx, _, _ = oracle_mod.morton_decode(int(leaf_of[1]), L)
+    assert qx == 2 ** L - 1
+    # one coincident cloud: side 1 (nothing to enclose), lower corner at the point
+    h1 = oracle_mod.HODLR3D(np.array([[0.25, -0.5, 2.0]] * 3), leaf_size=4, tol=1e-8,
+                            compress=False)
+    lo1, side1 = h1.box()
+    np.testing.assert_array_equal(lo1, [0.25, -0.5, 2.0])
+    assert side1 == 1.0
+    # the largest extent along z
+    pts_z = np.array([[0.0, 0.0, 0.0], [0.1, 0.2, 3.0], [0.05, -0.1, 1.0]])
+    hz = oracle_mod.HODLR3D(pts_z, leaf_size=1, tol=1e-8, compress=False)
+    loz, sidez = hz.box()
+    np.testing.assert_array_equal(loz, [0.0, -0.1, 0.0])
+    assert sidez == 3.0
