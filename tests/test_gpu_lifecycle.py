@@ -5,6 +5,7 @@ Every failure here is a host-side condition (an argument the library refuses,
 an allocator callback returning NULL); no kernel is made to fail.
 """
 import ctypes
+import gc
 
 import numpy as np
 import pytest
@@ -135,18 +136,26 @@ def test_allocator_failure_mid_build_leaks_nothing():
     total = ok.calls
     assert lib.h3d_destroy(h) == hodlr3d.H3D_OK
     assert not ok.live
-    torch.cuda.synchronize()
-    base = torch.cuda.memory_allocated()
     print(f"[alloc failure] a build makes {total} requests", flush=True)
-    for k in sorted({1, 2, 3, total // 4, total // 2, total - 1, total}):
-        if k < 1:
-            continue
-        fa = _FailingAllocator(k)
-        h = ctypes.c_void_p(123)
-        st = lib.h3d_build(ctypes.c_void_p(pts.data_ptr()), 6000, ctypes.byref(cfg),
-                           ctypes.byref(fa.struct), None, ctypes.byref(h))
-        assert st == hodlr3d.H3D_ENOMEM, (k, st)
-        assert h.value is None  # *out is NULL on failure
-        assert not fa.live, f"request {k} failing left {len(fa.live)} allocations held"
+    # tensors of earlier tests that the garbage collector frees in the middle
+    # of the loop would change torch's count: collect them first, and keep the
+    # collector off while the count is compared
+    gc.collect()
+    gc.disable()
+    try:
         torch.cuda.synchronize()
-        assert torch.cuda.memory_allocated() == base
+        base = torch.cuda.memory_allocated()
+        for k in sorted({1, 2, 3, total // 4, total // 2, total - 1, total}):
+            if k < 1:
+                continue
+            fa = _FailingAllocator(k)
+            h = ctypes.c_void_p(123)
+            st = lib.h3d_build(ctypes.c_void_p(pts.data_ptr()), 6000, ctypes.byref(cfg),
+                               ctypes.byref(fa.struct), None, ctypes.byref(h))
+            assert st == hodlr3d.H3D_ENOMEM, (k, st)
+            assert h.value is None  # *out is NULL on failure
+            assert not fa.live, f"request {k} failing left {len(fa.live)} allocations held"
+            torch.cuda.synchronize()
+            assert torch.cuda.memory_allocated() == base
+    finally:
+        gc.enable()
