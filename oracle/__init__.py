@@ -67,6 +67,10 @@ def _load():
     lib.oracle_build.restype = I
     lib.oracle_destroy.argtypes = [P]
     lib.oracle_apply.argtypes = [P, P, I64, P, I, I, I]
+    lib.oracle_apply.restype = I
+    lib.oracle_apply_lu.argtypes = [P, P, I64, P, I, I, I]
+    lib.oracle_apply_lu.restype = I
+    lib.oracle_export_lu.argtypes = [P, P]
     lib.oracle_set_factors.argtypes = [P, P, P, P]
     lib.oracle_set_factors.restype = I
     lib.oracle_depth.argtypes = [P]
@@ -317,14 +321,34 @@ class HODLR3D:
         if rc != 0:
             raise OracleError("oracle_set_factors failed")
 
-    def _apply(self, x, adjoint: bool, near: bool, far: bool):
+    def _apply(self, x, adjoint: bool, near: bool, far: bool, lu_form: bool = False):
         xc, nrhs, vec = _as_cols(x, self.n)
         y = np.empty((self.n, nrhs), order="F")
-        self._lib.oracle_apply(self._h, _ptr(xc), nrhs, _ptr(y), int(adjoint), int(near), int(far))
+        fn = self._lib.oracle_apply_lu if lu_form else self._lib.oracle_apply
+        st = fn(self._h, _ptr(xc), nrhs, _ptr(y), int(adjoint), int(near), int(far))
+        if st != 0:
+            raise OracleError(_ERR.get(st, str(st)))
         return y[:, 0] if vec else y
 
-    def matvec(self, x, near: bool = True, far: bool = True):
-        return self._apply(x, False, near, far)
+    def matvec(self, x, near: bool = True, far: bool = True, lu_form: bool = False):
+        """y = K~ x; lu_form applies every low-rank block as K(X,tau) R^-1 L^-1
+        K(sigma,Y) with regenerated entries (Sec. 4.1; Algorithm 2)."""
+        return self._apply(x, False, near, far, lu_form)
 
-    def rmatvec(self, x, near: bool = True, far: bool = True):
-        return self._apply(x, True, near, far)
+    def rmatvec(self, x, near: bool = True, far: bool = True, lu_form: bool = False):
+        return self._apply(x, True, near, far, lu_form)
+
+    def lu_factors(self):
+        """Packed LU factors of K(sigma, tau) per block (k_b x k_b column-major,
+        L on and below the diagonal, the unit-diagonal R above it),
+        concatenated in block order."""
+        r = self.far()["rank"]
+        out = np.empty(max(int((r * r).sum()), 1), dtype=np.float64)
+        self._lib.oracle_export_lu(self._h, _ptr(out))
+        return out[: int((r * r).sum())]
+
+    def block_lu(self, b: int) -> np.ndarray:
+        r = self.far()["rank"]
+        off = int((r[:b] * r[:b]).sum())
+        k = int(r[b])
+        return self.lu_factors()[off: off + k * k].reshape(k, k, order="F")

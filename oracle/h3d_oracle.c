@@ -23,6 +23,10 @@
  *                     block K(X,Y)                              Sec. 4.1, eq. (prank); Algorithm 1
  *   mat-vec           near field (self, E, F leaf blocks), then
  *                     low-rank applies level by level           Algorithm 2
+ *   pivot + LU form   K(X,tau) R^-1 L^-1 K(sigma,Y) psi(Y) with
+ *                     regenerated entries and the LU factors
+ *                     of K(sigma,tau) taken from ACA            Sec. 4.1, eqs. (prank), (LR);
+ *                                                              Algorithm 2, low-rank step
  *
  * Readings where the paper is silent (each is listed in the design notes of
  * the repository):
@@ -32,7 +36,10 @@
  *     rule |u_k||v_k| <= tol |S_k|_F, ties in every argmax to the lowest index;
  *   - coincident distinct points contribute 0 (f(0) := 0);
  *   - the low-rank blocks are kept as explicit factors U V^T; in exact
- *     arithmetic this equals the pivot/LU form of eq. (prank).
+ *     arithmetic this equals the pivot/LU form of eq. (prank), which
+ *     oracle_apply_lu applies from the same ACA run;
+ *   - the LU factors of K(sigma, tau) are read off the ACA factors at the
+ *     pivots (L from U, unit-diagonal R from V), in ACA's pivot order.
  *
  * Floating point: compiled with -ffp-contract=off; every sum runs in index
  * order.  Point order inside a leaf: ascending original index.
@@ -869,13 +876,134 @@ static void far_block_apply(const oracle_h3d *h, int64_t b, const double *xp, do
     }
 }
 
+/* ------------------------------------------------------------------ */
+/* The paper's storage form (Sec. 4.1, eqs. (prank) and (LR); the      */
+/* low-rank step of Algorithm 2): per block only the pivots sigma (rows */
+/* of X), tau (columns of Y) and the LU factors of K(sigma, tau) are    */
+/* kept; a product regenerates K(sigma, Y) and K(X, tau) and applies    */
+/* K(X,tau) R^-1 L^-1 K(sigma,Y) psi(Y) by forward and backward         */
+/* substitution.                                                        */
+/* ------------------------------------------------------------------ */
+
+/*
+ * LU factors of K(sigma, tau) for block b, taken from the ACA factors as a
+ * by-product (Sec. 4.1): with the pivots in the order ACA chose them,
+ *   L[a][l] = u_l[sigma_a]  (a >= l; lower triangular, diagonal = the pivots)
+ *   R[l][c] = v_l[tau_c]    (c >  l; R has a unit diagonal, v_l[tau_l] = 1)
+ * since u_l vanishes on the earlier pivot rows and v_l on the earlier pivot
+ * columns, K(sigma, tau) = U(sigma,:) V(tau,:)^T = L R.  Packed into one
+ * k x k column-major matrix: L on and below the diagonal, R above it.
+ */
+static void block_lu(const oracle_h3d *h, int64_t b, double *LU)
+{
+    int l = h->far_level[b];
+    int64_t m = box_count(h, l, h->far_t[b]);
+    int64_t nn = box_count(h, l, h->far_s[b]);
+    int64_t k = h->far_rank[b];
+    const double *U = h->U + h->far_uoff[b];
+    const double *V = h->V + h->far_voff[b];
+    const int64_t *sig = h->rowpiv + h->far_piv_off[b];
+    const int64_t *tau = h->colpiv + h->far_piv_off[b];
+    for (int64_t c = 0; c < k; ++c)         /* column c */
+        for (int64_t a = 0; a < k; ++a) {   /* row a */
+            if (a >= c)
+                LU[c * k + a] = U[c * m + sig[a]];   /* L[a][c] = u_c[sigma_a] */
+            else
+                LU[c * k + a] = V[a * nn + tau[c]];  /* R[a][c] = v_a[tau_c] */
+        }
+}
+
+/* the packed LU factors of every block, concatenated (k_b^2 values each) */
+void oracle_export_lu(const oracle_h3d *h, double *out)
+{
+    int64_t off = 0;
+    for (int64_t b = 0; b < h->nfar; ++b) {
+        block_lu(h, b, out + off);
+        off += h->far_rank[b] * h->far_rank[b];
+    }
+}
+
+/* K(X, tau) R^-1 L^-1 K(sigma, Y) applied to x_s (forward), or its transpose
+ * K(sigma,Y)^T L^-T R^-T K(X,tau)^T applied to x_t (adjoint); LU is the
+ * packed k x k matrix of block_lu, w a k-vector of workspace. */
+static void far_block_apply_lu(const oracle_h3d *h, int64_t b, const double *LU, const double *xp,
+                               double *yp, int adjoint, double *w)
+{
+    int l = h->far_level[b];
+    int64_t t0 = box_start(h, l, h->far_t[b]), m = box_count(h, l, h->far_t[b]);
+    int64_t s0 = box_start(h, l, h->far_s[b]), nn = box_count(h, l, h->far_s[b]);
+    int64_t k = h->far_rank[b];
+    const int64_t *sig = h->rowpiv + h->far_piv_off[b];
+    const int64_t *tau = h->colpiv + h->far_piv_off[b];
+    block_ctx ctx = {h, t0, s0};
+    if (!adjoint) {
+        /* w = K(sigma, Y) x(Y) */
+        for (int64_t a = 0; a < k; ++a) {
+            double acc = 0.0;
+            for (int64_t j = 0; j < nn; ++j)
+                acc += block_entry(&ctx, sig[a], j) * xp[s0 + j];
+            w[a] = acc;
+        }
+        /* w = L^-1 w: forward substitution */
+        for (int64_t a = 0; a < k; ++a) {
+            double acc = w[a];
+            for (int64_t c = 0; c < a; ++c)
+                acc -= LU[c * k + a] * w[c];
+            w[a] = acc / LU[a * k + a];
+        }
+        /* w = R^-1 w: backward substitution, unit diagonal */
+        for (int64_t a = k - 1; a >= 0; --a) {
+            double acc = w[a];
+            for (int64_t c = a + 1; c < k; ++c)
+                acc -= LU[c * k + a] * w[c];
+            w[a] = acc;
+        }
+        /* y(X) += K(X, tau) w */
+        for (int64_t i = 0; i < m; ++i) {
+            double acc = 0.0;
+            for (int64_t c = 0; c < k; ++c)
+                acc += block_entry(&ctx, i, tau[c]) * w[c];
+            yp[t0 + i] += acc;
+        }
+    } else {
+        /* w = K(X, tau)^T x(X) */
+        for (int64_t c = 0; c < k; ++c) {
+            double acc = 0.0;
+            for (int64_t i = 0; i < m; ++i)
+                acc += block_entry(&ctx, i, tau[c]) * xp[t0 + i];
+            w[c] = acc;
+        }
+        /* w = R^-T w: forward substitution with the unit lower R^T */
+        for (int64_t a = 0; a < k; ++a) {
+            double acc = w[a];
+            for (int64_t c = 0; c < a; ++c)
+                acc -= LU[a * k + c] * w[c];
+            w[a] = acc;
+        }
+        /* w = L^-T w: backward substitution with the upper L^T */
+        for (int64_t a = k - 1; a >= 0; --a) {
+            double acc = w[a];
+            for (int64_t c = a + 1; c < k; ++c)
+                acc -= LU[a * k + c] * w[c];
+            w[a] = acc / LU[a * k + a];
+        }
+        /* y(Y) += K(sigma, Y)^T w */
+        for (int64_t j = 0; j < nn; ++j) {
+            double acc = 0.0;
+            for (int64_t a = 0; a < k; ++a)
+                acc += block_entry(&ctx, sig[a], j) * w[a];
+            yp[s0 + j] += acc;
+        }
+    }
+}
+
 /*
  * y = K~ x (adjoint = 0) or y = K~^T x (adjoint = 1); x, y: n x nrhs,
  * column-major, original point order.  near != 0 includes the dense leaf
  * blocks, far != 0 the low-rank blocks (both set for the full product).
  */
-int oracle_apply(const oracle_h3d *h, const double *x, int64_t nrhs, double *y, int adjoint,
-                 int near, int far)
+static int apply_form(const oracle_h3d *h, const double *x, int64_t nrhs, double *y,
+                      int adjoint, int near, int far, int lu_form)
 {
     int64_t n = h->n;
     double *xp = malloc(sizeof(double) * (size_t)n);
@@ -885,6 +1013,14 @@ int oracle_apply(const oracle_h3d *h, const double *x, int64_t nrhs, double *y, 
         if (h->far_rank[b] > kmax)
             kmax = h->far_rank[b];
     double *z = malloc(sizeof(double) * (size_t)kmax);
+    double *LU = lu_form ? malloc(sizeof(double) * (size_t)(kmax * kmax)) : NULL;
+    if (!xp || !yp || !z || (lu_form && !LU)) {
+        free(xp);
+        free(yp);
+        free(z);
+        free(LU);
+        return OR_ENOMEM;
+    }
     for (int64_t c = 0; c < nrhs; ++c) {
         for (int64_t p = 0; p < n; ++p) {
             xp[p] = x[c * n + h->perm[p]];
@@ -908,8 +1044,14 @@ int oracle_apply(const oracle_h3d *h, const double *x, int64_t nrhs, double *y, 
         }
         if (far) {
             /* low-rank part, level 1..L, targets in Morton order, lists ascending */
-            for (int64_t b = 0; b < h->nfar; ++b)
-                far_block_apply(h, b, xp, yp, adjoint, z);
+            for (int64_t b = 0; b < h->nfar; ++b) {
+                if (lu_form) {
+                    block_lu(h, b, LU);
+                    far_block_apply_lu(h, b, LU, xp, yp, adjoint, z);
+                } else {
+                    far_block_apply(h, b, xp, yp, adjoint, z);
+                }
+            }
         }
         for (int64_t p = 0; p < n; ++p)
             y[c * n + h->perm[p]] = yp[p];
@@ -917,7 +1059,22 @@ int oracle_apply(const oracle_h3d *h, const double *x, int64_t nrhs, double *y, 
     free(xp);
     free(yp);
     free(z);
+    free(LU);
     return OR_OK;
+}
+
+int oracle_apply(const oracle_h3d *h, const double *x, int64_t nrhs, double *y, int adjoint,
+                 int near, int far)
+{
+    return apply_form(h, x, nrhs, y, adjoint, near, far, 0);
+}
+
+/* As oracle_apply, with every low-rank block applied in the pivot + LU form
+ * of Sec. 4.1 (entries of K(sigma,Y) and K(X,tau) regenerated). */
+int oracle_apply_lu(const oracle_h3d *h, const double *x, int64_t nrhs, double *y, int adjoint,
+                    int near, int far)
+{
+    return apply_form(h, x, nrhs, y, adjoint, near, far, 1);
 }
 
 /* ------------------------------------------------------------------ */
