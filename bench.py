@@ -1,36 +1,41 @@
 """Benchmark: HODLR3D mat-vec throughput on one MI355X.
 
-A step is one full mat-vec y = K~x (gather, near-field tiles, both factor
+A step is one full mat-vec Y = K~X (gather, near-field tiles, both factor
 streams, scatter) over the resident operator of the workload; the build
 (tree, lists, ACA, packing) happens before the timed region and is reported
 separately.  Prints one JSON line.
 
-The roofline object describes the dominant kernel of the step: its
-algorithmic bytes per launch (factor bytes it streams plus the x/z/y vectors
-it must touch) over its average launch time, taken with HIP events recorded
-by the library on the launch stream during the timed steps.
+Headline: the precision + batching form on 1,048,576 i.i.d. uniform points
+(Laplace, leaf <= 64, ACA tol 1e-7 in FP64): FP32 factors, 64 right-hand
+sides on the matrix cores.  Beside it, on the same points, the plain FP64
+form with one right-hand side (the baseline the gain is taken over), and the
+relative error of both on sampled rows of the exact dense product (the gate
+is 1e-6).
+
+The roofline object describes the dominant kernel of the headline step: its
+algorithmic flops per launch (2 per factor entry per right-hand side) over
+its average launch time, taken with HIP events recorded by the library on the
+launch stream during the timed steps, against the FP32 matrix-core peak; its
+algorithmic bytes per launch over the same time are reported beside it.  The
+baseline carries its own HBM roofline.
 
 The cpu_baseline object times the CPU oracle's exact dense direct sum on a
-bounded sample of target rows of the same workload (rows per second), and
-reports the GPU result's relative error on those rows.
+bounded sample of target rows of the headline workload (rows x 64 RHS per
+second) with every thread of the process's CPU share, and once with one
+thread; beside it, the oracle's own HODLR3D product (build and mat-vec) on
+the 16^3 grid and on 65,536 uniform points (the oracle cannot hold the
+1,048,576-point operator in reasonable time).
 
-The variants object measures the same workload with FP32 and BF16 factors,
-with FP32 factors recompressed to their optimal ranks (rank truncation), and
-with 64 right-hand sides (matrix-core path), each with its relative error
-on sampled rows of the exact product and its gain over the plain FP64 form,
-and the multi-problem form: 32 independent clouds (N_i in [8192, 131072],
-FP32 factors, tol 1e-7) multiplied in one persistent launch, beside the same
-problems' own products run one after another.
+The variants object measures the other storage forms (FP32 and BF16 factors,
+one and 64 right-hand sides) on the headline points, the plain FP64 form on
+262,144 points, and the multi-problem form (32 clouds, N_i in [8192, 131072],
+FP32 factors, tol 1e-7) in one persistent launch.
 
 roofline.traffic is the dominant kernel's HBM traffic per launch from the
 hardware counters FETCH_SIZE and WRITE_SIZE (rocprofv3 --pmc, one counter per
-run, on this workload), each divided by what the same counter reads for a
-plain 2 GiB device copy (--calibration-copy).  Readings are kept for the two
-kernels that take the largest share of the product (stage 2, and stage 1
-whose per-launch figure is the mean over its launches, one per level).  They
-hold for the sources they were taken on: if any library source that these
-kernels' code, their launches or the factor layout depend on has changed
-since, traffic is null.
+run), each divided by what the same counter reads for a plain 2 GiB device
+copy (--calibration-copy).  Readings hold for the sources they were taken on:
+if any library source has changed since, traffic is null.
 """
 from __future__ import annotations
 
@@ -39,6 +44,7 @@ import glob
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -50,37 +56,39 @@ import numpy as np  # noqa: E402
 METRIC = "HODLR3D matvec points·RHS/s vs plain FP64 GPU at rel err ≤1e-6; HBM GB/s"
 UNIT = "points·RHS/s"
 HBM_PEAK_GBS = 8000.0
+# dense matrix-core peaks of MI355X (TFLOP/s); BF16 factors are widened to FP32 tiles
+MFMA_PEAK_TFS = {"fp64": 78.6, "fp32": 157.3, "bf16": 157.3}
 DTYPE_NAMES = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
+GATE = 1e-6
 
-# Counter readings on uniform262k (FP64 factors, one RHS), KiB per dispatch
-# (stage 1: the mean over the four dispatches of one product), with the
-# copy-kernel scale of each counter.  The runs that produced them are listed in
-# profiles/; sources_sha256 identifies the library sources they were taken on
-# (see sources_digest).
+# Counter readings, KiB per dispatch (a kernel launched once per level: the
+# mean over its dispatches of one product), with the copy-kernel scale of each
+# counter.  The runs that produced them are listed in profiles/;
+# sources_sha256 identifies the library sources they were taken on.
 TRAFFIC = {
-    "workload": "uniform262k",
     "fetch_scale": 0.500016,
     "write_scale": 1.000000,
-    "kernels": {
-        "k_stage2": {"fetch_kib": 10105475.4375, "write_kib": 8198.3229},
-        "k_s1_wide": {"fetch_kib": 2551872.3438, "write_kib": 35194.4089},
-    },
-    "sources_sha256": "56043d14438b5b9a3065bde2e48fb7b01c5bfe4361b96bf4191d5524db659a6a",
+    "readings": [
+        {"workload": "uniform262k", "factor_dtype": "fp64", "nrhs": 1,
+         "sources_sha256": "56043d14438b5b9a3065bde2e48fb7b01c5bfe4361b96bf4191d5524db659a6a",
+         "scope": "stream",
+         "kernels": {"k_stage2": {"fetch_kib": 10105475.4375, "write_kib": 8198.3229},
+                     "k_s1_wide": {"fetch_kib": 2551872.3438, "write_kib": 35194.4089}}},
+    ],
 }
 
-
-# library sources of kernels launched on their own, on which the counter
-# readings above do not depend (many right-hand sides, many problems, optional
-# rank truncation, the fused finest level)
+# library sources of kernels launched on their own, on which the one-RHS
+# stream readings do not depend (many right-hand sides, many problems,
+# optional rank truncation, the fused finest level)
 OTHER_PATHS = ("batched.hip", "batch.hip", "truncate.hip", "leaf.hip")
 
 
-def sources_digest() -> str:
-    """sha256, in name order, over the library sources and header that the
-    stream kernels' code and launches and the factor layout depend on."""
+def sources_digest(scope: str = "all") -> str:
+    """sha256, in name order, over the library sources and header.  scope
+    'stream': without the files of kernels launched on their own."""
     h = hashlib.sha256()
     files = sorted(f for f in glob.glob(os.path.join(ROOT, "paper_2307_16303_amd", "csrc", "*"))
-                   if os.path.basename(f) not in OTHER_PATHS)
+                   if scope != "stream" or os.path.basename(f) not in OTHER_PATHS)
     files.append(os.path.join(ROOT, "include", "hodlr3d.h"))
     for f in files:
         h.update(os.path.basename(f).encode())
@@ -91,12 +99,14 @@ def sources_digest() -> str:
 
 def traffic_bytes(kernel: str, workload: str, factor_dtype: str, nrhs: int):
     """HBM bytes per launch from the stored counter readings, or None."""
-    t = TRAFFIC
-    k = None if t is None else t["kernels"].get(kernel)
-    if (k is None or t["workload"] != workload or factor_dtype != "fp64" or nrhs != 1
-            or t["sources_sha256"] != sources_digest()):
-        return None
-    return k["fetch_kib"] * 1024.0 / t["fetch_scale"] + k["write_kib"] * 1024.0 / t["write_scale"]
+    for r in TRAFFIC["readings"]:
+        k = r["kernels"].get(kernel)
+        if (k is None or r["workload"] != workload or r["factor_dtype"] != factor_dtype
+                or r["nrhs"] != nrhs or r["sources_sha256"] != sources_digest(r["scope"])):
+            continue
+        return (k["fetch_kib"] * 1024.0 / TRAFFIC["fetch_scale"]
+                + k["write_kib"] * 1024.0 / TRAFFIC["write_scale"])
+    return None
 
 
 def parse():
@@ -104,14 +114,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="uniform262k")
-    ap.add_argument("--factor-dtype", default="fp64", choices=["fp64", "fp32", "bf16"])
-    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--workload", default="uniform1m")
+    ap.add_argument("--factor-dtype", default="fp32", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--nrhs", type=int, default=64)
+    ap.add_argument("--adjoint", action="store_true", help="time the adjoint product instead")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip the FP32 / BF16 / 64-RHS forms measured beside the headline")
+                    help="skip the baseline and the other forms measured beside the headline")
+    ap.add_argument("--profile-levels", action="store_true",
+                    help="profile the factor streams level by level (one launch per level)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="after the timed steps, fill and copy a 2 GiB buffer: the plain "
                          "kernels that hardware byte counters are scaled by; then time "
@@ -119,16 +132,96 @@ def parse():
     return ap.parse_args()
 
 
-def time_products(op, x, steps, warmup):
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def build_op(pts, w, dt, truncate=False):
     import torch
+    from paper_2307_16303_amd import hodlr3d, inputs
+    t0 = time.perf_counter()
+    op = hodlr3d.build(torch.as_tensor(pts, device="cuda:0"), kernel=w["kernel"],
+                       leaf_size=w["leaf_size"], tol=w["tol"], factor_dtype=dt,
+                       box_lo=inputs.CUBE_LO, box_side=inputs.CUBE_SIDE, truncate=truncate)
+    torch.cuda.synchronize()
+    return op, time.perf_counter() - t0
+
+
+def time_products(op, x, steps, warmup, adjoint=False, profile=False, levels=False):
+    """Mean seconds per product over `steps` after `warmup`; the last output;
+    the library's per-kernel profile of the timed steps when asked."""
+    import torch
+    f = op.rmatvec if adjoint else op.matvec
     for _ in range(warmup):
-        y = op.matvec(x)
+        y = f(x)
+    torch.cuda.synchronize()
+    if profile:
+        op.profile(2 if levels else True)
+        op.profile_reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        y = op.matvec(x)
+        y = f(x)
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps, y
+    sec = (time.perf_counter() - t0) / steps
+    prof = None
+    if profile:
+        prof = op.profile_read()
+        op.profile(False)
+    return sec, y, prof
+
+
+def roofline_of(prof, workload, dt, nrhs):
+    """Roofline object of the dominant kernel of a profiled product: matrix-core
+    bound (FLOP/s) for the many-RHS kernels, HBM bound (GB/s) otherwise."""
+    dom = max(prof, key=lambda p: p["total_ms"])
+    avg_ms = dom["total_ms"] / max(dom["launches"], 1)
+    gbs = dom["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
+    traffic = traffic_bytes(dom["name"], workload, dt, nrhs)
+    common = {"traffic": None if traffic is None else round(traffic, 0), "kernel": dom["name"],
+              "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": dom["bytes_per_launch"]}
+    if "mfma" in dom["name"]:
+        tfs = dom["flops_per_launch"] / (avg_ms * 1e-3) / 1e12
+        peak = MFMA_PEAK_TFS[dt]
+        return {"bound": "mfma", "achieved": round(tfs, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(tfs / peak, 4), **common,
+                "flops_per_launch": dom["flops_per_launch"], "hbm_gbs": round(gbs, 1),
+                "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), **common}
+
+
+def kernel_table(prof):
+    return {p["name"]: {"ms": round(p["total_ms"] / max(p["launches"], 1), 4),
+                        "launches": p["launches"]} for p in prof}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_threads() -> int:
+    """Threads of this process's CPU share: its affinity set, capped by
+    OMP_NUM_THREADS when that is set."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def rel_err(a, b) -> float:
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def main():
@@ -141,49 +234,36 @@ def main():
 
     from paper_2307_16303_amd import hodlr3d, inputs
 
-    w = inputs.WORKLOADS[args.workload]
+    wname = args.workload
+    w = inputs.WORKLOADS[wname]
     n = w["n"]
-    pts = inputs.workload_points(args.workload)
-    x_np = inputs.workload_rhs(args.workload, None if args.nrhs == 1 else args.nrhs)
+    nrhs = args.nrhs
+    dt = args.factor_dtype
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    t0 = time.perf_counter()
-    op = hodlr3d.build(torch.as_tensor(pts, device=dev), kernel=w["kernel"],
-                       leaf_size=w["leaf_size"], tol=w["tol"], factor_dtype=args.factor_dtype,
-                       box_lo=inputs.CUBE_LO, box_side=inputs.CUBE_SIDE)
-    torch.cuda.synchronize()
-    build_s = time.perf_counter() - t0
-    st = op.stats()
-    print(f"[bench] built {args.workload}: depth {st['depth']}, {st['n_far']} far blocks, "
-          f"{st['factor_bytes'] / 1e9:.2f} GB factors, build {build_s:.1f} s", file=sys.stderr,
-          flush=True)
-    x = torch.as_tensor(x_np, device=dev)
-    for _ in range(args.warmup):
-        y = op.matvec(x)
-    torch.cuda.synchronize()
-    op.profile(True)
-    op.profile_reset()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        y = op.matvec(x)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = op.profile_read()
-    op.profile(False)
-    ms = 1e3 * elapsed / args.steps
-    value = n * args.nrhs / (elapsed / args.steps)
+    pts = inputs.workload_points(wname)
+    x1_np = inputs.workload_rhs(wname, None)
+    xh_np = x1_np if nrhs == 1 else inputs.workload_rhs(wname, nrhs)
+    # target rows whose exact products the oracle computes afterwards
+    rows_err = inputs.sample_rows(n, 2048, seed=3)
+    sampled = {}  # form -> (rhs id, GPU rows)
 
-    dom = max(prof, key=lambda p: p["total_ms"])
-    avg_ms = dom["total_ms"] / max(dom["launches"], 1)
-    achieved = dom["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
-    traffic = traffic_bytes(dom["name"], args.workload, args.factor_dtype, args.nrhs)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if traffic is None else round(traffic, 0),
-                "kernel": dom["name"], "avg_launch_ms": round(avg_ms, 4),
-                "bytes_per_launch": dom["bytes_per_launch"]}
-    kernels = {p["name"]: round(p["total_ms"] / max(p["launches"], 1), 4) for p in prof}
+    # ---- headline form ---------------------------------------------------
+    op, build_s = build_op(pts, w, dt)
+    st = op.stats()
+    log(f"built {wname} ({dt}): depth {st['depth']}, {st['n_far']} far blocks, "
+        f"{st['factor_bytes'] / 1e9:.2f} GB factors, build {build_s:.1f} s")
+    xh = torch.as_tensor(xh_np, device=dev)
+    sec, y, prof = time_products(op, xh, args.steps, args.warmup, adjoint=args.adjoint,
+                                 profile=True, levels=args.profile_levels)
+    ms = 1e3 * sec
+    value = n * nrhs / sec
+    log(f"headline {dt} {nrhs} RHS: {ms:.3f} ms, {value:.3e} {UNIT}")
+    roofline = roofline_of(prof, wname, dt, nrhs)
+    kernels = kernel_table(prof)
+    head_form = f"{dt}_{nrhs}rhs"
+    sampled[head_form] = ("h", y.detach().reshape(n, -1)[torch.as_tensor(rows_err, device=dev)]
+                          .cpu().numpy())
     copy_gbs = read_gbs = None
     if args.calibration_copy:
         # 2 GiB written by the fill, then 2 GiB read and 2 GiB written by the copy
@@ -198,9 +278,7 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         copy_gbs = 5 * 2 * 2 ** 31 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-        print(f"[bench] device copy: {copy_gbs:.1f} GB/s (read + write)", file=sys.stderr,
-              flush=True)
-        # a plain read stream: torch's sum over the same 2 GiB
+        log(f"device copy: {copy_gbs:.1f} GB/s (read + write)")
         s = a.sum()
         torch.cuda.synchronize()
         e0.record()
@@ -209,60 +287,81 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         read_gbs = 5 * 2 ** 31 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-        print(f"[bench] device read (sum): {read_gbs:.1f} GB/s", file=sys.stderr, flush=True)
+        log(f"device read (sum): {read_gbs:.1f} GB/s")
         del a, b, s
-    y_head = y.detach().cpu().numpy().reshape(n, -1)
+    variants = {}
+    rows_t = torch.as_tensor(rows_err, device=dev)
+
+    def run_variant(name, opv, dtv, nr, steps, warmup, extra=None, profile=False, wl=wname,
+                    nn=n, xnp=None):
+        xv = torch.as_tensor(xnp, device=dev)
+        sec_v, yv, prof_v = time_products(opv, xv, steps, warmup, profile=profile)
+        rec = {"workload": wl, "factor_dtype": dtv, "nrhs": nr, "ms_per_step": round(1e3 * sec_v, 4),
+               "value": round(nn * nr / sec_v, 1), "factor_bytes": opv.stats()["factor_bytes"]}
+        if extra:
+            rec.update(extra)
+        if prof_v:
+            rec["roofline"] = roofline_of(prof_v, wl, dtv, nr)
+            rec["kernel_ms"] = kernel_table(prof_v)
+        variants[name] = rec
+        log(f"{name}: {1e3 * sec_v:.3f} ms, {nn * nr / sec_v:.3e} {UNIT}")
+        return yv
+
+    if not args.no_variants and nrhs > 1:
+        yv = run_variant(f"{dt}_1rhs", op, dt, 1, max(5, args.steps), max(2, args.warmup),
+                         xnp=x1_np)
+        sampled[f"{dt}_1rhs"] = ("1", yv.reshape(n, -1)[rows_t].cpu().numpy())
     op.close()
-    del op
+    del op, y, xh
     torch.cuda.empty_cache()
 
-    # the same workload in the other storage forms and with 64 right-hand sides
-    variants = {}
-    var_y = {}
-    if not args.no_variants and args.factor_dtype == "fp64" and args.nrhs == 1:
-        x64_np = inputs.workload_rhs(args.workload, 64)
-        for name, dt, nr in (("fp32_1rhs", "fp32", 1), ("bf16_1rhs", "bf16", 1),
-                             ("fp64_64rhs", "fp64", 64), ("fp32_64rhs", "fp32", 64),
-                             ("bf16_64rhs", "bf16", 64)):
-            opv = hodlr3d.build(torch.as_tensor(pts, device=dev), kernel=w["kernel"],
-                                leaf_size=w["leaf_size"], tol=w["tol"], factor_dtype=dt,
-                                box_lo=inputs.CUBE_LO, box_side=inputs.CUBE_SIDE)
-            xv = torch.as_tensor(x_np if nr == 1 else x64_np, device=dev)
-            sec, yv = time_products(opv, xv, max(3, args.steps // (4 if nr > 1 else 1)),
-                                    max(1, args.warmup // 2))
-            var_y[name] = yv.detach().cpu().numpy().reshape(n, -1)
-            variants[name] = {"factor_dtype": dt, "nrhs": nr, "ms_per_step": round(1e3 * sec, 4),
-                              "value": round(n * nr / sec, 1),
-                              "gain_vs_fp64_1rhs": round(n * nr / sec / value, 2),
-                              "factor_bytes": opv.stats()["factor_bytes"]}
-            print(f"[bench] {name}: {1e3 * sec:.3f} ms, {n * nr / sec:.3e} {UNIT}", file=sys.stderr,
-                  flush=True)
-            opv.close()
-            del opv, xv, yv
-            torch.cuda.empty_cache()
-        # FP32 factors recompressed in FP64 to their optimal ranks at tol
-        opv = hodlr3d.build(torch.as_tensor(pts, device=dev), kernel=w["kernel"],
-                            leaf_size=w["leaf_size"], tol=w["tol"], factor_dtype="fp32",
-                            box_lo=inputs.CUBE_LO, box_side=inputs.CUBE_SIDE, truncate=True)
-        for name, nr in (("fp32_trunc_1rhs", 1), ("fp32_trunc_64rhs", 64)):
-            xv = torch.as_tensor(x_np if nr == 1 else x64_np, device=dev)
-            sec, yv = time_products(opv, xv, max(3, args.steps // (4 if nr > 1 else 1)),
-                                    max(1, args.warmup // 2))
-            var_y[name] = yv.detach().cpu().numpy().reshape(n, -1)
-            variants[name] = {"factor_dtype": "fp32", "truncated": True, "nrhs": nr,
-                              "ms_per_step": round(1e3 * sec, 4), "value": round(n * nr / sec, 1),
-                              "gain_vs_fp64_1rhs": round(n * nr / sec / value, 2),
-                              "factor_bytes": opv.stats()["factor_bytes"]}
-            print(f"[bench] {name}: {1e3 * sec:.3f} ms, {n * nr / sec:.3e} {UNIT}", file=sys.stderr,
-                  flush=True)
-            del xv, yv
-        opv.close()
-        del opv
+    baseline = None
+    if not args.no_variants:
+        # ---- the plain FP64 form, one right-hand side (the baseline) -----
+        op, bs = build_op(pts, w, "fp64")
+        log(f"built {wname} (fp64): {op.stats()['factor_bytes'] / 1e9:.2f} GB factors, "
+            f"build {bs:.1f} s")
+        yv = run_variant("fp64_1rhs", op, "fp64", 1, max(5, args.steps), max(2, args.warmup),
+                         extra={"build_s": round(bs, 2)}, profile=True, xnp=x1_np)
+        sampled["fp64_1rhs"] = ("1", yv.reshape(n, -1)[rows_t].cpu().numpy())
+        baseline = variants.pop("fp64_1rhs")
+        op.close()
+        del op, yv
+        torch.cuda.empty_cache()
+        # ---- BF16 factors with per-factor scale --------------------------
+        op, bs = build_op(pts, w, "bf16")
+        yv = run_variant("bf16_1rhs", op, "bf16", 1, max(5, args.steps), max(2, args.warmup),
+                         extra={"build_s": round(bs, 2)}, xnp=x1_np)
+        sampled["bf16_1rhs"] = ("1", yv.reshape(n, -1)[rows_t].cpu().numpy())
+        if nrhs > 1:
+            yv = run_variant(f"bf16_{nrhs}rhs", op, "bf16", nrhs, max(3, args.steps // 4),
+                             max(1, args.warmup // 2), xnp=xh_np)
+            sampled[f"bf16_{nrhs}rhs"] = ("h", yv.reshape(n, -1)[rows_t].cpu().numpy())
+        op.close()
+        del op, yv
+        torch.cuda.empty_cache()
+        # ---- 262,144 points, plain FP64, one RHS (and FP32 64 RHS) -------
+        w2 = inputs.WORKLOADS["uniform262k"]
+        pts2 = inputs.workload_points("uniform262k")
+        x2 = inputs.workload_rhs("uniform262k", None)
+        op, bs = build_op(pts2, w2, "fp64")
+        run_variant("uniform262k_fp64_1rhs", op, "fp64", 1, max(5, args.steps),
+                    max(2, args.warmup), extra={"build_s": round(bs, 2)}, profile=True,
+                    wl="uniform262k", nn=w2["n"], xnp=x2)
+        op.close()
+        del op
+        torch.cuda.empty_cache()
+        op, bs = build_op(pts2, w2, "fp32")
+        run_variant("uniform262k_fp32_64rhs", op, "fp32", 64, max(3, args.steps // 4),
+                    max(1, args.warmup // 2), extra={"build_s": round(bs, 2)}, profile=True,
+                    wl="uniform262k", nn=w2["n"], xnp=inputs.workload_rhs("uniform262k", 64))
+        op.close()
+        del op, pts2, x2
         torch.cuda.empty_cache()
 
-    # many uneven problems in one persistent launch
+    # ---- many uneven problems in one persistent launch --------------------
     batch_ys = None
-    if not args.no_variants and args.factor_dtype == "fp64" and args.nrhs == 1:
+    if not args.no_variants:
         bw = inputs.BATCH_WORKLOAD
         work = inputs.batch_workload(bw["count"])
         t0 = time.perf_counter()
@@ -299,71 +398,114 @@ def main():
             "ms_per_step": round(1e3 * tb, 4), "value": round(ntot / tb, 1),
             "own_products_in_sequence_ms": round(1e3 * ts, 4),
             "gain_vs_own_products": round(ts / tb, 2),
-            "factor_bytes": bst["factor_bytes"], "build_s": round(bbuild, 2)}
-        print(f"[bench] batch32: {1e3 * tb:.3f} ms ({1e3 * ts:.3f} ms as own products)",
-              file=sys.stderr, flush=True)
+            "factor_bytes": bst["factor_bytes"],
+            "hbm_gbs": round(bst["factor_bytes"] / tb / 1e9, 1), "build_s": round(bbuild, 2)}
+        log(f"batch32: {1e3 * tb:.3f} ms ({1e3 * ts:.3f} ms as own products)")
         batch_ys = [(work[i][0], work[i][1], ys[i].detach().cpu().numpy()) for i in (0, 17)]
         bop.close()
         del bop, xs, ys
         torch.cuda.empty_cache()
 
+    # ---- the CPU oracle: exact rows (errors and the baseline) -------------
     cpu = None
+    err_head = None
     if not args.no_cpu_baseline:
         import oracle
         oracle.build(force=False)
-        threads = min(16, os.cpu_count() or 1)
+        threads = cpu_threads()
         oracle.set_num_threads(threads)
-        y_np = y_head
-        xs = x_np.reshape(n, -1)
-        # a probe large enough for every thread to stay busy: the rate of a
-        # few dozen rows understates what the threads sustain several times
-        probe = inputs.sample_rows(n, min(n, 2048), seed=3)
+        # exact rows of the one-RHS forms
+        ref1 = oracle.dense_rows(pts, x1_np.reshape(n, 1), rows_err, kernel=w["kernel"])
+        # the headline sample: as many exact rows (all right-hand sides) as the
+        # threads finish in about cpu_seconds, measured on a probe first
+        xh2 = xh_np.reshape(n, -1)
+        probe = inputs.sample_rows(n, min(n, 4 * threads), seed=5)
         t0 = time.perf_counter()
-        oracle.dense_rows(pts, xs, probe, kernel=w["kernel"])
+        oracle.dense_rows(pts, xh2, probe, kernel=w["kernel"])
         per_row = (time.perf_counter() - t0) / probe.size
-        count = int(min(n, max(64, args.cpu_seconds / max(per_row, 1e-9))))
-        rows = inputs.sample_rows(n, count, seed=4)
+        count = int(min(rows_err.size, max(16, args.cpu_seconds / max(per_row, 1e-9))))
+        rows_c = rows_err[:count]
         t0 = time.perf_counter()
-        yd = oracle.dense_rows(pts, xs, rows, kernel=w["kernel"])
+        refh = oracle.dense_rows(pts, xh2, rows_c, kernel=w["kernel"])
         cpu_s = time.perf_counter() - t0
-        err = float(np.linalg.norm(y_np[rows] - yd) / np.linalg.norm(yd))
-        # accuracy of the other forms on sampled rows of the exact product
-        if var_y:
-            r64 = rows[:64]
-            yd64 = oracle.dense_rows(pts, inputs.workload_rhs(args.workload, 64), r64,
-                                     kernel=w["kernel"])
-            for name, yv in var_y.items():
-                ref = yd if yv.shape[1] == 1 else yd64
-                rr = rows if yv.shape[1] == 1 else r64
-                variants[name]["rel_err_on_sample"] = float(
-                    np.linalg.norm(yv[rr] - ref) / np.linalg.norm(ref))
+        # one thread, on a smaller sample
+        oracle.set_num_threads(1)
+        c1 = max(2, count // (2 * threads))
+        t0 = time.perf_counter()
+        oracle.dense_rows(pts, xh2, rows_c[:c1], kernel=w["kernel"])
+        cpu1_s = time.perf_counter() - t0
+        oracle.set_num_threads(threads)
+        for form, (rid, ygpu) in sampled.items():
+            if rid == "1":
+                e = rel_err(ygpu, ref1)
+            else:
+                e = rel_err(ygpu[:count], refh)
+            if form == head_form:
+                err_head = e
+            elif form == "fp64_1rhs" and baseline is not None:
+                baseline["rel_err_on_sample"] = e
+            elif form in variants:
+                variants[form]["rel_err_on_sample"] = e
         if batch_ys:
             errs = []
             for pts_i, x_i, y_i in batch_ys:
                 r_i = inputs.sample_rows(len(pts_i), 64, seed=3)
                 ref = oracle.dense_rows(pts_i, x_i, r_i, kernel=inputs.BATCH_WORKLOAD["kernel"])
-                errs.append(float(np.linalg.norm(y_i[r_i] - ref) / np.linalg.norm(ref)))
+                errs.append(rel_err(y_i[r_i], ref))
             variants["batch32_fp32"]["rel_err_on_sample"] = max(errs)
-        cpu = {"value": round(rows.size * args.nrhs / cpu_s, 1), "unit": UNIT,
-               "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": f"exact FP64 direct sum for {rows.size} sampled target rows of the "
-                         f"same N={n} workload ({cpu_s:.1f} s)",
-               "gpu_rel_err_on_sample": err}
+        # the oracle's own HODLR3D product where it finishes: the 16^3 grid and
+        # 65,536 uniform points (same kernel, leaf and tolerance rules)
+        hod = {}
+        for hname, hp, hx, htol in (
+                ("grid4096_tol1e-10", inputs.grid_points(16), inputs.uniform_rhs(4096, 0), 1e-10),
+                ("uniform65536_tol1e-7", inputs.uniform_points(65536, 0),
+                 inputs.normal_rhs(65536, 1), 1e-7)):
+            t0 = time.perf_counter()
+            H = oracle.HODLR3D(hp, kernel=w["kernel"], leaf_size=w["leaf_size"], tol=htol,
+                               box_lo=inputs.CUBE_LO, box_side=inputs.CUBE_SIDE)
+            hb = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            H.matvec(hx)
+            hm = time.perf_counter() - t0
+            oracle.set_num_threads(1)
+            t0 = time.perf_counter()
+            H.matvec(hx)
+            hm1 = time.perf_counter() - t0
+            oracle.set_num_threads(threads)
+            hod[hname] = {"n": len(hp), "build_s": round(hb, 2), "matvec_s": round(hm, 4),
+                          "matvec_s_1thread": round(hm1, 4),
+                          "value": round(len(hp) / hm, 1)}
+            del H
+        cpu = {"value": round(count * nrhs / cpu_s, 1), "unit": UNIT, "cores": threads,
+               "kind": "oracle",
+               "sample": f"exact FP64 direct sum, all {nrhs} right-hand sides, for {count} "
+                         f"sampled target rows of the same N={n} workload ({cpu_s:.1f} s)",
+               "value_1thread": round(c1 * nrhs / cpu1_s, 1),
+               "sample_1thread": f"{c1} of the same rows on one thread ({cpu1_s:.1f} s)",
+               "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+               "oracle_hodlr3d_matvec": hod}
 
+    if baseline is not None:
+        baseline["gain"] = round(value / baseline["value"], 2)
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": UNIT, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": DTYPE_NAMES[args.factor_dtype], "data": "synthetic",
+        "dtype": DTYPE_NAMES[dt], "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: N={n} i.i.d. uniform points in [-1,1]^3, "
-                        f"{w['kernel']} kernel, leaf <= {w['leaf_size']}, ACA tol {w['tol']}, "
-                        f"{args.factor_dtype} factors, {args.nrhs} RHS",
-            "n": n, "nrhs": args.nrhs, "depth": st["depth"], "far_blocks": st["n_far"],
+            "workload": f"{wname}: N={n} i.i.d. uniform points in [-1,1]^3, "
+                        f"{w['kernel']} kernel, leaf <= {w['leaf_size']}, ACA tol {w['tol']} "
+                        f"(FP64), {dt} factors, {nrhs} RHS"
+                        + (" (adjoint)" if args.adjoint else ""),
+            "n": n, "nrhs": nrhs, "depth": st["depth"], "far_blocks": st["n_far"],
             "factor_bytes": st["factor_bytes"], "rank_max": st["rank_max"],
             "build_s": round(build_s, 2), "aca_s": round(st["aca_ms"] / 1e3, 2),
             "kernel_ms": kernels, "parallelism": "single GPU",
         },
+        "rel_err_on_sample": err_head,
+        "meets_gate": None if err_head is None else bool(err_head <= GATE),
+        "gain_vs_fp64_1rhs": None if baseline is None else baseline["gain"],
+        "baseline_fp64_1rhs": baseline,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "device_copy_gbs": None if copy_gbs is None else round(copy_gbs, 1),
