@@ -283,6 +283,27 @@ h3d_status h3d_profile_reset(h3d_plan *plan);
 
 int32_t h3d_version(void);
 
+/*
+ * For callers that cannot allocate device memory during a product (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * y = K~ x exactly as h3d_matvec computes it (bitwise the same result), with
+ * every scratch buffer of the product taken from one static device array of
+ * H3D_NOALLOC_SCRATCH_BYTES per GPU instead of plan memory.  The call makes no
+ * hipMalloc, hipFree or other allocating call (profiling is off for it).
+ * Arguments as h3d_matvec, with nrhs < 8 (one to seven right-hand sides).
+ * The product needs 16 n nrhs bytes plus 8 bytes per stage-1 factor column
+ * and right-hand side (each part rounded up to 256 bytes); more than the array
+ * holds, or nrhs >= 8, gives H3D_EINVAL and launches nothing.  The array of a
+ * GPU is held from the library's first use of that GPU until the process
+ * ends.  Every call on one GPU shares it, whatever the plan: calls that
+ * overlap in time on one GPU (other streams, other threads) race and give
+ * wrong results; serialise them.  Nothing of one call's scratch is read by
+ * the next (every value is written before it is read).
+ */
+#define H3D_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+h3d_status h3d_matvec_noalloc(h3d_plan *plan, const void *x, void *y, int64_t nrhs,
+                              int64_t ldx, int64_t ldy, int32_t io_dtype, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -702,3 +702,81 @@ h3d_status h3d_profile_read(h3d_plan *plan, h3d_kernel_profile *out, int32_t cap
 }
 
 }  // extern "C"
+
+// ---- h3d_matvec_noalloc ----------------------------------------------------
+// Its scratch (the sorted input, the sorted sums and the stage-1 z values of
+// a vector product) lives in this array instead of plan memory.  Each GPU
+// holds its own copy from the module's load on that GPU until the process
+// ends.  Host code never uses the array's name as an address: the device
+// address of each GPU's copy is looked up once per device with
+// hipGetSymbolAddress and kept in g_scratch_addr.
+static __device__ __align__(256) unsigned char scratch[H3D_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<unsigned char *> g_scratch_addr;  // per device; nullptr until looked up
+
+// Device address of `scratch` on the current device (dev), looked up on the
+// first call for that device.
+unsigned char *scratch_address(int dev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (dev < 0)
+        h3d::fail(H3D_EDEVICE, "no current device");
+    if (size_t(dev) >= g_scratch_addr.size())
+        g_scratch_addr.resize(size_t(dev) + 1, nullptr);
+    if (!g_scratch_addr[size_t(dev)]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            h3d::fail(H3D_EDEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") +
+                                       hipGetErrorString(e));
+        g_scratch_addr[size_t(dev)] = static_cast<unsigned char *>(p);
+    }
+    return g_scratch_addr[size_t(dev)];
+}
+
+size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace
+
+extern "C" {
+
+h3d_status h3d_matvec_noalloc(h3d_plan *plan, const void *x, void *y, int64_t nrhs, int64_t ldx,
+                              int64_t ldy, int32_t io_dtype, void *hip_stream) {
+    const h3d_status st = matvec_check(plan, x, y, nrhs, ldx, ldy, io_dtype);
+    if (st != H3D_OK)
+        return st;
+    h3d::Plan &P = plan->P;
+    if (nrhs >= h3d::kBatchedMinRhs)
+        return invalid("h3d_matvec_noalloc takes nrhs < " + std::to_string(h3d::kBatchedMinRhs) +
+                       " (the matrix-core path of more right-hand sides keeps plan scratch)");
+    const size_t xb = round256(sizeof(double) * size_t(P.n) * size_t(nrhs));
+    const size_t zb = round256(sizeof(double) * size_t(h3d::vector_z_entries(P, nrhs)));
+    const size_t need = 2 * xb + zb;
+    if (need > size_t(H3D_NOALLOC_SCRATCH_BYTES))
+        return invalid("h3d_matvec_noalloc: this product needs " + std::to_string(need) +
+                       " bytes of scratch, more than the " +
+                       std::to_string(size_t(H3D_NOALLOC_SCRATCH_BYTES)) +
+                       " it holds; use h3d_matvec");
+    return guarded([&] {
+        DeviceScope ds(P.device);
+        unsigned char *base = scratch_address(P.device);
+        double *xp = reinterpret_cast<double *>(base);
+        double *yn = reinterpret_cast<double *>(base + xb);
+        double *z = reinterpret_cast<double *>(base + 2 * xb);
+        // profiling would create events: off for this call
+        const bool prof = P.prof.on;
+        P.prof.on = false;
+        try {
+            h3d::matvec_vector(P, x, y, nrhs, ldx, ldy, io_dtype, false, xp, yn, z,
+                               static_cast<hipStream_t>(hip_stream));
+        } catch (...) {
+            P.prof.on = prof;
+            throw;
+        }
+        P.prof.on = prof;
+    });
+}
+
+}  // extern "C"

@@ -32,7 +32,7 @@ EXPORTED_SYMBOLS = (
     "h3d_export", "h3d_destroy", "h3d_last_error", "h3d_profile_enable", "h3d_profile_read",
     "h3d_profile_reset", "h3d_version", "h3d_autotune", "h3d_graph_create",
     "h3d_graph_launch", "h3d_graph_destroy", "h3d_build_batch", "h3d_matvec_batch",
-    "h3d_batch_plan", "h3d_batch_check",
+    "h3d_batch_plan", "h3d_batch_check", "h3d_matvec_noalloc",
 )
 
 
@@ -129,7 +129,7 @@ def load_library():
     lib.h3d_build.argtypes = [P, I64, ctypes.POINTER(Config), ctypes.POINTER(Allocator), P,
                               ctypes.POINTER(P)]
     lib.h3d_build.restype = S
-    for f in ("h3d_matvec", "h3d_matvec_adjoint"):
+    for f in ("h3d_matvec", "h3d_matvec_adjoint", "h3d_matvec_noalloc"):
         getattr(lib, f).argtypes = [P, P, P, I64, I64, I64, I32, P]
         getattr(lib, f).restype = S
     lib.h3d_get_stats.argtypes = [P, ctypes.POINTER(Stats)]
@@ -248,7 +248,7 @@ class Operator:
         return self._h
 
     # -- products ---------------------------------------------------------
-    def _apply(self, x, adjoint: bool, out=None):
+    def _apply(self, x, adjoint: bool, out=None, noalloc: bool = False):
         torch = _torch()
         if not isinstance(x, torch.Tensor) or not x.is_cuda:
             raise TypeError("x must be a CUDA (HIP) tensor")
@@ -262,7 +262,9 @@ class Operator:
         y = torch.empty_like(xc) if out is None else out
         io = 0 if x.dtype == torch.float64 else 1
         stream = torch.cuda.current_stream(x.device).cuda_stream
-        fn = load_library().h3d_matvec_adjoint if adjoint else load_library().h3d_matvec
+        lib = load_library()
+        fn = (lib.h3d_matvec_noalloc if noalloc else
+              lib.h3d_matvec_adjoint if adjoint else lib.h3d_matvec)
         _check(fn(self._h, ctypes.c_void_p(xc.data_ptr()), ctypes.c_void_p(y.data_ptr()), nrhs,
                   self.n, self.n, io, ctypes.c_void_p(stream)))
         return y.reshape(-1) if vec else y.t()
@@ -274,6 +276,11 @@ class Operator:
     def rmatvec(self, x):
         """y = K~^T x with the same stored blocks."""
         return self._apply(x, adjoint=True)
+
+    def matvec_noalloc(self, x):
+        """y = K~ x (nrhs < 8) through h3d_matvec_noalloc: the library allocates
+        nothing during the product (its scratch is one static array per GPU)."""
+        return self._apply(x, adjoint=False, noalloc=True)
 
     def __matmul__(self, x):
         return self.matvec(x)
