@@ -77,7 +77,17 @@ enum {
      * ||(s_{r+1}, ..., s_k)||_2 <= tol ||s||_2, s the singular values of U V^T
      * (QR of U and V, SVD of the small core); blocks of rank above 256 and
      * boxes of more than 4096 points are kept.  Excludes H3D_FLAG_KEEP_PIVOTS. */
-    H3D_FLAG_TRUNCATE = 4
+    H3D_FLAG_TRUNCATE = 4,
+    /* the paper's storage form (Sec. 4.1, eqs. (prank) and (LR); the low-rank
+     * step of Algorithm 2): every block keeps only its ACA pivots sigma, tau
+     * and the LU factors of K(sigma, tau), k^2 + 2k values instead of
+     * (m + n) k; every product regenerates the entries of K(sigma, Y) and
+     * K(X, tau) and applies K(X,tau) R^-1 L^-1 K(sigma,Y) x(Y).  Needs
+     * factor_dtype H3D_F64 and ranks of at most 256 (H3D_ENOTIMPL otherwise;
+     * max_rank caps them); excludes H3D_FLAG_TRUNCATE; not for batches.
+     * h3d_export gives H3D_EXPORT_LU (and H3D_EXPORT_PIVOTS with
+     * H3D_FLAG_KEEP_PIVOTS), not the explicit factors. */
+    H3D_FLAG_LU_FORM = 8
 };
 
 typedef struct {
@@ -107,7 +117,8 @@ typedef struct {
     int32_t rank_max;
     int64_t n_rank_capped;                    /* blocks stopped by max_rank */
     int64_t factor_entries;                   /* sum over blocks of (m + n) k */
-    int64_t factor_bytes;                     /* stored bytes of U and V (+ scales) */
+    int64_t factor_bytes;                     /* stored bytes of U and V (+ scales); LU form:
+                                                 LU factors, pivot rows, adjoint order */
     int64_t factor_bytes_per_level[H3D_MAX_LEVELS];
     int64_t near_pair_evals;                  /* sum over near leaf pairs of m n */
     int64_t device_bytes;                     /* all device memory held by the plan */
@@ -241,7 +252,10 @@ typedef enum {
     H3D_EXPORT_NEAR = 3,      /* int64[3][n_near]: t, s, relation (0 self, 1 F, 2 E) */
     H3D_EXPORT_FACTORS_U = 4, /* double[sum m k]: U_b (m x k, column-major), block order */
     H3D_EXPORT_FACTORS_V = 5, /* double[sum n k]: V_b (n x k, column-major), block order */
-    H3D_EXPORT_PIVOTS = 6     /* int64[2][sum k]: row then column pivots (box-local) */
+    H3D_EXPORT_PIVOTS = 6,    /* int64[2][sum k]: row then column pivots (box-local) */
+    H3D_EXPORT_LU = 7         /* double[sum k^2], H3D_FLAG_LU_FORM plans: per block the
+                               * k x k column-major LU of K(sigma, tau), L on and below
+                               * the diagonal, the unit-diagonal R above it */
 } h3d_export_what;
 
 /* Copies one structure to host_buf.  With host_buf == NULL only *bytes is set
@@ -282,6 +296,7 @@ h3d_status h3d_profile_read(h3d_plan *plan, h3d_kernel_profile *out, int32_t cap
 h3d_status h3d_profile_reset(h3d_plan *plan);
 
 int32_t h3d_version(void);
+
 
 /*
  * For callers that cannot allocate device memory during a product (code under

@@ -167,6 +167,14 @@ h3d_status check_config(const h3d_config *cfg, const h3d_allocator *alloc) {
     if ((cfg->flags & H3D_FLAG_TRUNCATE) && (cfg->flags & H3D_FLAG_KEEP_PIVOTS))
         return invalid("truncated factors have no ACA pivots: H3D_FLAG_TRUNCATE excludes "
                        "H3D_FLAG_KEEP_PIVOTS");
+    if (cfg->flags & H3D_FLAG_LU_FORM) {
+        if (cfg->flags & H3D_FLAG_TRUNCATE)
+            return invalid("the pivot + LU form keeps the ACA pivots: H3D_FLAG_LU_FORM excludes "
+                           "H3D_FLAG_TRUNCATE");
+        if (cfg->factor_dtype != H3D_F64)
+            return invalid("the pivot + LU form stores FP64 LU factors: factor_dtype must be "
+                           "H3D_F64");
+    }
     return H3D_OK;
 }
 
@@ -279,6 +287,10 @@ h3d_status h3d_build_batch(int32_t nprob, const double *const *points, const int
     h3d_status st = check_config(cfg, alloc);
     if (st != H3D_OK)
         return st;
+    if (cfg->flags & H3D_FLAG_LU_FORM)
+        return g_last_error = "the persistent batch launch carries the explicit-factor kernels: "
+                              "H3D_FLAG_LU_FORM is not available for batches",
+               H3D_ENOTIMPL;
     for (int32_t i = 0; i < nprob; ++i) {
         if (!points[i])
             return invalid("points[" + std::to_string(i) + "] is NULL");
@@ -542,6 +554,9 @@ h3d_status h3d_export(const h3d_plan *plan, int32_t what, void *host_buf, size_t
         break;
     case H3D_EXPORT_FACTORS_U:
     case H3D_EXPORT_FACTORS_V: {
+        if (P.lu_form)
+            return invalid("a pivot + LU form plan stores no explicit factors: export "
+                           "H3D_EXPORT_LU");
         const int64_t ev = P.entries_v;
         need = size_t(what == H3D_EXPORT_FACTORS_V ? ev : P.stats.factor_entries - ev) * 8;
         break;
@@ -550,6 +565,11 @@ h3d_status h3d_export(const h3d_plan *plan, int32_t what, void *host_buf, size_t
         if (!P.blk_piv)
             return invalid("pivots were not kept (build with H3D_FLAG_KEEP_PIVOTS)");
         need = size_t(P.ncols) * 2 * 8;
+        break;
+    case H3D_EXPORT_LU:
+        if (!P.lu_form)
+            return invalid("H3D_EXPORT_LU needs a plan built with H3D_FLAG_LU_FORM");
+        need = size_t(P.lu_sq) * 8;
         break;
     default:
         return invalid("unknown export id");
@@ -629,6 +649,9 @@ h3d_status h3d_export(const h3d_plan *plan, int32_t what, void *host_buf, size_t
                 }
             break;
         }
+        case H3D_EXPORT_LU:
+            h3d::export_lu(P, static_cast<double *>(host_buf));
+            break;
         }
         *bytes = need;
     });

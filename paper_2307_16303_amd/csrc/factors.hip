@@ -340,9 +340,18 @@ void factors_build(Plan &P, hipStream_t s) {
     P.chunk_level = lc;
     P.panel_end = lc >= 1 ? P.lvl_blk[lc] : 0;
     const int shc = 3 * (P.L - lc);
+    P.lu_form = (P.cfg.flags & H3D_FLAG_LU_FORM) != 0;
     P.blk_rank = P.mem.alloc_n<int32_t>(nf);
     P.blk_uptr = P.mem.alloc_n<void *>(nf);
     P.blk_vptr = P.mem.alloc_n<void *>(nf);
+    if (P.lu_form) {
+        // no explicit factors: the pointer tables stay NULL; one LU per block
+        P.blk_lu = P.mem.alloc_n<void *>(nf);
+        H3D_HIP(hipMemsetAsync(P.blk_uptr, 0, sizeof(void *) * size_t(nf), s));
+        H3D_HIP(hipMemsetAsync(P.blk_vptr, 0, sizeof(void *) * size_t(nf), s));
+        H3D_HIP(hipMemsetAsync(P.blk_lu, 0, sizeof(void *) * size_t(nf), s));
+        P.leaf_fuse = 0;
+    }
     P.blk_col0 = P.mem.alloc_n<int64_t>(nf + 1);
     if (dt == H3D_BF16_SCALED)
         P.blk_scale = P.mem.alloc_n<float>(2 * nf);
@@ -353,7 +362,8 @@ void factors_build(Plan &P, hipStream_t s) {
     }
     H3D_HIP(hipMemsetAsync(P.blk_rank, 0, sizeof(int32_t) * size_t(nf), s));
 
-    const bool keep_piv = (P.cfg.flags & H3D_FLAG_KEEP_PIVOTS) != 0;
+    // the pivot + LU form needs the pivots (its build releases them unless kept)
+    const bool keep_piv = (P.cfg.flags & H3D_FLAG_KEEP_PIVOTS) != 0 || P.lu_form;
     if (keep_piv) {
         int64_t *kc2 = P.mem.alloc_n<int64_t>(nf + 1);
         H3D_HIP(hipMemsetAsync(kc2 + nf, 0, sizeof(int64_t), s));
@@ -423,6 +433,12 @@ void factors_build(Plan &P, hipStream_t s) {
                 truncate_batch(P, list, q0, q1, kws, ws, ws_off, base, overflow, s);
             // pack the finished blocks of the batch into their own chunk
             const int64_t nb = q1 - q0;
+            if (P.lu_form) {
+                lu_pack_batch(P, list, q0, q1, kws, ws, ws_off, base, mk, s);
+                H3D_HIP(hipStreamSynchronize(s));
+                q0 = q1;
+                continue;
+            }
             k_pack_sizes<<<grid_for(nb, 256), 256, 0, s>>>(q0, q1, list, P.blk_m, P.blk_n,
                                                            P.blk_rank, mk, nk);
             H3D_LAUNCH_CHECK();
@@ -532,6 +548,12 @@ void factors_build(Plan &P, hipStream_t s) {
     P.stats.factor_bytes = bytes;
     P.stats.rank_sum = P.ncols;
     P.stats.rank_max = rmax;
+    if (P.lu_form) {
+        // pivot rows, the adjoint's column order and the work items; the
+        // stored bytes are recounted there
+        lu_finish(P, s);
+        return;
+    }
 
     // adjoint stage-1 items of the panelled levels
     for (int l = 1; l < P.chunk_level; ++l) {

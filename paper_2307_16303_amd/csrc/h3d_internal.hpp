@@ -275,6 +275,24 @@ struct Plan {
     // stored factors
     int factor_dtype = H3D_F64;
     std::vector<void *> chunks;
+
+    // the pivot + LU form (H3D_FLAG_LU_FORM, lu_form.hip): per block the packed
+    // LU factors of K(sigma, tau); per factor column the sorted rows of its two
+    // pivot points; the adjoint's column order (blocks grouped by source);
+    // stage-1 work items and the partial sums of split blocks
+    bool lu_form = false;
+    void **blk_lu = nullptr;          // [nfar] k x k column-major
+    int64_t lu_sq = 0;                // sum of k^2
+    int32_t *lu_sig_row = nullptr;    // [ncols]
+    int32_t *lu_tau_row = nullptr;    // [ncols]
+    int64_t *lu_adj_col0 = nullptr;   // [nfar + 1] over the positions of src_blk
+    int32_t *lu_adj_col = nullptr;    // [ncols]
+    void *lu_items[2] = {};           // forward, adjoint
+    int64_t lu_nitems[2] = {};
+    void *lu_split[2] = {};
+    int64_t lu_nsplit[2] = {};
+    int64_t lu_wcols = 0;
+    double *lu_wpart = nullptr;
     h3d_stats stats{};
 
     // mat-vec scratch, grown on demand
@@ -413,6 +431,19 @@ void autotune(Plan &P, int64_t nrhs, hipStream_t s);
 void ensure_scratch(Plan &P, int64_t nrhs, hipStream_t s);
 void matvec_batched(Plan &P, const void *x, void *y, int64_t nrhs, int64_t ldx, int64_t ldy,
                     int io_dtype, bool adjoint, hipStream_t s);
+
+// near field of a product (FP64 entries, or FP32 entries for FP32/BF16 factors)
+void launch_near_field(Plan &P, int nrhs, const double *xp, double *yn, hipStream_t s);
+// the pivot + LU form (lu_form.hip)
+constexpr int kLuSlots = 4;                // 64-row register slots of the in-wave solves
+constexpr int kLuMaxRank = 64 * kLuSlots;  // largest rank the form takes
+constexpr int kLuGroup = 4;                // right-hand sides per pass of its kernels
+void lu_pack_batch(Plan &P, const int32_t *list, int64_t q0, int64_t q1, int kws, const double *ws,
+                   const int64_t *ws_off, int64_t ws_base, int64_t *scan_buf, hipStream_t s);
+void lu_finish(Plan &P, hipStream_t s);
+void matvec_lu(Plan &P, const void *x, void *y, int64_t nrhs, int64_t ldx, int64_t ldy,
+               int io_dtype, bool adjoint, double *xp, double *yn, double *z, hipStream_t s);
+void export_lu(const Plan &P, double *host_out);
 
 // device-wide exclusive scan; out may alias in; returns the total
 int64_t scan_exclusive_i64(Plan &P, const int64_t *in, int64_t *out, int64_t n, hipStream_t s);

@@ -493,7 +493,8 @@ void ensure_scratch(Plan &P, int64_t nrhs, hipStream_t s) {
 }
 
 void autotune(Plan &P, int64_t nrhs, hipStream_t s) {
-    if (P.nfar == 0 || nrhs >= kBatchedMinRhs)
+    // the pivot + LU form has no launch shapes to choose
+    if (P.nfar == 0 || nrhs >= kBatchedMinRhs || P.lu_form)
         return;
     // the tuner rebuilds the stage-1 work tables that earlier products used
     if (P.built)
@@ -521,7 +522,17 @@ void autotune(Plan &P, int64_t nrhs, hipStream_t s) {
     H3D_HIP(hipStreamSynchronize(s));
 }
 
+void launch_near_field(Plan &P, int nrhs, const double *xp, double *yn, hipStream_t s) {
+    if (nrhs == 1)
+        launch_near<1>(P, 1, xp, yn, s);
+    else
+        launch_near<4>(P, nrhs, xp, yn, s);
+}
+
 int64_t vector_z_entries(const Plan &P, int64_t nrhs) {
+    // the pivot + LU form runs kLuGroup right-hand sides at a time
+    if (P.lu_form)
+        return std::max<int64_t>(P.ncols, 1) * std::min<int64_t>(nrhs, kLuGroup);
     // one right-hand side with the finest level fused: z of that level (the
     // last columns) is never stored
     if (nrhs == 1 && P.L >= 1 && leaf_shape(P))
@@ -533,6 +544,16 @@ void matvec_vector(Plan &P, const void *x, void *y, int64_t nrhs, int64_t ldx, i
                    int io_dtype, bool adjoint, double *xp, double *yn, double *z, hipStream_t s) {
     const int64_t n = P.n;
     const int io_f32 = io_dtype == H3D_F32;
+    if (P.lu_form) {
+        // kLuGroup columns at a time through the same scratch
+        const size_t es = io_f32 ? 4 : 8;
+        for (int64_t c = 0; c < nrhs; c += kLuGroup)
+            matvec_lu(P, static_cast<const char *>(x) + size_t(c * ldx) * es,
+                      static_cast<char *>(y) + size_t(c * ldy) * es,
+                      std::min<int64_t>(kLuGroup, nrhs - c), ldx, ldy, io_dtype, adjoint, xp, yn, z,
+                      s);
+        return;
+    }
     {
         hipEvent_t ev = P.prof.begin(s);
         k_gather<<<grid_for(n, 256), 256, 0, s>>>(x, io_f32, ldx, n, int(nrhs), P.perm, xp);
@@ -568,6 +589,11 @@ void matvec_vector(Plan &P, const void *x, void *y, int64_t nrhs, int64_t ldx, i
 
 void matvec_run(Plan &P, const void *x, void *y, int64_t nrhs, int64_t ldx, int64_t ldy,
                 int io_dtype, bool adjoint, hipStream_t s) {
+    if (P.lu_form) {
+        ensure_scratch(P, std::min<int64_t>(nrhs, kLuGroup), s);
+        matvec_vector(P, x, y, nrhs, ldx, ldy, io_dtype, adjoint, P.xp, P.yp, P.z, s);
+        return;
+    }
     if (nrhs >= kBatchedMinRhs) {
         matvec_batched(P, x, y, nrhs, ldx, ldy, io_dtype, adjoint, s);
         return;

@@ -21,10 +21,11 @@ STATUS_NAMES = {0: "H3D_OK", 1: "H3D_EINVAL", 2: "H3D_ENOMEM", 3: "H3D_EDEVICE",
 KERNELS = {"laplace": 0, "yukawa": 1, "inv_r4": 2, "cos_r": 3}
 DTYPES = {"fp64": 0, "f64": 0, "fp32": 1, "f32": 1, "bf16": 2, "bf16_scaled": 2}
 EXPORTS = {"perm": 0, "leaf_off": 1, "far": 2, "near": 3, "factors_u": 4, "factors_v": 5,
-           "pivots": 6}
+           "pivots": 6, "lu": 7}
 FLAG_KEEP_PIVOTS = 1
 FLAG_NO_AUTOTUNE = 2
 FLAG_TRUNCATE = 4
+FLAG_LU_FORM = 8
 MAX_LEVELS = 11
 
 EXPORTED_SYMBOLS = (
@@ -306,7 +307,7 @@ class Operator:
         lib = load_library()
         nbytes = ctypes.c_size_t(0)
         _check(lib.h3d_export(self._h, wid, None, ctypes.byref(nbytes)))
-        dtype = np.float64 if what.startswith("factors") else np.int64
+        dtype = np.float64 if what.startswith("factors") or what == "lu" else np.int64
         buf = np.empty(max(nbytes.value // 8, 1), dtype=dtype)
         _check(lib.h3d_export(self._h, wid, buf.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nbytes)))
         buf = buf[: nbytes.value // 8]
@@ -383,7 +384,8 @@ class Graph:
 
 
 def _make_config(kernel, kernel_param, leaf_size, tol, factor_dtype, max_rank, max_depth, box_lo,
-                 box_side, workspace_bytes, keep_pivots, autotune, truncate=False) -> Config:
+                 box_side, workspace_bytes, keep_pivots, autotune, truncate=False,
+                 lu_form=False) -> Config:
     cfg = default_config()
     cfg.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     cfg.kernel_param = float(kernel_param)
@@ -398,7 +400,7 @@ def _make_config(kernel, kernel_param, leaf_size, tol, factor_dtype, max_rank, m
     cfg.box_side = float(box_side)
     cfg.workspace_bytes = int(workspace_bytes)
     cfg.flags = ((FLAG_KEEP_PIVOTS if keep_pivots else 0) | (0 if autotune else FLAG_NO_AUTOTUNE)
-                 | (FLAG_TRUNCATE if truncate else 0))
+                 | (FLAG_TRUNCATE if truncate else 0) | (FLAG_LU_FORM if lu_form else 0))
     return cfg
 
 
@@ -418,14 +420,17 @@ def build(points, kernel="laplace", kernel_param: float = 1.0, leaf_size: int = 
           tol: float = 1e-8, factor_dtype="fp64", max_rank: int = 0, max_depth: int = 10,
           box_lo=None, box_side: float = 0.0, workspace_bytes: int = 0,
           keep_pivots: bool = False, use_torch_allocator: bool = True,
-          autotune: bool = True, truncate: bool = False) -> Operator:
+          autotune: bool = True, truncate: bool = False, lu_form: bool = False) -> Operator:
     """Builds the HODLR3D operator of the n x 3 FP64 point cloud (moved to the GPU).
-    truncate=True recompresses every block's ACA factors to its optimal rank at tol."""
+    truncate=True recompresses every block's ACA factors to its optimal rank at tol.
+    lu_form=True keeps the paper's storage form: per block the ACA pivots and the
+    LU factors of K(sigma, tau), with the other entries regenerated in every product."""
     torch = _torch()
     lib = load_library()
     points = _device_points(points)
     cfg = _make_config(kernel, kernel_param, leaf_size, tol, factor_dtype, max_rank, max_depth,
-                       box_lo, box_side, workspace_bytes, keep_pivots, autotune, truncate)
+                       box_lo, box_side, workspace_bytes, keep_pivots, autotune, truncate,
+                       lu_form)
     device = points.device.index if points.device.index is not None else torch.cuda.current_device()
     alloc = _TorchAllocator(device) if use_torch_allocator else None
     handle = ctypes.c_void_p()
@@ -516,15 +521,16 @@ class BatchOperator:
 def build_batch(points_list, kernel="laplace", kernel_param: float = 1.0, leaf_size: int = 64,
                 tol: float = 1e-8, factor_dtype="fp64", max_rank: int = 0, max_depth: int = 10,
                 box_lo=None, box_side: float = 0.0, workspace_bytes: int = 0,
-                use_torch_allocator: bool = True) -> BatchOperator:
-    """Builds one operator per point cloud for products in one persistent launch."""
+                use_torch_allocator: bool = True, lu_form: bool = False) -> BatchOperator:
+    """Builds one operator per point cloud for products in one persistent launch
+    (explicit factors only: the library refuses lu_form=True for batches)."""
     torch = _torch()
     lib = load_library()
     pts = [_device_points(p) for p in points_list]
     if not pts:
         raise ValueError("points_list is empty")
     cfg = _make_config(kernel, kernel_param, leaf_size, tol, factor_dtype, max_rank, max_depth,
-                       box_lo, box_side, workspace_bytes, False, False)
+                       box_lo, box_side, workspace_bytes, False, False, lu_form=lu_form)
     device = pts[0].device.index if pts[0].device.index is not None else torch.cuda.current_device()
     alloc = _TorchAllocator(device) if use_torch_allocator else None
     P = ctypes.c_void_p * len(pts)
