@@ -297,6 +297,47 @@ h3d_status h3d_profile_reset(h3d_plan *plan);
 
 int32_t h3d_version(void);
 
+/*
+ * Iterative solve with the operator (Sec. 5.2, eqs. (IE) and (ILDiscrete)):
+ * restarted GMRES(restart) for (diag I + scale K~) x = f, the form of the
+ * collocation system of a second-kind integral equation (diag = 1 plus the
+ * self-cell integral, scale = the cell volume, for the Laplace kernel times
+ * 4 pi to turn 1/(4 pi r) into 1/r).  f, x: device, n doubles in the caller's
+ * point order; x holds the initial guess on entry and the solution on exit.
+ * Stops when the true relative residual |f - A x| / |f| falls below rtol
+ * (checked at the end of every cycle; the Givens estimate ends a cycle early)
+ * or after max_iter products.  Each iteration is one h3d_matvec plus
+ * classical Gram-Schmidt with one reorthogonalisation; the Krylov basis (n x
+ * (restart + 1) doubles) comes from the plan's allocator for the duration of
+ * the call.  Dot products reduce in a fixed order: the same call gives
+ * bitwise the same x.  info (host, may be NULL) receives the iterations, the
+ * cycles, whether rtol was met and the final residuals.  Errors: H3D_EINVAL
+ * for NULL or overlapping f and x, rtol outside (0, 1), restart outside
+ * 1..256, max_iter < 1, non-finite diag or scale; those of h3d_matvec.
+ * Synchronises hip_stream.
+ */
+typedef struct {
+    int32_t iterations;   /* operator products inside the Arnoldi steps */
+    int32_t cycles;       /* restart cycles completed */
+    int32_t converged;    /* 1 when the true relative residual < rtol */
+    double rel_residual;  /* true |f - A x| / |f| at exit */
+    double est_residual;  /* last Givens estimate */
+} h3d_solve_info;
+h3d_status h3d_solve_gmres(h3d_plan *plan, double diag, double scale, const double *f, double *x,
+                           double rtol, int32_t restart, int32_t max_iter, void *hip_stream,
+                           h3d_solve_info *info);
+
+/*
+ * The exact dense product y_i = sum_{j != i} f(|p_i - p_j|) x_j over all n
+ * points (eq. (Laplace3D) and the other kernels of h3d_kernel): the
+ * right-hand side "exact up to roundoff" of the solve experiment, and a
+ * reference for the compressed product.  points: device n x 3 FP64
+ * row-major; x, y: device n doubles, same order as the points, not
+ * overlapping.  O(n^2) kernel evaluations, one thread per row.  Errors:
+ * H3D_EINVAL for n < 1, NULL pointers, overlap or an unknown kernel.
+ */
+h3d_status h3d_dense_matvec(const double *points, int64_t n, int32_t kernel,
+                            double kernel_param, const double *x, double *y, void *hip_stream);
 
 /*
  * For callers that cannot allocate device memory during a product (code under

@@ -685,6 +685,60 @@ h3d_status h3d_destroy(h3d_plan *plan) {
     });
 }
 
+h3d_status h3d_solve_gmres(h3d_plan *plan, double diag, double scale, const double *f, double *x,
+                           double rtol, int32_t restart, int32_t max_iter, void *hip_stream,
+                           h3d_solve_info *info) {
+    if (const h3d_status ps = plan_status(plan); ps != H3D_OK)
+        return ps;
+    if (plan->batch)
+        return batch_plan_error();
+    h3d::Plan &P = plan->P;
+    if (!f || !x)
+        return invalid("f and x must be device pointers");
+    const uintptr_t fa = uintptr_t(f), xa = uintptr_t(x), nb = size_t(P.n) * 8;
+    if (fa < xa + nb && xa < fa + nb)
+        return invalid("f and x overlap");
+    if (!(rtol > 0.0 && rtol < 1.0))
+        return invalid("rtol must lie in (0, 1)");
+    if (restart < 1 || restart > h3d::kMaxRestart)
+        return invalid("restart must lie in [1, 256]");
+    if (max_iter < 1)
+        return invalid("max_iter must be >= 1");
+    if (!std::isfinite(diag) || !std::isfinite(scale))
+        return invalid("diag and scale must be finite");
+    return guarded([&] {
+        DeviceScope ds(P.device);
+        const h3d::SolveResult r = h3d::solve_gmres(P, diag, scale, f, x, rtol, restart, max_iter,
+                                                    static_cast<hipStream_t>(hip_stream));
+        if (info) {
+            info->iterations = r.iterations;
+            info->cycles = r.cycles;
+            info->converged = r.converged;
+            info->rel_residual = r.rel_residual;
+            info->est_residual = r.est_residual;
+        }
+    });
+}
+
+h3d_status h3d_dense_matvec(const double *points, int64_t n, int32_t kernel,
+                            double kernel_param, const double *x, double *y, void *hip_stream) {
+    if (n < 1)
+        return invalid("n must be >= 1");
+    if (!points || !x || !y)
+        return invalid("points, x and y must be device pointers");
+    if (kernel < H3D_LAPLACE || kernel > H3D_COS_R)
+        return invalid("unknown kernel");
+    if (!std::isfinite(kernel_param))
+        return invalid("kernel_param must be finite");
+    const uintptr_t xa = uintptr_t(x), ya = uintptr_t(y), nb = size_t(n) * 8;
+    if (xa < ya + nb && ya < xa + nb)
+        return invalid("x and y overlap");
+    return guarded([&] {
+        h3d::dense_matvec(points, n, kernel, kernel_param, x, y,
+                          static_cast<hipStream_t>(hip_stream));
+    });
+}
+
 h3d_status h3d_profile_enable(h3d_plan *plan, int32_t enable) {
     if (const h3d_status ps = plan_status(plan); ps != H3D_OK)
         return ps;

@@ -445,6 +445,18 @@ void matvec_lu(Plan &P, const void *x, void *y, int64_t nrhs, int64_t ldx, int64
                int io_dtype, bool adjoint, double *xp, double *yn, double *z, hipStream_t s);
 void export_lu(const Plan &P, double *host_out);
 
+// GMRES on (diag I + scale K~) x = f, and the exact dense product (solve.hip)
+constexpr int kMaxRestart = 256;
+struct SolveResult {
+    int iterations = 0, cycles = 0, converged = 0;
+    double rel_residual = 0.0;  // true relative residual at exit
+    double est_residual = 0.0;  // last Givens estimate
+};
+SolveResult solve_gmres(Plan &P, double diag, double scale, const double *f, double *x,
+                        double rtol, int restart, int max_iter, hipStream_t s);
+void dense_matvec(const double *pts, int64_t n, int kind, double kp, const double *x, double *y,
+                  hipStream_t s);
+
 // device-wide exclusive scan; out may alias in; returns the total
 int64_t scan_exclusive_i64(Plan &P, const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
 void scan_exclusive_i32_nototal(Plan &P, const int32_t *in, int32_t *out, int64_t n, hipStream_t s);

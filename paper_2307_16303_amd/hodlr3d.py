@@ -33,7 +33,8 @@ EXPORTED_SYMBOLS = (
     "h3d_export", "h3d_destroy", "h3d_last_error", "h3d_profile_enable", "h3d_profile_read",
     "h3d_profile_reset", "h3d_version", "h3d_autotune", "h3d_graph_create",
     "h3d_graph_launch", "h3d_graph_destroy", "h3d_build_batch", "h3d_matvec_batch",
-    "h3d_batch_plan", "h3d_batch_check", "h3d_matvec_noalloc",
+    "h3d_batch_plan", "h3d_batch_check", "h3d_matvec_noalloc", "h3d_solve_gmres",
+    "h3d_dense_matvec",
 )
 
 
@@ -91,6 +92,12 @@ class Stats(ctypes.Structure):
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("cycles", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+                ("est_residual", ctypes.c_double)]
 
 
 class Allocator(ctypes.Structure):
@@ -166,6 +173,11 @@ def load_library():
     lib.h3d_batch_plan.restype = S
     lib.h3d_batch_check.argtypes = [P, P]
     lib.h3d_batch_check.restype = S
+    D = ctypes.c_double
+    lib.h3d_solve_gmres.argtypes = [P, D, D, P, P, D, I32, I32, P, ctypes.POINTER(SolveInfo)]
+    lib.h3d_solve_gmres.restype = S
+    lib.h3d_dense_matvec.argtypes = [P, I64, I32, D, P, P, P]
+    lib.h3d_dense_matvec.restype = S
     lib.h3d_version.argtypes = []
     lib.h3d_version.restype = I32
     _lib = lib
@@ -286,6 +298,27 @@ class Operator:
     def __matmul__(self, x):
         return self.matvec(x)
 
+    def solve(self, f, diag: float, scale: float, x0=None, rtol: float = 1e-10,
+              restart: int = 50, max_iter: int = 1000):
+        """GMRES on (diag I + scale K~) x = f (Sec. 5.2).  f: (n,) float64 on the
+        operator's GPU.  Returns (x, info) with info a dict of iterations, cycles,
+        converged, rel_residual (true, at exit) and est_residual."""
+        torch = _torch()
+        if not isinstance(f, torch.Tensor) or not f.is_cuda or f.dtype != torch.float64:
+            raise TypeError("f must be a float64 CUDA tensor")
+        if f.dim() != 1:
+            raise ValueError("f must be a vector")
+        _check_rhs(f, self.n, self.device)
+        fc = f.contiguous()
+        x = torch.zeros_like(fc) if x0 is None else x0.to(torch.float64).contiguous().clone()
+        info = SolveInfo()
+        stream = torch.cuda.current_stream(f.device).cuda_stream
+        _check(load_library().h3d_solve_gmres(
+            self._h, float(diag), float(scale), ctypes.c_void_p(fc.data_ptr()),
+            ctypes.c_void_p(x.data_ptr()), float(rtol), int(restart), int(max_iter),
+            ctypes.c_void_p(stream), ctypes.byref(info)))
+        return x, {k: getattr(info, k) for k, _ in SolveInfo._fields_}
+
     # -- introspection ----------------------------------------------------
     def graph(self, x, adjoint: bool = False) -> "Graph":
         """Captures the product with this x (kept alive) into a replayable HIP graph."""
@@ -381,6 +414,25 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def dense_matvec(points, x, kernel="laplace", kernel_param: float = 1.0):
+    """The exact dense product y_i = sum_{j != i} f(|p_i - p_j|) x_j on the GPU
+    (points (n, 3) and x (n,) float64 CUDA tensors, same order)."""
+    torch = _torch()
+    points = _device_points(points)
+    n = points.shape[0]
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.float64 \
+            or x.shape != (n,):
+        raise TypeError(f"x must be a float64 CUDA tensor of shape ({n},)")
+    xc = x.contiguous()
+    y = torch.empty_like(xc)
+    kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    stream = torch.cuda.current_stream(points.device).cuda_stream
+    _check(load_library().h3d_dense_matvec(ctypes.c_void_p(points.data_ptr()), n, kid,
+                                           float(kernel_param), ctypes.c_void_p(xc.data_ptr()),
+                                           ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(stream)))
+    return y
 
 
 def _make_config(kernel, kernel_param, leaf_size, tol, factor_dtype, max_rank, max_depth, box_lo,
