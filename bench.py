@@ -27,9 +27,12 @@ the 16^3 grid and on 65,536 uniform points (the oracle cannot hold the
 1,048,576-point operator in reasonable time).
 
 The variants object measures the other storage forms (FP32 and BF16 factors,
-one and 64 right-hand sides) on the headline points, the plain FP64 form on
-262,144 points, and the multi-problem form (32 clouds, N_i in [8192, 131072],
-FP32 factors, tol 1e-7) in one persistent launch.
+one and 64 right-hand sides; the paper's own pivot + LU form, whose product
+regenerates the kernel entries and is bound by the vector ALUs) on the
+headline points, the plain FP64 and LU forms on 262,144 points, the
+multi-problem form (32 clouds, N_i in [8192, 131072], FP32 factors, tol 1e-7)
+in one persistent launch, and the integral-equation solve of Sec. 5.2 on a
+64^3 grid (GMRES to a relative residual of 1e-10).
 
 roofline.traffic is the dominant kernel's HBM traffic per launch from the
 hardware counters FETCH_SIZE and WRITE_SIZE (rocprofv3 --pmc, one counter per
@@ -58,6 +61,8 @@ UNIT = "points·RHS/s"
 HBM_PEAK_GBS = 8000.0
 # dense matrix-core peaks of MI355X (TFLOP/s); BF16 factors are widened to FP32 tiles
 MFMA_PEAK_TFS = {"fp64": 78.6, "fp32": 157.3, "bf16": 157.3}
+# FP64 vector ALU peak (TFLOP/s): the pivot + LU form's kernel evaluations
+VALU_FP64_PEAK_TFS = 78.6
 DTYPE_NAMES = {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}
 GATE = 1e-6
 
@@ -136,13 +141,14 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def build_op(pts, w, dt, truncate=False):
+def build_op(pts, w, dt, truncate=False, lu_form=False, tol=None):
     import torch
     from paper_2307_16303_amd import hodlr3d, inputs
     t0 = time.perf_counter()
     op = hodlr3d.build(torch.as_tensor(pts, device="cuda:0"), kernel=w["kernel"],
-                       leaf_size=w["leaf_size"], tol=w["tol"], factor_dtype=dt,
-                       box_lo=inputs.CUBE_LO, box_side=inputs.CUBE_SIDE, truncate=truncate)
+                       leaf_size=w["leaf_size"], tol=w["tol"] if tol is None else tol,
+                       factor_dtype=dt, box_lo=inputs.CUBE_LO, box_side=inputs.CUBE_SIDE,
+                       truncate=truncate, lu_form=lu_form)
     torch.cuda.synchronize()
     return op, time.perf_counter() - t0
 
@@ -180,6 +186,11 @@ def roofline_of(prof, workload, dt, nrhs):
     traffic = traffic_bytes(dom["name"], workload, dt, nrhs)
     common = {"traffic": None if traffic is None else round(traffic, 0), "kernel": dom["name"],
               "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": dom["bytes_per_launch"]}
+    if dom["name"].startswith("k_lu"):
+        tfs = dom["flops_per_launch"] / (avg_ms * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": round(tfs, 2), "peak": VALU_FP64_PEAK_TFS,
+                "unit": "TFLOP/s", "frac": round(tfs / VALU_FP64_PEAK_TFS, 4), **common,
+                "flops_per_launch": dom["flops_per_launch"], "hbm_gbs": round(gbs, 1)}
     if "mfma" in dom["name"]:
         tfs = dom["flops_per_launch"] / (avg_ms * 1e-3) / 1e12
         peak = MFMA_PEAK_TFS[dt]
@@ -218,6 +229,43 @@ def cpu_threads() -> int:
     if env.isdigit() and int(env) > 0:
         n = min(n, int(env))
     return max(1, n)
+
+
+def integral_equation(k: int, tol: float) -> dict:
+    """sigma + int_B sigma(y) / |x - y| dy = f on a k^3 collocation grid of
+    [-1,1]^3 (midpoint rule off the diagonal, the exact self-cell integral on
+    it): a known sigma, f from the exact dense product on the GPU, GMRES(50)
+    with the HODLR3D product to a relative residual of 1e-10."""
+    import torch
+    from paper_2307_16303_amd import hodlr3d, inputs
+    n = k ** 3
+    h = 2.0 / k
+    s3 = np.sqrt(3.0)
+    diag = 1.0 + h * h * (6.0 * np.log((1.0 + s3) / np.sqrt(2.0)) - np.pi / 2.0)
+    scale = 4.0 * np.pi * h ** 3  # the library's Laplace kernel is 1/(4 pi r)
+    pts = torch.as_tensor(inputs.grid_points(k), device="cuda:0")
+    sigma = torch.as_tensor(inputs.normal_rhs(n, seed=98), device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f = diag * sigma + scale * hodlr3d.dense_matvec(pts, sigma)
+    torch.cuda.synchronize()
+    dense_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    op = hodlr3d.build(pts, leaf_size=64, tol=tol, box_lo=inputs.CUBE_LO,
+                       box_side=inputs.CUBE_SIDE)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    x, info = op.solve(f, diag, scale, rtol=1e-10, restart=50, max_iter=500)
+    torch.cuda.synchronize()
+    solve_s = time.perf_counter() - t0
+    err = float(torch.linalg.norm(x - sigma) / torch.linalg.norm(sigma))
+    op.close()
+    log(f"ie_grid{k}: {info['iterations']} iterations, solve {solve_s:.3f} s, forward error "
+        f"{err:.2e}")
+    return {"n": n, "aca_tol": tol, "factor_dtype": "fp64", "rtol": 1e-10,
+            "build_s": round(build_s, 2), "solve_s": round(solve_s, 4),
+            "exact_rhs_s": round(dense_s, 4), **info, "forward_error": err}
 
 
 def rel_err(a, b) -> float:
@@ -340,6 +388,19 @@ def main():
         op.close()
         del op, yv
         torch.cuda.empty_cache()
+        # ---- the paper's storage form: pivots + LU of K(sigma, tau) -------
+        op, bs = build_op(pts, w, "fp64", lu_form=True)
+        st_lu = op.stats()
+        yv = run_variant("lu_fp64_1rhs", op, "fp64", 1, max(5, args.steps // 2),
+                         max(2, args.warmup // 2),
+                         extra={"build_s": round(bs, 2), "form": "pivots + LU (Sec. 4.1)",
+                                "stored_bytes": st_lu["factor_bytes"],
+                                "explicit_fp64_bytes": 8 * st_lu["factor_entries"]},
+                         profile=True, xnp=x1_np)
+        sampled["lu_fp64_1rhs"] = ("1", yv.reshape(n, -1)[rows_t].cpu().numpy())
+        op.close()
+        del op, yv
+        torch.cuda.empty_cache()
         # ---- 262,144 points, plain FP64, one RHS (and FP32 64 RHS) -------
         w2 = inputs.WORKLOADS["uniform262k"]
         pts2 = inputs.workload_points("uniform262k")
@@ -356,7 +417,20 @@ def main():
                     max(1, args.warmup // 2), extra={"build_s": round(bs, 2)}, profile=True,
                     wl="uniform262k", nn=w2["n"], xnp=inputs.workload_rhs("uniform262k", 64))
         op.close()
+        del op
+        torch.cuda.empty_cache()
+        op, bs = build_op(pts2, w2, "fp64", lu_form=True)
+        st_lu = op.stats()
+        run_variant("uniform262k_lu_fp64_1rhs", op, "fp64", 1, max(5, args.steps),
+                    max(2, args.warmup), profile=True, wl="uniform262k", nn=w2["n"], xnp=x2,
+                    extra={"build_s": round(bs, 2), "form": "pivots + LU (Sec. 4.1)",
+                           "stored_bytes": st_lu["factor_bytes"],
+                           "explicit_fp64_bytes": 8 * st_lu["factor_entries"]})
+        op.close()
         del op, pts2, x2
+        torch.cuda.empty_cache()
+        # ---- the integral equation of Sec. 5.2 on a 64^3 grid -------------
+        variants["ie_grid64"] = integral_equation(64, 1e-7)
         torch.cuda.empty_cache()
 
     # ---- many uneven problems in one persistent launch --------------------
