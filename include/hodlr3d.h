@@ -192,6 +192,18 @@ typedef struct h3d_graph h3d_graph;
 h3d_status h3d_graph_create(h3d_plan *plan, const void *x, void *y, int64_t nrhs, int64_t ldx,
                             int64_t ldy, int32_t io_dtype, int32_t adjoint, void *hip_stream,
                             h3d_graph **out);
+/*
+ * The same for a batch plan: the product of h3d_matvec_batch with these x
+ * and y (host arrays of nprob device pointers, copied into the graph; the
+ * buffers stay owned by the caller) captured once and replayed by
+ * h3d_graph_launch.  The graph pins the scratch of every problem and the
+ * batch's device tables: while it exists, h3d_matvec_batch with another nrhs,
+ * products of a member with more right-hand sides and h3d_destroy of the
+ * batch return H3D_EINVAL.  Replays give bitwise the eager result.
+ */
+h3d_status h3d_graph_create_batch(h3d_plan *batch, const void *const *x, void *const *y,
+                                  int64_t nrhs, int32_t io_dtype, void *hip_stream,
+                                  h3d_graph **out);
 h3d_status h3d_graph_launch(h3d_graph *graph, void *hip_stream);
 h3d_status h3d_graph_destroy(h3d_graph *graph);
 
@@ -223,9 +235,12 @@ h3d_status h3d_build_batch(int32_t nprob, const double *const *points, const int
  * x[i] and y[i] are n[i] x nrhs column-major with leading dimension n[i], in
  * problem i's original point order, of io_dtype (H3D_F64 or H3D_F32); y[i]
  * is overwritten and must not overlap x[i].  Asynchronous on hip_stream.
- * For nrhs < 8 each y[i] is bitwise the output of h3d_matvec on
- * h3d_batch_plan(batch, i) with the same x[i].  Products of one batch plan
- * must not overlap in time.
+ * Each y[i] is bitwise the output of h3d_matvec on h3d_batch_plan(batch, i)
+ * with the same x[i].  With nrhs >= 8 every problem's product is a set of
+ * dense GEMMs on the matrix cores that fills the GPU by itself, so the
+ * problems run back to back on the stream (the matrix-core path of
+ * h3d_matvec) instead of in the persistent launch.  Products of one batch
+ * plan must not overlap in time.
  */
 h3d_status h3d_matvec_batch(h3d_plan *batch, const void *const *x, void *const *y, int64_t nrhs,
                             int32_t io_dtype, void *hip_stream);

@@ -354,6 +354,21 @@ void batch_run(h3d_plan &bp, const void *const *x, void *const *y, int64_t nrhs,
     BatchState &B = *bp.batch;
     Plan &P = bp.P;
     const int nprob = int(B.subs.size());
+    if (nrhs >= kBatchedMinRhs) {
+        // Eight or more right-hand sides: every problem's product is a set of
+        // dense GEMMs on the matrix cores, large enough to fill the GPU on its
+        // own, so the problems run back to back on the stream.
+        hipEvent_t ev = P.prof.begin(s);
+        double bytes = 0.0, flops = 0.0;
+        for (int p = 0; p < nprob; ++p) {
+            Plan &Q = B.subs[size_t(p)]->P;
+            matvec_batched(Q, x[p], y[p], nrhs, Q.n, Q.n, io_dtype, false, s);
+            bytes += double(Q.stats.factor_bytes);
+            flops += 2.0 * double(Q.stats.factor_entries) * double(nrhs);
+        }
+        P.prof.end(s, ev, "k_batch_mfma", bytes, flops);
+        return;
+    }
     bool fresh = B.desc_nrhs != nrhs;
     for (int p = 0; p < nprob; ++p) {
         Plan &Q = B.subs[size_t(p)]->P;
@@ -364,6 +379,12 @@ void batch_run(h3d_plan &bp, const void *const *x, void *const *y, int64_t nrhs,
             fresh = true;
     }
     if (fresh) {
+        // the descriptors sit in device memory that captured graphs of the
+        // batch read at every replay
+        if (P.live_graphs > 0)
+            fail(H3D_EINVAL, "a batch product with other right-hand sides would rewrite the "
+                             "problem descriptors that captured graphs of the batch use: "
+                             "destroy them first");
         H3D_HIP(hipStreamSynchronize(s));
         write_descriptors(B, nrhs);
     }

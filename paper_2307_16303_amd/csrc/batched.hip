@@ -1182,6 +1182,15 @@ void ensure_batched_tables(Plan &P, hipStream_t s) {
             H3D_LAUNCH_CHECK();
             P.bt_s1[l] = make_items(P, nb, b0, cnt, &P.bt_ns1[l], s);
             P.mem.release(cnt);
+            if (P.factor_dtype != H3D_F64) {
+                // the ring kernel's items: (block, 16 MT columns)
+                int64_t *cnt4 = P.mem.alloc_n<int64_t>(nb + 1);
+                k_cnt_coltiles<<<grid_for(nb, 256), 256, 0, s>>>(b0, nb, P.blk_rank,
+                                                                16 * s1_ring_tiles(P, l), cnt4);
+                H3D_LAUNCH_CHECK();
+                P.bt_s1r[l] = make_items(P, nb, b0, cnt4, &P.bt_ns1r[l], s);
+                P.mem.release(cnt4);
+            }
         }
         // stage 2: (box, row tile) for the boxes of level l
         const int64_t nbox = pow8(l);
@@ -1191,6 +1200,15 @@ void ensure_batched_tables(Plan &P, hipStream_t s) {
         H3D_LAUNCH_CHECK();
         P.bt_s2[l] = make_items(P, nbox, 0, cnt, &P.bt_ns2[l], s);
         P.mem.release(cnt);
+        if (P.factor_dtype != H3D_F64) {
+            // the ring kernel's items: (box, 64-row tile)
+            int64_t *cnt4 = P.mem.alloc_n<int64_t>(nbox + 1);
+            k_cnt_rowtiles<<<grid_for(nbox, 256), 256, 0, s>>>(nbox, 3 * (L - l), P.leaf_off, 64,
+                                                              cnt4);
+            H3D_LAUNCH_CHECK();
+            P.bt_s2r[l] = make_items(P, nbox, 0, cnt4, &P.bt_ns2r[l], s);
+            P.mem.release(cnt4);
+        }
     }
     P.bt_ready = true;
 }
@@ -1264,8 +1282,14 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
     // of about 32 points (1,048,576 points) the fused chain was slower (62
     // against 27 ms, FP32)
     const int lfuse = (adjoint || P.mean_box[P.L] > kLeafRows) ? 0 : P.L;
+    // larger leaves (FP32/BF16 factors): both stages per leaf with z kept in
+    // registers (k_leaf_fused)
+    const int lfused = (!adjoint && DT != H3D_F64 && lfuse == 0 && P.L >= 1 &&
+                        leaf_fused_tables(P, s))
+                           ? P.L
+                           : 0;
     for (int l = 1; l <= P.L; ++l) {
-        if (P.bt_ns1[l] == 0 || l == lfuse)
+        if (P.bt_ns1[l] == 0 || l == lfuse || l == lfused)
             continue;
         hipEvent_t ev = P.prof.begin(s);
         // split levels: partial tiles of every row part, then their sum
@@ -1276,7 +1300,11 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
         adjoint ? P.blk_toff : P.blk_soff, adjoint ? P.blk_uptr : P.blk_vptr, P.blk_rank,     \
         P.blk_col0, P.blk_scale, Xs, NP, Z, int(adjoint && l < P.chunk_level), P.leaf_off,    \
         P.leaf_of, 3 * (P.L - P.chunk_level), P.bt_split[l], Zp)
-        if (P.bt_mt1[l] == 4)
+        if (DT != H3D_F64 && P.bt_split[l] == 0)
+            launch_s1_ring(P, l, adjoint, reinterpret_cast<const int2 *>(P.bt_s1r[l]),
+                           P.bt_ns1r[l], reinterpret_cast<const float *>(Xs), NP,
+                           reinterpret_cast<float *>(Z), s);
+        else if (P.bt_mt1[l] == 4)
             H3D_S1M(4);
         else if (P.bt_mt1[l] == 2)
             H3D_S1M(2);
@@ -1306,9 +1334,13 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
                    2.0 * ent * NP);
     }
     for (int l = 1; l <= P.L; ++l) {
-        if (P.bt_ns2[l] == 0 || P.lvl_blk[l + 1] <= P.lvl_blk[l] || l == lfuse)
+        if (P.bt_ns2[l] == 0 || P.lvl_blk[l + 1] <= P.lvl_blk[l] || l == lfuse || l == lfused)
             continue;
         hipEvent_t ev = P.prof.begin(s);
+        if constexpr (DT != H3D_F64) {
+            launch_s2_ring(P, l, adjoint, reinterpret_cast<const int2 *>(P.bt_s2r[l]),
+                           P.bt_ns2r[l], reinterpret_cast<const float *>(Z), NP, Y, s);
+        } else {
 #define H3D_S2M(MT)                                                                         \
     k_s2_mfma_w<DT, MT><<<int(P.bt_ns2[l]), 64, 0, s>>>(                                    \
         reinterpret_cast<const int2 *>(P.bt_s2[l]), P.bt_ns2[l], P.box_base[l], P.leaf_off,   \
@@ -1324,6 +1356,7 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
                 adjoint ? P.blk_vptr : P.blk_uptr, P.blk_rank, P.blk_col0, Z, NP, Y,
                 int(!adjoint && l < P.chunk_level), P.leaf_of, 3 * (P.L - P.chunk_level));
 #undef H3D_S2M
+        }
         H3D_LAUNCH_CHECK();
         const double ent = double(adjoint ? P.lvl_entries_v[l] : P.lvl_entries_u[l]);
         char name2[48];
@@ -1344,6 +1377,17 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
         char name[48];
         snprintf(name, sizeof(name), P.prof.levels ? "k_leaf_mfma_L%d" : "k_leaf_mfma", l);
         P.prof.end(s, ev, name, ent * es + double(n) * 16.0 * NP, 4.0 * ent * NP / 2.0);
+    }
+    if constexpr (DT != H3D_F64) {
+        if (lfused >= 1 && P.lvl_blk[lfused + 1] > P.lvl_blk[lfused]) {
+            const int l = lfused;
+            hipEvent_t ev = P.prof.begin(s);
+            launch_leaf_fused(P, reinterpret_cast<const float *>(Xs), NP, Y, s);
+            const double ent = double(P.lvl_entries_u[l] + P.lvl_entries_v[l]);
+            char name[48];
+            snprintf(name, sizeof(name), P.prof.levels ? "k_leaf_fused_L%d" : "k_leaf_fused", l);
+            P.prof.end(s, ev, name, ent * es + double(n) * 16.0 * NP, 2.0 * ent * NP);
+        }
     }
     {
         hipEvent_t ev = P.prof.begin(s);

@@ -16,6 +16,7 @@ struct h3d_graph {
     h3d_plan *plan = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    bool batch = false;  // a batch product: the members' scratch is pinned too
 };
 
 namespace h3d {
@@ -470,6 +471,90 @@ h3d_status h3d_graph_create(h3d_plan *plan, const void *x, void *y, int64_t nrhs
     return H3D_OK;
 }
 
+h3d_status h3d_graph_create_batch(h3d_plan *batch, const void *const *x, void *const *y,
+                                  int64_t nrhs, int32_t io_dtype, void *hip_stream,
+                                  h3d_graph **out) {
+    if (!out)
+        return invalid("out must not be NULL");
+    *out = nullptr;
+    if (const h3d_status ps = plan_status(batch); ps != H3D_OK)
+        return ps;
+    if (!batch->batch)
+        return invalid("not a batch plan (built by h3d_build_batch)");
+    if (!x || !y)
+        return invalid("x and y must be host arrays of device pointers");
+    const auto &subs = batch->batch->subs;
+    for (size_t i = 0; i < subs.size(); ++i) {
+        const int64_t ni = subs[i]->P.n;
+        const h3d_status st = matvec_check(subs[i], x[i], y[i], nrhs, ni, ni, io_dtype);
+        if (st != H3D_OK) {
+            g_last_error = "problem " + std::to_string(i) + ": " + g_last_error;
+            return st;
+        }
+    }
+    // the graph keeps the pointers: copies of the caller's arrays
+    std::vector<const void *> xs(x, x + subs.size());
+    std::vector<void *> ys(y, y + subs.size());
+    h3d_graph *g = nullptr;
+    hipStream_t cs = nullptr;
+    h3d_status st = guarded([&] {
+        h3d::Plan &P = batch->P;
+        DeviceScope ds(P.device);
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        // eager run: scratch, descriptors and tables outside the capture
+        h3d::batch_run(*batch, xs.data(), ys.data(), nrhs, io_dtype, s);
+        H3D_HIP(hipStreamSynchronize(s));
+        g = new h3d_graph();
+        g->plan = batch;
+        g->batch = true;
+        std::vector<bool> prof(subs.size() + 1);
+        prof[0] = P.prof.on;
+        P.prof.on = false;
+        for (size_t i = 0; i < subs.size(); ++i) {
+            prof[i + 1] = subs[i]->P.prof.on;
+            subs[i]->P.prof.on = false;
+        }
+        auto restore = [&] {
+            P.prof.on = prof[0];
+            for (size_t i = 0; i < subs.size(); ++i)
+                subs[i]->P.prof.on = prof[i + 1];
+        };
+        H3D_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        H3D_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        try {
+            h3d::batch_run(*batch, xs.data(), ys.data(), nrhs, io_dtype, cs);
+        } catch (...) {
+            hipGraph_t dead = nullptr;
+            (void)hipStreamEndCapture(cs, &dead);
+            if (dead)
+                (void)hipGraphDestroy(dead);
+            restore();
+            throw;
+        }
+        H3D_HIP(hipStreamEndCapture(cs, &g->graph));
+        restore();
+        H3D_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+        P.live_graphs += 1;
+        for (h3d_plan *q : subs)
+            q->P.live_graphs += 1;
+    });
+    if (cs)
+        (void)hipStreamDestroy(cs);
+    if (st != H3D_OK) {
+        if (g) {
+            if (g->exec)
+                (void)hipGraphExecDestroy(g->exec);
+            if (g->graph)
+                (void)hipGraphDestroy(g->graph);
+            delete g;
+        }
+        return st;
+    }
+    reg_add(g, kGraph);
+    *out = g;
+    return H3D_OK;
+}
+
 h3d_status h3d_graph_launch(h3d_graph *graph, void *hip_stream) {
     if (!graph || reg_kind(graph) != kGraph || !graph->exec)
         return invalid("not a live graph (NULL or destroyed)");
@@ -488,6 +573,9 @@ h3d_status h3d_graph_destroy(h3d_graph *graph) {
     return guarded([&] {
         // the plan outlives its graphs: h3d_destroy refuses a plan with live graphs
         graph->plan->P.live_graphs -= 1;
+        if (graph->batch)
+            for (h3d_plan *q : graph->plan->batch->subs)
+                q->P.live_graphs -= 1;
         DeviceScope ds(graph->plan->P.device);
         (void)hipDeviceSynchronize();
         if (graph->exec)

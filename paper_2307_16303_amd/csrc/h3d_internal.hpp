@@ -308,6 +308,10 @@ struct Plan {
     int64_t bt_ns1[kMaxLevels + 1] = {};
     int32_t *bt_s2[kMaxLevels + 1] = {};
     int64_t bt_ns2[kMaxLevels + 1] = {};
+    int32_t *bt_s1r[kMaxLevels + 1] = {};  // FP32/BF16 stage 1: (block, column tile group)
+    int64_t bt_ns1r[kMaxLevels + 1] = {};
+    int32_t *bt_s2r[kMaxLevels + 1] = {};  // FP32/BF16 stage 2: (box, 64-row tile)
+    int64_t bt_ns2r[kMaxLevels + 1] = {};
     int bt_mt1[kMaxLevels + 1] = {};  // 16-column tiles per stage-1 wave
     int bt_mt2[kMaxLevels + 1] = {};  // 16-row tiles per stage-2 wave
     int bt_split[kMaxLevels + 1] = {};  // stage-1 rows per part (0: columns not split)
@@ -315,6 +319,11 @@ struct Plan {
     int64_t bt_ngrp[kMaxLevels + 1] = {};
     void *bzp = nullptr;  // partial stage-1 tiles of the split levels
     size_t bzp_bytes = 0;
+    // fused finest level for leaves of 17..64 rows (leaf_fused.hip): leaves
+    // grouped by 16-row tile count
+    bool lf_ready = false, lf_ok = false;
+    int32_t *lf_items[4] = {};
+    int64_t lf_n[4] = {};
     void *bx = nullptr, *by = nullptr, *bz = nullptr;
     size_t bx_bytes = 0, by_bytes = 0, bz_bytes = 0;
 
@@ -434,6 +443,20 @@ void matvec_batched(Plan &P, const void *x, void *y, int64_t nrhs, int64_t ldx, 
 
 // near field of a product (FP64 entries, or FP32 entries for FP32/BF16 factors)
 void launch_near_field(Plan &P, int nrhs, const double *xp, double *yn, hipStream_t s);
+// many right-hand sides, FP32/BF16 factors: both stages of the finest level
+// in one pass per leaf for leaves of at most 64 rows (leaf_fused.hip)
+bool leaf_fused_tables(Plan &P, hipStream_t s);
+// stage 1 of one level (not split into row parts), FP32/BF16 factors, one
+// wave per (block, 16 MT factor columns) with a ring of fragment loads
+// (stage1_ring.hip); MT from the level's mean rank
+int s1_ring_tiles(const Plan &P, int l);
+void launch_s1_ring(Plan &P, int l, bool adjoint, const int2 *items, int64_t nitems,
+                    const float *Xs, int NP, float *Z, hipStream_t s);
+// stage 2 of one level, FP32/BF16 factors, one wave per (box, 64-row tile)
+// with a ring of fragment loads across the box's blocks (stage2_ring.hip)
+void launch_s2_ring(Plan &P, int l, bool adjoint, const int2 *items, int64_t nitems,
+                    const float *Z, int NP, double *Y, hipStream_t s);
+void launch_leaf_fused(Plan &P, const float *Xs, int NP, double *Y, hipStream_t s);
 // the pivot + LU form (lu_form.hip)
 constexpr int kLuSlots = 4;                // 64-row register slots of the in-wave solves
 constexpr int kLuMaxRank = 64 * kLuSlots;  // largest rank the form takes

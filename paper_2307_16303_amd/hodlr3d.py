@@ -34,7 +34,7 @@ EXPORTED_SYMBOLS = (
     "h3d_profile_reset", "h3d_version", "h3d_autotune", "h3d_graph_create",
     "h3d_graph_launch", "h3d_graph_destroy", "h3d_build_batch", "h3d_matvec_batch",
     "h3d_batch_plan", "h3d_batch_check", "h3d_matvec_noalloc", "h3d_solve_gmres",
-    "h3d_dense_matvec",
+    "h3d_dense_matvec", "h3d_graph_create_batch",
 )
 
 
@@ -157,6 +157,9 @@ def load_library():
     lib.h3d_profile_read.restype = S
     lib.h3d_graph_create.argtypes = [P, P, P, I64, I64, I64, I32, I32, P, ctypes.POINTER(P)]
     lib.h3d_graph_create.restype = S
+    lib.h3d_graph_create_batch.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), I64, I32, P,
+                                           ctypes.POINTER(P)]
+    lib.h3d_graph_create_batch.restype = S
     lib.h3d_graph_launch.argtypes = [P, P]
     lib.h3d_graph_launch.restype = S
     lib.h3d_graph_destroy.argtypes = [P]
@@ -554,6 +557,11 @@ class BatchOperator:
         _check(load_library().h3d_matvec_batch(self._h, xp, yp, nrhs, io, ctypes.c_void_p(stream)))
         return [y.reshape(-1) if vec else y.t() for y, vec in zip(ys, shapes)]
 
+    def graph(self, xs) -> "BatchGraph":
+        """Captures the batch product with these inputs (copied into buffers the
+        graph owns) into a replayable HIP graph."""
+        return BatchGraph(self, xs)
+
     def check(self) -> None:
         """Raises if a dependency wait of the last product gave up (synchronises)."""
         torch = _torch()
@@ -568,6 +576,56 @@ class BatchOperator:
     profile = Operator.profile
     profile_reset = Operator.profile_reset
     profile_read = Operator.profile_read
+
+
+class BatchGraph:
+    """The product of a batch for fixed input buffers, replayed from a captured HIP
+    graph.  Write new values into ``xs[i]`` (column-major copies, see set_x) and
+    call ``launch()``; the results are the returned views of the graph's outputs."""
+
+    def __init__(self, bop: "BatchOperator", xs):
+        torch = _torch()
+        if len(xs) != len(bop.ns):
+            raise ValueError(f"expected {len(bop.ns)} inputs, got {len(xs)}")
+        self.bop = bop
+        self.vec = xs[0].dim() == 1
+        self.nrhs = 1 if self.vec else xs[0].shape[1]
+        self.xs, self._ys = [], []
+        for x, n in zip(xs, bop.ns):
+            _check_rhs(x, n, bop.device)
+            xc = torch.empty((self.nrhs, n), dtype=x.dtype, device=x.device)
+            xc.copy_(x.reshape(n, -1).t())
+            self.xs.append(xc)
+            self._ys.append(torch.empty_like(xc))
+        io = 0 if xs[0].dtype == torch.float64 else 1
+        P = ctypes.c_void_p * len(bop.ns)
+        xp = P(*[c.data_ptr() for c in self.xs])
+        yp = P(*[y.data_ptr() for y in self._ys])
+        self._h = ctypes.c_void_p()
+        stream = torch.cuda.current_stream(self.xs[0].device).cuda_stream
+        _check(load_library().h3d_graph_create_batch(bop._h, xp, yp, self.nrhs, io,
+                                                     ctypes.c_void_p(stream),
+                                                     ctypes.byref(self._h)))
+
+    def set_x(self, i: int, x) -> None:
+        self.xs[i].copy_(x.reshape(self.bop.ns[i], -1).t())
+
+    def launch(self):
+        torch = _torch()
+        stream = torch.cuda.current_stream(self.xs[0].device).cuda_stream
+        _check(load_library().h3d_graph_launch(self._h, ctypes.c_void_p(stream)))
+        return [y.reshape(-1) if self.vec else y.t() for y in self._ys]
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(load_library().h3d_graph_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def build_batch(points_list, kernel="laplace", kernel_param: float = 1.0, leaf_size: int = 64,

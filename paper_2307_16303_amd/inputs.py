@@ -41,6 +41,17 @@ def clustered_points(n_uniform: int, n_ball: int, radius: float = 0.05,
     return np.ascontiguousarray(np.concatenate([u, b], axis=0))
 
 
+def two_density_points(n: int, frac_low: float, seed: int = 0) -> np.ndarray:
+    """n points uniform in [-1,1]^3 whose first round(frac_low n) are folded into
+    the half x <= 0 and the rest into x >= 0: two densities, so that leaves of
+    one depth hold from a few points to several times as many."""
+    p = uniform_points(n, seed)
+    k = int(round(frac_low * n))
+    p[:k, 0] = -np.abs(p[:k, 0])
+    p[k:, 0] = np.abs(p[k:, 0])
+    return np.ascontiguousarray(p)
+
+
 def uniform_rhs(n: int, seed: int = 0, nrhs: int | None = None) -> np.ndarray:
     shape = (n,) if nrhs is None else (n, nrhs)
     return np.random.default_rng(seed).uniform(-1.0, 1.0, shape)

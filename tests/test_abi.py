@@ -27,7 +27,7 @@ def declared_functions():
 
 def test_every_declared_symbol_is_exported(lib):
     names = declared_functions()
-    assert len(names) == 23, names
+    assert len(names) == 24, names
     out = subprocess.run(["nm", "-D", "--defined-only", hodlr3d.library_path()],
                          capture_output=True, text=True, check=True).stdout
     exported = set(re.findall(r" T (h3d_\w+)", out))

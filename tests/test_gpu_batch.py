@@ -113,15 +113,14 @@ def test_multiple_rhs_and_float32_io(mixed):
 
 def test_many_rhs_batch(mixed):
     """nrhs = 8 (the width from which a single operator's product uses the
-    matrix cores): every column of every problem against the problem's own
-    h3d_matvec (same factors, another summation order) and the oracle."""
+    matrix cores, and from which the batch runs its problems back to back on
+    them): every problem bitwise equal to its own h3d_matvec, and every column
+    against the oracle."""
     clouds, kw, bop = mixed
     xs = [inputs.normal_rhs(len(c), seed=90 + i, nrhs=8) for i, c in enumerate(clouds)]
     ys = batch_apply(bop, xs)
     for i, (x, y) in enumerate(zip(xs, ys)):
-        ys_solo = solo_apply(bop.plans[i], x)
-        for c in range(8):
-            assert rel(y[:, c], ys_solo[:, c]) <= 1e-13, (i, c)
+        np.testing.assert_array_equal(y, solo_apply(bop.plans[i], x), err_msg=f"problem {i}")
     for i in (0, 2):
         ref = oracle.HODLR3D(clouds[i], kernel="laplace", leaf_size=kw["leaf_size"], tol=kw["tol"],
                              box_lo=kw["box_lo"], box_side=kw["box_side"])
@@ -129,6 +128,39 @@ def test_many_rhs_batch(mixed):
         for c in range(8):
             assert rel(ys[i][:, c], yo[:, c]) <= 1e-13, (i, c)
     np.testing.assert_array_equal(batch_apply(bop, xs)[2], ys[2])  # reproducible
+
+
+@pytest.mark.parametrize("nrhs", [1, 8])
+def test_batch_graph_replay(nrhs):
+    """A batch product captured into a HIP graph: every replay bitwise equal to
+    the eager batch product, with eager work of the batch between replays;
+    while the graph lives, a batch product with another nrhs and the batch's
+    destruction are refused."""
+    torch = torch_mod()
+    clouds = [inputs.uniform_points(n, s) for n, s in ((3000, 21), (9000, 22), (700, 23))]
+    bop = build_batch(clouds, leaf_size=32, tol=1e-8, factor_dtype="fp32", **CUBE)
+    xs = [torch.as_tensor(inputs.normal_rhs(len(c), seed=24 + i,
+                                            nrhs=None if nrhs == 1 else nrhs), device="cuda")
+          for i, c in enumerate(clouds)]
+    eager = [y.cpu().numpy() for y in bop.matvec(xs)]
+    g = bop.graph(xs)
+    for _ in range(3):
+        outs = g.launch()
+        torch.cuda.synchronize()
+        for e, o in zip(eager, outs):
+            np.testing.assert_array_equal(o.cpu().numpy(), e)
+        bop.matvec(xs)  # eager work between the replays
+        torch.cuda.synchronize()
+    other = [torch.ones((len(c), 2 if nrhs == 1 else 17), dtype=torch.float64, device="cuda")
+             for c in clouds]
+    with pytest.raises(hodlr3d.H3DError):
+        bop.matvec(other)
+    lib = hodlr3d.load_library()
+    assert lib.h3d_destroy(bop._h) == hodlr3d.H3D_EINVAL
+    g.close()
+    bop.matvec(other)  # allowed once the graph is gone
+    torch.cuda.synchronize()
+    bop.close()
 
 
 @pytest.mark.parametrize("dtype", ["fp32", "bf16"])
