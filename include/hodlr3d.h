@@ -124,6 +124,8 @@ typedef struct {
     int64_t device_bytes;                     /* all device memory held by the plan */
     double build_ms;                          /* wall time of h3d_build */
     double aca_ms;                            /* part of it spent in ACA kernels */
+    int32_t tune_source;                      /* launch shapes: 0 defaults, 1 timed by the
+                                                 tuner, 2 read from H3D_TUNE_CACHE */
 } h3d_stats;
 
 /* Fills *cfg with defaults: Laplace, leaf_size 64, tol 1e-8, FP64 factors, no
@@ -165,7 +167,13 @@ h3d_status h3d_matvec_adjoint(h3d_plan *plan, const void *x, void *y, int64_t nr
  * Chooses the launch shapes of the factor streams for products with nrhs
  * right-hand sides (nrhs == 1, or any nrhs > 1 for the multi-column kernels)
  * by timing candidates on the plan's own factors on hip_stream.  h3d_build
- * runs it for nrhs == 1 unless H3D_FLAG_NO_AUTOTUNE is set.  The shapes only
+ * runs it for nrhs == 1 unless H3D_FLAG_NO_AUTOTUNE is set.  With the
+ * environment variable H3D_TUNE_CACHE naming a file, the choices are kept
+ * there as JSON under a key made of the GPU architecture, the factor type,
+ * one or several right-hand sides, the depth and per level the half-octave
+ * buckets of the mean box size and mean rank; a plan with a stored key takes
+ * the stored shapes (checked against its candidates) without timing
+ * (h3d_stats.tune_source tells which happened).  The shapes only
  * change the order of floating-point sums inside a product, never which
  * entries are summed; a plan's products stay bitwise reproducible.
  */

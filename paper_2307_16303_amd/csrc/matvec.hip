@@ -21,6 +21,11 @@
 // factors of the box that contains its row.  No atomics: every output row is
 // written by exactly one lane, and the summation order is fixed, so results
 // are bitwise reproducible.
+#include <unistd.h>
+
+#include <cmath>
+#include <cstdlib>
+
 #include "stage1_items.hpp"
 
 namespace h3d {
@@ -492,6 +497,144 @@ void ensure_scratch(Plan &P, int64_t nrhs, hipStream_t s) {
     P.scratch_nrhs = nrhs;
 }
 
+// ---- the tuner's cache ------------------------------------------------------
+// H3D_TUNE_CACHE names a JSON file mapping a plan's key (GPU architecture,
+// factor type, one or several right-hand sides, depth, and per level the
+// half-octave buckets of the mean box size and the mean rank) to the shapes
+// the tuner chose: [finest-level fusion, stage-2 waves, then per level
+// packed, S, U, passes, rows].  A plan whose key is found takes the stored
+// shapes (each checked against the level's candidates) instead of timing;
+// otherwise the tuner runs and adds its result.  The file is rewritten whole,
+// through a temporary file and a rename.
+
+int half_octave(double v) { return v <= 0.0 ? -1 : int(std::floor(2.0 * std::log2(v))); }
+
+std::string tune_key(const Plan &P, int cls) {
+    hipDeviceProp_t prop{};
+    H3D_HIP(hipGetDeviceProperties(&prop, P.device));
+    std::string arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    std::string k = arch + "|dt" + std::to_string(P.factor_dtype) + "|nr" +
+                    std::to_string(cls == 0 ? 1 : 4) + "|L" + std::to_string(P.L);
+    for (int l = 1; l <= P.L; ++l) {
+        const int64_t nb = P.lvl_blk[l + 1] - P.lvl_blk[l];
+        const double mr = nb > 0 ? double(P.lvl_rank_sum[l]) / double(nb) : 0.0;
+        k += "|" + std::to_string(half_octave(P.mean_box[l])) + ":" +
+             std::to_string(half_octave(mr));
+    }
+    return k;
+}
+
+std::map<std::string, std::vector<int>> read_tune_file(const char *path) {
+    std::map<std::string, std::vector<int>> out;
+    FILE *f = std::fopen(path, "rb");
+    if (!f)
+        return out;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0)
+        text.append(buf, got);
+    std::fclose(f);
+    // entries: "key": [int, int, ...]
+    size_t pos = 0;
+    for (;;) {
+        const size_t q0 = text.find('"', pos);
+        if (q0 == std::string::npos)
+            break;
+        const size_t q1 = text.find('"', q0 + 1);
+        if (q1 == std::string::npos)
+            break;
+        const size_t b0 = text.find('[', q1);
+        const size_t b1 = b0 == std::string::npos ? b0 : text.find(']', b0);
+        if (b1 == std::string::npos)
+            break;
+        std::vector<int> v;
+        const char *c = text.c_str() + b0 + 1;
+        const char *e = text.c_str() + b1;
+        while (c < e) {
+            char *end = nullptr;
+            const long x = std::strtol(c, &end, 10);
+            if (end == c) {
+                ++c;
+                continue;
+            }
+            v.push_back(int(x));
+            c = end;
+        }
+        out[text.substr(q0 + 1, q1 - q0 - 1)] = v;
+        pos = b1 + 1;
+    }
+    return out;
+}
+
+void write_tune_file(const char *path, const std::map<std::string, std::vector<int>> &m) {
+    const std::string tmp = std::string(path) + ".tmp." + std::to_string(long(getpid()));
+    FILE *f = std::fopen(tmp.c_str(), "wb");
+    if (!f)
+        return;  // the cache is an optimisation: an unwritable path only costs tuning time
+    std::fputs("{\n", f);
+    size_t i = 0;
+    for (const auto &kv : m) {
+        std::fprintf(f, "  \"%s\": [", kv.first.c_str());
+        for (size_t j = 0; j < kv.second.size(); ++j)
+            std::fprintf(f, j ? ", %d" : "%d", kv.second[j]);
+        std::fputs(++i < m.size() ? "],\n" : "]\n", f);
+    }
+    std::fputs("}\n", f);
+    const bool ok = std::fclose(f) == 0;
+    if (!ok || std::rename(tmp.c_str(), path) != 0)
+        std::remove(tmp.c_str());
+}
+
+// applies a stored entry when every value is one the tuner could have chosen
+bool tune_cache_apply(Plan &P, int cls, const std::vector<int> &v, bool narrow, hipStream_t s) {
+    if (v.size() != size_t(2 + 5 * P.L))
+        return false;
+    const std::vector<int> lc = leaf_candidates();
+    if (cls == 0 && std::find(lc.begin(), lc.end(), v[0]) == lc.end())
+        return false;
+    if (v[1] != 2 && v[1] != 4 && v[1] != 8)
+        return false;
+    std::vector<S1Shape> shapes(size_t(P.L) + 1);
+    for (int l = 1; l <= P.L; ++l) {
+        const int *e = v.data() + 2 + 5 * (l - 1);
+        S1Shape sh;
+        sh.packed = e[0];
+        sh.S = e[1];
+        sh.U = e[2];
+        sh.reps = e[3];
+        sh.rows = e[4];
+        bool known = P.lvl_blk[l + 1] <= P.lvl_blk[l];  // empty levels keep any shape
+        for (const S1Shape &c : s1_candidates(P, l, narrow, cls == 0))
+            known = known || (c.packed == sh.packed && c.S == sh.S && c.U == sh.U &&
+                              c.reps == sh.reps && c.rows == sh.rows);
+        known = known || (sh.packed == P.s1_shape[cls][l].packed && sh.S == P.s1_shape[cls][l].S &&
+                          sh.U == P.s1_shape[cls][l].U && sh.reps == P.s1_shape[cls][l].reps &&
+                          sh.rows == P.s1_shape[cls][l].rows);
+        if (!known)
+            return false;
+        shapes[size_t(l)] = sh;
+    }
+    for (int l = 1; l <= P.L; ++l)
+        if (P.lvl_blk[l + 1] > P.lvl_blk[l])
+            set_level_shape(P, cls, l, shapes[size_t(l)], s);
+    if (cls == 0 && !P.in_batch)
+        P.leaf_fuse = v[0];
+    P.s2_waves[cls] = v[1];
+    P.tuned[cls] = true;
+    return true;
+}
+
+std::vector<int> tune_cache_entry(const Plan &P, int cls) {
+    std::vector<int> v{cls == 0 ? std::max(P.leaf_fuse, 0) : 0, P.s2_waves[cls]};
+    for (int l = 1; l <= P.L; ++l) {
+        const S1Shape &sh = P.s1_shape[cls][l];
+        v.insert(v.end(), {sh.packed, sh.S, sh.U, sh.reps, sh.rows});
+    }
+    return v;
+}
+
 void autotune(Plan &P, int64_t nrhs, hipStream_t s) {
     // the pivot + LU form has no launch shapes to choose
     if (P.nfar == 0 || nrhs >= kBatchedMinRhs || P.lu_form)
@@ -501,6 +644,20 @@ void autotune(Plan &P, int64_t nrhs, hipStream_t s) {
         before_release(P, "autotuning");
     const int nr = nrhs == 1 ? 1 : int(std::min<int64_t>(nrhs, 4));
     ensure_scratch(P, std::max<int64_t>(nrhs, nr), s);
+    const int cls = nrhs == 1 ? 0 : 1;
+    const char *cache = std::getenv("H3D_TUNE_CACHE");
+    std::string key;
+    if (cache && *cache) {
+        key = tune_key(P, cls);
+        const auto m = read_tune_file(cache);
+        const auto it = m.find(key);
+        const bool narrow = nrhs == 1 && P.factor_dtype != H3D_F64;
+        if (it != m.end() && tune_cache_apply(P, cls, it->second, narrow, s)) {
+            H3D_HIP(hipStreamSynchronize(s));
+            P.stats.tune_source = 2;
+            return;
+        }
+    }
     auto go = [&](auto dt_tag) {
         constexpr int DT = decltype(dt_tag)::value;
         if (nrhs == 1)
@@ -520,6 +677,12 @@ void autotune(Plan &P, int64_t nrhs, hipStream_t s) {
         break;
     }
     H3D_HIP(hipStreamSynchronize(s));
+    P.stats.tune_source = 1;
+    if (cache && *cache) {
+        auto m = read_tune_file(cache);
+        m[key] = tune_cache_entry(P, cls);
+        write_tune_file(cache, m);
+    }
 }
 
 void launch_near_field(Plan &P, int nrhs, const double *xp, double *yn, hipStream_t s) {

@@ -80,6 +80,7 @@ class Stats(ctypes.Structure):
         ("device_bytes", ctypes.c_int64),
         ("build_ms", ctypes.c_double),
         ("aca_ms", ctypes.c_double),
+        ("tune_source", ctypes.c_int32),
     ]
 
     def to_dict(self) -> dict:
