@@ -1083,6 +1083,24 @@ __global__ void k_cnt_coltiles(int64_t b0, int64_t nb, const int32_t *__restrict
         cnt[b] = (rank[b0 + b] + tile - 1) / tile;
 }
 
+// tile counts of the blocks at positions b0 .. b0 + nb of perm (or of the
+// level order when perm is null)
+__global__ void k_cnt_coltiles_perm(int64_t b0, int64_t nb, const int32_t *__restrict__ rank,
+                                    const int64_t *__restrict__ perm, int tile,
+                                    int64_t *__restrict__ cnt) {
+    const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b < nb)
+        cnt[b] = (rank[perm ? perm[b0 + b] : b0 + b] + tile - 1) / tile;
+}
+
+// items made over positions of perm: replaces each position by its block
+__global__ void k_items_perm(int64_t n, const int64_t *__restrict__ perm,
+                             int32_t *__restrict__ items) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n)
+        items[2 * i] = int32_t(perm[items[2 * i]]);
+}
+
 // builds items for nb consecutive units whose tile counts are in cnt[0..nb)
 int32_t *make_items(Plan &P, int64_t nb, int64_t id0, int64_t *cnt, int64_t *count, hipStream_t s) {
     int64_t *raw = P.mem.alloc_n<int64_t>(nb + 1);
@@ -1115,6 +1133,10 @@ int tiles_for(int v, int dt) {
 int tiles_s2(int box, int dt) {
     return tiles_for(box, dt) > 1 ? 2 : 1;
 }
+
+// FP32/BF16 levels whose columns would be split take the ring kernel instead
+// when it has at least this many items (four per SIMD)
+constexpr int64_t kRingMinItems = 4096;
 
 // stage-1 columns of boxes above this size are split into parts of this many rows
 constexpr int kMfmaSplitBox = 2048;
@@ -1182,14 +1204,27 @@ void ensure_batched_tables(Plan &P, hipStream_t s) {
             H3D_LAUNCH_CHECK();
             P.bt_s1[l] = make_items(P, nb, b0, cnt, &P.bt_ns1[l], s);
             P.mem.release(cnt);
-            if (P.factor_dtype != H3D_F64) {
-                // the ring kernel's items: (block, 16 MT columns)
+        }
+        if (nb > 0 && P.factor_dtype != H3D_F64) {
+            // the ring kernel's items: (block, 16 MT columns), blocks in level
+            // order (grouped by target box: the adjoint's rows of X) and in
+            // source order (the forward's)
+            const int cols = 16 * s1_ring_tiles(P, l);
+            for (int dir = 0; dir < 2; ++dir) {
+                const int64_t *perm = dir == 0 ? P.src_blk : nullptr;
                 int64_t *cnt4 = P.mem.alloc_n<int64_t>(nb + 1);
-                k_cnt_coltiles<<<grid_for(nb, 256), 256, 0, s>>>(b0, nb, P.blk_rank,
-                                                                16 * s1_ring_tiles(P, l), cnt4);
+                k_cnt_coltiles_perm<<<grid_for(nb, 256), 256, 0, s>>>(b0, nb, P.blk_rank, perm,
+                                                                     cols, cnt4);
                 H3D_LAUNCH_CHECK();
-                P.bt_s1r[l] = make_items(P, nb, b0, cnt4, &P.bt_ns1r[l], s);
+                int64_t cnt_items = 0;
+                int32_t *items = make_items(P, nb, b0, cnt4, &cnt_items, s);
                 P.mem.release(cnt4);
+                if (perm && cnt_items > 0) {
+                    k_items_perm<<<grid_for(cnt_items, 256), 256, 0, s>>>(cnt_items, perm, items);
+                    H3D_LAUNCH_CHECK();
+                }
+                P.bt_s1r[l][dir] = items;
+                P.bt_ns1r[l][dir] = cnt_items;
             }
         }
         // stage 2: (box, row tile) for the boxes of level l
@@ -1208,6 +1243,8 @@ void ensure_batched_tables(Plan &P, hipStream_t s) {
             H3D_LAUNCH_CHECK();
             P.bt_s2r[l] = make_items(P, nbox, 0, cnt4, &P.bt_ns2r[l], s);
             P.mem.release(cnt4);
+            P.bt_s2k[l][0] = s2_ring_steps(P, l, false, s);
+            P.bt_s2k[l][1] = s2_ring_steps(P, l, true, s);
         }
     }
     P.bt_ready = true;
@@ -1300,9 +1337,14 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
         adjoint ? P.blk_toff : P.blk_soff, adjoint ? P.blk_uptr : P.blk_vptr, P.blk_rank,     \
         P.blk_col0, P.blk_scale, Xs, NP, Z, int(adjoint && l < P.chunk_level), P.leaf_off,    \
         P.leaf_of, 3 * (P.L - P.chunk_level), P.bt_split[l], Zp)
-        if (DT != H3D_F64 && P.bt_split[l] == 0)
-            launch_s1_ring(P, l, adjoint, reinterpret_cast<const int2 *>(P.bt_s1r[l]),
-                           P.bt_ns1r[l], reinterpret_cast<const float *>(Xs), NP,
+        // the ring kernel wherever its items fill the GPU; the few long
+        // columns of the coarsest levels keep the row-split kernels
+        const int dir = adjoint ? 1 : 0;
+        const bool ring =
+            DT != H3D_F64 && (P.bt_split[l] == 0 || P.bt_ns1r[l][dir] >= kRingMinItems);
+        if (ring)
+            launch_s1_ring(P, l, adjoint, reinterpret_cast<const int2 *>(P.bt_s1r[l][dir]),
+                           P.bt_ns1r[l][dir], reinterpret_cast<const float *>(Xs), NP,
                            reinterpret_cast<float *>(Z), s);
         else if (P.bt_mt1[l] == 4)
             H3D_S1M(4);
@@ -1318,7 +1360,7 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
                 int(adjoint && l < P.chunk_level), P.leaf_off, P.leaf_of,
                 3 * (P.L - P.chunk_level));
 #undef H3D_S1M
-        if (P.bt_split[l] > 0) {
+        if (!ring && P.bt_split[l] > 0) {
             H3D_LAUNCH_CHECK();
             const int cols = 16 * P.bt_mt1[l];
             const int64_t nt = P.bt_ngrp[l] * cols * NP;

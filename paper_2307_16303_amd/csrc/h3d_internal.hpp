@@ -308,10 +308,13 @@ struct Plan {
     int64_t bt_ns1[kMaxLevels + 1] = {};
     int32_t *bt_s2[kMaxLevels + 1] = {};
     int64_t bt_ns2[kMaxLevels + 1] = {};
-    int32_t *bt_s1r[kMaxLevels + 1] = {};  // FP32/BF16 stage 1: (block, column tile group)
-    int64_t bt_ns1r[kMaxLevels + 1] = {};
+    // FP32/BF16 stage 1: (block, column tile group), blocks in source order
+    // (forward) and in level order (adjoint)
+    int32_t *bt_s1r[kMaxLevels + 1][2] = {};
+    int64_t bt_ns1r[kMaxLevels + 1][2] = {};
     int32_t *bt_s2r[kMaxLevels + 1] = {};  // FP32/BF16 stage 2: (box, 64-row tile)
     int64_t bt_ns2r[kMaxLevels + 1] = {};
+    int32_t *bt_s2k[kMaxLevels + 1][2] = {};  // K-steps per box of the ring kernel (fwd, adj)
     int bt_mt1[kMaxLevels + 1] = {};  // 16-column tiles per stage-1 wave
     int bt_mt2[kMaxLevels + 1] = {};  // 16-row tiles per stage-2 wave
     int bt_split[kMaxLevels + 1] = {};  // stage-1 rows per part (0: columns not split)
@@ -454,6 +457,8 @@ void launch_s1_ring(Plan &P, int l, bool adjoint, const int2 *items, int64_t nit
                     const float *Xs, int NP, float *Z, hipStream_t s);
 // stage 2 of one level, FP32/BF16 factors, one wave per (box, 64-row tile)
 // with a ring of fragment loads across the box's blocks (stage2_ring.hip)
+// per box of level l, the K-steps of its blocks in the stage-2 ring kernel
+int32_t *s2_ring_steps(Plan &P, int l, bool adjoint, hipStream_t s);
 void launch_s2_ring(Plan &P, int l, bool adjoint, const int2 *items, int64_t nitems,
                     const float *Z, int NP, double *Y, hipStream_t s);
 void launch_leaf_fused(Plan &P, const float *Xs, int NP, double *Y, hipStream_t s);

@@ -1,4 +1,4 @@
-// Many right-hand sides, finest level, leaves of 17 to 64 rows: both stages
+// Many right-hand sides, finest level, leaves of at most 64 rows: both stages
 // of every block of a target leaf in one wave, with z never leaving the
 // registers.
 //
@@ -17,10 +17,21 @@
 // most 64 columns) are added into FP64 sums of the leaf's rows, which start
 // from Y (the near field and the coarser levels) and are written back once.
 //
+// Loads run ahead of the MFMAs through a ring of D stage-1 K-steps that
+// crosses blocks: each block's stage-1 steps are padded to a multiple of D
+// (padded steps load again the block's last rows and issue no MFMA), so the
+// refill cursor, exactly D steps ahead, enters the next block at slot 0 and
+// stage 2 runs once per block outside the unrolled ring.  The U_b columns of
+// the first UP column tiles are loaded when the block's stage 1 begins, the
+// others just before use.  The block metadata is read with scalar loads, one
+// block ahead.  Tile N, column n of the MFMA is right-hand side 4 n + N of the
+// group of 64, so a lane's four X values and four outputs of a row are
+// contiguous.
+//
 // One wave per leaf; leaves grouped by their 16-row tile count MT, one launch
 // per group (a block's rank is at most its leaf's row count, so it has at
-// most MT column tiles).  Every load is issued from indices clamped into the block and
-// masked where the MFMA uses it.
+// most MT column tiles).  Every load is issued from indices clamped into the
+// block and masked where the MFMA uses it.
 #include "product_items.hpp"
 
 namespace h3d {
@@ -41,13 +52,27 @@ template <> struct LFac<H3D_BF16_SCALED> {
     }
 };
 
+template <typename T> __device__ __forceinline__ T cload(const T *p) {
+    return *(const __attribute__((address_space(4))) T *)p;
+}
+
 __device__ __forceinline__ f4 mma(float a, float b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+template <int MT> struct LSlot {
+    float a[MT];
+    f4 x;
+};
+
+template <int MT> struct LfShape;  // ring depth, U tiles loaded ahead, waves per SIMD
+template <> struct LfShape<1> { static constexpr int D = 4, UP = 1, W = 3; };
+template <> struct LfShape<2> { static constexpr int D = 6, UP = 2, W = 2; };
+template <> struct LfShape<3> { static constexpr int D = 8, UP = 2, W = 1; };
+template <> struct LfShape<4> { static constexpr int D = 8, UP = 2, W = 1; };
+
 template <int DT, int MT>
-__global__ void __launch_bounds__(64)
-    __attribute__((amdgpu_waves_per_eu(MT == 1 ? 4 : (MT <= 3 ? 2 : 1))))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LfShape<MT>::W)))
     k_leaf_fused(const int32_t *__restrict__ items, int64_t nitems, int64_t gbase,
                  const int32_t *__restrict__ leaf_off, const int64_t *__restrict__ grp_begin,
                  void *const *__restrict__ uptr, void *const *__restrict__ vptr,
@@ -55,6 +80,7 @@ __global__ void __launch_bounds__(64)
                  const int32_t *__restrict__ slen, const float *__restrict__ scale2,
                  const float *__restrict__ Xs, int NP, double *__restrict__ Y) {
     using F = typename LFac<DT>::T;
+    constexpr int D = LfShape<MT>::D, UP = LfShape<MT>::UP;
     const int64_t w = blockIdx.x;
     if (w >= nitems)
         return;
@@ -71,82 +97,131 @@ __global__ void __launch_bounds__(64)
         ai[M] = i < bm;
         ic[M] = min(i, bm - 1);
     }
+    struct Blk {
+        int k, n;
+        int64_t so;
+        const F *V, *U;
+    };
+    auto load = [&](int64_t b) {
+        return Blk{cload(rank + b), cload(slen + b), int64_t(cload(soff + b)),
+                   static_cast<const F *>(cload(vptr + b)), static_cast<const F *>(cload(uptr + b))};
+    };
+    // stage-1 steps of a block padded to a multiple of D
+    auto padded = [](int n) { return (((n + 3) >> 2) + D - 1) / D * D; };
+    // first block of nonzero rank at or after b (e1 if none)
+    auto skip = [&](int64_t b) {
+        while (b < e1 && cload(rank + b) <= 0)
+            ++b;
+        return b;
+    };
+    const int64_t bfirst = skip(e0);
+    if (bfirst >= e1)
+        return;  // no far block: Y keeps its rows
     for (int nb = 0; nb < NP; nb += 64) {
-        const int ntl = min(4, (NP - nb) / 16);
-        // the leaf's rows of Y in FP64; each block's FP32 tiles are added into
-        // them after the block
+        const int nv = min(64, NP - nb);
+        const int bcol = nb + 4 * min(r16, nv / 4 - 1);
+        const bool lane_out = 4 * r16 < nv;
+        // the leaf's rows of Y in FP64; each block's FP32 tiles are added
+        // into them after the block
         double acc64[MT][4][4];
 #pragma unroll
         for (int M = 0; M < MT; ++M)
 #pragma unroll
-            for (int N = 0; N < 4; ++N)
+            for (int jj = 0; jj < 4; ++jj) {
+                const int r = 16 * M + 4 * q + jj;
+                const double *yp = Y + (bs + min(r, bm - 1)) * int64_t(NP) + bcol;
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    const int r = 16 * M + 4 * q + jj;
-                    acc64[M][N][jj] = (N < ntl && r < bm)
-                                          ? Y[(bs + r) * int64_t(NP) + nb + 16 * N + r16]
-                                          : 0.0;
-                }
-        for (int64_t b = e0; b < e1; ++b) {
-            const int k = rank[b];
-            if (k <= 0)
-                continue;
-            const int n = slen[b];
-            const int64_t so = soff[b];
-            const F *__restrict__ V = static_cast<const F *>(vptr[b]);
-            const F *__restrict__ U = static_cast<const F *>(uptr[b]);
-            const int KT = (k + 15) >> 4;
-            // ---- stage 1: C1[T][N] = (V^T X)[16 T .., 16 N ..]; k <= m, so
-            // the block has at most MT column tiles
+                for (int N = 0; N < 4; ++N)
+                    acc64[M][jj][N] = yp[N];
+            }
+        // refill cursor: block fb (metadata fc), padded step fs; the next
+        // block's metadata in flight
+        int64_t fb = bfirst;
+        Blk fc = load(fb);
+        int fS = padded(fc.n), fs = 0;
+        int64_t fnb = skip(fb + 1);
+        Blk fnx = fnb < e1 ? load(fnb) : fc;
+        auto fadvance = [&] {
+            if (++fs < fS)
+                return;
+            if (fnb >= e1) {  // past the last block: stay on its last step
+                fs = fS - 1;
+                return;
+            }
+            fb = fnb;
+            fc = fnx;
+            fS = padded(fc.n);
+            fs = 0;
+            fnb = skip(fb + 1);
+            if (fnb < e1)
+                fnx = load(fnb);
+        };
+        auto fill = [&](LSlot<MT> &R) {
+            const int jc = min(4 * fs + q, fc.n - 1);
+#pragma unroll
+            for (int T = 0; T < MT; ++T)
+                R.a[T] = LFac<DT>::ld(fc.V + int64_t(min(16 * T + r16, fc.k - 1)) * fc.n + jc);
+            R.x = *reinterpret_cast<const f4 *>(Xs + (fc.so + jc) * NP + bcol);
+        };
+        LSlot<MT> R[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            fill(R[d]);
+            fadvance();
+            __builtin_amdgcn_sched_barrier(0);  // slots in order (the waits count on it)
+        }
+        int64_t cb = bfirst;
+        Blk cc = fc;
+        cc = load(cb);
+        for (;;) {
+            const int k = cc.k, n = cc.n;
+            const int S1 = (n + 3) >> 2, S1p = padded(n), KT = (k + 15) >> 4;
+            // U_b columns of the first UP tiles, needed after this block's stage 1
+            float u[UP][4][MT];
+#pragma unroll
+            for (int T = 0; T < UP; ++T)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                    for (int M = 0; M < MT; ++M)
+                        u[T][jj][M] =
+                            LFac<DT>::ld(cc.U + int64_t(min(16 * T + 4 * q + jj, k - 1)) * bm + ic[M]);
             f4 C1[MT][4];
 #pragma unroll
             for (int T = 0; T < MT; ++T)
 #pragma unroll
                 for (int N = 0; N < 4; ++N)
                     C1[T][N] = f4{0.f, 0.f, 0.f, 0.f};
-            int cc[MT];
-            bool ac[MT];
+            auto chunk = [&](int s0) {
 #pragma unroll
-            for (int T = 0; T < MT; ++T) {
-                const int c = 16 * T + r16;
-                ac[T] = c < k;
-                cc[T] = min(c, k - 1);
-            }
-            auto frag1 = [&](int s, float (&a)[MT], float (&x)[4]) {
-                const int jc = min(4 * s + q, n - 1);
-#pragma unroll
-                for (int T = 0; T < MT; ++T)
-                    a[T] = T < KT ? LFac<DT>::ld(V + int64_t(cc[T]) * n + jc) : 0.f;
-#pragma unroll
-                for (int N = 0; N < 4; ++N)
-                    x[N] = Xs[(so + jc) * NP + nb + 16 * min(N, ntl - 1) + r16];
-            };
-            const int S1 = (n + 3) >> 2;
-            float a0[MT], x0[4], a1[MT], x1[4];
-            frag1(0, a0, x0);
-            auto step1 = [&](int s, const float (&a)[MT], const float (&x)[4]) {
-                const bool aj = 4 * s + q < n;
-#pragma unroll
-                for (int T = 0; T < MT; ++T)
-                    if (T < KT) {
-                        const float av = (aj && ac[T]) ? a[T] : 0.f;
+                for (int d = 0; d < D; ++d) {
+                    const int s = s0 + d;
+                    if (s < S1) {
+                        const bool aj = 4 * s + q < n;
+                        float xv[4];
 #pragma unroll
                         for (int N = 0; N < 4; ++N)
-                            C1[T][N] = mma(av, (aj && N < ntl) ? x[N] : 0.f, C1[T][N]);
+                            xv[N] = aj ? R[d].x[N] : 0.f;
+#pragma unroll
+                        for (int T = 0; T < MT; ++T)
+                            if (T < KT)
+#pragma unroll
+                                for (int N = 0; N < 4; ++N)
+                                    C1[T][N] = mma(R[d].a[T], xv[N], C1[T][N]);
                     }
+                    fill(R[d]);
+                    fadvance();
+                    __builtin_amdgcn_sched_barrier(0);
+                }
             };
-            for (int s = 0; s < S1; s += 2) {
-                if (s + 1 < S1)
-                    frag1(s + 1, a1, x1);
-                step1(s, a0, x0);
-                if (s + 1 >= S1)
-                    break;
-                if (s + 2 < S1)
-                    frag1(s + 2, a0, x0);
-                step1(s + 1, a1, x1);
-            }
+            // the first chunk on its own: its waits then count the U loads
+            // just issued (a shared loop header would count them as absent
+            // and wait for most of the ring at every block)
+            chunk(0);
+            for (int s0 = D; s0 < S1p; s0 += D)
+                chunk(s0);
             if constexpr (DT == H3D_BF16_SCALED) {
-                const float sc = scale2[2 * b] * scale2[2 * b + 1];
+                const float sc = scale2[2 * cb] * scale2[2 * cb + 1];
 #pragma unroll
                 for (int T = 0; T < MT; ++T)
 #pragma unroll
@@ -164,20 +239,23 @@ __global__ void __launch_bounds__(64)
             for (int T = 0; T < MT; ++T) {
                 if (T >= KT)
                     break;
-                float u[4][MT];
+                float ut[4][MT];
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    const int c = min(16 * T + 4 * q + jj, k - 1);
+                for (int jj = 0; jj < 4; ++jj)
 #pragma unroll
-                    for (int M = 0; M < MT; ++M)
-                        u[jj][M] = LFac<DT>::ld(U + int64_t(c) * bm + ic[M]);
-                }
+                    for (int M = 0; M < MT; ++M) {
+                        if (T < UP)
+                            ut[jj][M] = u[T < UP ? T : 0][jj][M];
+                        else
+                            ut[jj][M] = LFac<DT>::ld(
+                                cc.U + int64_t(min(16 * T + 4 * q + jj, k - 1)) * bm + ic[M]);
+                    }
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
                     const bool kc = 16 * T + 4 * q + jj < k;
 #pragma unroll
                     for (int M = 0; M < MT; ++M) {
-                        const float av = (kc && ai[M]) ? u[jj][M] : 0.f;
+                        const float av = (kc && ai[M]) ? ut[jj][M] : 0.f;
 #pragma unroll
                         for (int N = 0; N < 4; ++N)
                             C2[M][N] = mma(av, C1[T][N][jj], C2[M][N]);
@@ -190,19 +268,26 @@ __global__ void __launch_bounds__(64)
                 for (int N = 0; N < 4; ++N)
 #pragma unroll
                     for (int jj = 0; jj < 4; ++jj)
-                        acc64[M][N][jj] += double(C2[M][N][jj]);
+                        acc64[M][jj][N] += double(C2[M][N][jj]);
+            cb = skip(cb + 1);
+            if (cb >= e1)
+                break;
+            cc = load(cb);
         }
+        if (lane_out) {
 #pragma unroll
-        for (int M = 0; M < MT; ++M)
+            for (int M = 0; M < MT; ++M)
 #pragma unroll
-            for (int N = 0; N < 4; ++N)
-                if (N < ntl)
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int r = 16 * M + 4 * q + jj;
+                    if (r < bm) {
+                        double *yp = Y + (bs + r) * int64_t(NP) + nb + 4 * r16;
 #pragma unroll
-                    for (int jj = 0; jj < 4; ++jj) {
-                        const int r = 16 * M + 4 * q + jj;
-                        if (r < bm)
-                            Y[(bs + r) * int64_t(NP) + nb + 16 * N + r16] = acc64[M][N][jj];
+                        for (int N = 0; N < 4; ++N)
+                            yp[N] = acc64[M][jj][N];
                     }
+                }
+        }
     }
 }
 

@@ -1,18 +1,24 @@
 // Many right-hand sides, FP32/BF16 factors: stage 2 of one level, Y_t +=
 // sum_b U_b Z_b, with a deep ring of fragment loads.
 //
-// One wave per (target box, 64-row tile): four 16-row tiles M against the
-// four 16-column right-hand-side tiles N, 16 FP32 MFMAs per K-step of four
-// factor columns, so every fragment loaded feeds four MFMAs.  The K-steps run
-// over the columns of all blocks of the box in block order; a cursor walks
-// (block, first column) through the blocks' metadata, staged 64 blocks at a
-// time in LDS, and the fragments of the next D K-steps are in flight while a
-// step's MFMAs run (the ring crosses block boundaries, so it never drains
-// inside a box).  Every load is issued from indices clamped into its block
-// (past the last block: the last block's first column), and the values are
-// masked where the MFMA uses them.  The FP32 tiles are added into the FP64
-// rows of Y (read, add, write; each element belongs to one wave) at least
-// every 64 K-steps.
+// One wave per (target box, 64-row tile): four 16-row tiles M against four
+// 16-column right-hand-side tiles N, 16 FP32 MFMAs per K-step of four factor
+// columns, so every fragment loaded feeds four MFMAs.  The K-steps run over the
+// columns of all blocks of the box in block order; their count S is known from
+// a table (sum over the box's blocks of ceil(k_b / 4)), so the loop is a
+// steady part in which every step refills its ring slot and a tail without
+// refills: the compiler then counts the loads in flight exactly and waits for
+// one slot at a time.  The block cursor reads the blocks' rank, factor pointer
+// and first z index with scalar loads, one block ahead.  Past the last block
+// the loads stay on that block's first columns (never consumed).
+//
+// Tile N, column n of the MFMA is right-hand side 4 n + N of the group of 64,
+// so a lane's four B values (and its four outputs of a row) are contiguous:
+// one 16-byte load of z per K-step.  The wave's rows of Y are held in FP64
+// registers (read once before the K-steps, written once after them); the FP32
+// tiles are added into them at least every 64 K-steps.  Four waves of a
+// workgroup take four consecutive items, mostly the row tiles of one box, so
+// the box's z fragments are fetched once into the CU's caches for all four.
 #include "product_items.hpp"
 
 namespace h3d {
@@ -33,121 +39,117 @@ template <> struct RFac<H3D_BF16_SCALED> {
     }
 };
 
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+template <typename T> __device__ __forceinline__ T cload(const T *p) {
+    return *(const __attribute__((address_space(4))) T *)p;
 }
 
 struct Slot {
-    float a[4], b[4];
-    int kv;  // columns of the step still inside the block (<= 0: past the end)
+    float a[4];
+    f4 b;
 };
 
 template <int DT, int D>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1)))
     k_s2_ring(const int2 *__restrict__ items, int64_t nitems, int64_t gbase,
               const int32_t *__restrict__ leaf_off, int sh, const int64_t *__restrict__ grp_begin,
               const int64_t *__restrict__ grp_blk, void *const *__restrict__ fptr,
               const int32_t *__restrict__ rank, const int64_t *__restrict__ blk_col0,
-              const float *__restrict__ Z, int NP, double *__restrict__ Y, int panel,
-              const int32_t *__restrict__ leaf_of, int shc) {
+              const int32_t *__restrict__ steps, const float *__restrict__ Z, int NP,
+              double *__restrict__ Y, int panel, const int32_t *__restrict__ leaf_of, int shc) {
     using F = typename RFac<DT>::T;
-    __shared__ int32_t s_bk[64];
-    __shared__ int64_t s_bc[64];
-    __shared__ const F *s_bp[64];
-    const int64_t w = blockIdx.x;
+    const int64_t w = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (w >= nitems)
         return;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const int r16 = lane & 15, q = lane >> 4;
     const int2 it = items[w];
     const int64_t tb = it.x;
+    const int S = steps[tb];
+    if (S <= 0)
+        return;
     const int32_t bs = leaf_off[tb << sh], bm = leaf_off[(tb + 1) << sh] - bs;
     const int64_t e0 = grp_begin[gbase + tb], e1 = grp_begin[gbase + tb + 1];
-    if (e1 <= e0)
-        return;
     const int r0 = it.y * 64;
-    int iac[4];
-    bool ar[4];
-    int32_t poff[4], pld[4];  // element (row, c) of U_b at base + poff * k + c * pld
+    int32_t iac[4], poff[4], pld[4];  // element (row, c) of U_b at base + poff k + iac + c pld
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        const int i = r0 + 16 * t + r16;
-        ar[t] = i < bm;
-        iac[t] = min(i, bm - 1);
+        const int i = min(r0 + 16 * t + r16, bm - 1);
         int32_t pr0 = bs, ld = bm;
         if (panel) {  // row panels: this row's chunk box
-            const int32_t ch = leaf_of[bs + iac[t]] >> shc;
+            const int32_t ch = leaf_of[bs + i] >> shc;
             pr0 = leaf_off[ch << shc];
             ld = leaf_off[(ch + 1) << shc] - pr0;
         }
         poff[t] = pr0 - bs;
         pld[t] = ld;
-        iac[t] = bs + iac[t] - pr0;  // row inside the panel
+        iac[t] = bs + i - pr0;  // row inside the panel
     }
+    struct Blk {
+        int k;
+        const F *p;
+        int64_t col0;
+    };
+    // the block tables are read-only here: constant-space loads stay scalar
+    auto load = [&](int64_t qq) {
+        const int64_t bj = grp_blk ? cload(grp_blk + qq) : qq;
+        return Blk{cload(rank + bj), static_cast<const F *>(cload(fptr + bj)), cload(blk_col0 + bj)};
+    };
     for (int nb = 0; nb < NP; nb += 64) {
-        const int ntl = min(4, (NP - nb) / 16);
-        // block cursor over the box's blocks, their metadata 64 at a time in
-        // LDS; the current block's pointer, first z index and rank in registers
-        int64_t qw = e0;
-        int nbk = 0, ib = -1, c = 0;
-        bool done = false;
-        const F *lbase = nullptr;
-        int64_t lcol0 = 0;
-        int lk = 1;
-        auto stage = [&](int64_t q0) {
-            nbk = int(min<int64_t>(64, e1 - q0));
-            wave_sync();
-            if (lane < nbk) {
-                const int64_t bj = grp_blk ? grp_blk[q0 + lane] : q0 + lane;
-                s_bk[lane] = rank[bj];
-                s_bc[lane] = blk_col0[bj];
-                s_bp[lane] = static_cast<const F *>(fptr[bj]);
+        const int nv = min(64, NP - nb);
+        const int bcol = nb + 4 * min(r16, nv / 4 - 1);
+        // this wave's rows of Y (rows past the box: the last row, not written)
+        double acc64[4][4][4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const int r = min(r0 + 16 * t + 4 * q + jj, bm - 1);
+                const double *yp = Y + (bs + r) * int64_t(NP) + bcol;
+#pragma unroll
+                for (int N = 0; N < 4; ++N)
+                    acc64[t][jj][N] = yp[N];
             }
-            wave_sync();
+        // cursor: current block and column; the next block's metadata in flight
+        int64_t qn = e0;
+        Blk cur = load(qn);
+        ++qn;
+        while (cur.k <= 0 && qn < e1) {
+            cur = load(qn);
+            ++qn;
+        }
+        Blk nxt = qn < e1 ? load(qn) : cur;
+        int c = 0;
+        int32_t roff[4];
+        auto set_rows = [&] {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                roff[t] = poff[t] * cur.k + iac[t];
         };
-        auto next_block = [&] {  // the next block of nonzero rank, or done
-            for (;;) {
-                if (++ib >= nbk) {
-                    qw += nbk;
-                    if (qw >= e1) {
-                        done = true;
-                        return;
-                    }
-                    stage(qw);
-                    ib = 0;
-                }
-                const int kk = s_bk[ib];
-                if (kk > 0) {
-                    lk = kk;
-                    lbase = s_bp[ib];
-                    lcol0 = s_bc[ib];
-                    c = 0;
+        set_rows();
+        auto advance = [&] {
+            c += 4;
+            if (c < cur.k)
+                return;
+            c = 0;
+            while (qn < e1) {
+                const Blk b = nxt;
+                ++qn;
+                if (qn < e1)
+                    nxt = load(qn);
+                if (b.k > 0) {
+                    cur = b;
+                    set_rows();
                     return;
                 }
             }
+            // past the last block: the cursor stays on it
         };
-        stage(qw);
-        next_block();
-        if (done)
-            continue;  // every block of the box has rank 0
-        // past the end, loads stay on the last block's first column
-        auto fill = [&](Slot &S) {
-            const int cs = done ? 0 : c;
-            S.kv = done ? 0 : lk - c;
-            const int cc = min(cs + q, lk - 1);
+        auto fill = [&](Slot &R) {
+            const int cc = min(c + q, cur.k - 1);
 #pragma unroll
             for (int t = 0; t < 4; ++t)
-                S.a[t] = RFac<DT>::ld(lbase + int64_t(poff[t]) * lk + iac[t] + int64_t(cc) * pld[t]);
-#pragma unroll
-            for (int N = 0; N < 4; ++N)
-                S.b[N] = Z[(lcol0 + cc) * NP + nb + 16 * min(N, ntl - 1) + r16];
-            if (!done) {
-                c += 4;
-                if (c >= lk)
-                    next_block();
-            }
+                R.a[t] = RFac<DT>::ld(cur.p + roff[t] + int64_t(cc) * pld[t]);
+            R.b = *reinterpret_cast<const f4 *>(Z + (cur.col0 + cc) * NP + bcol);
         };
         f4 C[4][4];
 #pragma unroll
@@ -155,61 +157,104 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2)))
 #pragma unroll
             for (int N = 0; N < 4; ++N)
                 C[t][N] = f4{0.f, 0.f, 0.f, 0.f};
-        int ks = 0;
         auto flush = [&] {
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int N = 0; N < 4; ++N) {
-                    if (N < ntl)
 #pragma unroll
-                        for (int jj = 0; jj < 4; ++jj) {
-                            const int r = r0 + 16 * t + 4 * q + jj;
-                            if (r < bm) {
-                                double *yp = Y + (bs + r) * int64_t(NP) + nb + 16 * N + r16;
-                                *yp = *yp + double(C[t][N][jj]);
-                            }
-                        }
+                    for (int jj = 0; jj < 4; ++jj)
+                        acc64[t][jj][N] += double(C[t][N][jj]);
                     C[t][N] = f4{0.f, 0.f, 0.f, 0.f};
                 }
-            ks = 0;
         };
+        // columns of the step still inside its block (a partial last step of
+        // a block has kv < 4)
         Slot R[D];
+        int kv[D];
 #pragma unroll
-        for (int d = 0; d < D; ++d)
+        for (int d = 0; d < D; ++d) {
+            kv[d] = cur.k - c;
             fill(R[d]);
-        bool more = true;
-        while (more) {
+            advance();
+            __builtin_amdgcn_sched_barrier(0);  // slots in order (the waits count on it)
+        }
+        auto step = [&](int d) {
+            const bool ak = q < kv[d];
+            float bv[4];
 #pragma unroll
-            for (int d = 0; d < D; ++d) {
-                if (R[d].kv <= 0) {
-                    more = false;
-                    break;
-                }
-                const bool ak = q < R[d].kv;
-                float av[4], bv[4];
+            for (int N = 0; N < 4; ++N)
+                bv[N] = ak ? R[d].b[N] : 0.f;
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    av[t] = (ak && ar[t]) ? R[d].a[t] : 0.f;
+            for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int N = 0; N < 4; ++N)
-                    bv[N] = (ak && N < ntl) ? R[d].b[N] : 0.f;
+                    C[t][N] = __builtin_amdgcn_mfma_f32_16x16x4f32(R[d].a[t], bv[N], C[t][N], 0, 0,
+                                                                   0);
+        };
+        int s0 = 0, ks = 0;
+        for (; s0 + D <= S; s0 += D) {
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
-#pragma unroll
-                    for (int N = 0; N < 4; ++N)
-                        C[t][N] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], bv[N], C[t][N], 0, 0,
-                                                                       0);
-                if (++ks == 64)
-                    flush();
+            for (int d = 0; d < D; ++d) {
+                step(d);
+                kv[d] = cur.k - c;
                 fill(R[d]);
+                advance();
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            ks += D;
+            if (ks + D > 64) {
+                flush();
+                ks = 0;
             }
         }
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            if (s0 + d < S)
+                step(d);
         flush();
+        if (4 * r16 < nv) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int r = r0 + 16 * t + 4 * q + jj;
+                    if (r < bm) {
+                        double *yp = Y + (bs + r) * int64_t(NP) + nb + 4 * r16;
+#pragma unroll
+                        for (int N = 0; N < 4; ++N)
+                            yp[N] = acc64[t][jj][N];
+                    }
+                }
+        }
     }
 }
 
+// K-steps of every box of a level: sum over its blocks of ceil(k_b / 4)
+__global__ void k_s2_steps(int64_t nbox, int64_t gbase, const int64_t *__restrict__ grp_begin,
+                           const int64_t *__restrict__ grp_blk, const int32_t *__restrict__ rank,
+                           int32_t *__restrict__ steps) {
+    const int64_t tb = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (tb >= nbox)
+        return;
+    int64_t sum = 0;
+    for (int64_t e = grp_begin[gbase + tb]; e < grp_begin[gbase + tb + 1]; ++e) {
+        const int k = rank[grp_blk ? grp_blk[e] : e];
+        sum += k > 0 ? (k + 3) / 4 : 0;
+    }
+    steps[tb] = int32_t(sum);
+}
+
 }  // namespace
+
+int32_t *s2_ring_steps(Plan &P, int l, bool adjoint, hipStream_t s) {
+    const int64_t nbox = pow8(l);
+    int32_t *out = P.mem.alloc_n<int32_t>(std::max<int64_t>(nbox, 1));
+    k_s2_steps<<<grid_for(nbox, 256), 256, 0, s>>>(nbox, P.box_base[l], P.tgt_begin,
+                                                  adjoint ? P.src_blk : nullptr, P.blk_rank, out);
+    H3D_LAUNCH_CHECK();
+    return out;
+}
 
 void launch_s2_ring(Plan &P, int l, bool adjoint, const int2 *items, int64_t nitems,
                     const float *Z, int NP, double *Y, hipStream_t s) {
@@ -218,11 +263,12 @@ void launch_s2_ring(Plan &P, int l, bool adjoint, const int2 *items, int64_t nit
     const int panel = int(!adjoint && l < P.chunk_level);
     const int64_t *gblk = adjoint ? P.src_blk : nullptr;
     void *const *fp = adjoint ? P.blk_vptr : P.blk_uptr;
+    const int32_t *steps = P.bt_s2k[l][adjoint ? 1 : 0];
     const int shc = 3 * (P.L - P.chunk_level);
 #define H3D_S2R(DT)                                                                             \
-    k_s2_ring<DT, 8><<<int(nitems), 64, 0, s>>>(items, nitems, P.box_base[l], P.leaf_off,        \
-                                                3 * (P.L - l), P.tgt_begin, gblk, fp, P.blk_rank, \
-                                                P.blk_col0, Z, NP, Y, panel, P.leaf_of, shc)
+    k_s2_ring<DT, 8><<<int((nitems + 3) / 4), 256, 0, s>>>(                                     \
+        items, nitems, P.box_base[l], P.leaf_off, 3 * (P.L - l), P.tgt_begin, gblk, fp,          \
+        P.blk_rank, P.blk_col0, steps, Z, NP, Y, panel, P.leaf_of, shc)
     if (P.factor_dtype == H3D_F32)
         H3D_S2R(H3D_F32);
     else
