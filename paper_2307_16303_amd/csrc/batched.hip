@@ -292,310 +292,6 @@ __global__ void __launch_bounds__(64)
     }
 }
 
-// ---------------------------------------------------------------------------
-// stage 2 of one level: one wave per (box, 16-row tile); Y updated in place
-template <int DT>
-__global__ void __launch_bounds__(64)
-    k_s2_mfma(const int2 *__restrict__ items, int64_t nitems, int64_t gbase,
-              const int32_t *__restrict__ leaf_off, int sh, const int64_t *__restrict__ grp_begin,
-              const int64_t *__restrict__ grp_blk, void *const *__restrict__ fptr,
-              const int32_t *__restrict__ rank, const int64_t *__restrict__ blk_col0,
-              const typename CT<DT>::T *__restrict__ Z, int NP, double *__restrict__ Y, int panel,
-              const int32_t *__restrict__ leaf_of, int shc) {
-    using C = CT<DT>;
-    using T = typename C::T;
-    using F = typename FacB<DT>::T;
-    __shared__ int32_t s_bk[64];
-    __shared__ int64_t s_bc[64];
-    __shared__ const F *s_bp[64];
-    const int64_t w = blockIdx.x;
-    if (w >= nitems)
-        return;
-    const int lane = threadIdx.x;
-    const int2 it = items[w];
-    const int64_t tb = it.x;
-    const int32_t bs = leaf_off[tb << sh], bm = leaf_off[(tb + 1) << sh] - bs;
-    const int r0 = it.y * 16;
-    const int ia = r0 + (lane & 15);  // A row (box row) of this lane
-    const bool ar = ia < bm;
-    const int iac = min(ia, bm - 1);  // a row of the box, for unmasked loads
-    // row panels (forward above the chunk level): this row's chunk box
-    int32_t pr0 = bs, pld = bm;
-    if (panel) {
-        const int32_t ch = leaf_of[bs + iac] >> shc;
-        pr0 = leaf_off[ch << shc];
-        pld = leaf_off[(ch + 1) << shc] - pr0;
-    }
-    const int64_t e0 = grp_begin[gbase + tb], e1 = grp_begin[gbase + tb + 1];
-    for (int nb = 0; nb < NP; nb += 16 * kNT) {
-        const int ntl = min(kNT, (NP - nb) / 16);
-        double acc64[kNT][4];
-#pragma unroll
-        for (int q = 0; q < kNT; ++q)
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-                const int r = r0 + C::row(lane, jj);
-                acc64[q][jj] = (q < ntl && r < bm) ? Y[(bs + r) * int64_t(NP) + nb + 16 * q + (lane & 15)] : 0.0;
-            }
-        for (int64_t q0 = e0; q0 < e1; q0 += 64) {
-            // metadata of the box's next 64 blocks, staged in LDS
-            const int nbk = int(min<int64_t>(64, e1 - q0));
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (lane < nbk) {
-                const int64_t bj = grp_blk ? grp_blk[q0 + lane] : q0 + lane;
-                s_bk[lane] = rank[bj];
-                s_bc[lane] = blk_col0[bj];
-                s_bp[lane] = static_cast<const F *>(fptr[bj]);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            for (int ib = 0; ib < nbk; ++ib) {
-                const int k = s_bk[ib];
-                const int64_t col0 = s_bc[ib];
-                typename C::V4 acc[kNT];
-#pragma unroll
-                for (int q = 0; q < kNT; ++q)
-                    acc[q] = typename C::V4{0, 0, 0, 0};
-                if constexpr (DT == H3D_F64) {
-                    const F *__restrict__ p = s_bp[ib] + (int64_t(pr0 - bs) * k + (bs + ia - pr0));
-                    for (int c0 = 0; c0 < k; c0 += 4) {
-                        const int c = c0 + (lane >> 4);
-                        const bool ak = c < k;
-                        const T a = (ar && ak) ? T(FacB<DT>::ld(p + int64_t(c) * pld)) : T(0);
-                        T bv[kNT];
-#pragma unroll
-                        for (int q = 0; q < kNT; ++q)
-                            bv[q] = (ak && q < ntl) ? Z[(col0 + c) * NP + nb + 16 * q + (lane & 15)] : T(0);
-#pragma unroll
-                        for (int q = 0; q < kNT; ++q)
-                            if (q < ntl)
-                                acc[q] = C::mfma(a, bv[q], acc[q]);
-                    }
-                } else if (k > 0) {
-                    // FP32/BF16 tiles (measured: slower with FP64 tiles, whose
-                    // fragments take twice the registers): every load from a column
-                    // of the block and a tile of the RHS, raw values masked where
-                    // they are used, and the fragments of the next K-step loaded
-                    // while the current one runs
-                    const F *__restrict__ p = s_bp[ib] + (int64_t(pr0 - bs) * k + (bs + iac - pr0));
-                    auto frag = [&](int c0, T &a, T (&bv)[kNT]) {
-                        const int cc = min(c0 + (lane >> 4), k - 1);
-                        a = T(FacB<DT>::ld(p + int64_t(cc) * pld));
-#pragma unroll
-                        for (int q = 0; q < kNT; ++q)
-                            bv[q] = Z[(col0 + cc) * NP + nb + 16 * min(q, ntl - 1) + (lane & 15)];
-                    };
-                    auto step = [&](int c0, const T ra, const T (&rb)[kNT]) {
-                        const bool ak = c0 + (lane >> 4) < k;
-                        const T a = (ar && ak) ? ra : T(0);
-#pragma unroll
-                        for (int q = 0; q < kNT; ++q)
-                            acc[q] = C::mfma(a, (ak && q < ntl) ? rb[q] : T(0), acc[q]);
-                    };
-                    T a0, b0[kNT], a1, b1[kNT];
-                    frag(0, a0, b0);
-                    for (int c0 = 0; c0 < k; c0 += 8) {
-                        if (c0 + 4 < k)
-                            frag(c0 + 4, a1, b1);
-                        step(c0, a0, b0);
-                        if (c0 + 4 >= k)
-                            break;
-                        if (c0 + 8 < k)
-                            frag(c0 + 8, a0, b0);
-                        step(c0 + 4, a1, b1);
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < kNT; ++q)
-#pragma unroll
-                    for (int jj = 0; jj < 4; ++jj)
-                        acc64[q][jj] += double(acc[q][jj]);
-        
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < kNT; ++q)
-            if (q < ntl)
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    const int r = r0 + C::row(lane, jj);
-                    if (r < bm)
-                        Y[(bs + r) * int64_t(NP) + nb + 16 * q + (lane & 15)] = acc64[q][jj];
-                }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Wide forms.  A wave holds MT 16-row (stage 2) or 16-column (stage 1) tiles
-// against the kNT 16-wide RHS tiles, so every B fragment loaded (a row of Z
-// or X, shared by all rows or columns of the block) feeds MT MFMAs; FP32
-// tiles are flushed into FP64 every 64 K-steps.
-
-// stage 2 of one level: one wave per (box, 16 MT-row tile); the K loop runs
-// over the columns of all blocks of the box; Y updated in place
-template <int DT, int MT>
-__global__ void __launch_bounds__(64)
-    k_s2_mfma_w(const int2 *__restrict__ items, int64_t nitems, int64_t gbase,
-                const int32_t *__restrict__ leaf_off, int sh, const int64_t *__restrict__ grp_begin,
-                const int64_t *__restrict__ grp_blk, void *const *__restrict__ fptr,
-                const int32_t *__restrict__ rank, const int64_t *__restrict__ blk_col0,
-                const typename CT<DT>::T *__restrict__ Z, int NP, double *__restrict__ Y, int panel,
-                const int32_t *__restrict__ leaf_of, int shc) {
-    using C = CT<DT>;
-    using T = typename C::T;
-    using F = typename FacB<DT>::T;
-    __shared__ int32_t s_bk[64];
-    __shared__ int64_t s_bc[64];
-    __shared__ const F *s_bp[64];
-    const int64_t w = blockIdx.x;
-    if (w >= nitems)
-        return;
-    const int lane = threadIdx.x;
-    const int2 it = items[w];
-    const int64_t tb = it.x;
-    const int32_t bs = leaf_off[tb << sh], bm = leaf_off[(tb + 1) << sh] - bs;
-    const int r0 = it.y * 16 * MT;
-    // ia: the lane's row of tile t; iac: that row clamped into the box, which
-    // every load addresses (rows past the box are masked where used)
-    int ia[MT], iac[MT];
-    bool ar[MT];
-    int32_t pr0[MT], pld[MT];
-#pragma unroll
-    for (int t = 0; t < MT; ++t) {
-        ia[t] = r0 + 16 * t + (lane & 15);
-        ar[t] = ia[t] < bm;
-        iac[t] = min(ia[t], bm - 1);
-        pr0[t] = bs;
-        pld[t] = bm;
-        if (panel) {  // row panels: this row's chunk box
-            const int32_t ch = leaf_of[bs + iac[t]] >> shc;
-            pr0[t] = leaf_off[ch << shc];
-            pld[t] = leaf_off[(ch + 1) << shc] - pr0[t];
-        }
-    }
-    const int64_t e0 = grp_begin[gbase + tb], e1 = grp_begin[gbase + tb + 1];
-    for (int nb = 0; nb < NP; nb += 16 * kNT) {
-        const int ntl = min(kNT, (NP - nb) / 16);
-        // FP64 tiles accumulate in place from Y; FP32 tiles are flushed into acc64
-        constexpr int A64 = DT == H3D_F64 ? 1 : MT;
-        double acc64[A64][kNT][4];
-        typename C::V4 acc[MT][kNT];
-#pragma unroll
-        for (int t = 0; t < MT; ++t)
-#pragma unroll
-            for (int q = 0; q < kNT; ++q)
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    const int r = r0 + 16 * t + C::row(lane, jj);
-                    const double y0 = (q < ntl && r < bm)
-                                          ? Y[(bs + r) * int64_t(NP) + nb + 16 * q + (lane & 15)]
-                                          : 0.0;
-                    if constexpr (DT == H3D_F64) {
-                        acc[t][q][jj] = y0;
-                    } else {
-                        acc[t][q][jj] = 0.0f;
-                        acc64[t][q][jj] = y0;
-                    }
-                }
-        int steps = 0;
-        for (int64_t q0 = e0; q0 < e1; q0 += 64) {
-            // metadata of the box's next 64 blocks, staged in LDS
-            const int nbk = int(min<int64_t>(64, e1 - q0));
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (lane < nbk) {
-                const int64_t bj = grp_blk ? grp_blk[q0 + lane] : q0 + lane;
-                s_bk[lane] = rank[bj];
-                s_bc[lane] = blk_col0[bj];
-                s_bp[lane] = static_cast<const F *>(fptr[bj]);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            for (int ib = 0; ib < nbk; ++ib) {
-                const int k = s_bk[ib];
-                const int64_t col0 = s_bc[ib];
-                const F *__restrict__ base = s_bp[ib];
-                if (k <= 0)
-                    continue;
-                const F *p[MT];
-#pragma unroll
-                for (int t = 0; t < MT; ++t)
-                    p[t] = base + (int64_t(pr0[t] - bs) * k + (bs + iac[t] - pr0[t]));
-                // a ring of D K-steps of the block's fragments in flight: every
-                // load from a row clamped into the box, a column clamped into the
-                // block and a tile clamped into the RHS, masked where the MFMA
-                // uses it, so the sums are those of one K-step at a time
-                constexpr int D = 2;
-                auto frag = [&](int cs, T (&a)[MT], T (&bv)[kNT]) {
-                    const int cc = min(cs + (lane >> 4), k - 1);
-#pragma unroll
-                    for (int t = 0; t < MT; ++t)
-                        a[t] = T(FacB<DT>::ld(p[t] + int64_t(cc) * pld[t]));
-#pragma unroll
-                    for (int q = 0; q < kNT; ++q)
-                        bv[q] = Z[(col0 + cc) * NP + nb + 16 * min(q, ntl - 1) + (lane & 15)];
-                };
-                T ab[D][MT], bb[D][kNT];
-#pragma unroll
-                for (int d = 0; d < D; ++d)
-                    frag(4 * d, ab[d], bb[d]);
-                for (int c0 = 0; c0 < k; c0 += 4 * D) {
-#pragma unroll
-                    for (int d = 0; d < D; ++d) {
-                        const int cs = c0 + 4 * d;
-                        if (cs >= k)
-                            break;
-                        const bool ak = cs + (lane >> 4) < k;
-#pragma unroll
-                        for (int t = 0; t < MT; ++t) {
-                            const T a = (ar[t] && ak) ? ab[d][t] : T(0);
-#pragma unroll
-                            for (int q = 0; q < kNT; ++q)  // tiles past the RHS: 0
-                                acc[t][q] = C::mfma(a, (ak && q < ntl) ? bb[d][q] : T(0), acc[t][q]);
-                        }
-                        if (cs + 4 * D < k)
-                            frag(cs + 4 * D, ab[d], bb[d]);
-                        if constexpr (DT != H3D_F64) {
-                            if (++steps == 64) {
-                                steps = 0;
-#pragma unroll
-                                for (int t = 0; t < MT; ++t)
-#pragma unroll
-                                    for (int q = 0; q < kNT; ++q) {
-#pragma unroll
-                                        for (int jj = 0; jj < 4; ++jj)
-                                            acc64[t][q][jj] += double(acc[t][q][jj]);
-                                        acc[t][q] = typename C::V4{0, 0, 0, 0};
-                                    }
-                            }
-                        }
-                    }
-                }
-        
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < MT; ++t)
-#pragma unroll
-            for (int q = 0; q < kNT; ++q)
-                if (q < ntl)
-#pragma unroll
-                    for (int jj = 0; jj < 4; ++jj) {
-                        const int r = r0 + 16 * t + C::row(lane, jj);
-                        double v = double(acc[t][q][jj]);
-                        if constexpr (DT != H3D_F64)
-                            v += acc64[t][q][jj];
-                        if (r < bm)
-                            Y[(bs + r) * int64_t(NP) + nb + 16 * q + (lane & 15)] = v;
-                    }
-    }
-}
-
 // stage 1: one wave per (block, 16 MT-column tile of its factor)
 template <int DT, int MT>
 __global__ void __launch_bounds__(64)
@@ -1126,15 +822,7 @@ int tiles_for(int v, int dt) {
     return v >= 48 ? 4 : (v >= 24 ? 2 : 1);
 }
 
-// stage 2, FP64 tiles: two 16-row tiles per wave for boxes of 24 or more
-// points (measured on 262,144 points, 64 RHS, levels 2-4: 2.16 / 4.10 /
-// 4.54 ms with two tiles, 2.44 / 4.41 / 5.17 with four, 2.95 / 5.22 / 6.53
-// with one)
-int tiles_s2(int box, int dt) {
-    return tiles_for(box, dt) > 1 ? 2 : 1;
-}
-
-// FP32/BF16 levels whose columns would be split take the ring kernel instead
+// Levels whose columns would be split take the ring kernel instead
 // when it has at least this many items (four per SIMD)
 constexpr int64_t kRingMinItems = 4096;
 
@@ -1149,7 +837,6 @@ void ensure_batched_tables(Plan &P, hipStream_t s) {
     for (int l = 1; l <= L; ++l) {
         const int64_t nbl = P.lvl_blk[l + 1] - P.lvl_blk[l];
         const int mean_rank = nbl > 0 ? int(P.lvl_rank_sum[l] / nbl) : 0;
-        P.bt_mt2[l] = tiles_s2(P.mean_box[l], P.factor_dtype);
         // (split items keep the tile index in 8 bits)
         P.bt_split[l] =
             (P.mean_box[l] > kMfmaSplitBox && P.stats.rank_max < 255 * 16) ? kMfmaSplitRows : 0;
@@ -1205,11 +892,11 @@ void ensure_batched_tables(Plan &P, hipStream_t s) {
             P.bt_s1[l] = make_items(P, nb, b0, cnt, &P.bt_ns1[l], s);
             P.mem.release(cnt);
         }
-        if (nb > 0 && P.factor_dtype != H3D_F64) {
-            // the ring kernel's items: (block, 16 MT columns), blocks in level
+        if (nb > 0) {
+            // the ring kernels' items: (block, 16 MT columns), blocks in level
             // order (grouped by target box: the adjoint's rows of X) and in
-            // source order (the forward's)
-            const int cols = 16 * s1_ring_tiles(P, l);
+            // source order (the forward's); FP64 tiles two columns wide
+            const int cols = P.factor_dtype == H3D_F64 ? 32 : 16 * s1_ring_tiles(P, l);
             for (int dir = 0; dir < 2; ++dir) {
                 const int64_t *perm = dir == 0 ? P.src_blk : nullptr;
                 int64_t *cnt4 = P.mem.alloc_n<int64_t>(nb + 1);
@@ -1227,16 +914,9 @@ void ensure_batched_tables(Plan &P, hipStream_t s) {
                 P.bt_ns1r[l][dir] = cnt_items;
             }
         }
-        // stage 2: (box, row tile) for the boxes of level l
+        // stage 2: (box, 64-row tile) for the boxes of level l
         const int64_t nbox = pow8(l);
-        int64_t *cnt = P.mem.alloc_n<int64_t>(nbox + 1);
-        k_cnt_rowtiles<<<grid_for(nbox, 256), 256, 0, s>>>(nbox, 3 * (L - l), P.leaf_off,
-                                                          16 * P.bt_mt2[l], cnt);
-        H3D_LAUNCH_CHECK();
-        P.bt_s2[l] = make_items(P, nbox, 0, cnt, &P.bt_ns2[l], s);
-        P.mem.release(cnt);
-        if (P.factor_dtype != H3D_F64) {
-            // the ring kernel's items: (box, 64-row tile)
+        {
             int64_t *cnt4 = P.mem.alloc_n<int64_t>(nbox + 1);
             k_cnt_rowtiles<<<grid_for(nbox, 256), 256, 0, s>>>(nbox, 3 * (L - l), P.leaf_off, 64,
                                                               cnt4);
@@ -1245,6 +925,10 @@ void ensure_batched_tables(Plan &P, hipStream_t s) {
             P.mem.release(cnt4);
             P.bt_s2k[l][0] = s2_ring_steps(P, l, false, s);
             P.bt_s2k[l][1] = s2_ring_steps(P, l, true, s);
+            if (P.factor_dtype == H3D_BF16_SCALED)
+                P.bt_s2k16[l] = s2_bf16_steps(P, l, s);
+            if (l < P.chunk_level)
+                P.bt_pk[l] = panel_steps(P, l, s);
         }
     }
     P.bt_ready = true;
@@ -1265,11 +949,22 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
     for (int l = 1; l <= P.L; ++l)
         if (P.bt_split[l] > 0 && P.bt_ns1[l] > 0)
             need_zp = std::max(need_zp, size_t(P.bt_ns1[l]) * 16 * P.bt_mt1[l] * NP * sizeof(T));
+    // forward products with BF16 factors run the far field on the BF16 matrix
+    // cores, with x split into BF16 hi/lo words
+    const bool bf16mc = DT == H3D_BF16_SCALED && !adjoint;
+    const size_t need_xh = bf16mc ? size_t(n) * NP * sizeof(uint32_t) : 0;
     // every buffer is grown before the first launch of the product
     if (need_x > P.bx_bytes || need_y > P.by_bytes || need_z > P.bz_bytes ||
-        need_zp > P.bzp_bytes) {
-        if (P.bx || P.bzp)
+        need_zp > P.bzp_bytes || need_xh > P.bxh_bytes) {
+        if (P.bx || P.bzp || P.bxh)
             before_release(P, "a product with more right-hand sides");
+        if (need_xh > P.bxh_bytes) {
+            P.mem.release(P.bxh);
+            P.bxh = nullptr;
+            P.bxh_bytes = 0;
+            P.bxh = P.mem.alloc(need_xh);
+            P.bxh_bytes = need_xh;
+        }
         if (need_x > P.bx_bytes || need_y > P.by_bytes || need_z > P.bz_bytes) {
             P.mem.release(P.bx);
             P.mem.release(P.by);
@@ -1303,6 +998,17 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
         H3D_LAUNCH_CHECK();
         P.prof.end(s, ev, "k_gather_pm", double(n) * (4.0 + (io_f32 ? 4 : 8) * nrhs + sizeof(T) * NP), 0.0);
     }
+    // a level's far field runs on the BF16 matrix cores when its stage-1
+    // items fill the GPU (the few long columns of the coarsest levels take
+    // the FP32 row-split kernels; a level's z is written and read in one form)
+    auto bf16_level = [&](int l) { return P.bt_ns1r[l][0] >= kRingMinItems; };
+    uint32_t *Xh = static_cast<uint32_t *>(P.bxh);
+    uint32_t *Zh = reinterpret_cast<uint32_t *>(P.bz);
+    if (bf16mc) {
+        hipEvent_t ev = P.prof.begin(s);
+        launch_split_x(reinterpret_cast<const float *>(Xs), n * NP, Xh, s);
+        P.prof.end(s, ev, "k_split_x", double(n) * NP * 8.0, 0.0);
+    }
     {
         hipEvent_t ev = P.prof.begin(s);
         if (P.bt_nnear > 0)
@@ -1321,8 +1027,7 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
     const int lfuse = (adjoint || P.mean_box[P.L] > kLeafRows) ? 0 : P.L;
     // larger leaves (FP32/BF16 factors): both stages per leaf with z kept in
     // registers (k_leaf_fused)
-    const int lfused = (!adjoint && DT != H3D_F64 && lfuse == 0 && P.L >= 1 &&
-                        leaf_fused_tables(P, s))
+    const int lfused = (DT != H3D_F64 && lfuse == 0 && P.L >= 1 && leaf_fused_tables(P, s))
                            ? P.L
                            : 0;
     for (int l = 1; l <= P.L; ++l) {
@@ -1340,9 +1045,15 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
         // the ring kernel wherever its items fill the GPU; the few long
         // columns of the coarsest levels keep the row-split kernels
         const int dir = adjoint ? 1 : 0;
-        const bool ring =
-            DT != H3D_F64 && (P.bt_split[l] == 0 || P.bt_ns1r[l][dir] >= kRingMinItems);
-        if (ring)
+        const bool ring = P.bt_split[l] == 0 || P.bt_ns1r[l][dir] >= kRingMinItems;
+        if (DT == H3D_F64 && ring)
+            launch_s1_ring64(P, l, adjoint, reinterpret_cast<const int2 *>(P.bt_s1r[l][dir]),
+                             P.bt_ns1r[l][dir], reinterpret_cast<const double *>(Xs), NP,
+                             reinterpret_cast<double *>(Z), s);
+        else if (bf16mc && bf16_level(l))
+            launch_s1_bf16(P, l, reinterpret_cast<const int2 *>(P.bt_s1r[l][0]), P.bt_ns1r[l][0], Xh,
+                           NP, Zh, s);
+        else if (ring)
             launch_s1_ring(P, l, adjoint, reinterpret_cast<const int2 *>(P.bt_s1r[l][dir]),
                            P.bt_ns1r[l][dir], reinterpret_cast<const float *>(Xs), NP,
                            reinterpret_cast<float *>(Z), s);
@@ -1360,7 +1071,7 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
                 int(adjoint && l < P.chunk_level), P.leaf_off, P.leaf_of,
                 3 * (P.L - P.chunk_level));
 #undef H3D_S1M
-        if (!ring && P.bt_split[l] > 0) {
+        if (!(bf16mc && bf16_level(l)) && !ring && P.bt_split[l] > 0) {
             H3D_LAUNCH_CHECK();
             const int cols = 16 * P.bt_mt1[l];
             const int64_t nt = P.bt_ngrp[l] * cols * NP;
@@ -1371,38 +1082,35 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
         H3D_LAUNCH_CHECK();
         const double ent = double(adjoint ? P.lvl_entries_u[l] : P.lvl_entries_v[l]);
         char name[48];
-        snprintf(name, sizeof(name), P.prof.levels ? "k_s1_mfma_L%d" : "k_s1_mfma", l);
+        if (bf16mc && bf16_level(l))
+            snprintf(name, sizeof(name), P.prof.levels ? "k_s1_bf16_L%d" : "k_s1_bf16", l);
+        else
+            snprintf(name, sizeof(name), P.prof.levels ? "k_s1_mfma_L%d" : "k_s1_mfma", l);
         P.prof.end(s, ev, name, ent * es + double(P.lvl_rank_sum[l]) * sizeof(T) * NP,
                    2.0 * ent * NP);
     }
     for (int l = 1; l <= P.L; ++l) {
-        if (P.bt_ns2[l] == 0 || P.lvl_blk[l + 1] <= P.lvl_blk[l] || l == lfuse || l == lfused)
+        if (P.bt_ns2r[l] == 0 || P.lvl_blk[l + 1] <= P.lvl_blk[l] || l == lfuse || l == lfused)
             continue;
         hipEvent_t ev = P.prof.begin(s);
         if constexpr (DT != H3D_F64) {
-            launch_s2_ring(P, l, adjoint, reinterpret_cast<const int2 *>(P.bt_s2r[l]),
-                           P.bt_ns2r[l], reinterpret_cast<const float *>(Z), NP, Y, s);
+            if (bf16mc && bf16_level(l))
+                launch_s2_bf16(P, l, reinterpret_cast<const int2 *>(P.bt_s2r[l]), P.bt_ns2r[l], Zh,
+                               NP, Y, s);
+            else
+                launch_s2_ring(P, l, adjoint, reinterpret_cast<const int2 *>(P.bt_s2r[l]),
+                               P.bt_ns2r[l], reinterpret_cast<const float *>(Z), NP, Y, s);
         } else {
-#define H3D_S2M(MT)                                                                         \
-    k_s2_mfma_w<DT, MT><<<int(P.bt_ns2[l]), 64, 0, s>>>(                                    \
-        reinterpret_cast<const int2 *>(P.bt_s2[l]), P.bt_ns2[l], P.box_base[l], P.leaf_off,   \
-        3 * (P.L - l), P.tgt_begin, adjoint ? P.src_blk : nullptr,                           \
-        adjoint ? P.blk_vptr : P.blk_uptr, P.blk_rank, P.blk_col0, Z, NP, Y,                 \
-        int(!adjoint && l < P.chunk_level), P.leaf_of, 3 * (P.L - P.chunk_level))
-        if (P.bt_mt2[l] == 2)
-            H3D_S2M(2);
-        else
-            k_s2_mfma<DT><<<int(P.bt_ns2[l]), 64, 0, s>>>(
-                reinterpret_cast<const int2 *>(P.bt_s2[l]), P.bt_ns2[l], P.box_base[l],
-                P.leaf_off, 3 * (P.L - l), P.tgt_begin, adjoint ? P.src_blk : nullptr,
-                adjoint ? P.blk_vptr : P.blk_uptr, P.blk_rank, P.blk_col0, Z, NP, Y,
-                int(!adjoint && l < P.chunk_level), P.leaf_of, 3 * (P.L - P.chunk_level));
-#undef H3D_S2M
+            launch_s2_ring64(P, l, adjoint, reinterpret_cast<const int2 *>(P.bt_s2r[l]),
+                             P.bt_ns2r[l], reinterpret_cast<const double *>(Z), NP, Y, s);
         }
         H3D_LAUNCH_CHECK();
         const double ent = double(adjoint ? P.lvl_entries_v[l] : P.lvl_entries_u[l]);
         char name2[48];
-        snprintf(name2, sizeof(name2), P.prof.levels ? "k_s2_mfma_L%d" : "k_s2_mfma", l);
+        if (bf16mc && bf16_level(l))
+            snprintf(name2, sizeof(name2), P.prof.levels ? "k_s2_bf16_L%d" : "k_s2_bf16", l);
+        else
+            snprintf(name2, sizeof(name2), P.prof.levels ? "k_s2_mfma_L%d" : "k_s2_mfma", l);
         P.prof.end(s, ev, name2,
                    ent * es + double(P.lvl_rank_sum[l]) * sizeof(T) * NP + double(n) * 16.0 * NP,
                    2.0 * ent * NP);
@@ -1424,7 +1132,7 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
         if (lfused >= 1 && P.lvl_blk[lfused + 1] > P.lvl_blk[lfused]) {
             const int l = lfused;
             hipEvent_t ev = P.prof.begin(s);
-            launch_leaf_fused(P, reinterpret_cast<const float *>(Xs), NP, Y, s);
+            launch_leaf_fused(P, reinterpret_cast<const float *>(Xs), NP, Y, adjoint, s);
             const double ent = double(P.lvl_entries_u[l] + P.lvl_entries_v[l]);
             char name[48];
             snprintf(name, sizeof(name), P.prof.levels ? "k_leaf_fused_L%d" : "k_leaf_fused", l);

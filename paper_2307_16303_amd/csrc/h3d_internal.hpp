@@ -306,8 +306,6 @@ struct Plan {
     int64_t bt_nnear = 0;
     int32_t *bt_s1[kMaxLevels + 1] = {};
     int64_t bt_ns1[kMaxLevels + 1] = {};
-    int32_t *bt_s2[kMaxLevels + 1] = {};
-    int64_t bt_ns2[kMaxLevels + 1] = {};
     // FP32/BF16 stage 1: (block, column tile group), blocks in source order
     // (forward) and in level order (adjoint)
     int32_t *bt_s1r[kMaxLevels + 1][2] = {};
@@ -315,8 +313,9 @@ struct Plan {
     int32_t *bt_s2r[kMaxLevels + 1] = {};  // FP32/BF16 stage 2: (box, 64-row tile)
     int64_t bt_ns2r[kMaxLevels + 1] = {};
     int32_t *bt_s2k[kMaxLevels + 1][2] = {};  // K-steps per box of the ring kernel (fwd, adj)
+    int32_t *bt_s2k16[kMaxLevels + 1] = {};    // BF16 stage 2: K-steps of 16 columns per box
+    int32_t *bt_pk[kMaxLevels + 1] = {};  // adjoint stage 1 above the chunk level: K-steps per box
     int bt_mt1[kMaxLevels + 1] = {};  // 16-column tiles per stage-1 wave
-    int bt_mt2[kMaxLevels + 1] = {};  // 16-row tiles per stage-2 wave
     int bt_split[kMaxLevels + 1] = {};  // stage-1 rows per part (0: columns not split)
     int32_t *bt_grp[kMaxLevels + 1] = {};  // split levels: (first item, parts) per tile
     int64_t bt_ngrp[kMaxLevels + 1] = {};
@@ -329,6 +328,8 @@ struct Plan {
     int64_t lf_n[4] = {};
     void *bx = nullptr, *by = nullptr, *bz = nullptr;
     size_t bx_bytes = 0, by_bytes = 0, bz_bytes = 0;
+    void *bxh = nullptr;  // BF16 factors: x as BF16 hi/lo words (bf16_mfma.hip)
+    size_t bxh_bytes = 0;
 
     Profiler prof;
     bool built = false;
@@ -457,11 +458,25 @@ void launch_s1_ring(Plan &P, int l, bool adjoint, const int2 *items, int64_t nit
                     const float *Xs, int NP, float *Z, hipStream_t s);
 // stage 2 of one level, FP32/BF16 factors, one wave per (box, 64-row tile)
 // with a ring of fragment loads across the box's blocks (stage2_ring.hip)
+// FP64 matrix-core ring kernels (stage_ring64.hip)
+void launch_s1_ring64(Plan &P, int l, bool adjoint, const int2 *items, int64_t nitems,
+                      const double *Xs, int NP, double *Z, hipStream_t s);
+void launch_s2_ring64(Plan &P, int l, bool adjoint, const int2 *items, int64_t nitems,
+                      const double *Z, int NP, double *Y, hipStream_t s);
+// BF16 matrix-core stages (forward products with BF16 factors)
+int32_t *s2_bf16_steps(Plan &P, int l, hipStream_t s);
+void launch_split_x(const float *Xs, int64_t count, uint32_t *Xh, hipStream_t s);
+void launch_s1_bf16(Plan &P, int l, const int2 *items, int64_t nitems, const uint32_t *Xh, int NP,
+                    uint32_t *Zh, hipStream_t s);
+void launch_s2_bf16(Plan &P, int l, const int2 *items, int64_t nitems, const uint32_t *Zh, int NP,
+                    double *Y, hipStream_t s);
+// per box of level l (above the chunk level), the K-steps of its row panels
+int32_t *panel_steps(Plan &P, int l, hipStream_t s);
 // per box of level l, the K-steps of its blocks in the stage-2 ring kernel
 int32_t *s2_ring_steps(Plan &P, int l, bool adjoint, hipStream_t s);
 void launch_s2_ring(Plan &P, int l, bool adjoint, const int2 *items, int64_t nitems,
                     const float *Z, int NP, double *Y, hipStream_t s);
-void launch_leaf_fused(Plan &P, const float *Xs, int NP, double *Y, hipStream_t s);
+void launch_leaf_fused(Plan &P, const float *Xs, int NP, double *Y, bool adjoint, hipStream_t s);
 // the pivot + LU form (lu_form.hip)
 constexpr int kLuSlots = 4;                // 64-row register slots of the in-wave solves
 constexpr int kLuMaxRank = 64 * kLuSlots;  // largest rank the form takes

@@ -28,6 +28,10 @@
 // group of 64, so a lane's four X values and four outputs of a row are
 // contiguous.
 //
+// The adjoint is the same product with U and V exchanged: the blocks of a
+// source leaf (through the source-grouped block table), stage 1 over the
+// target rows with U_b, stage 2 into the source leaf's rows with V_b.
+//
 // One wave per leaf; leaves grouped by their 16-row tile count MT, one launch
 // per group (a block's rank is at most its leaf's row count, so it has at
 // most MT column tiles).  Every load is issued from indices clamped into the
@@ -52,10 +56,6 @@ template <> struct LFac<H3D_BF16_SCALED> {
     }
 };
 
-template <typename T> __device__ __forceinline__ T cload(const T *p) {
-    return *(const __attribute__((address_space(4))) T *)p;
-}
-
 __device__ __forceinline__ f4 mma(float a, float b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
@@ -75,13 +75,14 @@ template <int DT, int MT>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LfShape<MT>::W)))
     k_leaf_fused(const int32_t *__restrict__ items, int64_t nitems, int64_t gbase,
                  const int32_t *__restrict__ leaf_off, const int64_t *__restrict__ grp_begin,
+                 const int64_t *__restrict__ grp_blk,
                  void *const *__restrict__ uptr, void *const *__restrict__ vptr,
                  const int32_t *__restrict__ rank, const int32_t *__restrict__ soff,
                  const int32_t *__restrict__ slen, const float *__restrict__ scale2,
                  const float *__restrict__ Xs, int NP, double *__restrict__ Y) {
     using F = typename LFac<DT>::T;
     constexpr int D = LfShape<MT>::D, UP = LfShape<MT>::UP;
-    const int64_t w = blockIdx.x;
+    const int64_t w = dev::xcd_run(blockIdx.x, gridDim.x);  // neighbouring leaves share sources
     if (w >= nitems)
         return;
     const int lane = threadIdx.x;
@@ -101,16 +102,19 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LfShape
         int k, n;
         int64_t so;
         const F *V, *U;
+        int64_t id;
     };
     auto load = [&](int64_t b) {
-        return Blk{cload(rank + b), cload(slen + b), int64_t(cload(soff + b)),
-                   static_cast<const F *>(cload(vptr + b)), static_cast<const F *>(cload(uptr + b))};
+        const int64_t bj = grp_blk ? dev::cload(grp_blk + b) : b;
+        return Blk{dev::cload(rank + bj), dev::cload(slen + bj), int64_t(dev::cload(soff + bj)),
+                   static_cast<const F *>(dev::cload(vptr + bj)), static_cast<const F *>(dev::cload(uptr + bj)),
+                   bj};
     };
     // stage-1 steps of a block padded to a multiple of D
     auto padded = [](int n) { return (((n + 3) >> 2) + D - 1) / D * D; };
     // first block of nonzero rank at or after b (e1 if none)
     auto skip = [&](int64_t b) {
-        while (b < e1 && cload(rank + b) <= 0)
+        while (b < e1 && dev::cload(rank + (grp_blk ? dev::cload(grp_blk + b) : b)) <= 0)
             ++b;
         return b;
     };
@@ -221,7 +225,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LfShape
             for (int s0 = D; s0 < S1p; s0 += D)
                 chunk(s0);
             if constexpr (DT == H3D_BF16_SCALED) {
-                const float sc = scale2[2 * cb] * scale2[2 * cb + 1];
+                const float sc = scale2[2 * cc.id] * scale2[2 * cc.id + 1];
 #pragma unroll
                 for (int T = 0; T < MT; ++T)
 #pragma unroll
@@ -326,12 +330,19 @@ bool leaf_fused_tables(Plan &P, hipStream_t s) {
     return true;
 }
 
-void launch_leaf_fused(Plan &P, const float *Xs, int NP, double *Y, hipStream_t s) {
+void launch_leaf_fused(Plan &P, const float *Xs, int NP, double *Y, bool adjoint, hipStream_t s) {
     const int l = P.L;
+    // the adjoint: blocks taken by source leaf, U and V exchanged, the rows of
+    // stage 1 in the target leaf
+    const int64_t *gblk = adjoint ? P.src_blk : nullptr;
+    void *const *p1 = adjoint ? P.blk_uptr : P.blk_vptr;  // stage-1 factor (K over its rows)
+    void *const *p2 = adjoint ? P.blk_vptr : P.blk_uptr;  // stage-2 factor (the leaf's rows)
+    const int32_t *off1 = adjoint ? P.blk_toff : P.blk_soff;
+    const int32_t *len1 = adjoint ? P.blk_m : P.blk_n;
 #define H3D_LF(DT, MT)                                                                          \
     k_leaf_fused<DT, MT><<<int(P.lf_n[MT - 1]), 64, 0, s>>>(                                    \
-        P.lf_items[MT - 1], P.lf_n[MT - 1], P.box_base[l], P.leaf_off, P.tgt_begin, P.blk_uptr,  \
-        P.blk_vptr, P.blk_rank, P.blk_soff, P.blk_n, P.blk_scale, Xs, NP, Y)
+        P.lf_items[MT - 1], P.lf_n[MT - 1], P.box_base[l], P.leaf_off, P.tgt_begin, gblk, p2,    \
+        p1, P.blk_rank, off1, len1, P.blk_scale, Xs, NP, Y)
     for (int mt = 1; mt <= 4; ++mt) {
         if (P.lf_n[mt - 1] == 0)
             continue;

@@ -10,6 +10,22 @@
 namespace h3d {
 namespace dev {
 
+// Workgroups are dealt to the eight XCDs in turn, each XCD with its own L2.
+// Renumbering workgroup b as below gives every XCD a contiguous run of the
+// grid (XCD x takes q or q + 1 consecutive numbers), so neighbouring work
+// items, which share inputs, meet in one L2.  A bijection on [0, nwg).
+__device__ __forceinline__ int64_t xcd_run(int64_t b, int64_t nwg) {
+    const int64_t q = nwg >> 3, r = nwg & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
+// A load from a table that no wave writes during the kernel: through the
+// constant address space it stays a scalar load when the index is uniform,
+// also after the kernel's own global stores or atomics.
+template <typename T> __device__ __forceinline__ T cload(const T *p) {
+    return *(const __attribute__((address_space(4))) T *)p;
+}
+
 // Factor loads.  Plain loads keep the lines in L2: a column slice rarely
 // starts on a 128-byte line, and the part of a line that the next slice
 // needs is then still cached (with the non-temporal hint such lines were

@@ -43,6 +43,7 @@ template <> struct SFac<H3D_BF16_SCALED> {
 template <int MT> struct S1Slot {
     float a[MT];
     f4 b;
+    int kv;  // PANEL: rows of the chunk box from this step's first row
 };
 
 template <int DT, int MT, int D, bool ACC64, bool PANEL>
@@ -52,9 +53,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
               const int32_t *__restrict__ rank, const int64_t *__restrict__ blk_col0,
               const float *__restrict__ scale2, const float *__restrict__ Xs, int NP,
               float *__restrict__ Z, const int32_t *__restrict__ leaf_off,
-              const int32_t *__restrict__ leaf_of, int shc) {
+              const int32_t *__restrict__ leaf_of, int shc, int shl,
+              const int32_t *__restrict__ psteps) {
     using F = typename SFac<DT>::T;
-    const int64_t w = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int64_t w = dev::xcd_run(blockIdx.x, gridDim.x) * 4 +
+                      __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (w >= nitems)
         return;
     const int lane = threadIdx.x & 63;
@@ -74,7 +77,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 #pragma unroll
     for (int t = 0; t < MT; ++t)
         cc[t] = min(c0 + 16 * t + r16, k - 1);
-    const int S = (len + 3) >> 2;  // K-steps
+    // K-steps.  PANEL (the adjoint above the chunk level): U_b is stored as one
+    // row panel per chunk box of the target box, so the rows are taken chunk
+    // box by chunk box, each padded to whole K-steps (the count per box from
+    // a table), with a scalar cursor over the chunk boxes one ahead.
+    const int S = PANEL ? psteps[leaf_of[off] >> shl] : (len + 3) >> 2;
+    const int ch_last = PANEL ? (leaf_of[off + len - 1] >> shc) : 0;
     for (int nb = 0; nb < NP; nb += 64) {
         const int nv = min(64, NP - nb);
         const int bcol = nb + 4 * min(r16, nv / 4 - 1);
@@ -95,19 +103,62 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
                     for (int jj = 0; jj < 4; ++jj)
                         acc64[t][N][jj] = 0.0;
         }
-        auto fill = [&](int s, S1Slot<MT> &sl) {
-            const int jc = min(4 * s + q, len - 1);
-#pragma unroll
-            for (int t = 0; t < MT; ++t) {
-                int64_t ea = int64_t(cc[t]) * len + jc;
-                if constexpr (PANEL)  // U_b stored as row panels (adjoint above the chunk level)
-                    ea = panel_off(leaf_off, leaf_of, shc, off, k, jc, cc[t]);
-                sl.a[t] = SFac<DT>::ld(p + ea);
+        // chunk cursor (PANEL): rows [pr0, pr0 + plen) of chunk box ch, step cs
+        int ch = 0, cs = 0, pr0 = 0, plen = 1, nch = 0, npr0 = 0, nplen = 1;
+        auto chunk_rows = [&](int c, int &r0, int &n) {
+            r0 = dev::cload(leaf_off + (int64_t(c) << shc));
+            n = dev::cload(leaf_off + (int64_t(c + 1) << shc)) - r0;
+        };
+        auto next_chunk = [&](int c) {  // next chunk box with rows after c (ch_last + 1: none)
+            int r0, n;
+            for (++c; c <= ch_last; ++c) {
+                chunk_rows(c, r0, n);
+                if (n > 0)
+                    break;
             }
-            sl.b = *reinterpret_cast<const f4 *>(Xs + (int64_t(off) + jc) * NP + bcol);
+            return c;
+        };
+        if constexpr (PANEL) {
+            ch = leaf_of[off] >> shc;
+            chunk_rows(ch, pr0, plen);
+            nch = next_chunk(ch);
+            if (nch <= ch_last)
+                chunk_rows(nch, npr0, nplen);
+        }
+        auto padvance = [&] {
+            if (4 * ++cs < plen)
+                return;
+            if (nch > ch_last) {  // past the last chunk: stay on its last step
+                --cs;
+                return;
+            }
+            ch = nch;
+            pr0 = npr0;
+            plen = nplen;
+            cs = 0;
+            nch = next_chunk(ch);
+            if (nch <= ch_last)
+                chunk_rows(nch, npr0, nplen);
+        };
+        auto fill = [&](int s, S1Slot<MT> &sl) {
+            if constexpr (PANEL) {
+                const int lr = min(4 * cs + q, plen - 1);
+                const int64_t base = int64_t(pr0 - off) * k + lr;
+#pragma unroll
+                for (int t = 0; t < MT; ++t)
+                    sl.a[t] = SFac<DT>::ld(p + base + int64_t(cc[t]) * plen);
+                sl.b = *reinterpret_cast<const f4 *>(Xs + (int64_t(pr0) + lr) * NP + bcol);
+                sl.kv = plen - 4 * cs;
+            } else {
+                const int jc = min(4 * s + q, len - 1);
+#pragma unroll
+                for (int t = 0; t < MT; ++t)
+                    sl.a[t] = SFac<DT>::ld(p + int64_t(cc[t]) * len + jc);
+                sl.b = *reinterpret_cast<const f4 *>(Xs + (int64_t(off) + jc) * NP + bcol);
+            }
         };
         auto step = [&](int s, const S1Slot<MT> &sl) {
-            const bool aj = 4 * s + q < len;
+            const bool aj = PANEL ? q < sl.kv : 4 * s + q < len;
             float bv[4];
 #pragma unroll
             for (int N = 0; N < 4; ++N)
@@ -122,6 +173,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             fill(d, R[d]);
+            if constexpr (PANEL)
+                padvance();
             __builtin_amdgcn_sched_barrier(0);  // slots in order (the waits count on it)
         }
         // steady part: every step refills its slot (past the end: clamped rows,
@@ -132,6 +185,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
             for (int d = 0; d < D; ++d) {
                 step(s0 + d, R[d]);
                 fill(s0 + d + D, R[d]);
+                if constexpr (PANEL)
+                    padvance();
                 // keep each refill right after its step: the scheduler would
                 // otherwise sink the loads of all steps below all the MFMAs
                 __builtin_amdgcn_sched_barrier(0);
@@ -178,7 +233,29 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     }
 }
 
+// K-steps of the row panels of every box of level l (sum over its chunk boxes
+// of ceil(rows / 4)); sh: 3 (chunk level - l), shc: 3 (L - chunk level)
+__global__ void k_panel_steps(int64_t nbox, int sh, int shc, const int32_t *__restrict__ leaf_off,
+                              int32_t *__restrict__ steps) {
+    const int64_t tb = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (tb >= nbox)
+        return;
+    int64_t sum = 0;
+    for (int64_t c = tb << sh; c < (tb + 1) << sh; ++c)
+        sum += (leaf_off[(c + 1) << shc] - leaf_off[c << shc] + 3) >> 2;
+    steps[tb] = int32_t(sum);
+}
+
 }  // namespace
+
+int32_t *panel_steps(Plan &P, int l, hipStream_t s) {
+    const int64_t nbox = pow8(l);
+    int32_t *out = P.mem.alloc_n<int32_t>(std::max<int64_t>(nbox, 1));
+    k_panel_steps<<<grid_for(nbox, 256), 256, 0, s>>>(nbox, 3 * (P.chunk_level - l),
+                                                     3 * (P.L - P.chunk_level), P.leaf_off, out);
+    H3D_LAUNCH_CHECK();
+    return out;
+}
 
 int s1_ring_tiles(const Plan &P, int l) {
     const int64_t nbl = P.lvl_blk[l + 1] - P.lvl_blk[l];
@@ -203,7 +280,7 @@ void launch_s1_ring(Plan &P, int l, bool adjoint, const int2 *items, int64_t nit
 #define H3D_S1R(DT, MT, A, PN)                                                                  \
     k_s1_ring<DT, MT, (MT <= 2 ? 8 : 6), A, PN><<<int((nitems + 3) / 4), 256, 0, s>>>(         \
         items, nitems, len, off, ptr, P.blk_rank, P.blk_col0, P.blk_scale, Xs, NP, Z,           \
-        P.leaf_off, P.leaf_of, shc)
+        P.leaf_off, P.leaf_of, shc, 3 * (P.L - l), P.bt_pk[l])
 #define H3D_S1R_PN(DT, MT, A)                                                                   \
     if (panel)                                                                                  \
         H3D_S1R(DT, MT, A, true);                                                               \

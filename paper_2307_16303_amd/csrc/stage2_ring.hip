@@ -39,10 +39,6 @@ template <> struct RFac<H3D_BF16_SCALED> {
     }
 };
 
-template <typename T> __device__ __forceinline__ T cload(const T *p) {
-    return *(const __attribute__((address_space(4))) T *)p;
-}
-
 struct Slot {
     float a[4];
     f4 b;
@@ -57,7 +53,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1)))
               const int32_t *__restrict__ steps, const float *__restrict__ Z, int NP,
               double *__restrict__ Y, int panel, const int32_t *__restrict__ leaf_of, int shc) {
     using F = typename RFac<DT>::T;
-    const int64_t w = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    const int64_t w = dev::xcd_run(blockIdx.x, gridDim.x) * 4 +
+                      __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (w >= nitems)
         return;
     const int lane = threadIdx.x & 63;
@@ -91,8 +88,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1)))
     };
     // the block tables are read-only here: constant-space loads stay scalar
     auto load = [&](int64_t qq) {
-        const int64_t bj = grp_blk ? cload(grp_blk + qq) : qq;
-        return Blk{cload(rank + bj), static_cast<const F *>(cload(fptr + bj)), cload(blk_col0 + bj)};
+        const int64_t bj = grp_blk ? dev::cload(grp_blk + qq) : qq;
+        return Blk{dev::cload(rank + bj), static_cast<const F *>(dev::cload(fptr + bj)), dev::cload(blk_col0 + bj)};
     };
     for (int nb = 0; nb < NP; nb += 64) {
         const int nv = min(64, NP - nb);

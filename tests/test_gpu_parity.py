@@ -442,10 +442,13 @@ def test_many_rhs_low_precision(rhs_cloud, dtype, bound):
     """FP32 and BF16 factors on the matrix cores, every column of a 64-RHS
     product and of its adjoint, element by element against the oracle applying
     the GPU's own stored factors in FP64 (exported exactly: FP32 values, or
-    BF16 values times their power-of-two scales).  What remains is the FP32
-    arithmetic of the GPU path (x, z and near-field entries rounded to FP32,
-    FP32 MFMA accumulation flushed to FP64), bounded by `bound`.  Against the
-    exact dense rows FP32 stays within 1e-6; BF16's storage error is reported."""
+    BF16 values times their power-of-two scales).  What remains is the
+    arithmetic of the GPU path, bounded by `bound`: for FP32 factors x, z and
+    the near-field entries rounded to FP32 and FP32 MFMA sums flushed to FP64;
+    for BF16 factors the forward far field runs on the BF16 matrix cores with
+    x and z carried as BF16 hi + lo pairs (2^-18 relative each) and FP32 sums.
+    Against the exact dense rows FP32 stays within 1e-6; BF16's storage error
+    is reported."""
     pts, kw = rhs_cloud
     X = inputs.normal_rhs(len(pts), seed=32, nrhs=64)
     op = gpu_build(pts, factor_dtype=dtype, **kw)
