@@ -191,7 +191,7 @@ def roofline_of(prof, workload, dt, nrhs):
         return {"bound": "alu", "achieved": round(tfs, 2), "peak": VALU_FP64_PEAK_TFS,
                 "unit": "TFLOP/s", "frac": round(tfs / VALU_FP64_PEAK_TFS, 4), **common,
                 "flops_per_launch": dom["flops_per_launch"], "hbm_gbs": round(gbs, 1)}
-    if "mfma" in dom["name"]:
+    if "mfma" in dom["name"] or dom["name"].startswith("k_leaf_fused"):
         tfs = dom["flops_per_launch"] / (avg_ms * 1e-3) / 1e12
         peak = MFMA_PEAK_TFS[dt]
         return {"bound": "mfma", "achieved": round(tfs, 2), "peak": peak, "unit": "TFLOP/s",
@@ -341,11 +341,13 @@ def main():
     rows_t = torch.as_tensor(rows_err, device=dev)
 
     def run_variant(name, opv, dtv, nr, steps, warmup, extra=None, profile=False, wl=wname,
-                    nn=n, xnp=None):
+                    nn=n, xnp=None, adjoint=False):
         xv = torch.as_tensor(xnp, device=dev)
-        sec_v, yv, prof_v = time_products(opv, xv, steps, warmup, profile=profile)
+        sec_v, yv, prof_v = time_products(opv, xv, steps, warmup, adjoint=adjoint, profile=profile)
         rec = {"workload": wl, "factor_dtype": dtv, "nrhs": nr, "ms_per_step": round(1e3 * sec_v, 4),
                "value": round(nn * nr / sec_v, 1), "factor_bytes": opv.stats()["factor_bytes"]}
+        if adjoint:
+            rec["product"] = "adjoint"
         if extra:
             rec.update(extra)
         if prof_v:
@@ -359,6 +361,10 @@ def main():
         yv = run_variant(f"{dt}_1rhs", op, dt, 1, max(5, args.steps), max(2, args.warmup),
                          xnp=x1_np)
         sampled[f"{dt}_1rhs"] = ("1", yv.reshape(n, -1)[rows_t].cpu().numpy())
+        if not args.adjoint:
+            # the adjoint product of the headline form on the same plan
+            run_variant(f"{dt}_{nrhs}rhs_adjoint", op, dt, nrhs, max(3, args.steps // 4),
+                        max(1, args.warmup // 2), profile=True, xnp=xh_np, adjoint=True)
     op.close()
     del op, y, xh
     torch.cuda.empty_cache()
@@ -409,13 +415,24 @@ def main():
         run_variant("uniform262k_fp64_1rhs", op, "fp64", 1, max(5, args.steps),
                     max(2, args.warmup), extra={"build_s": round(bs, 2)}, profile=True,
                     wl="uniform262k", nn=w2["n"], xnp=x2)
+        x2h = inputs.workload_rhs("uniform262k", 64)
+        run_variant("uniform262k_fp64_64rhs", op, "fp64", 64, max(3, args.steps // 4),
+                    max(1, args.warmup // 2), profile=True, wl="uniform262k", nn=w2["n"],
+                    xnp=x2h)
         op.close()
         del op
         torch.cuda.empty_cache()
         op, bs = build_op(pts2, w2, "fp32")
         run_variant("uniform262k_fp32_64rhs", op, "fp32", 64, max(3, args.steps // 4),
                     max(1, args.warmup // 2), extra={"build_s": round(bs, 2)}, profile=True,
-                    wl="uniform262k", nn=w2["n"], xnp=inputs.workload_rhs("uniform262k", 64))
+                    wl="uniform262k", nn=w2["n"], xnp=x2h)
+        op.close()
+        del op
+        torch.cuda.empty_cache()
+        op, bs = build_op(pts2, w2, "bf16")
+        run_variant("uniform262k_bf16_64rhs", op, "bf16", 64, max(3, args.steps // 4),
+                    max(1, args.warmup // 2), extra={"build_s": round(bs, 2)}, profile=True,
+                    wl="uniform262k", nn=w2["n"], xnp=x2h)
         op.close()
         del op
         torch.cuda.empty_cache()

@@ -18,8 +18,9 @@
 // right-hand side 4 n + N of a group of 64 (as in the FP32 ring kernels), so
 // a lane's four x or z words of a row are one 16-byte load.
 //
-// Stage 1: one wave per (block, 16 MT factor columns); a K-step is 16 source
-// rows.  A lane's four K slots are four consecutive rows of a V_b column: one
+// Stage 1: one wave per run of G consecutive (block, 16 MT factor columns)
+// items, the refill cursor crossing the items (each padded to whole rings);
+// a K-step is 16 source rows.  A lane's four K slots are four consecutive rows of a V_b column: one
 // 8-byte piece at any 2-byte alignment, read as the three aligned words that
 // hold it (the factor chunks end with 256 bytes of slack).
 // Stage 2: two waves per (target box, 64-row tile), 32 rows each; a K-step is
@@ -100,102 +101,141 @@ template <int MT> struct S1Slot {
 
 template <int MT, int D>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-    k_s1_bf16(const int2 *__restrict__ items, int64_t nitems, const int32_t *__restrict__ seg_len,
-              const int32_t *__restrict__ seg_off, void *const *__restrict__ seg_ptr,
-              const int32_t *__restrict__ rank, const int64_t *__restrict__ blk_col0,
-              const float *__restrict__ scale2, const uint32_t *__restrict__ Xh, int NP,
-              uint32_t *__restrict__ Zh) {
+    k_s1_bf16(const int2 *__restrict__ items, int64_t nitems, int G,
+              const int32_t *__restrict__ seg_len, const int32_t *__restrict__ seg_off,
+              void *const *__restrict__ seg_ptr, const int32_t *__restrict__ rank,
+              const int64_t *__restrict__ blk_col0, const float *__restrict__ scale2,
+              const uint32_t *__restrict__ Xh, int NP, uint32_t *__restrict__ Zh) {
     const int64_t w = dev::xcd_run(blockIdx.x, gridDim.x) * 4 +
                       __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (w >= nitems)
+    const int64_t i0 = w * G;
+    if (i0 >= nitems)
         return;
+    const int64_t i1 = min(i0 + int64_t(G), nitems);
     const int lane = threadIdx.x & 63;
     const int r16 = lane & 15, q = lane >> 4;
-    const int2 it = items[w];
-    const int b = it.x, c0 = it.y * 16 * MT;
-    const int len = seg_len[b], k = rank[b];
-    if (k <= 0 || len <= 0)
-        return;
-    const int64_t off = seg_off[b];
-    const int64_t col0 = blk_col0[b];
-    const uint16_t *__restrict__ p = static_cast<const uint16_t *>(seg_ptr[b]);
-    const float sc = scale2[2 * b] * scale2[2 * b + 1];
-    int64_t ce[MT];  // first element of this lane's column of tile T (clamped into the block)
-#pragma unroll
-    for (int T = 0; T < MT; ++T)
-        ce[T] = int64_t(min(c0 + 16 * T + r16, k - 1)) * len;
-    const int S = (len + 15) >> 4;  // K-steps of 16 rows
+    struct Item {
+        int b, c0, len, k;
+        int64_t off;
+        const uint16_t *p;
+    };
+    auto load_item = [&](int64_t i) {
+        const uint64_t v = dev::cload(reinterpret_cast<const uint64_t *>(items + i));
+        const int b = int(uint32_t(v)), grp = int(uint32_t(v >> 32));  // (block, column group)
+        return Item{b, grp * 16 * MT, dev::cload(seg_len + b), dev::cload(rank + b),
+                    int64_t(dev::cload(seg_off + b)),
+                    static_cast<const uint16_t *>(dev::cload(seg_ptr + b))};
+    };
+    auto padded = [](int len) { return (((len + 15) >> 4) + D - 1) / D * D; };
     for (int nb = 0; nb < NP; nb += 64) {
         const int nv = min(64, NP - nb);
         const int bcol = nb + 4 * min(r16, nv / 4 - 1);
-        f4 C[MT][4];
-#pragma unroll
-        for (int T = 0; T < MT; ++T)
-#pragma unroll
-            for (int N = 0; N < 4; ++N)
-                C[T][N] = f4{0.f, 0.f, 0.f, 0.f};
-        auto fill = [&](int s, S1Slot<MT> &R) {
-            const int j0 = min(16 * s + 4 * q, len - 1);
+        // refill cursor (item fi, padded K-step fs of 16 rows), the next item ahead
+        int64_t fi = i0;
+        Item fc = load_item(fi);
+        Item fn = fi + 1 < i1 ? load_item(fi + 1) : fc;
+        int fS = padded(fc.len), fs = 0;
+        int64_t ce[MT];  // first element of this lane's column of tile T (clamped into the block)
+        auto set_cols = [&] {
 #pragma unroll
             for (int T = 0; T < MT; ++T)
-                ld4_raw(p + ce[T] + j0, R.a[T], R.odd[T]);
+                ce[T] = int64_t(min(fc.c0 + 16 * T + r16, fc.k - 1)) * fc.len;
+        };
+        set_cols();
+        auto fadvance = [&] {
+            if (++fs < fS)
+                return;
+            if (fi + 1 >= i1) {  // past the last item: stay on its last step
+                fs = fS - 1;
+                return;
+            }
+            ++fi;
+            fc = fn;
+            fS = padded(fc.len);
+            fs = 0;
+            set_cols();
+            if (fi + 1 < i1)
+                fn = load_item(fi + 1);
+        };
+        auto fill = [&](S1Slot<MT> &R) {
+            const int j0 = min(16 * fs + 4 * q, fc.len - 1);
+#pragma unroll
+            for (int T = 0; T < MT; ++T)
+                ld4_raw(fc.p + ce[T] + j0, R.a[T], R.odd[T]);
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                R.x[i] = *(const u4 *)((GU32 *)(Xh + (off + min(16 * s + 4 * q + i, len - 1)) * NP +
+                R.x[i] = *(const u4 *)((GU32 *)(Xh + (fc.off + min(16 * fs + 4 * q + i, fc.len - 1)) *
+                                                         NP +
                                                  bcol));
-        };
-        auto step = [&](int s, const S1Slot<MT> &R) {
-            uint32_t mlo, mhi;
-            slot_masks(len - (16 * s + 4 * q), mlo, mhi);
-            s4 bh[4], bl[4];
-#pragma unroll
-            for (int N = 0; N < 4; ++N) {
-                bh[N] = pack_hi(R.x[0][N], R.x[1][N], R.x[2][N], R.x[3][N]);
-                bl[N] = pack_lo(R.x[0][N], R.x[1][N], R.x[2][N], R.x[3][N]);
-            }
-#pragma unroll
-            for (int T = 0; T < MT; ++T) {
-                const s4 a = fix4(R.a[T], R.odd[T], mlo, mhi);
-#pragma unroll
-                for (int N = 0; N < 4; ++N) {
-                    C[T][N] = mma(a, bh[N], C[T][N]);
-                    C[T][N] = mma(a, bl[N], C[T][N]);
-                }
-            }
         };
         S1Slot<MT> R[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            fill(d, R[d]);
+            fill(R[d]);
+            fadvance();
             __builtin_amdgcn_sched_barrier(0);  // slots in order (the waits count on it)
         }
-        int s0 = 0;
-        for (; s0 + D <= S; s0 += D) {
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                step(s0 + d, R[d]);
-                fill(s0 + d + D, R[d]);  // past the end: clamped rows, never consumed
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        }
-#pragma unroll
-        for (int d = 0; d < D; ++d)
-            if (s0 + d < S)
-                step(s0 + d, R[d]);
-        if (4 * r16 < nv) {
+        Item cn = load_item(i0);  // the consumed item's metadata, one item ahead
+        for (int64_t ci = i0; ci < i1; ++ci) {
+            const Item cc = cn;
+            if (ci + 1 < i1)
+                cn = load_item(ci + 1);
+            const int S = (cc.len + 15) >> 4, Sp = padded(cc.len);
+            f4 C[MT][4];
 #pragma unroll
             for (int T = 0; T < MT; ++T)
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    const int c = c0 + 16 * T + 4 * q + jj;
-                    if (c < k) {
-                        u4 o;
+                for (int N = 0; N < 4; ++N)
+                    C[T][N] = f4{0.f, 0.f, 0.f, 0.f};
+            auto step = [&](int s, const S1Slot<MT> &R) {
+                uint32_t mlo, mhi;
+                slot_masks(cc.len - (16 * s + 4 * q), mlo, mhi);
+                s4 bh[4], bl[4];
 #pragma unroll
-                        for (int N = 0; N < 4; ++N)
-                            o[N] = split_hl(C[T][N][jj] * sc);
-                        *reinterpret_cast<u4 *>(Zh + (col0 + c) * NP + nb + 4 * r16) = o;
+                for (int N = 0; N < 4; ++N) {
+                    bh[N] = pack_hi(R.x[0][N], R.x[1][N], R.x[2][N], R.x[3][N]);
+                    bl[N] = pack_lo(R.x[0][N], R.x[1][N], R.x[2][N], R.x[3][N]);
+                }
+#pragma unroll
+                for (int T = 0; T < MT; ++T) {
+                    const s4 a = fix4(R.a[T], R.odd[T], mlo, mhi);
+#pragma unroll
+                    for (int N = 0; N < 4; ++N) {
+                        C[T][N] = mma(a, bh[N], C[T][N]);
+                        C[T][N] = mma(a, bl[N], C[T][N]);
                     }
                 }
+            };
+            auto chunk = [&](int s0) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    if (s0 + d < S)
+                        step(s0 + d, R[d]);
+                    fill(R[d]);
+                    fadvance();
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            };
+            chunk(0);  // on its own: its waits count the previous item's stores
+            for (int s0 = D; s0 < Sp; s0 += D)
+                chunk(s0);
+            const float sc = scale2[2 * cc.b] * scale2[2 * cc.b + 1];
+            const int64_t col0 = dev::cload(blk_col0 + cc.b);
+            if (4 * r16 < nv) {
+#pragma unroll
+                for (int T = 0; T < MT; ++T)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const int c = cc.c0 + 16 * T + 4 * q + jj;
+                        if (c < cc.k) {
+                            u4 o;
+#pragma unroll
+                            for (int N = 0; N < 4; ++N)
+                                o[N] = split_hl(C[T][N][jj] * sc);
+                            *reinterpret_cast<u4 *>(Zh + (col0 + c) * NP + nb + 4 * r16) = o;
+                        }
+                    }
+            }
         }
     }
 }
@@ -412,10 +452,14 @@ void launch_s1_bf16(Plan &P, int l, const int2 *items, int64_t nitems, const uin
     if (nitems <= 0)
         return;
     const int mt = s1_ring_tiles(P, l);
+    // levels of boxes under 256 points (under 16 K-steps of 16 rows): G items
+    // per wave, about 16 waves per SIMD; one item per wave otherwise
+    const int G = P.mean_box[l] < 256 ? int(std::max<int64_t>(1, nitems / 16384)) : 1;
+    const int nwg = int(((nitems + G - 1) / G + 3) / 4);
 #define H3D_S1B(MT)                                                                             \
-    k_s1_bf16<MT, (MT == 4 ? 2 : 3)><<<int((nitems + 3) / 4), 256, 0, s>>>(items, nitems, P.blk_n, P.blk_soff,   \
-                                                           P.blk_vptr, P.blk_rank, P.blk_col0,  \
-                                                           P.blk_scale, Xh, NP, Zh)
+    k_s1_bf16<MT, (MT <= 2 ? 4 : (MT == 3 ? 3 : 2))><<<nwg, 256, 0, s>>>(items, nitems, G, P.blk_n, P.blk_soff,  \
+                                                         P.blk_vptr, P.blk_rank, P.blk_col0,    \
+                                                         P.blk_scale, Xh, NP, Zh)
     switch (mt) {
     case 1: H3D_S1B(1); break;
     case 2: H3D_S1B(2); break;

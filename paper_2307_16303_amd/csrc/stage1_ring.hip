@@ -233,6 +233,179 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     }
 }
 
+// The same product with a run of G consecutive items per wave, for levels of
+// many short columns: the refill cursor runs across the items, so the ring
+// never drains between them.  Each item's K-steps are padded to a multiple of
+// D (padded steps load the item's last rows again and issue no MFMA), so the
+// refill cursor enters the next item at slot 0 and the write-out of an item
+// runs outside the unrolled ring; the first D steps of an item are written
+// out on their own, so that their waits count the stores of the previous
+// item's write-out.
+template <int DT, int MT, int D, bool ACC64>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+    k_s1_ring_g(const int2 *__restrict__ items, int64_t nitems, int G,
+                const int32_t *__restrict__ seg_len, const int32_t *__restrict__ seg_off,
+                void *const *__restrict__ seg_ptr, const int32_t *__restrict__ rank,
+                const int64_t *__restrict__ blk_col0, const float *__restrict__ scale2,
+                const float *__restrict__ Xs, int NP, float *__restrict__ Z) {
+    using F = typename SFac<DT>::T;
+    const int64_t w = dev::xcd_run(blockIdx.x, gridDim.x) * 4 +
+                      __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t i0 = w * G;
+    if (i0 >= nitems)
+        return;
+    const int64_t i1 = min(i0 + int64_t(G), nitems);
+    const int lane = threadIdx.x & 63;
+    const int r16 = lane & 15, q = lane >> 4;
+    struct Item {
+        int b, c0, len, k;
+        int64_t off;
+        const F *p;
+    };
+    auto load_item = [&](int64_t i) {
+        const uint64_t v = dev::cload(reinterpret_cast<const uint64_t *>(items + i));
+        const int2 it{int(uint32_t(v)), int(uint32_t(v >> 32))};  // (block, column group)
+        return Item{it.x, it.y * 16 * MT, dev::cload(seg_len + it.x), dev::cload(rank + it.x),
+                    int64_t(dev::cload(seg_off + it.x)),
+                    static_cast<const F *>(dev::cload(seg_ptr + it.x))};
+    };
+    auto padded = [](int len) { return (((len + 3) >> 2) + D - 1) / D * D; };
+    for (int nb = 0; nb < NP; nb += 64) {
+        const int nv = min(64, NP - nb);
+        const int bcol = nb + 4 * min(r16, nv / 4 - 1);
+        // refill cursor: item fi (fc), padded step fs; the next item's metadata ahead
+        int64_t fi = i0;
+        Item fc = load_item(fi);
+        Item fn = fi + 1 < i1 ? load_item(fi + 1) : fc;
+        int fS = padded(fc.len), fs = 0;
+        int64_t fcol[MT];  // this lane's first element of each tile's column (clamped)
+        auto set_cols = [&] {
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+                fcol[t] = int64_t(min(fc.c0 + 16 * t + r16, fc.k - 1)) * fc.len;
+        };
+        set_cols();
+        auto fadvance = [&] {
+            if (++fs < fS)
+                return;
+            if (fi + 1 >= i1) {  // past the last item: stay on its last step
+                fs = fS - 1;
+                return;
+            }
+            ++fi;
+            fc = fn;
+            fS = padded(fc.len);
+            fs = 0;
+            set_cols();
+            if (fi + 1 < i1)
+                fn = load_item(fi + 1);
+        };
+        auto fill = [&](S1Slot<MT> &R) {
+            const int jc = min(4 * fs + q, fc.len - 1);
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+                R.a[t] = SFac<DT>::ld(fc.p + fcol[t] + jc);
+            R.b = *reinterpret_cast<const f4 *>(Xs + (fc.off + jc) * NP + bcol);
+        };
+        S1Slot<MT> R[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            fill(R[d]);
+            fadvance();
+            __builtin_amdgcn_sched_barrier(0);  // slots in order (the waits count on it)
+        }
+        Item cn = load_item(i0);  // the consumed item's metadata, one item ahead
+        for (int64_t ci = i0; ci < i1; ++ci) {
+            const Item cc = cn;
+            if (ci + 1 < i1)
+                cn = load_item(ci + 1);
+            const int S = (cc.len + 3) >> 2, Sp = padded(cc.len);
+            f4 C[MT][4];
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+#pragma unroll
+                for (int N = 0; N < 4; ++N)
+                    C[t][N] = f4{0.f, 0.f, 0.f, 0.f};
+            constexpr int A64 = ACC64 ? MT : 1;
+            double acc64[A64][4][4];
+            if constexpr (ACC64) {
+#pragma unroll
+                for (int t = 0; t < MT; ++t)
+#pragma unroll
+                    for (int N = 0; N < 4; ++N)
+#pragma unroll
+                        for (int jj = 0; jj < 4; ++jj)
+                            acc64[t][N][jj] = 0.0;
+            }
+            auto chunk = [&](int s0) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const int s = s0 + d;
+                    if (s < S) {
+                        const bool aj = 4 * s + q < cc.len;
+                        float bv[4];
+#pragma unroll
+                        for (int N = 0; N < 4; ++N)
+                            bv[N] = aj ? R[d].b[N] : 0.f;
+#pragma unroll
+                        for (int t = 0; t < MT; ++t)
+#pragma unroll
+                            for (int N = 0; N < 4; ++N)
+                                C[t][N] = __builtin_amdgcn_mfma_f32_16x16x4f32(R[d].a[t], bv[N],
+                                                                               C[t][N], 0, 0, 0);
+                    }
+                    fill(R[d]);
+                    fadvance();
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            };
+            chunk(0);
+            int ks = D;
+            for (int s0 = D; s0 < Sp; s0 += D) {
+                if constexpr (ACC64) {
+                    if (ks + D > 64) {
+                        ks = 0;
+#pragma unroll
+                        for (int t = 0; t < MT; ++t)
+#pragma unroll
+                            for (int N = 0; N < 4; ++N) {
+#pragma unroll
+                                for (int jj = 0; jj < 4; ++jj)
+                                    acc64[t][N][jj] += double(C[t][N][jj]);
+                                C[t][N] = f4{0.f, 0.f, 0.f, 0.f};
+                            }
+                    }
+                }
+                chunk(s0);
+                ks += D;
+            }
+            float sc = 1.f;
+            if (DT == H3D_BF16_SCALED)
+                sc = scale2[2 * cc.b] * scale2[2 * cc.b + 1];
+            const int64_t col0 = dev::cload(blk_col0 + cc.b);
+            if (4 * r16 < nv) {
+#pragma unroll
+                for (int t = 0; t < MT; ++t)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const int c = cc.c0 + 16 * t + 4 * q + jj;
+                        if (c < cc.k) {
+                            f4 o;
+#pragma unroll
+                            for (int N = 0; N < 4; ++N) {
+                                double v = double(C[t][N][jj]);
+                                if constexpr (ACC64)
+                                    v += acc64[t][N][jj];
+                                o[N] = float(v * sc);
+                            }
+                            *reinterpret_cast<f4 *>(Z + (col0 + c) * NP + nb + 4 * r16) = o;
+                        }
+                    }
+            }
+        }
+    }
+}
+
 // K-steps of the row panels of every box of level l (sum over its chunk boxes
 // of ceil(rows / 4)); sh: 3 (chunk level - l), shc: 3 (L - chunk level)
 __global__ void k_panel_steps(int64_t nbox, int sh, int shc, const int32_t *__restrict__ leaf_off,
@@ -277,15 +450,24 @@ void launch_s1_ring(Plan &P, int l, bool adjoint, const int2 *items, int64_t nit
     void *const *ptr = adjoint ? P.blk_uptr : P.blk_vptr;
     const int shc = 3 * (P.L - P.chunk_level);
     // ring of eight K-steps (six for three or four tiles, within 256 registers)
+    // levels of boxes under 64 points: G items per wave, about 16 waves per
+    // SIMD (one item per wave measured faster for longer columns)
+    const int G = P.mean_box[l] < 64 ? int(std::max<int64_t>(1, nitems / 16384)) : 1;
+    const int nwg = int(((nitems + G - 1) / G + 3) / 4);
 #define H3D_S1R(DT, MT, A, PN)                                                                  \
     k_s1_ring<DT, MT, (MT <= 2 ? 8 : 6), A, PN><<<int((nitems + 3) / 4), 256, 0, s>>>(         \
         items, nitems, len, off, ptr, P.blk_rank, P.blk_col0, P.blk_scale, Xs, NP, Z,           \
         P.leaf_off, P.leaf_of, shc, 3 * (P.L - l), P.bt_pk[l])
+#define H3D_S1G(DT, MT, A)                                                                      \
+    k_s1_ring_g<DT, MT, (MT <= 2 ? 8 : 6), A><<<nwg, 256, 0, s>>>(                              \
+        items, nitems, G, len, off, ptr, P.blk_rank, P.blk_col0, P.blk_scale, Xs, NP, Z)
 #define H3D_S1R_PN(DT, MT, A)                                                                   \
     if (panel)                                                                                  \
         H3D_S1R(DT, MT, A, true);                                                               \
+    else if (G == 1)                                                                            \
+        H3D_S1R(DT, MT, A, false);                                                              \
     else                                                                                        \
-        H3D_S1R(DT, MT, A, false);
+        H3D_S1G(DT, MT, A);
 #define H3D_S1R_DT(DT)                                                                          \
     if (acc) {                                                                                  \
         if (mt == 1) {                                                                          \
@@ -308,6 +490,7 @@ void launch_s1_ring(Plan &P, int l, bool adjoint, const int2 *items, int64_t nit
     }
 #undef H3D_S1R_DT
 #undef H3D_S1R_PN
+#undef H3D_S1G
 #undef H3D_S1R
     H3D_LAUNCH_CHECK();
 }

@@ -127,6 +127,133 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     }
 }
 
+// Stage 1 with a run of G consecutive items per wave (levels of many short
+// columns): the refill cursor runs across the items, each padded to a
+// multiple of D steps, as in the FP32 multi-item kernel.
+template <int D>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+    k_s1_ring64_g(const int2 *__restrict__ items, int64_t nitems, int G,
+                  const int32_t *__restrict__ seg_len, const int32_t *__restrict__ seg_off,
+                  void *const *__restrict__ seg_ptr, const int32_t *__restrict__ rank,
+                  const int64_t *__restrict__ blk_col0, const double *__restrict__ Xs, int NP,
+                  double *__restrict__ Z) {
+    constexpr int MT = kMT64;
+    const int64_t w = dev::xcd_run(blockIdx.x, gridDim.x) * 4 +
+                      __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t i0 = w * G;
+    if (i0 >= nitems)
+        return;
+    const int64_t i1 = min(i0 + int64_t(G), nitems);
+    const int lane = threadIdx.x & 63;
+    const int r16 = lane & 15, q = lane >> 4;
+    struct Item {
+        int b, c0, len, k;
+        int64_t off;
+        const double *p;
+    };
+    auto load_item = [&](int64_t i) {
+        const uint64_t v = dev::cload(reinterpret_cast<const uint64_t *>(items + i));
+        const int2 it{int(uint32_t(v)), int(uint32_t(v >> 32))};  // (block, column group)
+        return Item{it.x, it.y * 16 * MT, dev::cload(seg_len + it.x), dev::cload(rank + it.x),
+                    int64_t(dev::cload(seg_off + it.x)),
+                    static_cast<const double *>(dev::cload(seg_ptr + it.x))};
+    };
+    auto padded = [](int len) { return (((len + 3) >> 2) + D - 1) / D * D; };
+    for (int nb = 0; nb < NP; nb += 64) {
+        const int nv = min(64, NP - nb);
+        const int bcol = nb + 4 * min(r16, nv / 4 - 1);
+        int64_t fi = i0;
+        Item fc = load_item(fi);
+        Item fn = fi + 1 < i1 ? load_item(fi + 1) : fc;
+        int fS = padded(fc.len), fs = 0;
+        int64_t fcol[MT];
+        auto set_cols = [&] {
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+                fcol[t] = int64_t(min(fc.c0 + 16 * t + r16, fc.k - 1)) * fc.len;
+        };
+        set_cols();
+        auto fadvance = [&] {
+            if (++fs < fS)
+                return;
+            if (fi + 1 >= i1) {
+                fs = fS - 1;
+                return;
+            }
+            ++fi;
+            fc = fn;
+            fS = padded(fc.len);
+            fs = 0;
+            set_cols();
+            if (fi + 1 < i1)
+                fn = load_item(fi + 1);
+        };
+        auto fill = [&](S1Slot64 &R) {
+            const int jc = min(4 * fs + q, fc.len - 1);
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+                R.a[t] = *(GF64 *)(fc.p + fcol[t] + jc);
+            R.b = *reinterpret_cast<const d4 *>(Xs + (fc.off + jc) * NP + bcol);
+        };
+        S1Slot64 R[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            fill(R[d]);
+            fadvance();
+            __builtin_amdgcn_sched_barrier(0);  // slots in order (the waits count on it)
+        }
+        Item cn = load_item(i0);  // the consumed item's metadata, one item ahead
+        for (int64_t ci = i0; ci < i1; ++ci) {
+            const Item cc = cn;
+            if (ci + 1 < i1)
+                cn = load_item(ci + 1);
+            const int S = (cc.len + 3) >> 2, Sp = padded(cc.len);
+            d4 C[MT][4];
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+#pragma unroll
+                for (int N = 0; N < 4; ++N)
+                    C[t][N] = d4{0.0, 0.0, 0.0, 0.0};
+            auto chunk = [&](int s0) {
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const int s = s0 + d;
+                    if (s < S) {
+                        const bool aj = 4 * s + q < cc.len;
+#pragma unroll
+                        for (int t = 0; t < MT; ++t)
+#pragma unroll
+                            for (int N = 0; N < 4; ++N)
+                                C[t][N] = mma64(R[d].a[t], aj ? R[d].b[N] : 0.0, C[t][N]);
+                    }
+                    fill(R[d]);
+                    fadvance();
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            };
+            chunk(0);  // on its own: its waits count the previous item's stores
+            for (int s0 = D; s0 < Sp; s0 += D)
+                chunk(s0);
+            const int64_t col0 = dev::cload(blk_col0 + cc.b);
+            if (4 * r16 < nv) {
+#pragma unroll
+                for (int t = 0; t < MT; ++t)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const int c = cc.c0 + 16 * t + 4 * jj + q;
+                        if (c < cc.k) {
+                            d4 o;
+#pragma unroll
+                            for (int N = 0; N < 4; ++N)
+                                o[N] = C[t][N][jj];
+                            *reinterpret_cast<d4 *>(Z + (col0 + c) * NP + nb + 4 * r16) = o;
+                        }
+                    }
+            }
+        }
+    }
+}
+
 struct S2Slot64 {
     double a[2];
     d4 b;
@@ -297,14 +424,20 @@ void launch_s1_ring64(Plan &P, int l, bool adjoint, const int2 *items, int64_t n
     const int32_t *off = adjoint ? P.blk_toff : P.blk_soff;
     void *const *ptr = adjoint ? P.blk_uptr : P.blk_vptr;
     const int shc = 3 * (P.L - P.chunk_level);
-    const int nwg = int((nitems + 3) / 4);
-    if (panel)
-        k_s1_ring64<8, true><<<nwg, 256, 0, s>>>(items, nitems, len, off, ptr, P.blk_rank,
-                                                 P.blk_col0, Xs, NP, Z, P.leaf_off, P.leaf_of, shc);
-    else
-        k_s1_ring64<8, false><<<nwg, 256, 0, s>>>(items, nitems, len, off, ptr, P.blk_rank,
-                                                  P.blk_col0, Xs, NP, Z, P.leaf_off, P.leaf_of,
-                                                  shc);
+    if (panel) {
+        k_s1_ring64<8, true><<<int((nitems + 3) / 4), 256, 0, s>>>(
+            items, nitems, len, off, ptr, P.blk_rank, P.blk_col0, Xs, NP, Z, P.leaf_off,
+            P.leaf_of, shc);
+    } else if (P.mean_box[l] >= 64) {  // one item per wave (faster for longer columns)
+        k_s1_ring64<8, false><<<int((nitems + 3) / 4), 256, 0, s>>>(
+            items, nitems, len, off, ptr, P.blk_rank, P.blk_col0, Xs, NP, Z, P.leaf_off,
+            P.leaf_of, shc);
+    } else {
+        // levels of boxes under 64 points: G items per wave, about 16 waves per SIMD
+        const int G = int(std::max<int64_t>(1, nitems / 16384));
+        k_s1_ring64_g<8><<<int(((nitems + G - 1) / G + 3) / 4), 256, 0, s>>>(
+            items, nitems, G, len, off, ptr, P.blk_rank, P.blk_col0, Xs, NP, Z);
+    }
     H3D_LAUNCH_CHECK();
 }
 
