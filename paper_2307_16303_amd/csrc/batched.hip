@@ -65,41 +65,71 @@ template <> struct CT<H3D_F64> {
 
 constexpr int kNT = 4;  // 16-wide RHS tiles per pass (64 columns)
 
-// x (caller order, column-major, io type) -> Xs (sorted, point-major, width NP)
-__global__ void k_gather_pm(const void *__restrict__ x, int io_f32, int64_t ldx, int64_t n,
-                            int nrhs, int NP, const int32_t *__restrict__ perm, int ct_f64,
-                            void *__restrict__ Xs) {
-    const int64_t p = int64_t(blockIdx.x) * blockDim.y + threadIdx.y;
-    if (p >= n)
-        return;
-    const int64_t src = perm[p];
-    for (int r = threadIdx.x; r < NP; r += blockDim.x) {
+// x (caller order, column-major, io type) -> Xs (sorted, point-major, width NP).
+// Through LDS, in caller order: a workgroup takes 64 points
+// (consecutive in the caller's order) and 64 right-hand sides, reads the
+// columns of x coalesced, and writes each point's 64 values as one
+// contiguous piece of its row iperm[i] of Xs.  Columns past nrhs are zero.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_gather_t(const void *__restrict__ x, int io_f32, int64_t ldx, int64_t n, int nrhs, int NP,
+               const int32_t *__restrict__ iperm, T *__restrict__ Xs) {
+    __shared__ T tile[64][65];
+    const int64_t i0 = int64_t(blockIdx.x) * 64;
+    const int r0 = blockIdx.y * 64;
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int rr = e >> 6, ii = e & 63;
+        const int64_t i = i0 + ii;
+        const int r = r0 + rr;
         double v = 0.0;
-        if (r < nrhs)
-            v = io_f32 ? double(static_cast<const float *>(x)[r * ldx + src])
-                       : static_cast<const double *>(x)[r * ldx + src];
-        if (ct_f64)
-            static_cast<double *>(Xs)[p * NP + r] = v;
-        else
-            static_cast<float *>(Xs)[p * NP + r] = float(v);
+        if (r < nrhs && i < n)
+            v = io_f32 ? double(static_cast<const float *>(x)[r * ldx + i])
+                       : static_cast<const double *>(x)[r * ldx + i];
+        tile[ii][rr] = T(v);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int ii = e >> 6, rr = e & 63;
+        const int64_t i = i0 + ii;
+        if (i < n && r0 + rr < NP)
+            Xs[int64_t(iperm[i]) * NP + r0 + rr] = tile[ii][rr];
     }
 }
 
-// Y (sorted, point-major FP64) -> y (caller order, column-major, io type)
-__global__ void k_scatter_pm(const double *__restrict__ Y, int64_t n, int nrhs, int NP,
-                             const int32_t *__restrict__ perm, void *__restrict__ y, int64_t ldy,
-                             int io_f32) {
-    const int64_t p = int64_t(blockIdx.x) * blockDim.y + threadIdx.y;
-    if (p >= n)
-        return;
-    const int64_t dst = perm[p];
-    for (int r = threadIdx.x; r < nrhs; r += blockDim.x) {
-        const double v = Y[p * NP + r];
-        if (io_f32)
-            static_cast<float *>(y)[r * ldy + dst] = float(v);
-        else
-            static_cast<double *>(y)[r * ldy + dst] = v;
+// Y (sorted, point-major FP64) -> y (caller order, column-major) through LDS:
+// a workgroup takes 64 points in the caller's order and 64 right-hand sides,
+// reads each point's row iperm[i] of Y contiguously and writes the columns
+// of y coalesced.
+__global__ void __launch_bounds__(256)
+    k_scatter_t(const double *__restrict__ Y, int64_t n, int nrhs, int NP,
+                const int32_t *__restrict__ iperm, void *__restrict__ y, int64_t ldy, int io_f32) {
+    __shared__ double tile[64][65];
+    const int64_t i0 = int64_t(blockIdx.x) * 64;
+    const int r0 = blockIdx.y * 64;
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int ii = e >> 6, rr = e & 63;
+        const int64_t i = i0 + ii;
+        tile[ii][rr] = (i < n && r0 + rr < NP) ? Y[int64_t(iperm[i]) * NP + r0 + rr] : 0.0;
     }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int rr = e >> 6, ii = e & 63;
+        const int64_t i = i0 + ii;
+        const int r = r0 + rr;
+        if (r < nrhs && i < n) {
+            if (io_f32)
+                static_cast<float *>(y)[r * ldy + i] = float(tile[ii][rr]);
+            else
+                static_cast<double *>(y)[r * ldy + i] = tile[ii][rr];
+        }
+    }
+}
+
+// caller index -> sorted row
+__global__ void k_iperm(int64_t n, const int32_t *__restrict__ perm, int32_t *__restrict__ iperm) {
+    const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p < n)
+        iperm[perm[p]] = int32_t(p);
 }
 
 // ---------------------------------------------------------------------------
@@ -931,6 +961,9 @@ void ensure_batched_tables(Plan &P, hipStream_t s) {
                 P.bt_pk[l] = panel_steps(P, l, s);
         }
     }
+    P.iperm = P.mem.alloc_n<int32_t>(std::max<int64_t>(P.n, 1));
+    k_iperm<<<grid_for(P.n, 256), 256, 0, s>>>(P.n, P.perm, P.iperm);
+    H3D_LAUNCH_CHECK();
     P.bt_ready = true;
 }
 
@@ -992,9 +1025,8 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
     const double es = DT == H3D_F64 ? 8.0 : (DT == H3D_F32 ? 4.0 : 2.0);
     {
         hipEvent_t ev = P.prof.begin(s);
-        dim3 blk(16, 16);
-        k_gather_pm<<<grid_for(n, 16), blk, 0, s>>>(x, io_f32, ldx, n, nrhs, NP, P.perm,
-                                                    DT == H3D_F64, Xs);
+        const dim3 grid(unsigned((n + 63) / 64), unsigned(NP / 64 + (NP % 64 ? 1 : 0)));
+        k_gather_t<T><<<grid, 256, 0, s>>>(x, io_f32, ldx, n, nrhs, NP, P.iperm, Xs);
         H3D_LAUNCH_CHECK();
         P.prof.end(s, ev, "k_gather_pm", double(n) * (4.0 + (io_f32 ? 4 : 8) * nrhs + sizeof(T) * NP), 0.0);
     }
@@ -1141,8 +1173,8 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
     }
     {
         hipEvent_t ev = P.prof.begin(s);
-        dim3 blk(16, 16);
-        k_scatter_pm<<<grid_for(n, 16), blk, 0, s>>>(Y, n, nrhs, NP, P.perm, y, ldy, io_f32);
+        const dim3 grid(unsigned((n + 63) / 64), unsigned(NP / 64 + (NP % 64 ? 1 : 0)));
+        k_scatter_t<<<grid, 256, 0, s>>>(Y, n, nrhs, NP, P.iperm, y, ldy, io_f32);
         H3D_LAUNCH_CHECK();
         P.prof.end(s, ev, "k_scatter_pm", double(n) * (4.0 + 8.0 * nrhs + (io_f32 ? 4 : 8) * nrhs), 0.0);
     }

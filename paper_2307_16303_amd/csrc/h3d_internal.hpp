@@ -212,6 +212,7 @@ struct Plan {
 
     // tree
     int32_t *perm = nullptr;      // [n] sorted row -> original index
+    int32_t *iperm = nullptr;     // [n] original index -> sorted row (many-RHS tables)
     double *px = nullptr, *py = nullptr, *pz = nullptr;  // [n] sorted coordinates
     int32_t *leaf_off = nullptr;  // [8^L + 1]
     int32_t *leaf_of = nullptr;   // [n] leaf of each sorted row

@@ -17,9 +17,11 @@
 // most 64 columns) are added into FP64 sums of the leaf's rows, which start
 // from Y (the near field and the coarser levels) and are written back once.
 //
-// Loads run ahead of the MFMAs through a ring of D stage-1 K-steps that
-// crosses blocks: each block's stage-1 steps are padded to a multiple of D
-// (padded steps load again the block's last rows and issue no MFMA), so the
+// Loads run ahead of the MFMAs through a ring of D stage-1 super-steps (four
+// K-steps, 16 source rows; a lane's four factor values of a super-step are
+// consecutive rows of its column, read at once) that crosses blocks: each
+// block's super-steps are padded to a multiple of D (padded steps load again
+// the block's last rows and issue no MFMA), so the
 // refill cursor, exactly D steps ahead, enters the next block at slot 0 and
 // stage 2 runs once per block outside the unrolled ring.  The U_b columns of
 // the first UP column tiles are loaded when the block's stage 1 begins, the
@@ -60,16 +62,39 @@ __device__ __forceinline__ f4 mma(float a, float b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-template <int MT> struct LSlot {
-    float a[MT];
-    f4 x;
+// four consecutive factor values of a column (any element alignment; the
+// HSA targets run with unaligned access enabled)
+typedef float f4a4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef uint32_t u2a2 __attribute__((ext_vector_type(2), aligned(2)));
+template <int DT> struct LQuad;
+template <> struct LQuad<H3D_F32> {
+    static __device__ __forceinline__ f4 ld(const float *p) {
+        const f4a4 v = *(const __attribute__((address_space(1))) f4a4 *)p;
+        return f4{v[0], v[1], v[2], v[3]};
+    }
+};
+template <> struct LQuad<H3D_BF16_SCALED> {
+    static __device__ __forceinline__ f4 ld(const uint16_t *p) {
+        const u2a2 w = *(const __attribute__((address_space(1))) u2a2 *)p;
+        return f4{__uint_as_float(w[0] << 16), __uint_as_float(w[0] & 0xffff0000u),
+                  __uint_as_float(w[1] << 16), __uint_as_float(w[1] & 0xffff0000u)};
+    }
 };
 
-template <int MT> struct LfShape;  // ring depth, U tiles loaded ahead, waves per SIMD
-template <> struct LfShape<1> { static constexpr int D = 4, UP = 1, W = 3; };
-template <> struct LfShape<2> { static constexpr int D = 6, UP = 2, W = 2; };
-template <> struct LfShape<3> { static constexpr int D = 8, UP = 2, W = 1; };
-template <> struct LfShape<4> { static constexpr int D = 8, UP = 2, W = 1; };
+// a super-step: four K-steps of stage 1 (16 source rows); K-step i gives the
+// lane of K slot q the row 16 S + 4 q + i, so a lane's factor values of the
+// four K-steps are four consecutive rows of its column (one load)
+template <int MT> struct LSlot {
+    f4 a[MT];  // rows 16 S + 4 q .. + 3 of this lane's column of tile T
+    f4 x[4];   // [i]: right-hand sides 4 r16 .. 4 r16 + 3 of row 16 S + 4 q + i
+};
+
+// ring depth in super-steps, U tiles loaded ahead, waves per SIMD
+template <int MT> struct LfShape;
+template <> struct LfShape<1> { static constexpr int D = 1, UP = 1, W = 3; };
+template <> struct LfShape<2> { static constexpr int D = 2, UP = 1, W = 2; };
+template <> struct LfShape<3> { static constexpr int D = 2, UP = 2, W = 1; };
+template <> struct LfShape<4> { static constexpr int D = 2, UP = 2, W = 1; };
 
 template <int DT, int MT>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LfShape<MT>::W)))
@@ -110,8 +135,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LfShape
                    static_cast<const F *>(dev::cload(vptr + bj)), static_cast<const F *>(dev::cload(uptr + bj)),
                    bj};
     };
-    // stage-1 steps of a block padded to a multiple of D
-    auto padded = [](int n) { return (((n + 3) >> 2) + D - 1) / D * D; };
+    // stage-1 super-steps of a block padded to a multiple of D
+    auto padded = [](int n) { return (((n + 15) >> 4) + D - 1) / D * D; };
     // first block of nonzero rank at or after b (e1 if none)
     auto skip = [&](int64_t b) {
         while (b < e1 && dev::cload(rank + (grp_blk ? dev::cload(grp_blk + b) : b)) <= 0)
@@ -161,11 +186,17 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LfShape
                 fnx = load(fnb);
         };
         auto fill = [&](LSlot<MT> &R) {
-            const int jc = min(4 * fs + q, fc.n - 1);
+            const int j0 = 16 * fs + 4 * q;
+            const int ja = j0 < fc.n ? j0 : 0;  // a group wholly past the block: any rows
+            // (a group reads at most three values past its column: the next
+            // column, the next block or the chunk's 256 bytes of slack)
 #pragma unroll
             for (int T = 0; T < MT; ++T)
-                R.a[T] = LFac<DT>::ld(fc.V + int64_t(min(16 * T + r16, fc.k - 1)) * fc.n + jc);
-            R.x = *reinterpret_cast<const f4 *>(Xs + (fc.so + jc) * NP + bcol);
+                R.a[T] = LQuad<DT>::ld(fc.V + int64_t(min(16 * T + r16, fc.k - 1)) * fc.n + ja);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                R.x[i] = *reinterpret_cast<const f4 *>(Xs + (fc.so + min(j0 + i, fc.n - 1)) * NP +
+                                                       bcol);
         };
         LSlot<MT> R[D];
 #pragma unroll
@@ -179,7 +210,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LfShape
         cc = load(cb);
         for (;;) {
             const int k = cc.k, n = cc.n;
-            const int S1 = (n + 3) >> 2, S1p = padded(n), KT = (k + 15) >> 4;
+            const int S1 = (n + 15) >> 4, S1p = padded(n), KT = (k + 15) >> 4;
             // U_b columns of the first UP tiles, needed after this block's stage 1
             float u[UP][4][MT];
 #pragma unroll
@@ -201,17 +232,20 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LfShape
                 for (int d = 0; d < D; ++d) {
                     const int s = s0 + d;
                     if (s < S1) {
-                        const bool aj = 4 * s + q < n;
-                        float xv[4];
 #pragma unroll
-                        for (int N = 0; N < 4; ++N)
-                            xv[N] = aj ? R[d].x[N] : 0.f;
+                        for (int i = 0; i < 4; ++i) {
+                            const bool aj = 16 * s + 4 * q + i < n;
+                            float xv[4];
 #pragma unroll
-                        for (int T = 0; T < MT; ++T)
-                            if (T < KT)
+                            for (int N = 0; N < 4; ++N)
+                                xv[N] = aj ? R[d].x[i][N] : 0.f;
 #pragma unroll
-                                for (int N = 0; N < 4; ++N)
-                                    C1[T][N] = mma(R[d].a[T], xv[N], C1[T][N]);
+                            for (int T = 0; T < MT; ++T)
+                                if (T < KT)
+#pragma unroll
+                                    for (int N = 0; N < 4; ++N)
+                                        C1[T][N] = mma(R[d].a[T][i], xv[N], C1[T][N]);
+                        }
                     }
                     fill(R[d]);
                     fadvance();

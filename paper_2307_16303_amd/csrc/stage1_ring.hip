@@ -233,6 +233,171 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     }
 }
 
+// The same product (forward, one item per wave) with each lane's A fragments
+// read four K-steps at a time.  The assignment of rows to K slots is free as
+// long as both operands follow it: K-step i of super-step S gives the lane of
+// K slot q the row 16 S + 4 q + i, so a lane's factor values of four K-steps
+// are four consecutive rows of its column, one 16-byte (FP32) or 8-byte
+// (BF16) load instead of four 4-byte loads that each touch 16 cache lines.
+// The ring holds D2 super-steps.  Rows past the block are masked; their loads
+// stay inside the factor chunk (at most three values past a column, which
+// ends at the next column, the next block or the chunk's 256 bytes of slack).
+// vectors of 4-byte (FP32) and 2-byte (BF16) alignment: global loads at any
+// element offset (the HSA targets run with unaligned access enabled)
+typedef float f4a4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef uint32_t u2a2 __attribute__((ext_vector_type(2), aligned(2)));
+template <int DT> struct QLoad;
+template <> struct QLoad<H3D_F32> {
+    static __device__ __forceinline__ f4 ld(const float *p) {
+        const f4a4 v = *(const __attribute__((address_space(1))) f4a4 *)p;
+        return f4{v[0], v[1], v[2], v[3]};
+    }
+};
+template <> struct QLoad<H3D_BF16_SCALED> {
+    static __device__ __forceinline__ f4 ld(const uint16_t *p) {
+        const u2a2 w = *(const __attribute__((address_space(1))) u2a2 *)p;
+        return f4{__uint_as_float(w[0] << 16), __uint_as_float(w[0] & 0xffff0000u),
+                  __uint_as_float(w[1] << 16), __uint_as_float(w[1] & 0xffff0000u)};
+    }
+};
+
+template <int MT> struct QSlot {
+    f4 a[MT];  // rows 16 S + 4 q .. + 3 of this lane's column of tile t
+    f4 b[4];   // [K-step i]: right-hand sides 4 r16 .. 4 r16 + 3 of row 16 S + 4 q + i
+};
+
+template <int DT, int MT, int D2, bool ACC64>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+    k_s1_quad(const int2 *__restrict__ items, int64_t nitems, const int32_t *__restrict__ seg_len,
+              const int32_t *__restrict__ seg_off, void *const *__restrict__ seg_ptr,
+              const int32_t *__restrict__ rank, const int64_t *__restrict__ blk_col0,
+              const float *__restrict__ scale2, const float *__restrict__ Xs, int NP,
+              float *__restrict__ Z) {
+    using F = typename SFac<DT>::T;
+    const int64_t w = dev::xcd_run(blockIdx.x, gridDim.x) * 4 +
+                      __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (w >= nitems)
+        return;
+    const int lane = threadIdx.x & 63;
+    const int r16 = lane & 15, q = lane >> 4;
+    const int2 it = items[w];
+    const int b = it.x, c0 = it.y * 16 * MT;
+    const int len = seg_len[b], k = rank[b];
+    if (k <= 0 || len <= 0)
+        return;
+    const int64_t off = seg_off[b];
+    const int64_t col0 = blk_col0[b];
+    const F *__restrict__ p = static_cast<const F *>(seg_ptr[b]);
+    float sc = 1.f;
+    if (DT == H3D_BF16_SCALED)
+        sc = scale2[2 * b] * scale2[2 * b + 1];
+    int64_t ce[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+        ce[t] = int64_t(min(c0 + 16 * t + r16, k - 1)) * len;
+    const int S = (len + 15) >> 4;  // super-steps of 16 rows
+    for (int nb = 0; nb < NP; nb += 64) {
+        const int nv = min(64, NP - nb);
+        const int bcol = nb + 4 * min(r16, nv / 4 - 1);
+        f4 C[MT][4];
+#pragma unroll
+        for (int t = 0; t < MT; ++t)
+#pragma unroll
+            for (int N = 0; N < 4; ++N)
+                C[t][N] = f4{0.f, 0.f, 0.f, 0.f};
+        constexpr int A64 = ACC64 ? MT : 1;
+        double acc64[A64][4][4];
+        if constexpr (ACC64) {
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+#pragma unroll
+                for (int N = 0; N < 4; ++N)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj)
+                        acc64[t][N][jj] = 0.0;
+        }
+        auto fill = [&](int s, QSlot<MT> &R) {
+            const int j0 = 16 * s + 4 * q;
+            const int ja = j0 < len ? j0 : 0;  // a group wholly past the block: any rows
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+                R.a[t] = QLoad<DT>::ld(p + ce[t] + ja);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                R.b[i] = *reinterpret_cast<const f4 *>(Xs + (off + min(j0 + i, len - 1)) * NP + bcol);
+        };
+        auto step = [&](int s, const QSlot<MT> &R) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const bool aj = 16 * s + 4 * q + i < len;
+                float bv[4];
+#pragma unroll
+                for (int N = 0; N < 4; ++N)
+                    bv[N] = aj ? R.b[i][N] : 0.f;
+#pragma unroll
+                for (int t = 0; t < MT; ++t)
+#pragma unroll
+                    for (int N = 0; N < 4; ++N)
+                        C[t][N] = __builtin_amdgcn_mfma_f32_16x16x4f32(R.a[t][i], bv[N], C[t][N], 0,
+                                                                       0, 0);
+            }
+        };
+        QSlot<MT> R[D2];
+#pragma unroll
+        for (int d = 0; d < D2; ++d) {
+            fill(d, R[d]);
+            __builtin_amdgcn_sched_barrier(0);  // slots in order (the waits count on it)
+        }
+        int s0 = 0, ks = 0;
+        for (; s0 + D2 <= S; s0 += D2) {
+#pragma unroll
+            for (int d = 0; d < D2; ++d) {
+                step(s0 + d, R[d]);
+                fill(s0 + d + D2, R[d]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if constexpr (ACC64) {
+                ks += 4 * D2;
+                if (ks + 4 * D2 > 64) {
+                    ks = 0;
+#pragma unroll
+                    for (int t = 0; t < MT; ++t)
+#pragma unroll
+                        for (int N = 0; N < 4; ++N) {
+#pragma unroll
+                            for (int jj = 0; jj < 4; ++jj)
+                                acc64[t][N][jj] += double(C[t][N][jj]);
+                            C[t][N] = f4{0.f, 0.f, 0.f, 0.f};
+                        }
+                }
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < D2; ++d)
+            if (s0 + d < S)
+                step(s0 + d, R[d]);
+        if (4 * r16 < nv) {
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int c = c0 + 16 * t + 4 * q + jj;
+                    if (c < k) {
+                        f4 o;
+#pragma unroll
+                        for (int N = 0; N < 4; ++N) {
+                            double v = double(C[t][N][jj]);
+                            if constexpr (ACC64)
+                                v += acc64[t][N][jj];
+                            o[N] = float(v * sc);
+                        }
+                        *reinterpret_cast<f4 *>(Z + (col0 + c) * NP + nb + 4 * r16) = o;
+                    }
+                }
+        }
+    }
+}
+
 // The same product with a run of G consecutive items per wave, for levels of
 // many short columns: the refill cursor runs across the items, so the ring
 // never drains between them.  Each item's K-steps are padded to a multiple of
@@ -461,11 +626,14 @@ void launch_s1_ring(Plan &P, int l, bool adjoint, const int2 *items, int64_t nit
 #define H3D_S1G(DT, MT, A)                                                                      \
     k_s1_ring_g<DT, MT, (MT <= 2 ? 8 : 6), A><<<nwg, 256, 0, s>>>(                              \
         items, nitems, G, len, off, ptr, P.blk_rank, P.blk_col0, P.blk_scale, Xs, NP, Z)
+#define H3D_S1Q(DT, MT, A)                                                                      \
+    k_s1_quad<DT, MT, 2, A><<<int((nitems + 3) / 4), 256, 0, s>>>(                              \
+        items, nitems, len, off, ptr, P.blk_rank, P.blk_col0, P.blk_scale, Xs, NP, Z)
 #define H3D_S1R_PN(DT, MT, A)                                                                   \
     if (panel)                                                                                  \
         H3D_S1R(DT, MT, A, true);                                                               \
     else if (G == 1)                                                                            \
-        H3D_S1R(DT, MT, A, false);                                                              \
+        H3D_S1Q(DT, MT, A);                                                                     \
     else                                                                                        \
         H3D_S1G(DT, MT, A);
 #define H3D_S1R_DT(DT)                                                                          \
@@ -490,6 +658,7 @@ void launch_s1_ring(Plan &P, int l, bool adjoint, const int2 *items, int64_t nit
     }
 #undef H3D_S1R_DT
 #undef H3D_S1R_PN
+#undef H3D_S1Q
 #undef H3D_S1G
 #undef H3D_S1R
     H3D_LAUNCH_CHECK();
