@@ -315,7 +315,7 @@ struct Plan {
     int64_t bt_ns2r[kMaxLevels + 1] = {};
     int32_t *bt_s2k[kMaxLevels + 1][2] = {};  // K-steps per box of the ring kernel (fwd, adj)
     int32_t *bt_s2k16[kMaxLevels + 1] = {};    // BF16 stage 2: K-steps of 16 columns per box
-    int32_t *bt_pk[kMaxLevels + 1] = {};  // adjoint stage 1 above the chunk level: K-steps per box
+    int32_t *bt_pk[kMaxLevels + 1] = {};  // adjoint stage 1 above the chunk level: 16-row super-steps per box
     int bt_mt1[kMaxLevels + 1] = {};  // 16-column tiles per stage-1 wave
     int bt_split[kMaxLevels + 1] = {};  // stage-1 rows per part (0: columns not split)
     int32_t *bt_grp[kMaxLevels + 1] = {};  // split levels: (first item, parts) per tile

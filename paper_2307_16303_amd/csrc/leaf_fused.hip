@@ -9,11 +9,14 @@
 //            k factor columns.
 // On the 16x16x4 FP32 matrix core a lane holds element jj of its accumulator
 // at row 4 (lane / 16) + jj, column lane % 16; the B operand of a K-step is
-// the element at row lane / 16 of the four K rows.  Taking stage 2's K-steps
-// as (T, jj) with the K rows 16 T + 4 q + jj (q = lane / 16), the B operand of
+// the element at row lane / 16 of the four K rows.  Row rho of stage 1's tile
+// T is factor column 16 T + 4 (rho % 4) + rho / 4, so element jj of lane q's
+// accumulator T is column 16 T + 4 jj + q (q = lane / 16).  Taking stage 2's
+// K-steps as (T, jj), with the K rows 16 T + 4 jj .. + 3, the B operand of
 // step (T, jj) is exactly element jj of stage 1's accumulator T: stage 1's
-// results feed stage 2 in place, without LDS or memory.  Stage 2's A operand
-// is then U_b's column 16 T + 4 q + jj.  Each block's FP32 stage-2 tiles (at
+// results feed stage 2 in place, without LDS or memory, and a block of rank
+// k takes only the K-steps with 16 T + 4 jj < k.  Stage 2's A operand is then
+// U_b's column 16 T + 4 jj + q.  Each block's FP32 stage-2 tiles (at
 // most 64 columns) are added into FP64 sums of the leaf's rows, which start
 // from Y (the near field and the coarser levels) and are written back once.
 //
@@ -92,7 +95,7 @@ template <int MT> struct LSlot {
 // ring depth in super-steps, U tiles loaded ahead, waves per SIMD
 template <int MT> struct LfShape;
 template <> struct LfShape<1> { static constexpr int D = 1, UP = 1, W = 3; };
-template <> struct LfShape<2> { static constexpr int D = 2, UP = 1, W = 2; };
+template <> struct LfShape<2> { static constexpr int D = 2, UP = 2, W = 2; };
 template <> struct LfShape<3> { static constexpr int D = 2, UP = 2, W = 1; };
 template <> struct LfShape<4> { static constexpr int D = 2, UP = 2, W = 1; };
 
@@ -112,6 +115,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LfShape
         return;
     const int lane = threadIdx.x;
     const int r16 = lane & 15, q = lane >> 4;
+    const int cs1 = 4 * (r16 & 3) + (r16 >> 2);  // this lane's factor column in a stage-1 tile
     const int64_t t = items[w];
     const int32_t bs = leaf_off[t], bm = leaf_off[t + 1] - bs;
     const int64_t e0 = grp_begin[gbase + t], e1 = grp_begin[gbase + t + 1];
@@ -192,7 +196,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LfShape
             // column, the next block or the chunk's 256 bytes of slack)
 #pragma unroll
             for (int T = 0; T < MT; ++T)
-                R.a[T] = LQuad<DT>::ld(fc.V + int64_t(min(16 * T + r16, fc.k - 1)) * fc.n + ja);
+                R.a[T] = LQuad<DT>::ld(fc.V + int64_t(min(16 * T + cs1, fc.k - 1)) * fc.n + ja);
 #pragma unroll
             for (int i = 0; i < 4; ++i)
                 R.x[i] = *reinterpret_cast<const f4 *>(Xs + (fc.so + min(j0 + i, fc.n - 1)) * NP +
@@ -220,7 +224,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LfShape
 #pragma unroll
                     for (int M = 0; M < MT; ++M)
                         u[T][jj][M] =
-                            LFac<DT>::ld(cc.U + int64_t(min(16 * T + 4 * q + jj, k - 1)) * bm + ic[M]);
+                            LFac<DT>::ld(cc.U + int64_t(min(16 * T + 4 * jj + q, k - 1)) * bm + ic[M]);
             f4 C1[MT][4];
 #pragma unroll
             for (int T = 0; T < MT; ++T)
@@ -266,7 +270,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LfShape
                     for (int N = 0; N < 4; ++N)
                         C1[T][N] *= sc;
             }
-            // ---- stage 2: C2[M][N] = U[16 M .., 16 T + 4 q + jj] C1[T][N][jj]
+            // ---- stage 2: C2[M][N] = U[16 M .., 16 T + 4 jj + q] C1[T][N][jj]
             f4 C2[MT][4];
 #pragma unroll
             for (int M = 0; M < MT; ++M)
@@ -286,11 +290,13 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LfShape
                             ut[jj][M] = u[T < UP ? T : 0][jj][M];
                         else
                             ut[jj][M] = LFac<DT>::ld(
-                                cc.U + int64_t(min(16 * T + 4 * q + jj, k - 1)) * bm + ic[M]);
+                                cc.U + int64_t(min(16 * T + 4 * jj + q, k - 1)) * bm + ic[M]);
                     }
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
-                    const bool kc = 16 * T + 4 * q + jj < k;
+                    if (16 * T + 4 * jj >= k)
+                        break;  // columns 16 T + 4 jj .. all past the rank
+                    const bool kc = 16 * T + 4 * jj + q < k;
 #pragma unroll
                     for (int M = 0; M < MT; ++M) {
                         const float av = (kc && ai[M]) ? ut[jj][M] : 0.f;

@@ -5,21 +5,27 @@
 // One wave per (block, 16 MT factor columns), four waves per workgroup on
 // consecutive items; forward items run in source-box order, so the blocks of
 // one source box (the same rows of X) run side by side on one CU.  MT
-// 16-column tiles against the
-// four 16-column right-hand-side tiles, 4 MT FP32 MFMAs per K-step of four
-// source rows, so every X fragment feeds MT MFMAs and every factor fragment
-// four.  The fragments of the next D K-steps are in flight while a step's
-// MFMAs run: the loop is a steady part in which every step refills its slot
-// and a tail of fewer than D steps without refills, so the compiler counts
-// the loads in flight exactly and waits for one slot at a time.  Every load is
-// issued from a row and column clamped into the block; rows past the block
-// are masked where the MFMA uses them, columns past the rank are computed and
-// not written.  Tile N, column n of the MFMA is right-hand side 4 n + N of the
-// group of 64, so a lane's four B values and four outputs are contiguous (one
-// 16-byte load or store).  Levels whose boxes hold at most 256 points sum each
-// column's rows in FP32 (at most 64 K-steps, as the other many-RHS kernels
-// flush); longer ones flush the FP32 tiles into FP64 sums every 64 K-steps.
-// Levels split into row parts keep the split kernels.
+// 16-column tiles against the four 16-column right-hand-side tiles, 4 MT FP32
+// MFMAs per K-step of four source rows, so every X fragment feeds MT MFMAs and
+// every factor fragment four.  The assignment of rows to K slots is free as
+// long as both operands follow it: K-step i of a super-step S (16 rows) gives
+// the lane of K slot q the row 16 S + 4 q + i, so a lane's factor values of
+// the four K-steps are four consecutive rows of its column, one 16-byte
+// (FP32) or 8-byte (BF16) load instead of four 4-byte loads that each touch 16
+// cache lines.  The fragments of the next D2 super-steps are in flight while
+// a step's MFMAs run: the loop is a steady part in which every step refills
+// its slot and a tail of fewer than D2 steps without refills, so the compiler
+// counts the loads in flight exactly and waits for one slot at a time.  Rows
+// past the block are masked where the MFMA uses them; their loads stay inside
+// the factor chunk (at most three values past a column, which ends at the next
+// column, the next block or the chunk's 256 bytes of slack); columns past the
+// rank are computed and not written.  Tile N, column n of the MFMA is
+// right-hand side 4 n + N of the group of 64, so a lane's four B values and
+// four outputs are contiguous (one 16-byte load or store).  Levels whose boxes
+// hold at most 256 points sum each column's rows in FP32 (at most 64 K-steps,
+// as the other many-RHS kernels flush); longer ones flush the FP32 tiles into
+// FP64 sums every 64 K-steps.  Levels split into row parts keep the split
+// kernels.
 #include "product_items.hpp"
 
 namespace h3d {
@@ -40,208 +46,6 @@ template <> struct SFac<H3D_BF16_SCALED> {
     }
 };
 
-template <int MT> struct S1Slot {
-    float a[MT];
-    f4 b;
-    int kv;  // PANEL: rows of the chunk box from this step's first row
-};
-
-template <int DT, int MT, int D, bool ACC64, bool PANEL>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-    k_s1_ring(const int2 *__restrict__ items, int64_t nitems, const int32_t *__restrict__ seg_len,
-              const int32_t *__restrict__ seg_off, void *const *__restrict__ seg_ptr,
-              const int32_t *__restrict__ rank, const int64_t *__restrict__ blk_col0,
-              const float *__restrict__ scale2, const float *__restrict__ Xs, int NP,
-              float *__restrict__ Z, const int32_t *__restrict__ leaf_off,
-              const int32_t *__restrict__ leaf_of, int shc, int shl,
-              const int32_t *__restrict__ psteps) {
-    using F = typename SFac<DT>::T;
-    const int64_t w = dev::xcd_run(blockIdx.x, gridDim.x) * 4 +
-                      __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (w >= nitems)
-        return;
-    const int lane = threadIdx.x & 63;
-    const int r16 = lane & 15, q = lane >> 4;
-    const int2 it = items[w];
-    const int b = it.x, c0 = it.y * 16 * MT;
-    const int len = seg_len[b], k = rank[b];
-    if (k <= 0 || len <= 0)
-        return;
-    const int32_t off = seg_off[b];
-    const int64_t col0 = blk_col0[b];
-    const F *__restrict__ p = static_cast<const F *>(seg_ptr[b]);
-    float sc = 1.f;
-    if (DT == H3D_BF16_SCALED)
-        sc = scale2[2 * b] * scale2[2 * b + 1];
-    int cc[MT];  // this lane's factor column of tile t (clamped; outputs past k are not written)
-#pragma unroll
-    for (int t = 0; t < MT; ++t)
-        cc[t] = min(c0 + 16 * t + r16, k - 1);
-    // K-steps.  PANEL (the adjoint above the chunk level): U_b is stored as one
-    // row panel per chunk box of the target box, so the rows are taken chunk
-    // box by chunk box, each padded to whole K-steps (the count per box from
-    // a table), with a scalar cursor over the chunk boxes one ahead.
-    const int S = PANEL ? psteps[leaf_of[off] >> shl] : (len + 3) >> 2;
-    const int ch_last = PANEL ? (leaf_of[off + len - 1] >> shc) : 0;
-    for (int nb = 0; nb < NP; nb += 64) {
-        const int nv = min(64, NP - nb);
-        const int bcol = nb + 4 * min(r16, nv / 4 - 1);
-        f4 C[MT][4];
-#pragma unroll
-        for (int t = 0; t < MT; ++t)
-#pragma unroll
-            for (int N = 0; N < 4; ++N)
-                C[t][N] = f4{0.f, 0.f, 0.f, 0.f};
-        constexpr int A64 = ACC64 ? MT : 1;
-        double acc64[A64][4][4];
-        if constexpr (ACC64) {
-#pragma unroll
-            for (int t = 0; t < MT; ++t)
-#pragma unroll
-                for (int N = 0; N < 4; ++N)
-#pragma unroll
-                    for (int jj = 0; jj < 4; ++jj)
-                        acc64[t][N][jj] = 0.0;
-        }
-        // chunk cursor (PANEL): rows [pr0, pr0 + plen) of chunk box ch, step cs
-        int ch = 0, cs = 0, pr0 = 0, plen = 1, nch = 0, npr0 = 0, nplen = 1;
-        auto chunk_rows = [&](int c, int &r0, int &n) {
-            r0 = dev::cload(leaf_off + (int64_t(c) << shc));
-            n = dev::cload(leaf_off + (int64_t(c + 1) << shc)) - r0;
-        };
-        auto next_chunk = [&](int c) {  // next chunk box with rows after c (ch_last + 1: none)
-            int r0, n;
-            for (++c; c <= ch_last; ++c) {
-                chunk_rows(c, r0, n);
-                if (n > 0)
-                    break;
-            }
-            return c;
-        };
-        if constexpr (PANEL) {
-            ch = leaf_of[off] >> shc;
-            chunk_rows(ch, pr0, plen);
-            nch = next_chunk(ch);
-            if (nch <= ch_last)
-                chunk_rows(nch, npr0, nplen);
-        }
-        auto padvance = [&] {
-            if (4 * ++cs < plen)
-                return;
-            if (nch > ch_last) {  // past the last chunk: stay on its last step
-                --cs;
-                return;
-            }
-            ch = nch;
-            pr0 = npr0;
-            plen = nplen;
-            cs = 0;
-            nch = next_chunk(ch);
-            if (nch <= ch_last)
-                chunk_rows(nch, npr0, nplen);
-        };
-        auto fill = [&](int s, S1Slot<MT> &sl) {
-            if constexpr (PANEL) {
-                const int lr = min(4 * cs + q, plen - 1);
-                const int64_t base = int64_t(pr0 - off) * k + lr;
-#pragma unroll
-                for (int t = 0; t < MT; ++t)
-                    sl.a[t] = SFac<DT>::ld(p + base + int64_t(cc[t]) * plen);
-                sl.b = *reinterpret_cast<const f4 *>(Xs + (int64_t(pr0) + lr) * NP + bcol);
-                sl.kv = plen - 4 * cs;
-            } else {
-                const int jc = min(4 * s + q, len - 1);
-#pragma unroll
-                for (int t = 0; t < MT; ++t)
-                    sl.a[t] = SFac<DT>::ld(p + int64_t(cc[t]) * len + jc);
-                sl.b = *reinterpret_cast<const f4 *>(Xs + (int64_t(off) + jc) * NP + bcol);
-            }
-        };
-        auto step = [&](int s, const S1Slot<MT> &sl) {
-            const bool aj = PANEL ? q < sl.kv : 4 * s + q < len;
-            float bv[4];
-#pragma unroll
-            for (int N = 0; N < 4; ++N)
-                bv[N] = aj ? sl.b[N] : 0.f;
-#pragma unroll
-            for (int t = 0; t < MT; ++t)
-#pragma unroll
-                for (int N = 0; N < 4; ++N)
-                    C[t][N] = __builtin_amdgcn_mfma_f32_16x16x4f32(sl.a[t], bv[N], C[t][N], 0, 0, 0);
-        };
-        S1Slot<MT> R[D];
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            fill(d, R[d]);
-            if constexpr (PANEL)
-                padvance();
-            __builtin_amdgcn_sched_barrier(0);  // slots in order (the waits count on it)
-        }
-        // steady part: every step refills its slot (past the end: clamped rows,
-        // never consumed); then a tail of fewer than D steps without refills
-        int s0 = 0, ks = 0;
-        for (; s0 + D <= S; s0 += D) {
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                step(s0 + d, R[d]);
-                fill(s0 + d + D, R[d]);
-                if constexpr (PANEL)
-                    padvance();
-                // keep each refill right after its step: the scheduler would
-                // otherwise sink the loads of all steps below all the MFMAs
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            if constexpr (ACC64) {
-                ks += D;
-                if (ks + D > 64) {
-                    ks = 0;
-#pragma unroll
-                    for (int t = 0; t < MT; ++t)
-#pragma unroll
-                        for (int N = 0; N < 4; ++N) {
-#pragma unroll
-                            for (int jj = 0; jj < 4; ++jj)
-                                acc64[t][N][jj] += double(C[t][N][jj]);
-                            C[t][N] = f4{0.f, 0.f, 0.f, 0.f};
-                        }
-                }
-            }
-        }
-#pragma unroll
-        for (int d = 0; d < D; ++d)
-            if (s0 + d < S)
-                step(s0 + d, R[d]);
-        if (4 * r16 < nv) {
-#pragma unroll
-            for (int t = 0; t < MT; ++t)
-#pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    const int c = c0 + 16 * t + 4 * q + jj;
-                    if (c < k) {
-                        f4 o;
-#pragma unroll
-                        for (int N = 0; N < 4; ++N) {
-                            double v = double(C[t][N][jj]);
-                            if constexpr (ACC64)
-                                v += acc64[t][N][jj];
-                            o[N] = float(v * sc);
-                        }
-                        *reinterpret_cast<f4 *>(Z + (col0 + c) * NP + nb + 4 * r16) = o;
-                    }
-                }
-        }
-    }
-}
-
-// The same product (forward, one item per wave) with each lane's A fragments
-// read four K-steps at a time.  The assignment of rows to K slots is free as
-// long as both operands follow it: K-step i of super-step S gives the lane of
-// K slot q the row 16 S + 4 q + i, so a lane's factor values of four K-steps
-// are four consecutive rows of its column, one 16-byte (FP32) or 8-byte
-// (BF16) load instead of four 4-byte loads that each touch 16 cache lines.
-// The ring holds D2 super-steps.  Rows past the block are masked; their loads
-// stay inside the factor chunk (at most three values past a column, which
-// ends at the next column, the next block or the chunk's 256 bytes of slack).
 // vectors of 4-byte (FP32) and 2-byte (BF16) alignment: global loads at any
 // element offset (the HSA targets run with unaligned access enabled)
 typedef float f4a4 __attribute__((ext_vector_type(4), aligned(4)));
@@ -264,15 +68,18 @@ template <> struct QLoad<H3D_BF16_SCALED> {
 template <int MT> struct QSlot {
     f4 a[MT];  // rows 16 S + 4 q .. + 3 of this lane's column of tile t
     f4 b[4];   // [K-step i]: right-hand sides 4 r16 .. 4 r16 + 3 of row 16 S + 4 q + i
+    int kv;    // PANEL: rows of the chunk box from this super-step's first row
 };
 
-template <int DT, int MT, int D2, bool ACC64>
+template <int DT, int MT, int D2, bool ACC64, bool PANEL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     k_s1_quad(const int2 *__restrict__ items, int64_t nitems, const int32_t *__restrict__ seg_len,
               const int32_t *__restrict__ seg_off, void *const *__restrict__ seg_ptr,
               const int32_t *__restrict__ rank, const int64_t *__restrict__ blk_col0,
               const float *__restrict__ scale2, const float *__restrict__ Xs, int NP,
-              float *__restrict__ Z) {
+              float *__restrict__ Z, const int32_t *__restrict__ leaf_off,
+              const int32_t *__restrict__ leaf_of, int shc, int shl,
+              const int32_t *__restrict__ psteps) {
     using F = typename SFac<DT>::T;
     const int64_t w = dev::xcd_run(blockIdx.x, gridDim.x) * 4 +
                       __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -291,11 +98,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     float sc = 1.f;
     if (DT == H3D_BF16_SCALED)
         sc = scale2[2 * b] * scale2[2 * b + 1];
-    int64_t ce[MT];
+    int cc[MT];  // this lane's factor column of tile t (clamped; outputs past k are not written)
 #pragma unroll
     for (int t = 0; t < MT; ++t)
-        ce[t] = int64_t(min(c0 + 16 * t + r16, k - 1)) * len;
-    const int S = (len + 15) >> 4;  // super-steps of 16 rows
+        cc[t] = min(c0 + 16 * t + r16, k - 1);
+    // super-steps.  PANEL (the adjoint above the chunk level): U_b is stored
+    // as one row panel per chunk box of the target box, so the rows are taken
+    // chunk box by chunk box, each padded to whole super-steps (the count per
+    // box from a table), with a scalar cursor over the chunk boxes one ahead.
+    const int S = PANEL ? psteps[leaf_of[off] >> shl] : (len + 15) >> 4;
+    const int ch_last = PANEL ? (leaf_of[off + len - 1] >> shc) : 0;
     for (int nb = 0; nb < NP; nb += 64) {
         const int nv = min(64, NP - nb);
         const int bcol = nb + 4 * min(r16, nv / 4 - 1);
@@ -316,20 +128,63 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
                     for (int jj = 0; jj < 4; ++jj)
                         acc64[t][N][jj] = 0.0;
         }
+        // chunk cursor (PANEL): rows [pr0, pr0 + plen) of chunk box ch, super-step cs
+        int ch = 0, cs = 0, pr0 = 0, plen = 1, nch = 0, npr0 = 0, nplen = 1;
+        auto chunk_rows = [&](int c, int &r0, int &n) {
+            r0 = dev::cload(leaf_off + (int64_t(c) << shc));
+            n = dev::cload(leaf_off + (int64_t(c + 1) << shc)) - r0;
+        };
+        auto next_chunk = [&](int c) {  // next chunk box with rows after c (ch_last + 1: none)
+            int r0, n;
+            for (++c; c <= ch_last; ++c) {
+                chunk_rows(c, r0, n);
+                if (n > 0)
+                    break;
+            }
+            return c;
+        };
+        if constexpr (PANEL) {
+            ch = leaf_of[off] >> shc;
+            chunk_rows(ch, pr0, plen);
+            nch = next_chunk(ch);
+            if (nch <= ch_last)
+                chunk_rows(nch, npr0, nplen);
+        }
+        auto padvance = [&] {
+            if (16 * ++cs < plen)
+                return;
+            if (nch > ch_last) {  // past the last chunk: stay on its last super-step
+                --cs;
+                return;
+            }
+            ch = nch;
+            pr0 = npr0;
+            plen = nplen;
+            cs = 0;
+            nch = next_chunk(ch);
+            if (nch <= ch_last)
+                chunk_rows(nch, npr0, nplen);
+        };
         auto fill = [&](int s, QSlot<MT> &R) {
-            const int j0 = 16 * s + 4 * q;
-            const int ja = j0 < len ? j0 : 0;  // a group wholly past the block: any rows
+            // rows j0 .. j0 + 3 of the block (PANEL: of the chunk box's panel)
+            const int rows = PANEL ? plen : len;
+            const int j0 = (PANEL ? 16 * cs : 16 * s) + 4 * q;
+            const int ja = j0 < rows ? j0 : 0;  // a group wholly past the rows: any rows
+            const int64_t base = PANEL ? int64_t(pr0 - off) * k : 0;
+            const int64_t r0 = PANEL ? pr0 : off;
 #pragma unroll
             for (int t = 0; t < MT; ++t)
-                R.a[t] = QLoad<DT>::ld(p + ce[t] + ja);
+                R.a[t] = QLoad<DT>::ld(p + base + int64_t(cc[t]) * rows + ja);
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                R.b[i] = *reinterpret_cast<const f4 *>(Xs + (off + min(j0 + i, len - 1)) * NP + bcol);
+                R.b[i] = *reinterpret_cast<const f4 *>(Xs + (r0 + min(j0 + i, rows - 1)) * NP + bcol);
+            if constexpr (PANEL)
+                R.kv = plen - 16 * cs;
         };
         auto step = [&](int s, const QSlot<MT> &R) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const bool aj = 16 * s + 4 * q + i < len;
+                const bool aj = PANEL ? 4 * q + i < R.kv : 16 * s + 4 * q + i < len;
                 float bv[4];
 #pragma unroll
                 for (int N = 0; N < 4; ++N)
@@ -346,14 +201,22 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 #pragma unroll
         for (int d = 0; d < D2; ++d) {
             fill(d, R[d]);
+            if constexpr (PANEL)
+                padvance();
             __builtin_amdgcn_sched_barrier(0);  // slots in order (the waits count on it)
         }
+        // steady part: every step refills its slot (past the end: clamped rows,
+        // never consumed); then a tail of fewer than D2 steps without refills
         int s0 = 0, ks = 0;
         for (; s0 + D2 <= S; s0 += D2) {
 #pragma unroll
             for (int d = 0; d < D2; ++d) {
                 step(s0 + d, R[d]);
                 fill(s0 + d + D2, R[d]);
+                if constexpr (PANEL)
+                    padvance();
+                // keep each refill right after its step: the scheduler would
+                // otherwise sink the loads of all steps below all the MFMAs
                 __builtin_amdgcn_sched_barrier(0);
             }
             if constexpr (ACC64) {
@@ -398,9 +261,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     }
 }
 
+template <int MT> struct S1Slot {
+    float a[MT];
+    f4 b;
+};
+
 // The same product with a run of G consecutive items per wave, for levels of
-// many short columns: the refill cursor runs across the items, so the ring
-// never drains between them.  Each item's K-steps are padded to a multiple of
+// many short columns, one K-step (four rows) per slot: the refill cursor runs
+// across the items, so the ring never drains between them.  Each item's
+// K-steps are padded to a multiple of
 // D (padded steps load the item's last rows again and issue no MFMA), so the
 // refill cursor enters the next item at slot 0 and the write-out of an item
 // runs outside the unrolled ring; the first D steps of an item are written
@@ -571,8 +440,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     }
 }
 
-// K-steps of the row panels of every box of level l (sum over its chunk boxes
-// of ceil(rows / 4)); sh: 3 (chunk level - l), shc: 3 (L - chunk level)
+// super-steps of the row panels of every box of level l (sum over its chunk
+// boxes of ceil(rows / 16)); sh: 3 (chunk level - l), shc: 3 (L - chunk level)
 __global__ void k_panel_steps(int64_t nbox, int sh, int shc, const int32_t *__restrict__ leaf_off,
                               int32_t *__restrict__ steps) {
     const int64_t tb = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -580,7 +449,7 @@ __global__ void k_panel_steps(int64_t nbox, int sh, int shc, const int32_t *__re
         return;
     int64_t sum = 0;
     for (int64_t c = tb << sh; c < (tb + 1) << sh; ++c)
-        sum += (leaf_off[(c + 1) << shc] - leaf_off[c << shc] + 3) >> 2;
+        sum += (leaf_off[(c + 1) << shc] - leaf_off[c << shc] + 15) >> 4;
     steps[tb] = int32_t(sum);
 }
 
@@ -614,26 +483,23 @@ void launch_s1_ring(Plan &P, int l, bool adjoint, const int2 *items, int64_t nit
     const int32_t *off = adjoint ? P.blk_toff : P.blk_soff;
     void *const *ptr = adjoint ? P.blk_uptr : P.blk_vptr;
     const int shc = 3 * (P.L - P.chunk_level);
-    // ring of eight K-steps (six for three or four tiles, within 256 registers)
-    // levels of boxes under 64 points: G items per wave, about 16 waves per
-    // SIMD (one item per wave measured faster for longer columns)
+    // one item per wave: a ring of two super-steps (eight K-steps); levels of
+    // boxes under 64 points: G items per wave, about 16 waves per SIMD, a ring
+    // of eight K-steps (six for three or four tiles, within 256 registers)
     const int G = P.mean_box[l] < 64 ? int(std::max<int64_t>(1, nitems / 16384)) : 1;
     const int nwg = int(((nitems + G - 1) / G + 3) / 4);
-#define H3D_S1R(DT, MT, A, PN)                                                                  \
-    k_s1_ring<DT, MT, (MT <= 2 ? 8 : 6), A, PN><<<int((nitems + 3) / 4), 256, 0, s>>>(         \
-        items, nitems, len, off, ptr, P.blk_rank, P.blk_col0, P.blk_scale, Xs, NP, Z,           \
-        P.leaf_off, P.leaf_of, shc, 3 * (P.L - l), P.bt_pk[l])
 #define H3D_S1G(DT, MT, A)                                                                      \
     k_s1_ring_g<DT, MT, (MT <= 2 ? 8 : 6), A><<<nwg, 256, 0, s>>>(                              \
         items, nitems, G, len, off, ptr, P.blk_rank, P.blk_col0, P.blk_scale, Xs, NP, Z)
-#define H3D_S1Q(DT, MT, A)                                                                      \
-    k_s1_quad<DT, MT, 2, A><<<int((nitems + 3) / 4), 256, 0, s>>>(                              \
-        items, nitems, len, off, ptr, P.blk_rank, P.blk_col0, P.blk_scale, Xs, NP, Z)
+#define H3D_S1Q(DT, MT, A, PN)                                                                  \
+    k_s1_quad<DT, MT, 2, A, PN><<<int((nitems + 3) / 4), 256, 0, s>>>(                          \
+        items, nitems, len, off, ptr, P.blk_rank, P.blk_col0, P.blk_scale, Xs, NP, Z,           \
+        P.leaf_off, P.leaf_of, shc, 3 * (P.L - l), P.bt_pk[l])
 #define H3D_S1R_PN(DT, MT, A)                                                                   \
     if (panel)                                                                                  \
-        H3D_S1R(DT, MT, A, true);                                                               \
+        H3D_S1Q(DT, MT, A, true);                                                               \
     else if (G == 1)                                                                            \
-        H3D_S1Q(DT, MT, A);                                                                     \
+        H3D_S1Q(DT, MT, A, false);                                                              \
     else                                                                                        \
         H3D_S1G(DT, MT, A);
 #define H3D_S1R_DT(DT)                                                                          \
@@ -660,7 +526,6 @@ void launch_s1_ring(Plan &P, int l, bool adjoint, const int2 *items, int64_t nit
 #undef H3D_S1R_PN
 #undef H3D_S1Q
 #undef H3D_S1G
-#undef H3D_S1R
     H3D_LAUNCH_CHECK();
 }
 

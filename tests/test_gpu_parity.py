@@ -479,6 +479,33 @@ def test_many_rhs_low_precision(rhs_cloud, dtype, bound):
 
 
 @pytest.mark.parametrize("dtype,bound", [("fp32", 1e-6), ("bf16", 1e-5)])
+def test_many_rhs_row_panel_levels(dtype, bound):
+    """A tree deep enough for U_b to be stored as row panels above the chunk
+    level: 60,000 points, leaves of 32, depth 4; levels 3 and 4 hold 117 and
+    15 points per box on average, so the chunk level is 3 and level 2's
+    adjoint stage 1 walks the row panels chunk box by chunk box (16-row
+    super-steps padded per chunk box).  Three columns of a 64-RHS product and
+    of its adjoint (lanes 0, 37 and 63 of the group of 64), element by element
+    against the oracle applying the GPU's own factors."""
+    n = 60000
+    pts = inputs.uniform_points(n, seed=35)
+    kw = dict(leaf_size=32, tol=1e-7, **CUBE)
+    op = gpu_build(pts, factor_dtype=dtype, **kw)
+    assert op.stats()["depth"] == 4
+    X = inputs.normal_rhs(n, seed=36, nrhs=64)
+    Y, Ya = gpu_apply(op, X), gpu_apply(op, X, adjoint=True)
+    ref = oracle.HODLR3D(pts, **oracle_kw(kw))
+    ref.set_factors(op.export("far")[5], op.export("factors_u"), op.export("factors_v"))
+    cols = [0, 37, 63]
+    e2, einf = colwise_errors(Y[:, cols], ref.matvec(X[:, cols]))
+    ea2, eainf = colwise_errors(Ya[:, cols], ref.rmatvec(X[:, cols]))
+    print(f"[row panels] {dtype}: column 2-norm {e2:.3e}, element {einf:.3e}; adjoint "
+          f"{ea2:.3e}, {eainf:.3e}")
+    assert e2 <= bound and einf <= bound and ea2 <= bound and eainf <= bound
+    op.close()
+
+
+@pytest.mark.parametrize("dtype,bound", [("fp32", 1e-6), ("bf16", 1e-5)])
 def test_many_rhs_fused_leaves_of_64(dtype, bound):
     """The finest level in one pass per leaf for leaves of 17 to 64 rows on
     average, with leaves of every 16-row tile count (1 to 4): 14,000 points of
