@@ -3,7 +3,10 @@
 //
 // One wave per (target box, 64-row tile): four 16-row tiles M against four
 // 16-column right-hand-side tiles N, 16 FP32 MFMAs per K-step of four factor
-// columns, so every fragment loaded feeds four MFMAs.  The K-steps run over the
+// columns, so every fragment loaded feeds four MFMAs.  Where the factor's
+// columns are contiguous over the box's rows (all but the row panels), tile
+// t's MFMA row r is row 4 r + t of the 64, so that a lane's four A values of a
+// K-step are four consecutive rows of its column, read with one load.  The K-steps run over the
 // columns of all blocks of the box in block order; their count S is known from
 // a table (sum over the box's blocks of ceil(k_b / 4)), so the loop is a
 // steady part in which every step refills its ring slot and a tail without
@@ -39,12 +42,38 @@ template <> struct RFac<H3D_BF16_SCALED> {
     }
 };
 
+// QUAD: tile t, row r of the MFMA is row r0 + 4 r + t of the tile of 64,
+// so a lane's four A values of a K-step are four consecutive rows of one
+// factor column (one 16-byte FP32 or 8-byte BF16 load); otherwise row
+// r0 + 16 t + r (row panels: a tile may cross chunk boxes).
+typedef float f4a4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef uint32_t u2a2 __attribute__((ext_vector_type(2), aligned(2)));
+template <int DT> struct RQuad;
+template <> struct RQuad<H3D_F32> {
+    static __device__ __forceinline__ f4 ld(const float *p) {
+        const f4a4 v = *(const __attribute__((address_space(1))) f4a4 *)p;
+        return f4{v[0], v[1], v[2], v[3]};
+    }
+};
+template <> struct RQuad<H3D_BF16_SCALED> {
+    static __device__ __forceinline__ f4 ld(const uint16_t *p) {
+        const u2a2 w = *(const __attribute__((address_space(1))) u2a2 *)p;
+        return f4{__uint_as_float(w[0] << 16), __uint_as_float(w[0] & 0xffff0000u),
+                  __uint_as_float(w[1] << 16), __uint_as_float(w[1] & 0xffff0000u)};
+    }
+};
+
 struct Slot {
-    float a[4];
+    f4 a;  // [t]: this lane's A value of tile t
     f4 b;
 };
 
-template <int DT, int D>
+// the Y row of tile t, accumulator element jj of lane quarter q
+template <bool QUAD> __device__ __forceinline__ int s2_row(int r0, int t, int q, int jj) {
+    return QUAD ? r0 + 16 * q + 4 * jj + t : r0 + 16 * t + 4 * q + jj;
+}
+
+template <int DT, int D, bool QUAD>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1)))
     k_s2_ring(const int2 *__restrict__ items, int64_t nitems, int64_t gbase,
               const int32_t *__restrict__ leaf_off, int sh, const int64_t *__restrict__ grp_begin,
@@ -70,7 +99,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1)))
     int32_t iac[4], poff[4], pld[4];  // element (row, c) of U_b at base + poff k + iac + c pld
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        const int i = min(r0 + 16 * t + r16, bm - 1);
+        // QUAD: the first of the lane's four rows (a group starting past the
+        // box reads any rows of the column: it is never written)
+        const int i = min(QUAD ? r0 + 4 * r16 : r0 + 16 * t + r16, bm - 1);
         int32_t pr0 = bs, ld = bm;
         if (panel) {  // row panels: this row's chunk box
             const int32_t ch = leaf_of[bs + i] >> shc;
@@ -100,7 +131,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1)))
         for (int t = 0; t < 4; ++t)
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
-                const int r = min(r0 + 16 * t + 4 * q + jj, bm - 1);
+                const int r = min(s2_row<QUAD>(r0, t, q, jj), bm - 1);
                 const double *yp = Y + (bs + r) * int64_t(NP) + bcol;
 #pragma unroll
                 for (int N = 0; N < 4; ++N)
@@ -143,9 +174,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1)))
         };
         auto fill = [&](Slot &R) {
             const int cc = min(c + q, cur.k - 1);
+            if constexpr (QUAD) {
+                // (at most three values past the column: the next column, the
+                // next block or the chunk's 256 bytes of slack)
+                R.a = RQuad<DT>::ld(cur.p + roff[0] + int64_t(cc) * pld[0]);
+            } else {
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-                R.a[t] = RFac<DT>::ld(cur.p + roff[t] + int64_t(cc) * pld[t]);
+                for (int t = 0; t < 4; ++t)
+                    R.a[t] = RFac<DT>::ld(cur.p + roff[t] + int64_t(cc) * pld[t]);
+            }
             R.b = *reinterpret_cast<const f4 *>(Z + (cur.col0 + cc) * NP + bcol);
         };
         f4 C[4][4];
@@ -215,7 +252,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1)))
             for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
-                    const int r = r0 + 16 * t + 4 * q + jj;
+                    const int r = s2_row<QUAD>(r0, t, q, jj);
                     if (r < bm) {
                         double *yp = Y + (bs + r) * int64_t(NP) + nb + 4 * r16;
 #pragma unroll
@@ -262,14 +299,21 @@ void launch_s2_ring(Plan &P, int l, bool adjoint, const int2 *items, int64_t nit
     void *const *fp = adjoint ? P.blk_vptr : P.blk_uptr;
     const int32_t *steps = P.bt_s2k[l][adjoint ? 1 : 0];
     const int shc = 3 * (P.L - P.chunk_level);
-#define H3D_S2R(DT)                                                                             \
-    k_s2_ring<DT, 8><<<int((nitems + 3) / 4), 256, 0, s>>>(                                     \
+#define H3D_S2R(DT, Q)                                                                          \
+    k_s2_ring<DT, 8, Q><<<int((nitems + 3) / 4), 256, 0, s>>>(                                  \
         items, nitems, P.box_base[l], P.leaf_off, 3 * (P.L - l), P.tgt_begin, gblk, fp,          \
         P.blk_rank, P.blk_col0, steps, Z, NP, Y, panel, P.leaf_of, shc)
-    if (P.factor_dtype == H3D_F32)
-        H3D_S2R(H3D_F32);
-    else
-        H3D_S2R(H3D_BF16_SCALED);
+    if (P.factor_dtype == H3D_F32) {
+        if (panel)
+            H3D_S2R(H3D_F32, false);
+        else
+            H3D_S2R(H3D_F32, true);
+    } else {
+        if (panel)
+            H3D_S2R(H3D_BF16_SCALED, false);
+        else
+            H3D_S2R(H3D_BF16_SCALED, true);
+    }
 #undef H3D_S2R
     H3D_LAUNCH_CHECK();
 }
