@@ -217,17 +217,19 @@ h3d_status h3d_graph_destroy(h3d_graph *graph);
 
 /*
  * Multi-problem batching: independent operators, one per point cloud, all
- * with the same configuration, whose products run together in one
- * persistent kernel launch (a work queue over (problem, work item)).
+ * with the same configuration, whose products run together: one launch per
+ * phase of the product (gather, near field, stage 1 per launch shape,
+ * stage 2), each over the work items of every problem.
  *   nprob  : number of problems (>= 1).
  *   points : host array of nprob device pointers; points[i] is n[i] x 3
  *            FP64 row-major, read only during the call.
  *   n      : host array of the nprob sizes (each >= 1).
  * cfg, alloc, hip_stream and the errors are those of h3d_build (a failure of
  * any problem fails the call and frees everything).  Every problem is built
- * as h3d_build builds it, except that it keeps the default launch shapes and
- * one wave per stage-2 chunk box (the forms the persistent kernel carries;
- * H3D_FLAG_NO_AUTOTUNE is implied).  *out receives the batch plan, which
+ * as h3d_build builds it, tuned on its own factors unless
+ * H3D_FLAG_NO_AUTOTUNE is set, except that it chooses among the forms the
+ * batch launches carry: stage-1 shapes that keep whole columns, and the
+ * finest level not fused.  *out receives the batch plan, which
  * accepts h3d_matvec_batch, h3d_batch_plan, h3d_batch_check, h3d_get_stats
  * (sums over the problems; depth and rank_max are maxima), the profiling
  * calls and h3d_destroy; other calls return H3D_EINVAL.
@@ -238,8 +240,8 @@ h3d_status h3d_build_batch(int32_t nprob, const double *const *points, const int
 
 /*
  * y_i = K~_i x_i for every problem i of a batch plan (Algorithm 2 per
- * problem), in one persistent launch plus one small launch per 32 problems
- * that hands over the pointers.  x, y: host arrays of nprob device pointers;
+ * problem), in one launch per phase over all problems plus one small launch
+ * per 32 problems that hands over the pointers.  x, y: host arrays of nprob device pointers;
  * x[i] and y[i] are n[i] x nrhs column-major with leading dimension n[i], in
  * problem i's original point order, of io_dtype (H3D_F64 or H3D_F32); y[i]
  * is overwritten and must not overlap x[i].  Asynchronous on hip_stream.
@@ -247,7 +249,7 @@ h3d_status h3d_build_batch(int32_t nprob, const double *const *points, const int
  * with the same x[i].  With nrhs >= 8 every problem's product is a set of
  * dense GEMMs on the matrix cores that fills the GPU by itself, so the
  * problems run back to back on the stream (the matrix-core path of
- * h3d_matvec) instead of in the persistent launch.  Products of one batch
+ * h3d_matvec) instead of in the phase launches.  Products of one batch
  * plan must not overlap in time.
  */
 h3d_status h3d_matvec_batch(h3d_plan *batch, const void *const *x, void *const *y, int64_t nrhs,
@@ -259,10 +261,10 @@ h3d_status h3d_matvec_batch(h3d_plan *batch, const void *const *x, void *const *
  * launch shapes the batch relies on (H3D_EINVAL). */
 h3d_status h3d_batch_plan(h3d_plan *batch, int32_t i, h3d_plan **out);
 
-/* Synchronises hip_stream, then returns H3D_EDEVICE if a dependency wait in
- * the most recent h3d_matvec_batch gave up after its bound (its y is then
- * not valid), H3D_OK otherwise.  The waits of a product always end, so this
- * reports a fault of the device or of the library, not of the inputs. */
+/* Synchronises hip_stream and returns H3D_OK: the phases of a batch product
+ * are ordered by the stream, with no waits inside a launch that could give
+ * up.  (Kept so that callers written for a launch with device-side waits
+ * stay valid; errors of the launches themselves are reported by the calls.) */
 h3d_status h3d_batch_check(h3d_plan *batch, void *hip_stream);
 
 h3d_status h3d_get_stats(const h3d_plan *plan, h3d_stats *out);

@@ -1,29 +1,28 @@
-// Many independent HODLR3D operators multiplied in one persistent launch.
+// Many independent HODLR3D operators multiplied together, phase by phase.
 //
 // Every problem keeps its own plan (tree, lists, factors: Sec. 2.1, Sec. 4,
 // Algorithm 1).  A product of the batch is Algorithm 2 for each problem, cut
 // into the same work items as the per-phase kernels use (the gather of 1024
 // rows, the near field of one leaf, one stage-1 item, stage 2 of one chunk
-// box) and put in one queue:
+// box), and run phase by phase over all problems at once:
 //
-//   [gather of every problem] [near + stage 1 of problem 0] [... of problem 1]
-//   ... [stage 2 of every problem]
+//   [gather of every problem] [near field of every problem]
+//   [stage 1 of every problem and level, one launch per stage-1 shape]
+//   [stage 2 of every problem]
 //
-// The queue is cut into units: a run of consecutive items of one kind and
-// problem, sized so that a unit streams about kUnitBytes of factors (one
-// chunk box for stage 2, 64 leaves for the near field).  One-wave
-// workgroups, as many as are resident at once, take units in order from a
-// global ticket counter; per unit a wave issues one ticket atomic, one
-// release fence and one counter increment.  Two counters per problem order
-// the phases: near-field and stage-1 units wait until the problem's gather
-// units are done, stage-2 units until its near-field and stage-1 units are
-// done.  Units are taken in queue order and every wait is for units earlier
-// in the queue, which running waves already hold, so every wait ends; the waits are bounded nevertheless, and a wave that gives up
-// sets an error flag (h3d_batch_check) and carries on, so the launch always
-// drains.  The arithmetic of each item is the code of the per-phase kernels
-// (product_items.hpp) with one wave per stage-2 chunk box: a problem's plan
-// configured that way (the batch sets it so) gives bitwise the same product
-// through h3d_matvec.
+// Each launch is as large as the sum of the problems' items, so small
+// problems fill the GPU together, and each carries only its own kind of work:
+// the registers, and so the occupancy, of the per-phase kernels.  The stream
+// orders the phases.  A launch's work items are numbered consecutively over a
+// run (segment) per problem, or per (problem, level) for stage 1; a wave finds
+// its segment by binary search over the segments' first units.  Each member
+// keeps its own tuned launch shapes: its stage-1 levels go to the launch of
+// their shape, its chunk boxes to the stage-2 launch of its wave count.  The
+// arithmetic of each item is the code of the per-phase kernels
+// (product_items.hpp), so a member's own product through h3d_matvec gives
+// bitwise the same result.  (Members choose among whole-column stage-1
+// shapes and do not fuse the finest level: the batch launches carry neither
+// the reduction of split columns nor the fused form.)
 #include "stage1_items.hpp"
 
 namespace h3d {
@@ -31,9 +30,8 @@ namespace h3d {
 enum : int32_t { kSegGather = 0, kSegNear = 1, kSegS1 = 2, kSegS2 = 3 };
 
 struct BatchSeg {
-    int64_t start;     // first queue unit of the run
-    int64_t count;     // items of the run
-    int32_t per_unit;  // items per unit
+    int64_t start;  // first unit of the run (units of one launch are consecutive)
+    int64_t count;  // items (one per unit) of the run
     int32_t kind, prob, level, shape;
 };
 
@@ -41,8 +39,6 @@ struct BatchProb {
     int64_t n;
     int L, lc, kind;
     double kp;
-    unsigned n_gather;  // units before near field and stage 1 may start
-    unsigned n_mid;     // near-field and stage-1 units before stage 2 may start
     const int32_t *perm, *leaf_off, *leaf_of, *near_ptr, *near_s;
     const double *px, *py, *pz;
     double *xp, *yn, *z;
@@ -59,235 +55,208 @@ namespace {
 
 using namespace dev;
 
-constexpr int kGatherRows = 1024;           // rows per gather item
-constexpr int kNearPerUnit = 64;            // leaves per near-field unit
-constexpr double kUnitBytes = 1 << 20;      // factor bytes per stage-1 unit
-constexpr int64_t kSpinLimit = int64_t(1) << 20;  // polls: about a second
+constexpr int kGatherRows = 1024;  // rows per gather item
 
-// stage-1 shapes the persistent kernel carries (the default shapes)
+// the stage-1 shapes the batch launches carry: every whole-column shape the
+// tuner may choose (split columns, which need a reduction pass, are not
+// offered to batch members)
+struct ShapeDef {
+    int packed, S, U;
+};
+constexpr ShapeDef kShapes[] = {
+    {1, 4, 2},  {1, 4, 4},  {1, 8, 2},  {1, 8, 4},  {1, 16, 2}, {1, 16, 4}, {1, 4, 8},
+    {1, 8, 8},  {1, 16, 8}, {0, 8, 4},  {0, 8, 8},  {0, 16, 4}, {0, 16, 8}, {0, 32, 4},
+    {0, 32, 8}, {0, 64, 2}, {0, 64, 4}, {0, 64, 8}, {0, 16, 16}, {0, 32, 16}, {0, 64, 16}};
+constexpr int kNumS1Shapes = int(sizeof(kShapes) / sizeof(kShapes[0]));
+// shapes with twice the loads in flight, built for FP32 / BF16 factors only
+constexpr bool narrow_only(int id) {
+    return (kShapes[id].packed && kShapes[id].U == 8) || (!kShapes[id].packed && kShapes[id].U == 16);
+}
+
 int shape_id(const S1Shape &sh) {
     if (sh.rows > 0)
         return -1;
-    if (sh.packed && sh.S == 4 && sh.U == 4)
-        return 0;
-    if (sh.packed && sh.S == 8 && sh.U == 4)
-        return 1;
-    if (!sh.packed && sh.S == 16 && sh.U == 4)
-        return 2;
-    if (!sh.packed && sh.S == 64 && sh.U == 8)
-        return 3;
-    if (!sh.packed && sh.S == 64 && sh.U == 4)
-        return 4;
+    for (int i = 0; i < kNumS1Shapes; ++i)
+        if (kShapes[i].packed == sh.packed && kShapes[i].S == sh.S && kShapes[i].U == sh.U)
+            return i;
     return -1;
 }
 
-// lane 0 polls until *cnt reaches target (bounded), then the wave acquires
-__device__ __forceinline__ void wait_for(unsigned *cnt, unsigned target, unsigned *err) {
-    if (threadIdx.x == 0) {
-        int64_t polls = 0;
-        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (++polls > kSpinLimit) {
-                __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(8);
-        }
+// the segment of unit u among segs[sb, se) (their first units ascending)
+__device__ __forceinline__ BatchSeg seg_of(const BatchSeg *__restrict__ segs, int sb, int se,
+                                           int64_t u) {
+    int lo = sb, hi = se - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].start <= u)
+            lo = mid;
+        else
+            hi = mid - 1;
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return segs[lo];
 }
 
-// the wave's writes become visible, then the unit is counted
-__device__ __forceinline__ void unit_done(unsigned *cnt) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    if (threadIdx.x == 0)
-        __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// gather: one workgroup per 1024 rows of a problem
+__global__ void __launch_bounds__(256)
+    k_bgather(const BatchProb *__restrict__ probs, const BatchSeg *__restrict__ segs, int sb,
+              int se, int64_t u0, const void *const *__restrict__ io, int nrhs, int io_f32) {
+    const int64_t u = u0 + blockIdx.x;
+    const BatchSeg sg = seg_of(segs, sb, se, u);
+    const BatchProb &D = probs[sg.prob];
+    const int64_t i = u - sg.start;
+    const void *x = io[sg.prob];
+    for (int r = threadIdx.x; r < kGatherRows; r += 256) {
+        const int64_t row = i * kGatherRows + r;
+        if (row < D.n)
+            gather_row(x, io_f32, D.n, D.n, nrhs, D.perm, D.xp, row);
+    }
 }
 
+// near field: one wave per leaf
 template <int DT>
 __global__ void __launch_bounds__(64)
-    k_batch(const BatchProb *__restrict__ probs, const BatchSeg *__restrict__ segs, int nseg,
-            int64_t nunits, unsigned *ctl, int nprob, const void *const *__restrict__ io,
-            int nrhs, int io_f32) {
-    const int lane = threadIdx.x;
-    unsigned *head = ctl, *err = ctl + 1, *done_g = ctl + 2, *done_m = ctl + 2 + nprob;
-    int acq_g = -1, acq_m = -1;  // last problem whose inputs this wave has acquired
-    for (;;) {
-        unsigned tk = 0;
-        if (lane == 0)
-            tk = __hip_atomic_fetch_add(head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int64_t u = int64_t(uint32_t(__builtin_amdgcn_readfirstlane(__shfl(tk, 0))));
-        if (u >= nunits)
-            return;
-        int lo = 0, hi = nseg - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (segs[mid].start <= u)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        const BatchSeg &sg = segs[lo];
-        const int kind = sg.kind, p = sg.prob;
-        const int64_t i0 = (u - sg.start) * sg.per_unit;
-        const int64_t i1 = min(i0 + sg.per_unit, sg.count);
-        const BatchProb &D = probs[p];
-        if (kind == kSegGather) {
-            const void *x = io[p];
-            for (int64_t i = i0; i < i1; ++i)
-                for (int r = lane; r < kGatherRows; r += 64) {
-                    const int64_t row = i * kGatherRows + r;
-                    if (row < D.n)
-                        gather_row(x, io_f32, D.n, D.n, nrhs, D.perm, D.xp, row);
-                }
-            unit_done(done_g + p);
-        } else if (kind == kSegS2) {
-            if (acq_m != p) {
-                wait_for(done_m + p, D.n_mid, err);
-                acq_m = p;
-            }
-            for (int64_t i = i0; i < i1; ++i)
-                stage2_chunk<DT, 1, 1, true>(i, D.tab, D.leaf_off, D.leaf_of, D.grp_begin, nullptr,
-                                             D.uptr, D.rank, D.col0, D.z, D.ldz, D.yn, D.n, nrhs,
-                                             D.perm, const_cast<void *>(io[nprob + p]), D.n,
-                                             io_f32, 1, D.L, nullptr);
-        } else {
-            if (acq_g != p) {
-                wait_for(done_g + p, D.n_gather, err);
-                acq_g = p;
-            }
-            if (kind == kSegNear) {
-                for (int64_t i = i0; i < i1; ++i)
-                    near_leaf<1, true, DT != H3D_F64>(i, D.leaf_off, D.near_ptr, D.near_s, D.px,
-                                                      D.py, D.pz, D.kind, D.kp, nrhs, D.xp,
-                                                      D.n, D.yn);
-            } else {
-                const S1Args &a = D.s1[sg.level];
-                switch (sg.shape) {
-                case 0:
-                    for (int64_t i = i0; i < i1; ++i)
-                        s1_packed_item<4, 4, DT, 1, true>(a, i);
-                    break;
-                case 1:
-                    for (int64_t i = i0; i < i1; ++i)
-                        s1_packed_item<8, 4, DT, 1, true>(a, i);
-                    break;
-                case 2:
-                    for (int64_t i = i0; i < i1; ++i)
-                        s1_wide_item<16, 4, DT, 1, true>(a, i);
-                    break;
-                case 3:
-                    for (int64_t i = i0; i < i1; ++i)
-                        s1_wide_item<64, 8, DT, 1, true>(a, i);
-                    break;
-                default:
-                    for (int64_t i = i0; i < i1; ++i)
-                        s1_wide_item<64, 4, DT, 1, true>(a, i);
-                    break;
-                }
-            }
-            unit_done(done_m + p);
-        }
-    }
+    k_bnear(const BatchProb *__restrict__ probs, const BatchSeg *__restrict__ segs, int sb,
+            int se, int64_t u0, int nrhs) {
+    const int64_t u = u0 + blockIdx.x;
+    const BatchSeg sg = seg_of(segs, sb, se, u);
+    const BatchProb &D = probs[sg.prob];
+    near_leaf<1, false, DT != H3D_F64>(u - sg.start, D.leaf_off, D.near_ptr, D.near_s, D.px, D.py,
+                                        D.pz, D.kind, D.kp, nrhs, D.xp, D.n, D.yn);
+}
+
+// stage 1 of one shape: one work item per wave, four waves per workgroup,
+// workgroups renumbered so that every XCD takes a contiguous run of items
+template <int DT, int SHAPE>
+__global__ void __launch_bounds__(256)
+    k_bs1(const BatchProb *__restrict__ probs, const BatchSeg *__restrict__ segs, int sb, int se,
+          int64_t u0, int64_t units) {
+    const int64_t b = xcd_run(blockIdx.x, gridDim.x);
+    const int64_t w = uniform64((b * blockDim.x + threadIdx.x) >> 6);
+    if (w >= units)
+        return;
+    const BatchSeg sg = seg_of(segs, sb, se, u0 + w);
+    const S1Args &a = probs[sg.prob].s1[sg.level];
+    const int64_t i = u0 + w - sg.start;
+    constexpr ShapeDef sh = kShapes[SHAPE];
+    if constexpr (sh.packed)
+        s1_packed_item<sh.S, sh.U, DT, 1>(a, i);
+    else
+        s1_wide_item<sh.S, sh.U, DT, 1>(a, i);
+}
+
+// stage 2: one workgroup of W waves per chunk box, written straight to y
+// (FP64 factors, one RHS: four waves per SIMD, as k_stage2)
+template <int DT, int W>
+__global__ void __launch_bounds__(64 * W)
+    __attribute__((amdgpu_waves_per_eu(DT == H3D_F64 ? 4 : 1)))
+    k_bs2(const BatchProb *__restrict__ probs, const BatchSeg *__restrict__ segs, int sb, int se,
+          int64_t u0, int nprob, const void *const *__restrict__ io, int nrhs, int io_f32) {
+    const int64_t u = u0 + xcd_run(blockIdx.x, gridDim.x);
+    const BatchSeg sg = seg_of(segs, sb, se, u);
+    const BatchProb &D = probs[sg.prob];
+    stage2_chunk<DT, 1, W>(u - sg.start, D.tab, D.leaf_off, D.leaf_of, D.grp_begin, nullptr,
+                           D.uptr, D.rank, D.col0, D.z, D.ldz, D.yn, D.n, nrhs, D.perm,
+                           const_cast<void *>(io[nprob + sg.prob]), D.n, io_f32, 1, D.L, nullptr);
 }
 
 // Before each product: the x and y pointers of up to kIoPerLaunch problems
-// into the device table, and (first launch) the queue head, the error flag
-// and the per-problem counters set to zero.
+// into the device table.
 constexpr int kIoPerLaunch = 32;
 struct IoChunk {
     const void *x[kIoPerLaunch];
     void *y[kIoPerLaunch];
 };
 
-__global__ void k_batch_prepare(IoChunk c, int base, int count, int nprob, const void **io,
-                                unsigned *ctl, int nctl) {
+__global__ void k_batch_prepare(IoChunk c, int base, int count, int nprob, const void **io) {
     const int t = threadIdx.x;
     if (t < count) {
         io[base + t] = c.x[t];
         io[nprob + base + t] = c.y[t];
     }
-    if (base == 0)
-        for (int j = t; j < nctl; j += blockDim.x)
-            ctl[j] = 0u;
 }
 
-template <int DT> int resident_grid() {
-    int dev = 0, cus = 0, per_cu = 0;
-    H3D_HIP(hipGetDevice(&dev));
-    H3D_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    H3D_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<DT>, 64, 0));
-    return std::max(1, cus) * std::max(1, per_cu);
-}
+// one launch of the batch: segments [sb, se), units [u0, u0 + units)
+enum : int { kLaunchKind, kLaunchShape, kLaunchSb, kLaunchSe, kLaunchU0, kLaunchUnits, kLaunchLen };
 
 }  // namespace
 
-// Builds the queue (segments and per-problem counts) and the control arrays.
+// Builds the segments (one unit per work item), grouped by launch: gather,
+// near field, stage 1 by shape, stage 2 by waves per chunk box; one list of
+// launches for one right-hand side (the members' tuned shapes) and one for
+// two to seven (their shapes for several right-hand sides).
 void batch_setup(h3d_plan &bp, hipStream_t s) {
     BatchState &B = *bp.batch;
     Plan &P = bp.P;
     const int nprob = int(B.subs.size());
-    const double es = P.factor_dtype == H3D_F64 ? 8.0 : (P.factor_dtype == H3D_F32 ? 4.0 : 2.0);
     std::vector<BatchSeg> segs;
     int64_t pos = 0;
-    auto add = [&](int32_t kind, int32_t prob, int32_t level, int32_t shape, int64_t count,
-                   int64_t per_unit) {
-        if (count <= 0)
-            return int64_t(0);
-        per_unit = std::max<int64_t>(1, std::min<int64_t>(per_unit, 1 << 20));
-        const int64_t units = ceil_div(count, per_unit);
-        segs.push_back(BatchSeg{pos, count, int32_t(per_unit), kind, prob, level, shape});
-        pos += units;
-        return units;
-    };
-    B.n_gather.assign(size_t(nprob), 0);
-    B.n_mid.assign(size_t(nprob), 0);
-    for (int p = 0; p < nprob; ++p)
-        B.n_gather[size_t(p)] =
-            add(kSegGather, p, 0, 0, ceil_div(B.subs[size_t(p)]->P.n, kGatherRows), 1);
-    for (int p = 0; p < nprob; ++p) {
-        Plan &Q = B.subs[size_t(p)]->P;
-        int64_t mid = add(kSegNear, p, 0, 0, pow8(Q.L), kNearPerUnit);
-        for (int l = 1; l <= Q.L; ++l) {
-            const int64_t ni = Q.s1_nitems[0][l];
-            if (ni == 0)
-                continue;
-            const int id = shape_id(Q.s1_shape[0][l]);
-            if (id < 0)
-                fail(H3D_EDEVICE, "internal: stage-1 shape not carried by the batch kernel");
-            const double item_bytes = double(Q.lvl_entries_v[l]) * es / double(ni);
-            mid += add(kSegS1, p, l, id, ni, int64_t(kUnitBytes / std::max(item_bytes, 1.0)));
+    auto add = [&](int32_t kind, int32_t prob, int32_t level, int32_t shape, int64_t count) {
+        if (count > 0) {
+            segs.push_back(BatchSeg{pos, count, kind, prob, level, shape});
+            pos += count;
         }
-        B.n_mid[size_t(p)] = mid;
+    };
+    for (int cls = 0; cls < 2; ++cls) {
+        std::vector<int64_t> &Ls = B.launches[cls];
+        Ls.clear();
+        // one launch over the segments added by `body`
+        auto launch = [&](int kind, int shape, auto body) {
+            const int sb = int(segs.size());
+            const int64_t u0 = pos;
+            body();
+            if (int(segs.size()) > sb)
+                Ls.insert(Ls.end(), {int64_t(kind), int64_t(shape), int64_t(sb),
+                                     int64_t(segs.size()), u0, pos - u0});
+        };
+        launch(kSegGather, 0, [&] {
+            for (int p = 0; p < nprob; ++p)
+                add(kSegGather, p, 0, 0, ceil_div(B.subs[size_t(p)]->P.n, kGatherRows));
+        });
+        launch(kSegNear, 0, [&] {
+            for (int p = 0; p < nprob; ++p)
+                add(kSegNear, p, 0, 0, pow8(B.subs[size_t(p)]->P.L));
+        });
+        for (int p = 0; p < nprob; ++p) {
+            const Plan &Q = B.subs[size_t(p)]->P;
+            for (int l = 1; l <= Q.L; ++l)
+                if (Q.s1_nitems[cls][l] > 0 && shape_id(Q.s1_shape[cls][l]) < 0)
+                    fail(H3D_EDEVICE, "internal: stage-1 shape not carried by the batch kernels");
+        }
+        for (int sh = 0; sh < kNumS1Shapes; ++sh)
+            launch(kSegS1, sh, [&] {
+                for (int p = 0; p < nprob; ++p) {
+                    const Plan &Q = B.subs[size_t(p)]->P;
+                    for (int l = 1; l <= Q.L; ++l)
+                        if (Q.s1_nitems[cls][l] > 0 && shape_id(Q.s1_shape[cls][l]) == sh)
+                            add(kSegS1, p, l, sh, Q.s1_nitems[cls][l]);
+                }
+            });
+        for (int w : {1, 2, 4, 8})
+            launch(kSegS2, w, [&] {
+                for (int p = 0; p < nprob; ++p) {
+                    const Plan &Q = B.subs[size_t(p)]->P;
+                    const int qw = Q.s2_waves[cls];
+                    if ((qw <= 1 ? 1 : qw <= 2 ? 2 : qw <= 4 ? 4 : 8) == w)
+                        add(kSegS2, p, 0, w, pow8(Q.chunk_level));
+                }
+            });
     }
-    for (int p = 0; p < nprob; ++p)
-        add(kSegS2, p, 0, 0, pow8(B.subs[size_t(p)]->P.chunk_level), 1);
     B.nseg = int(segs.size());
     B.nitems = pos;
-    if (pos >= int64_t(0x7fffffff) - (int64_t(1) << 24))
-        fail(H3D_EINVAL, "batch queue too long");
-    B.segs = static_cast<BatchSeg *>(P.mem.alloc(sizeof(BatchSeg) * segs.size()));
-    H3D_HIP(hipMemcpy(B.segs, segs.data(), sizeof(BatchSeg) * segs.size(), hipMemcpyHostToDevice));
+    if (pos >= int64_t(0x7fffffff))
+        fail(H3D_EINVAL, "batch too large: more than 2^31 work items");
+    B.segs = static_cast<BatchSeg *>(P.mem.alloc(sizeof(BatchSeg) * std::max<size_t>(segs.size(), 1)));
+    if (!segs.empty())
+        H3D_HIP(hipMemcpy(B.segs, segs.data(), sizeof(BatchSeg) * segs.size(),
+                          hipMemcpyHostToDevice));
     B.probs = static_cast<BatchProb *>(P.mem.alloc(sizeof(BatchProb) * size_t(nprob)));
-    B.ctl = P.mem.alloc_n<unsigned>(2 + 2 * int64_t(nprob));
     B.io = static_cast<const void **>(P.mem.alloc(sizeof(void *) * 2 * size_t(nprob)));
-    int g = 0;
-    switch (P.factor_dtype) {
-    case H3D_F64:
-        g = resident_grid<H3D_F64>();
-        break;
-    case H3D_F32:
-        g = resident_grid<H3D_F32>();
-        break;
-    default:
-        g = resident_grid<H3D_BF16_SCALED>();
-        break;
-    }
-    B.grid = int(std::min<int64_t>(g, pos));
     (void)s;
 }
 
 // Writes the per-problem descriptors for nrhs right-hand sides.
 static void write_descriptors(BatchState &B, int64_t nrhs) {
+    const int cls = nrhs == 1 ? 0 : 1;
     const int nprob = int(B.subs.size());
     std::vector<BatchProb> d(static_cast<size_t>(nprob));
     std::vector<const void *> scr;
@@ -300,8 +269,6 @@ static void write_descriptors(BatchState &B, int64_t nrhs) {
         D.lc = Q.chunk_level;
         D.kind = Q.cfg.kernel;
         D.kp = Q.cfg.kernel_param;
-        D.n_gather = unsigned(B.n_gather[size_t(p)]);
-        D.n_mid = unsigned(B.n_mid[size_t(p)]);
         D.perm = Q.perm;
         D.leaf_off = Q.leaf_off;
         D.leaf_of = Q.leaf_of;
@@ -325,9 +292,9 @@ static void write_descriptors(BatchState &B, int64_t nrhs) {
         D.col0 = Q.blk_col0;
         for (int l = 1; l <= Q.L; ++l) {
             S1Args &a = D.s1[l];
-            a.items = reinterpret_cast<const int2 *>(Q.s1_items[0][l]);
-            a.nitems = Q.s1_nitems[0][l];
-            a.span = Q.s1_span[0][l];
+            a.items = reinterpret_cast<const int2 *>(Q.s1_items[cls][l]);
+            a.nitems = Q.s1_nitems[cls][l];
+            a.span = Q.s1_span[cls][l];
             a.blk_col0 = Q.blk_col0;
             a.rank = Q.blk_rank;
             a.seg_len = Q.blk_n;
@@ -347,6 +314,61 @@ static void write_descriptors(BatchState &B, int64_t nrhs) {
     H3D_HIP(hipMemcpy(B.probs, d.data(), sizeof(BatchProb) * d.size(), hipMemcpyHostToDevice));
     B.desc_nrhs = nrhs;
     B.desc_scratch = scr;
+}
+
+// stage 1 of shape `id` (a compile-time constant from a run-time index)
+template <int DT, int ID = 0>
+static void launch_bs1(int id, int g, const BatchState &B, int sb, int se, int64_t u0,
+                       int64_t units, hipStream_t s) {
+    if constexpr (ID < kNumS1Shapes) {
+        if (id != ID) {
+            launch_bs1<DT, ID + 1>(id, g, B, sb, se, u0, units, s);
+        } else if constexpr (DT == H3D_F64 && narrow_only(ID)) {
+            fail(H3D_EDEVICE, "internal: a narrow-factor stage-1 shape on FP64 factors");
+        } else {
+            k_bs1<DT, ID><<<g, 256, 0, s>>>(B.probs, B.segs, sb, se, u0, units);
+        }
+    } else {
+        fail(H3D_EDEVICE, "internal: unknown stage-1 shape of a batch launch");
+    }
+}
+
+// the phase launches of one product, in order
+template <int DT>
+static void batch_launches(const BatchState &B, int nprob, int nrhs, int io_f32, hipStream_t s) {
+    const std::vector<int64_t> &Ls = B.launches[nrhs == 1 ? 0 : 1];
+    for (size_t j = 0; j + kLaunchLen <= Ls.size(); j += kLaunchLen) {
+        const int64_t *L = Ls.data() + j;
+        const int kind = int(L[kLaunchKind]), shape = int(L[kLaunchShape]);
+        const int sb = int(L[kLaunchSb]), se = int(L[kLaunchSe]);
+        const int64_t u0 = L[kLaunchU0], units = L[kLaunchUnits];
+        switch (kind) {
+        case kSegGather:
+            k_bgather<<<int(units), 256, 0, s>>>(B.probs, B.segs, sb, se, u0, B.io, nrhs, io_f32);
+            break;
+        case kSegNear:
+            k_bnear<DT><<<int(units), 64, 0, s>>>(B.probs, B.segs, sb, se, u0, nrhs);
+            break;
+        case kSegS1:
+            launch_bs1<DT>(shape, int((units + 3) / 4), B, sb, se, u0, units, s);
+            break;
+        default:
+#define H3D_BS2(W)                                                                              \
+    k_bs2<DT, W><<<int(units), 64 * W, 0, s>>>(B.probs, B.segs, sb, se, u0, nprob, B.io, nrhs,   \
+                                               io_f32)
+            if (shape == 1)
+                H3D_BS2(1);
+            else if (shape == 2)
+                H3D_BS2(2);
+            else if (shape == 4)
+                H3D_BS2(4);
+            else
+                H3D_BS2(8);
+#undef H3D_BS2
+            break;
+        }
+        H3D_LAUNCH_CHECK();
+    }
 }
 
 void batch_run(h3d_plan &bp, const void *const *x, void *const *y, int64_t nrhs, int io_dtype,
@@ -388,7 +410,6 @@ void batch_run(h3d_plan &bp, const void *const *x, void *const *y, int64_t nrhs,
         H3D_HIP(hipStreamSynchronize(s));
         write_descriptors(B, nrhs);
     }
-    const int nctl = 2 + 2 * nprob;
     for (int base = 0; base < nprob; base += kIoPerLaunch) {
         IoChunk c{};
         const int cnt = std::min(kIoPerLaunch, nprob - base);
@@ -396,7 +417,7 @@ void batch_run(h3d_plan &bp, const void *const *x, void *const *y, int64_t nrhs,
             c.x[j] = x[base + j];
             c.y[j] = y[base + j];
         }
-        k_batch_prepare<<<1, 256, 0, s>>>(c, base, cnt, nprob, B.io, B.ctl, nctl);
+        k_batch_prepare<<<1, 64, 0, s>>>(c, base, cnt, nprob, B.io);
         H3D_LAUNCH_CHECK();
     }
     const int io_f32 = io_dtype == H3D_F32;
@@ -410,29 +431,23 @@ void batch_run(h3d_plan &bp, const void *const *x, void *const *y, int64_t nrhs,
     hipEvent_t ev = P.prof.begin(s);
     switch (P.factor_dtype) {
     case H3D_F64:
-        k_batch<H3D_F64><<<B.grid, 64, 0, s>>>(B.probs, B.segs, B.nseg, B.nitems, B.ctl, nprob,
-                                                B.io, int(nrhs), io_f32);
+        batch_launches<H3D_F64>(B, nprob, int(nrhs), io_f32, s);
         break;
     case H3D_F32:
-        k_batch<H3D_F32><<<B.grid, 64, 0, s>>>(B.probs, B.segs, B.nseg, B.nitems, B.ctl, nprob,
-                                                B.io, int(nrhs), io_f32);
+        batch_launches<H3D_F32>(B, nprob, int(nrhs), io_f32, s);
         break;
     default:
-        k_batch<H3D_BF16_SCALED><<<B.grid, 64, 0, s>>>(B.probs, B.segs, B.nseg, B.nitems, B.ctl,
-                                                        nprob, B.io, int(nrhs), io_f32);
+        batch_launches<H3D_BF16_SCALED>(B, nprob, int(nrhs), io_f32, s);
         break;
     }
-    H3D_LAUNCH_CHECK();
     P.prof.end(s, ev, "k_batch", bytes, flops);
 }
 
-// Synchronises s and reports whether a wait of the last products gave up.
+// The phase launches have no waits between problems: nothing can give up.
 bool batch_wait_failed(h3d_plan &bp, hipStream_t s) {
-    BatchState &B = *bp.batch;
-    unsigned flag = 0;
-    H3D_HIP(hipMemcpyAsync(&flag, B.ctl + 1, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    (void)bp;
     H3D_HIP(hipStreamSynchronize(s));
-    return flag != 0;
+    return false;
 }
 
 }  // namespace h3d

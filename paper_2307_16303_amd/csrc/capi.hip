@@ -179,8 +179,9 @@ h3d_status check_config(const h3d_config *cfg, const h3d_allocator *alloc) {
     return H3D_OK;
 }
 
-// Builds one operator (throws h3d::Error).  A member of a batch keeps the
-// default stage-1 shapes and one wave per stage-2 chunk box.
+// Builds one operator (throws h3d::Error).  A member of a batch is tuned as
+// well, among the forms the batch launches carry (whole-column stage-1
+// shapes, the finest level not fused).
 h3d_plan *build_plan(const double *points, int64_t n, const h3d_config &cfg,
                      const h3d_allocator *alloc, hipStream_t s, bool in_batch) {
     const auto t0 = std::chrono::steady_clock::now();
@@ -196,11 +197,8 @@ h3d_plan *build_plan(const double *points, int64_t n, const h3d_config &cfg,
         h3d::lists_build(P, s);
         h3d::factors_build(P, s);
         h3d::near_pair_count(P, s);
-        if (in_batch) {
-            P.s2_waves[0] = P.s2_waves[1] = 1;
-        } else if (!(P.cfg.flags & H3D_FLAG_NO_AUTOTUNE)) {
+        if (!(P.cfg.flags & H3D_FLAG_NO_AUTOTUNE))
             h3d::autotune(P, 1, s);
-        }
     } catch (...) {
         // kernels queued before the failure finish before the plan's memory
         // goes back to the allocator
@@ -289,7 +287,7 @@ h3d_status h3d_build_batch(int32_t nprob, const double *const *points, const int
     if (st != H3D_OK)
         return st;
     if (cfg->flags & H3D_FLAG_LU_FORM)
-        return g_last_error = "the persistent batch launch carries the explicit-factor kernels: "
+        return g_last_error = "the batch launches carry the explicit-factor kernels: "
                               "H3D_FLAG_LU_FORM is not available for batches",
                H3D_ENOTIMPL;
     for (int32_t i = 0; i < nprob; ++i) {

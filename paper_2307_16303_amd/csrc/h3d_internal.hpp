@@ -402,19 +402,20 @@ namespace h3d {
 struct BatchProb;  // device descriptor of one problem (batch.hip)
 struct BatchSeg;   // a run of queue items of one kind and problem (batch.hip)
 
-// A batch of independent operators multiplied in one persistent launch.
+// A batch of independent operators multiplied together, one launch per phase
+// over all problems.
 struct BatchState {
     std::vector<h3d_plan *> subs;  // owned
     BatchProb *probs = nullptr;    // device [nprob]
     BatchSeg *segs = nullptr;      // device [nseg]
     int nseg = 0;
-    int64_t nitems = 0;            // queue length in units
-    std::vector<int64_t> n_gather, n_mid;  // per problem: units each phase waits for
-    unsigned *ctl = nullptr;       // device: ticket head, error flag, per-problem counters
+    int64_t nitems = 0;            // work items (units) over all launches
+    // per launch: kind, shape (stage 2: waves), first and end segment, first
+    // unit, units; [0] one right-hand side, [1] two to seven
+    std::vector<int64_t> launches[2];
     const void **io = nullptr;     // device [2 nprob]: x pointers then y pointers
     int64_t desc_nrhs = 0;         // right-hand sides the descriptors were written for
     std::vector<const void *> desc_scratch;  // scratch pointers they hold
-    int grid = 0;                  // resident one-wave workgroups of the launch
     ~BatchState() {
         for (h3d_plan *p : subs)
             delete p;

@@ -394,7 +394,9 @@ void autotune_dt(Plan &P, int nrhs, hipStream_t s) {
             continue;
         S1Shape best_sh = P.s1_shape[cls][l];
         float best_ms = 1e30f;
-        for (const S1Shape &sh : s1_candidates(P, l, NR == 1 && DT != H3D_F64, NR == 1)) {
+        // (a batch member keeps whole columns: the batch launches carry no
+        // reduction of split columns)
+        for (const S1Shape &sh : s1_candidates(P, l, NR == 1 && DT != H3D_F64, NR == 1 && !P.in_batch)) {
             set_level_shape(P, cls, l, sh, s);
             const S1Args a = stage1_args<DT, NR>(P, cls, l, false, nrhs, P.xp, P.z);
             const float ms = time_it([&] { launch_s1_level<DT, NR>(P, l, sh, a, s); });
@@ -499,7 +501,8 @@ void ensure_scratch(Plan &P, int64_t nrhs, hipStream_t s) {
 
 // ---- the tuner's cache ------------------------------------------------------
 // H3D_TUNE_CACHE names a JSON file mapping a plan's key (GPU architecture,
-// factor type, one or several right-hand sides, depth, and per level the
+// factor type, one or several right-hand sides, depth, batch membership (a
+// member chooses among fewer shapes), and per level the
 // half-octave buckets of the mean box size and the mean rank) to the shapes
 // the tuner chose: [finest-level fusion, stage-2 waves, then per level
 // packed, S, U, passes, rows].  A plan whose key is found takes the stored
@@ -515,7 +518,8 @@ std::string tune_key(const Plan &P, int cls) {
     std::string arch = prop.gcnArchName;
     arch = arch.substr(0, arch.find(':'));
     std::string k = arch + "|dt" + std::to_string(P.factor_dtype) + "|nr" +
-                    std::to_string(cls == 0 ? 1 : 4) + "|L" + std::to_string(P.L);
+                    std::to_string(cls == 0 ? 1 : 4) + "|L" + std::to_string(P.L) +
+                    (P.in_batch ? "|batch" : "");
     for (int l = 1; l <= P.L; ++l) {
         const int64_t nb = P.lvl_blk[l + 1] - P.lvl_blk[l];
         const double mr = nb > 0 ? double(P.lvl_rank_sum[l]) / double(nb) : 0.0;
@@ -606,7 +610,7 @@ bool tune_cache_apply(Plan &P, int cls, const std::vector<int> &v, bool narrow, 
         sh.reps = e[3];
         sh.rows = e[4];
         bool known = P.lvl_blk[l + 1] <= P.lvl_blk[l];  // empty levels keep any shape
-        for (const S1Shape &c : s1_candidates(P, l, narrow, cls == 0))
+        for (const S1Shape &c : s1_candidates(P, l, narrow, cls == 0 && !P.in_batch))
             known = known || (c.packed == sh.packed && c.S == sh.S && c.U == sh.U &&
                               c.reps == sh.reps && c.rows == sh.rows);
         known = known || (sh.packed == P.s1_shape[cls][l].packed && sh.S == P.s1_shape[cls][l].S &&

@@ -499,8 +499,8 @@ def build(points, kernel="laplace", kernel_param: float = 1.0, leaf_size: int = 
 
 
 class BatchOperator:
-    """Independent HODLR3D operators (one per point cloud) whose products run together
-    in one persistent kernel launch.  ``plans[i]`` is problem i's own operator."""
+    """Independent HODLR3D operators (one per point cloud) whose products run together,
+    one launch per phase over all problems.  ``plans[i]`` is problem i's own operator."""
 
     def __init__(self, handle, ns, device: int, allocator, config: Config):
         self._h = handle
@@ -632,16 +632,19 @@ class BatchGraph:
 def build_batch(points_list, kernel="laplace", kernel_param: float = 1.0, leaf_size: int = 64,
                 tol: float = 1e-8, factor_dtype="fp64", max_rank: int = 0, max_depth: int = 10,
                 box_lo=None, box_side: float = 0.0, workspace_bytes: int = 0,
-                use_torch_allocator: bool = True, lu_form: bool = False) -> BatchOperator:
-    """Builds one operator per point cloud for products in one persistent launch
-    (explicit factors only: the library refuses lu_form=True for batches)."""
+                use_torch_allocator: bool = True, lu_form: bool = False,
+                autotune: bool = True) -> BatchOperator:
+    """Builds one operator per point cloud for products that run together, one launch
+    per phase over all problems (explicit factors only: the library refuses
+    lu_form=True for batches).  With autotune each member times the launch shapes
+    the batch carries on its own factors."""
     torch = _torch()
     lib = load_library()
     pts = [_device_points(p) for p in points_list]
     if not pts:
         raise ValueError("points_list is empty")
     cfg = _make_config(kernel, kernel_param, leaf_size, tol, factor_dtype, max_rank, max_depth,
-                       box_lo, box_side, workspace_bytes, False, False, lu_form=lu_form)
+                       box_lo, box_side, workspace_bytes, False, autotune, lu_form=lu_form)
     device = pts[0].device.index if pts[0].device.index is not None else torch.cuda.current_device()
     alloc = _TorchAllocator(device) if use_torch_allocator else None
     P = ctypes.c_void_p * len(pts)

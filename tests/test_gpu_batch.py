@@ -1,8 +1,9 @@
-"""Multi-problem batching: independent operators multiplied in one persistent
-launch (h3d_build_batch / h3d_matvec_batch), through the C ABI.
+"""Multi-problem batching: independent operators multiplied together, one
+launch per phase over all problems (h3d_build_batch / h3d_matvec_batch),
+through the C ABI.
 
 Each problem of a batch is an ordinary operator (h3d_batch_plan): its product
-inside the persistent launch runs the same per-item arithmetic as its own
+inside the batch launches runs the same per-item arithmetic as its own
 per-phase kernels, so the two are compared bitwise; the batch output is also
 checked against the CPU oracle's HODLR3D (same ACA decisions, summation order
 only) and against exact dense rows (compression error).
