@@ -181,6 +181,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
             if (ci + 1 < i1)
                 cn = load_item(ci + 1);
             const int S = (cc.len + 15) >> 4, Sp = padded(cc.len);
+            const int nt = min(MT, (cc.k - cc.c0 + 15) >> 4);
             f4 C[MT][4];
 #pragma unroll
             for (int T = 0; T < MT; ++T)
@@ -198,6 +199,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
                 }
 #pragma unroll
                 for (int T = 0; T < MT; ++T) {
+                    if (T >= nt)  // tiles past the block's columns issue no MFMA
+                        break;
                     const s4 a = fix4(R.a[T], R.odd[T], mlo, mhi);
 #pragma unroll
                     for (int N = 0; N < 4; ++N) {

@@ -102,6 +102,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 #pragma unroll
     for (int t = 0; t < MT; ++t)
         cc[t] = min(c0 + 16 * t + r16, k - 1);
+    // tiles holding columns of the block (the others issue no MFMA; their
+    // loads stay, so that every step keeps the same count in flight)
+    const int nt = __builtin_amdgcn_readfirstlane(min(MT, (k - c0 + 15) >> 4));
     // super-steps.  PANEL (the adjoint above the chunk level): U_b is stored
     // as one row panel per chunk box of the target box, so the rows are taken
     // chunk box by chunk box, each padded to whole super-steps (the count per
@@ -191,10 +194,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
                     bv[N] = aj ? R.b[i][N] : 0.f;
 #pragma unroll
                 for (int t = 0; t < MT; ++t)
+                    if (t < nt)
 #pragma unroll
-                    for (int N = 0; N < 4; ++N)
-                        C[t][N] = __builtin_amdgcn_mfma_f32_16x16x4f32(R.a[t][i], bv[N], C[t][N], 0,
-                                                                       0, 0);
+                        for (int N = 0; N < 4; ++N)
+                            C[t][N] = __builtin_amdgcn_mfma_f32_16x16x4f32(R.a[t][i], bv[N],
+                                                                           C[t][N], 0, 0, 0);
             }
         };
         QSlot<MT> R[D2];
@@ -354,6 +358,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
             if (ci + 1 < i1)
                 cn = load_item(ci + 1);
             const int S = (cc.len + 3) >> 2, Sp = padded(cc.len);
+            const int nt = min(MT, (cc.k - cc.c0 + 15) >> 4);
             f4 C[MT][4];
 #pragma unroll
             for (int t = 0; t < MT; ++t)
@@ -383,10 +388,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
                             bv[N] = aj ? R[d].b[N] : 0.f;
 #pragma unroll
                         for (int t = 0; t < MT; ++t)
+                            if (t < nt)  // tiles past the block's columns issue no MFMA
 #pragma unroll
-                            for (int N = 0; N < 4; ++N)
-                                C[t][N] = __builtin_amdgcn_mfma_f32_16x16x4f32(R[d].a[t], bv[N],
-                                                                               C[t][N], 0, 0, 0);
+                                for (int N = 0; N < 4; ++N)
+                                    C[t][N] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                        R[d].a[t], bv[N], C[t][N], 0, 0, 0);
                     }
                     fill(R[d]);
                     fadvance();

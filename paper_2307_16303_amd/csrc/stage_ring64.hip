@@ -61,6 +61,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 #pragma unroll
     for (int t = 0; t < MT; ++t)
         cc[t] = min(c0 + 16 * t + r16, k - 1);
+    const int nt = __builtin_amdgcn_readfirstlane(min(MT, (k - c0 + 15) >> 4));
     const int S = (len + 3) >> 2;
     for (int nb = 0; nb < NP; nb += 64) {
         const int nv = min(64, NP - nb);
@@ -86,9 +87,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
             const bool aj = 4 * s + q < len;
 #pragma unroll
             for (int t = 0; t < MT; ++t)
+                if (t < nt)  // tiles past the block's columns issue no MFMA
 #pragma unroll
-                for (int N = 0; N < 4; ++N)
-                    C[t][N] = mma64(sl.a[t], aj ? sl.b[N] : 0.0, C[t][N]);
+                    for (int N = 0; N < 4; ++N)
+                        C[t][N] = mma64(sl.a[t], aj ? sl.b[N] : 0.0, C[t][N]);
         };
         S1Slot64 R[D];
 #pragma unroll
@@ -208,6 +210,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
             if (ci + 1 < i1)
                 cn = load_item(ci + 1);
             const int S = (cc.len + 3) >> 2, Sp = padded(cc.len);
+            const int nt = min(MT, (cc.k - cc.c0 + 15) >> 4);
             d4 C[MT][4];
 #pragma unroll
             for (int t = 0; t < MT; ++t)
@@ -222,9 +225,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
                         const bool aj = 4 * s + q < cc.len;
 #pragma unroll
                         for (int t = 0; t < MT; ++t)
+                            if (t < nt)  // tiles past the block's columns issue no MFMA
 #pragma unroll
-                            for (int N = 0; N < 4; ++N)
-                                C[t][N] = mma64(R[d].a[t], aj ? R[d].b[N] : 0.0, C[t][N]);
+                                for (int N = 0; N < 4; ++N)
+                                    C[t][N] = mma64(R[d].a[t], aj ? R[d].b[N] : 0.0, C[t][N]);
                     }
                     fill(R[d]);
                     fadvance();
