@@ -1043,7 +1043,11 @@ void batched_dt(Plan &P, const void *x, void *y, int nrhs, int64_t ldx, int64_t 
     }
     {
         hipEvent_t ev = P.prof.begin(s);
-        if (P.bt_nnear > 0)
+        // FP32 entries: one wave per leaf when every leaf holds at most 64
+        // rows, one per (leaf, 16-row tile) otherwise and for FP64 entries
+        const bool by_leaf = DT != H3D_F64 && P.bt_nnear > 0 &&
+                             launch_near_leaves(P, reinterpret_cast<const float *>(Xs), NP, Y, s);
+        if (P.bt_nnear > 0 && !by_leaf)
             k_near_mfma<DT><<<int(P.bt_nnear), 64, 0, s>>>(
                 reinterpret_cast<const int2 *>(P.bt_near), P.bt_nnear, P.leaf_off, P.near_ptr,
                 P.near_s, P.px, P.py, P.pz, P.cfg.kernel, P.cfg.kernel_param, Xs, NP, Y);

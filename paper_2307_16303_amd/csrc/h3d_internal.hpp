@@ -479,6 +479,9 @@ int32_t *s2_ring_steps(Plan &P, int l, bool adjoint, hipStream_t s);
 void launch_s2_ring(Plan &P, int l, bool adjoint, const int2 *items, int64_t nitems,
                     const float *Z, int NP, double *Y, hipStream_t s);
 void launch_leaf_fused(Plan &P, const float *Xs, int NP, double *Y, bool adjoint, hipStream_t s);
+// many-RHS near field with FP32 entries, one wave per leaf of at most 64 rows
+// (false, with nothing launched, when some leaf holds more)
+bool launch_near_leaves(Plan &P, const float *Xs, int NP, double *Y, hipStream_t s);
 // the pivot + LU form (lu_form.hip)
 constexpr int kLuSlots = 4;                // 64-row register slots of the in-wave solves
 constexpr int kLuMaxRank = 64 * kLuSlots;  // largest rank the form takes

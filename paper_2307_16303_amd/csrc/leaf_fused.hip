@@ -335,6 +335,153 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(LfShape
     }
 }
 
+// Many right-hand sides, near field with FP32 entries (the FP32 and BF16
+// factor forms): one wave per target leaf of at most 16 MT rows, all its row
+// tiles at once, so that every fragment of x is loaded once for the leaf (one
+// wave per 16-row tile read the rows of x of all the leaf's near leaves once
+// per tile).  A K-step takes four source points of a near leaf (K slot q =
+// point j0 + q); a lane evaluates the entries of its MT target rows against
+// its source point in FP32 (distances formed in FP64 and rounded once), and
+// its four x values of the point are one 16-byte load (tile N, column n is
+// right-hand side 4 n + N).  Entries of rows past the leaf, of source points
+// past the near leaf and of a point with itself are zero.  The FP32 sums of
+// a row run in the same order as in the one-tile-per-wave form.  The loads of
+// the next two K-steps are in flight while a step's MFMAs run (a cursor over
+// the near leaves' K-steps in list order, with the steady part and tail of
+// the other rings).
+struct NSlot {
+    double xj, yj, zj;  // this lane's source point
+    int64_t gj;
+    bool ok;            // the point lies inside its near leaf
+    f4 xv;              // its right-hand sides 4 r16 .. 4 r16 + 3
+};
+
+template <int MT, int KIND>
+__global__ void __launch_bounds__(256)
+    k_near_leaf(const int32_t *__restrict__ items, int64_t nitems,
+                const int32_t *__restrict__ leaf_off, const int32_t *__restrict__ near_ptr,
+                const int32_t *__restrict__ near_s, const double *__restrict__ px,
+                const double *__restrict__ py, const double *__restrict__ pz, int kind, float kp,
+                const float *__restrict__ Xs, int NP, double *__restrict__ Y) {
+    const int64_t w = dev::xcd_run(blockIdx.x, gridDim.x) * 4 +
+                      __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (w >= nitems)
+        return;
+    const int lane = threadIdx.x & 63;
+    const int r16 = lane & 15, q = lane >> 4;
+    const int64_t t = dev::cload(items + w);
+    const int32_t t0 = dev::cload(leaf_off + t), m = dev::cload(leaf_off + t + 1) - t0;
+    const int e0 = dev::cload(near_ptr + t), e1 = dev::cload(near_ptr + t + 1);
+    double xi[MT], yi[MT], zi[MT];
+    int64_t gi[MT];
+    bool ai[MT];
+#pragma unroll
+    for (int T = 0; T < MT; ++T) {
+        const int i = 16 * T + r16;
+        ai[T] = i < m;
+        gi[T] = t0 + (ai[T] ? i : 0);
+        xi[T] = px[gi[T]];
+        yi[T] = py[gi[T]];
+        zi[T] = pz[gi[T]];
+    }
+    int S = 0;  // K-steps of four source points over the near leaves
+    for (int e = e0; e < e1; ++e) {
+        const int32_t sl = dev::cload(near_s + e);
+        S += (dev::cload(leaf_off + sl + 1) - dev::cload(leaf_off + sl) + 3) >> 2;
+    }
+    if (S == 0)
+        return;
+    for (int nb = 0; nb < NP; nb += 64) {
+        const int nv = min(64, NP - nb);
+        const int bcol = nb + 4 * min(r16, nv / 4 - 1);
+        f4 acc[MT][4];
+#pragma unroll
+        for (int T = 0; T < MT; ++T)
+#pragma unroll
+            for (int N = 0; N < 4; ++N)
+                acc[T][N] = f4{0.f, 0.f, 0.f, 0.f};
+        // refill cursor over the K-steps of the near leaves in list order,
+        // two steps in flight; past the last step it stays there (never
+        // consumed)
+        int fe = e0, fj = 0;
+        int32_t fs0 = 0, fns = 1;
+        auto leaf_rows = [&](int e) {
+            const int32_t sl = dev::cload(near_s + e);
+            fs0 = dev::cload(leaf_off + sl);
+            fns = dev::cload(leaf_off + sl + 1) - fs0;
+        };
+        leaf_rows(fe);
+        auto fill = [&](NSlot &R) {
+            const int j = fj + q;
+            R.gj = fs0 + min(j, fns - 1);
+            R.ok = j < fns;
+            R.xj = px[R.gj];
+            R.yj = py[R.gj];
+            R.zj = pz[R.gj];
+            R.xv = *reinterpret_cast<const f4 *>(Xs + R.gj * NP + bcol);
+        };
+        auto advance = [&] {
+            if ((fj += 4) < fns)
+                return;
+            if (fe + 1 >= e1) {  // past the last step: stay on it
+                fj -= 4;
+                return;
+            }
+            fj = 0;
+            leaf_rows(++fe);
+        };
+        auto step = [&](const NSlot &R) {
+            float a[MT];
+#pragma unroll
+            for (int T = 0; T < MT; ++T) {
+                const double dx = xi[T] - R.xj, dy = yi[T] - R.yj, dz = zi[T] - R.zj;
+                const float r2 = float(dx * dx + dy * dy + dz * dz);
+                a[T] = (ai[T] && R.ok && R.gj != gi[T])
+                           ? dev::kernel_f32(KIND >= 0 ? KIND : kind, kp, r2)
+                           : 0.f;
+            }
+#pragma unroll
+            for (int T = 0; T < MT; ++T)
+#pragma unroll
+                for (int N = 0; N < 4; ++N)
+                    acc[T][N] = mma(a[T], R.xv[N], acc[T][N]);
+        };
+        NSlot R[2];
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            fill(R[d]);
+            advance();
+            __builtin_amdgcn_sched_barrier(0);  // slots in order (the waits count on it)
+        }
+        int s0 = 0;
+        for (; s0 + 2 <= S; s0 += 2) {
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+                step(R[d]);
+                fill(R[d]);
+                advance();
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        if (s0 < S)
+            step(R[0]);
+        if (4 * r16 < nv) {
+#pragma unroll
+            for (int T = 0; T < MT; ++T)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int r = 16 * T + 4 * q + jj;
+                    if (r < m) {
+                        double *yp = Y + (t0 + r) * int64_t(NP) + nb + 4 * r16;
+#pragma unroll
+                        for (int N = 0; N < 4; ++N)
+                            yp[N] = double(acc[T][N][jj]);
+                    }
+                }
+        }
+    }
+}
+
 }  // namespace
 
 // Leaves of the finest level grouped by 16-row tile count (1..4); false when
@@ -404,6 +551,41 @@ void launch_leaf_fused(Plan &P, const float *Xs, int NP, double *Y, bool adjoint
         H3D_LAUNCH_CHECK();
     }
 #undef H3D_LF
+}
+
+// The near field of a many-RHS product with FP32 entries, one wave per leaf
+// (false when the leaf classes do not apply: some leaf holds more than 64
+// rows).
+bool launch_near_leaves(Plan &P, const float *Xs, int NP, double *Y, hipStream_t s) {
+    if (P.L < 1 || !leaf_fused_tables(P, s))
+        return false;
+    const float kp = float(P.cfg.kernel_param);
+    // the Laplace kernel has launches of its own (the general ones carry
+    // every kernel's formula)
+    const bool lap = P.cfg.kernel == H3D_LAPLACE;
+#define H3D_NL(MT, K)                                                                           \
+    k_near_leaf<MT, K><<<int((P.lf_n[MT - 1] + 3) / 4), 256, 0, s>>>(                          \
+        P.lf_items[MT - 1], P.lf_n[MT - 1], P.leaf_off, P.near_ptr, P.near_s, P.px, P.py, P.pz, \
+        P.cfg.kernel, kp, Xs, NP, Y)
+#define H3D_NLK(MT)                                                                             \
+    if (lap)                                                                                    \
+        H3D_NL(MT, H3D_LAPLACE);                                                                \
+    else                                                                                        \
+        H3D_NL(MT, -1);
+    for (int mt = 1; mt <= 4; ++mt) {
+        if (P.lf_n[mt - 1] == 0)
+            continue;
+        switch (mt) {
+        case 1: H3D_NLK(1) break;
+        case 2: H3D_NLK(2) break;
+        case 3: H3D_NLK(3) break;
+        default: H3D_NLK(4) break;
+        }
+        H3D_LAUNCH_CHECK();
+    }
+#undef H3D_NLK
+#undef H3D_NL
+    return true;
 }
 
 }  // namespace h3d
