@@ -130,6 +130,9 @@ def parse():
                     help="skip the baseline and the other forms measured beside the headline")
     ap.add_argument("--profile-levels", action="store_true",
                     help="profile the factor streams level by level (one launch per level)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the multi-problem batch variant and print its figures "
+                         "(a profiling aid; not the bench line)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="after the timed steps, fill and copy a 2 GiB buffer: the plain "
                          "kernels that hardware byte counters are scaled by; then time "
@@ -272,6 +275,59 @@ def rel_err(a, b) -> float:
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def batch_variant(args, dev):
+    """The bench's multi-problem workload as one batch: its time per product, and
+    that of the members' own products in sequence; returns (figures, two
+    problems' outputs for the error check)."""
+    import torch
+
+    from paper_2307_16303_amd import hodlr3d, inputs
+    bw = inputs.BATCH_WORKLOAD
+    work = inputs.batch_workload(bw["count"])
+    t0 = time.perf_counter()
+    bop = hodlr3d.build_batch([torch.as_tensor(p, device=dev) for p, _ in work],
+                              kernel=bw["kernel"], leaf_size=bw["leaf_size"], tol=bw["tol"],
+                              factor_dtype=bw["factor_dtype"], box_lo=inputs.CUBE_LO,
+                              box_side=inputs.CUBE_SIDE)
+    torch.cuda.synchronize()
+    bbuild = time.perf_counter() - t0
+    xs = [torch.as_tensor(x, device=dev) for _, x in work]
+    nb = max(3, args.steps // 2)
+    for _ in range(max(1, args.warmup // 2)):
+        ys = bop.matvec(xs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(nb):
+        ys = bop.matvec(xs)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / nb
+    bop.check()
+    for p, x in zip(bop.plans, xs):
+        p.matvec(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(nb):
+        for p, x in zip(bop.plans, xs):
+            p.matvec(x)
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t0) / nb
+    ntot = sum(len(p) for p, _ in work)
+    bst = bop.stats()
+    fig = {
+        "factor_dtype": bw["factor_dtype"], "nrhs": 1, "problems": len(work), "n_total": ntot,
+        "ms_per_step": round(1e3 * tb, 4), "value": round(ntot / tb, 1),
+        "own_products_in_sequence_ms": round(1e3 * ts, 4),
+        "gain_vs_own_products": round(ts / tb, 2),
+        "factor_bytes": bst["factor_bytes"],
+        "hbm_gbs": round(bst["factor_bytes"] / tb / 1e9, 1), "build_s": round(bbuild, 2)}
+    log(f"batch32: {1e3 * tb:.3f} ms ({1e3 * ts:.3f} ms as own products)")
+    outs = [(work[i][0], work[i][1], ys[i].detach().cpu().numpy()) for i in (0, 17)]
+    bop.close()
+    del bop, xs, ys
+    torch.cuda.empty_cache()
+    return fig, outs
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -281,6 +337,13 @@ def main():
     import torch
 
     from paper_2307_16303_amd import hodlr3d, inputs
+
+    if args.batch_only:
+        dev = torch.device("cuda:0")
+        torch.cuda.set_device(dev)
+        fig, _ = batch_variant(args, dev)
+        print(json.dumps({"batch32_fp32": fig}), flush=True)
+        return
 
     wname = args.workload
     w = inputs.WORKLOADS[wname]
@@ -450,52 +513,10 @@ def main():
         variants["ie_grid64"] = integral_equation(64, 1e-7)
         torch.cuda.empty_cache()
 
-    # ---- many uneven problems in one persistent launch --------------------
+    # ---- many uneven problems multiplied together -------------------------
     batch_ys = None
     if not args.no_variants:
-        bw = inputs.BATCH_WORKLOAD
-        work = inputs.batch_workload(bw["count"])
-        t0 = time.perf_counter()
-        bop = hodlr3d.build_batch([torch.as_tensor(p, device=dev) for p, _ in work],
-                                  kernel=bw["kernel"], leaf_size=bw["leaf_size"], tol=bw["tol"],
-                                  factor_dtype=bw["factor_dtype"], box_lo=inputs.CUBE_LO,
-                                  box_side=inputs.CUBE_SIDE)
-        torch.cuda.synchronize()
-        bbuild = time.perf_counter() - t0
-        xs = [torch.as_tensor(x, device=dev) for _, x in work]
-        nb = max(3, args.steps // 2)
-        for _ in range(max(1, args.warmup // 2)):
-            ys = bop.matvec(xs)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(nb):
-            ys = bop.matvec(xs)
-        torch.cuda.synchronize()
-        tb = (time.perf_counter() - t0) / nb
-        bop.check()
-        for p, x in zip(bop.plans, xs):
-            p.matvec(x)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(nb):
-            for p, x in zip(bop.plans, xs):
-                p.matvec(x)
-        torch.cuda.synchronize()
-        ts = (time.perf_counter() - t0) / nb
-        ntot = sum(len(p) for p, _ in work)
-        bst = bop.stats()
-        variants["batch32_fp32"] = {
-            "factor_dtype": bw["factor_dtype"], "nrhs": 1, "problems": len(work), "n_total": ntot,
-            "ms_per_step": round(1e3 * tb, 4), "value": round(ntot / tb, 1),
-            "own_products_in_sequence_ms": round(1e3 * ts, 4),
-            "gain_vs_own_products": round(ts / tb, 2),
-            "factor_bytes": bst["factor_bytes"],
-            "hbm_gbs": round(bst["factor_bytes"] / tb / 1e9, 1), "build_s": round(bbuild, 2)}
-        log(f"batch32: {1e3 * tb:.3f} ms ({1e3 * ts:.3f} ms as own products)")
-        batch_ys = [(work[i][0], work[i][1], ys[i].detach().cpu().numpy()) for i in (0, 17)]
-        bop.close()
-        del bop, xs, ys
-        torch.cuda.empty_cache()
+        variants["batch32_fp32"], batch_ys = batch_variant(args, dev)
 
     # ---- the CPU oracle: exact rows (errors and the baseline) -------------
     cpu = None
