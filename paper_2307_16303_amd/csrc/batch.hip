@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(64)
     const int64_t u = u0 + blockIdx.x;
     const BatchSeg sg = seg_of(segs, sb, se, u);
     const BatchProb &D = probs[sg.prob];
-    near_leaf<1, false, DT != H3D_F64>(u - sg.start, D.leaf_off, D.near_ptr, D.near_s, D.px, D.py,
+    near_leaf<1, DT != H3D_F64>(u - sg.start, D.leaf_off, D.near_ptr, D.near_s, D.px, D.py,
                                         D.pz, D.kind, D.kp, nrhs, D.xp, D.n, D.yn);
 }
 

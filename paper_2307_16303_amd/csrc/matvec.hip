@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(64)
            const int32_t *__restrict__ near_s, const double *__restrict__ px,
            const double *__restrict__ py, const double *__restrict__ pz, int kind, double kp,
            int nrhs, const double *__restrict__ xp, int64_t n, double *__restrict__ yn) {
-    near_leaf<NR, false, E32, KIND>(blockIdx.x, leaf_off, near_ptr, near_s, px, py, pz, kind, kp,
+    near_leaf<NR, E32, KIND>(blockIdx.x, leaf_off, near_ptr, near_s, px, py, pz, kind, kp,
                                     nrhs, xp, n, yn);
 }
 

@@ -1,7 +1,7 @@
 // Per-item device code of the mat-vec (Algorithm 2): the gather of one row,
 // the near field of one leaf and stage 2 of one chunk box (stage-1 work items:
 // stage1_items.hpp).  The per-phase kernels of a single operator and the
-// persistent kernel of a batch of operators both call these functions, so a
+// phase launches of a batch of operators both call these functions, so a
 // problem computes the same sums in either form.
 #pragma once
 
@@ -61,19 +61,6 @@ __device__ __forceinline__ typename Fac<DT>::T fac_raw(const typename Fac<DT>::T
 template <int DT, bool NT = false>
 __device__ __forceinline__ double fac_ld(const typename Fac<DT>::T *p) {
     return Fac<DT>::cvt(fac_raw<DT, NT>(p));
-}
-
-// Reads of data that another wave of the same launch may have written (the
-// persistent multi-problem kernel: xp, the near-field sums, z).  A relaxed
-// atomic load is always a vector load, so the value comes through the caches
-// that the acquire fence of the waiting wave invalidated, never through the
-// scalar cache; outside that kernel (LIVE = false) plain loads let the
-// compiler use scalar loads for wave-uniform values.
-template <bool LIVE> __device__ __forceinline__ double rd(const double *p) {
-    if constexpr (LIVE)
-        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-    else
-        return *p;
 }
 
 __device__ __forceinline__ double kernel_f(int kind, double kp, double r) {
@@ -141,7 +128,7 @@ constexpr int kChunk = 128;
 // E32: kernel entries evaluated in FP32 (forms with FP32 or BF16 factors),
 // accumulated in FP64.  KIND >= 0 fixes the kernel at compile time (only its
 // formula is inlined into the loop); -1 takes `kind`.
-template <int NR, bool LIVE = false, bool E32 = false, int KIND = -1>
+template <int NR, bool E32 = false, int KIND = -1>
 __device__ __forceinline__ void near_leaf(int64_t t, const int32_t *__restrict__ leaf_off,
                                           const int32_t *__restrict__ near_ptr,
                                           const int32_t *__restrict__ near_s,
@@ -223,7 +210,7 @@ __device__ __forceinline__ void near_leaf(int64_t t, const int32_t *__restrict__
                             sz[jj] = pz[gj];
 #pragma unroll
                             for (int c = 0; c < NR; ++c)
-                                sv[c][jj] = (rb + c < nrhs) ? rd<LIVE>(xp + (rb + c) * n + gj) : 0.0;
+                                sv[c][jj] = (rb + c < nrhs) ? xp[(rb + c) * n + gj] : 0.0;
                         }
                     }
                     __syncthreads();
@@ -267,7 +254,7 @@ struct S2Tab {
     int panel;  // the factors streamed are U_b stored as row panels above lc
 };
 
-template <int DT, int NR, int U2, bool LIVE = false>
+template <int DT, int NR, int U2>
 __device__ __forceinline__ void stage2_block(const typename Fac<DT>::T *__restrict__ p, int bm, int k,
                                              const double *__restrict__ zz, int64_t ldz, int rb,
                                              int nrhs, double (&acc)[NR]) {
@@ -284,20 +271,20 @@ __device__ __forceinline__ void stage2_block(const typename Fac<DT>::T *__restri
 #pragma unroll
             for (int q = 0; q < NR; ++q)
                 if (NR == 1 || rb + q < nrhs)
-                    acc[q] += Fac<DT>::cvt(v[u]) * rd<LIVE>(zz + (rb + q) * ldz + c + u);
+                    acc[q] += Fac<DT>::cvt(v[u]) * zz[(rb + q) * ldz + c + u];
     }
     for (; c < k; ++c) {
         const double v = fac_ld<DT, kS2NonTemporal>(p + int64_t(c) * bm);
 #pragma unroll
         for (int q = 0; q < NR; ++q)
             if (NR == 1 || rb + q < nrhs)
-                acc[q] += v * rd<LIVE>(zz + (rb + q) * ldz + c);
+                acc[q] += v * zz[(rb + q) * ldz + c];
     }
 }
 
 // The same for two rows per lane, d rows apart (d = 0 for a lane whose second
 // row lies past the box: it then repeats its first load and drops the sum).
-template <int DT, int NR, int U2, bool LIVE = false>
+template <int DT, int NR, int U2>
 __device__ __forceinline__ void stage2_block2(const typename Fac<DT>::T *__restrict__ p, int d,
                                               int bm, int k, const double *__restrict__ zz,
                                               int64_t ldz, int rb, int nrhs, double (&a0)[NR],
@@ -316,7 +303,7 @@ __device__ __forceinline__ void stage2_block2(const typename Fac<DT>::T *__restr
 #pragma unroll
             for (int q = 0; q < NR; ++q)
                 if (NR == 1 || rb + q < nrhs) {
-                    const double zq = rd<LIVE>(zz + (rb + q) * ldz + c + u);
+                    const double zq = zz[(rb + q) * ldz + c + u];
                     a0[q] += Fac<DT>::cvt(v[u]) * zq;
                     a1[q] += Fac<DT>::cvt(w[u]) * zq;
                 }
@@ -327,14 +314,14 @@ __device__ __forceinline__ void stage2_block2(const typename Fac<DT>::T *__restr
 #pragma unroll
         for (int q = 0; q < NR; ++q)
             if (NR == 1 || rb + q < nrhs) {
-                const double zq = rd<LIVE>(zz + (rb + q) * ldz + c);
+                const double zq = zz[(rb + q) * ldz + c];
                 a0[q] += v * zq;
                 a1[q] += w * zq;
             }
     }
 }
 
-template <int DT, int NR, int kS2Waves, bool LIVE = false>
+template <int DT, int NR, int kS2Waves>
 __device__ __forceinline__ void
     stage2_chunk(int64_t B, const S2Tab &tab, const int32_t *__restrict__ leaf_off,
                  const int32_t *__restrict__ leaf_of, const int64_t *__restrict__ grp_begin,
@@ -364,8 +351,8 @@ __device__ __forceinline__ void
 #pragma unroll
             for (int c = 0; c < NR; ++c) {
                 const bool ok = wv == 0 && (NR == 1 || rb + c < nrhs);
-                acc[0][c] = ok ? rd<LIVE>(yn + (rb + c) * n + rrA) : 0.0;
-                acc[1][c] = (ok && two) ? rd<LIVE>(yn + (rb + c) * n + rrA + dB) : 0.0;
+                acc[0][c] = ok ? yn[(rb + c) * n + rrA] : 0.0;
+                acc[1][c] = (ok && two) ? yn[(rb + c) * n + rrA + dB] : 0.0;
             }
             // levels whose boxes contain the whole chunk box: wave-uniform;
             // the waves of the workgroup take every kS2Waves-th block
@@ -385,10 +372,10 @@ __device__ __forceinline__ void
                     const T *p = static_cast<const T *>(fptr[bi]) +
                                  (pan ? int64_t(r0 - bs) * kb + (rrA - r0) : int64_t(rrA - bs));
                     if (two)
-                        stage2_block2<DT, NR, 8, LIVE>(p, dB, ld, kb, z + blk_col0[bi],
+                        stage2_block2<DT, NR, 8>(p, dB, ld, kb, z + blk_col0[bi],
                                                                   ldz, rb, nrhs, acc[0], acc[1]);
                     else
-                        stage2_block<DT, NR, 8, LIVE>(p, ld, kb, z + blk_col0[bi], ldz,
+                        stage2_block<DT, NR, 8>(p, ld, kb, z + blk_col0[bi], ldz,
                                                                  rb, nrhs, acc[0]);
                 }
             }
@@ -412,7 +399,7 @@ __device__ __forceinline__ void
                         for (int64_t e = e0 + wv; e < e1; e += kS2Waves) {
                             const int64_t bi = grp_blk[e];
                             const T *p = static_cast<const T *>(fptr[bi]) + loc;
-                            stage2_block<DT, NR, 4, LIVE>(p, bm, rank[bi], z + blk_col0[bi], ldz, rb,
+                            stage2_block<DT, NR, 4>(p, bm, rank[bi], z + blk_col0[bi], ldz, rb,
                                                           nrhs, ah);
                         }
                     } else if (e1 > e0) {
@@ -428,7 +415,7 @@ __device__ __forceinline__ void
                         const T *pf = static_cast<const T *>(fptr[e0]);
                         const T *pl = static_cast<const T *>(fptr[e1 - 1]);
                         if (pl + int64_t(bm) * rank[e1 - 1] == pf + int64_t(bm) * kt) {
-                            stage2_block<DT, NR, 8, LIVE>(pf + loc + int64_t(cb) * bm, bm, ce - cb,
+                            stage2_block<DT, NR, 8>(pf + loc + int64_t(cb) * bm, bm, ce - cb,
                                                           z + zc0 + cb, ldz, rb, nrhs, ah);
                         } else {
                             for (int64_t e = e0; e < e1; ++e) {
@@ -437,7 +424,7 @@ __device__ __forceinline__ void
                                     break;
                                 const int lo = max(cb, c0), hi = min(ce, c0 + rank[e]);
                                 if (lo < hi)
-                                    stage2_block<DT, NR, 8, LIVE>(
+                                    stage2_block<DT, NR, 8>(
                                         static_cast<const T *>(fptr[e]) + loc +
                                             int64_t(lo - c0) * bm,
                                         bm, hi - lo, z + zc0 + lo, ldz, rb, nrhs, ah);

@@ -1,7 +1,7 @@
 // Stage-1 work items of the mat-vec (Algorithm 2, low-rank part): the dot
 // products z = V_b^T x_s (in the adjoint U_b^T x_t) of one item of a level.
 // Called by the per-level stage-1 kernels of a single operator and by the
-// persistent kernel of a batch of operators.
+// stage-1 launches of a batch of operators.
 #pragma once
 
 #include "product_items.hpp"
@@ -83,7 +83,7 @@ struct S1Args {
     double *zp;
 };
 
-template <int S, int U, int DT, int NR, bool LIVE = false>
+template <int S, int U, int DT, int NR>
 __device__ __forceinline__ void s1_wide_item(const S1Args &a, int64_t w) {
     using T = typename Fac<DT>::T;
     constexpr int NS = 64 / S;
@@ -130,7 +130,7 @@ __device__ __forceinline__ void s1_wide_item(const S1Args &a, int64_t w) {
 #pragma unroll
                     for (int q = 0; q < NR; ++q) {
                         const double xr = (NR == 1 || rb + q < a.nrhs)
-                                              ? rd<LIVE>(xp + (rb + q) * a.n + off + jc)
+                                              ? xp[(rb + q) * a.n + off + jc]
                                               : 0.0;
                         xv[i][q] = j < j1 ? xr : 0.0;
                     }
@@ -171,7 +171,7 @@ __device__ __forceinline__ void s1_wide_item(const S1Args &a, int64_t w) {
     }
 }
 
-template <int S, int U, int DT, int NR, bool LIVE = false>
+template <int S, int U, int DT, int NR>
 __device__ __forceinline__ void s1_packed_item(const S1Args &a, int64_t w) {
     using T = typename Fac<DT>::T;
     const int2 item = a.items[w];
@@ -213,7 +213,7 @@ __device__ __forceinline__ void s1_packed_item(const S1Args &a, int64_t w) {
 #pragma unroll
                     for (int q = 0; q < NR; ++q) {
                         const double xr = (NR == 1 || rb + q < a.nrhs)
-                                              ? rd<LIVE>(xp + (rb + q) * a.n + off + jc)
+                                              ? xp[(rb + q) * a.n + off + jc]
                                               : 0.0;
                         xv[i][q] = j < jend ? xr : 0.0;
                     }
@@ -255,7 +255,7 @@ __device__ __forceinline__ void s1_packed_item(const S1Args &a, int64_t w) {
 // panels of the target box in row order.
 constexpr int kPanelCols = 8;
 
-template <int DT, int NR, bool LIVE = false>
+template <int DT, int NR>
 __device__ __forceinline__ void s1_panel_item(const S1Args &a, const int32_t *__restrict__ leaf_off,
                                               const int32_t *__restrict__ box, int shc, int shl,
                                               int64_t w) {
@@ -289,7 +289,7 @@ __device__ __forceinline__ void s1_panel_item(const S1Args &a, const int32_t *__
                 double xv[NR];
 #pragma unroll
                 for (int q = 0; q < NR; ++q)
-                    xv[q] = (NR == 1 || rb + q < a.nrhs) ? rd<LIVE>(xp + (rb + q) * a.n + r0 + j)
+                    xv[q] = (NR == 1 || rb + q < a.nrhs) ? xp[(rb + q) * a.n + r0 + j]
                                                          : 0.0;
                 // cb < k: columns clamped into the block, every load issued
                 T vr[U];
