@@ -31,7 +31,7 @@ one and 64 right-hand sides; the paper's own pivot + LU form, whose product
 regenerates the kernel entries and is bound by the vector ALUs) on the
 headline points, the plain FP64 and LU forms on 262,144 points, the
 multi-problem form (32 clouds, N_i in [8192, 131072], FP32 factors, tol 1e-7)
-in one persistent launch, and the integral-equation solve of Sec. 5.2 on a
+as one batch (one launch per phase over all problems), and the integral-equation solve of Sec. 5.2 on a
 64^3 grid (GMRES to a relative residual of 1e-10).
 
 roofline.traffic is the dominant kernel's HBM traffic per launch from the
@@ -75,10 +75,21 @@ TRAFFIC = {
     "write_scale": 1.000000,
     "readings": [
         {"workload": "uniform262k", "factor_dtype": "fp64", "nrhs": 1,
-         "sources_sha256": "56043d14438b5b9a3065bde2e48fb7b01c5bfe4361b96bf4191d5524db659a6a",
+         "sources_sha256": "c26bd6a6f1da06e71dd99ed05899a4613ea90f77bba3e8beed6a11814197a7d3",
          "scope": "stream",
-         "kernels": {"k_stage2": {"fetch_kib": 10105475.4375, "write_kib": 8198.3229},
-                     "k_s1_wide": {"fetch_kib": 2551872.3438, "write_kib": 35194.4089}}},
+         "kernels": {"k_stage2": {"fetch_kib": 10105433.125, "write_kib": 8198.9375},
+                     "k_s1_wide": {"fetch_kib": 2545312.3438, "write_kib": 35339.5156},
+                     "k_leaf": {"fetch_kib": 1854402.8125, "write_kib": 2839.5312}}},
+        # the headline: 64 right-hand sides on the matrix cores (per launch:
+        # a level of stage 1 or stage 2; the finest level and the near field
+        # are one launch group each)
+        {"workload": "uniform1m", "factor_dtype": "fp32", "nrhs": 64,
+         "sources_sha256": "82c82b1751465f1c8d28a10b39401090af9781d06734c8617d804d758a3e134d",
+         "scope": "all",
+         "kernels": {"k_s1_mfma": {"fetch_kib": 5705423.0156, "write_kib": 1019414.2344},
+                     "k_s2_mfma": {"fetch_kib": 5464061.9219, "write_kib": 524288.0625},
+                     "k_leaf_fused": {"fetch_kib": 16534871.125, "write_kib": 524288.5},
+                     "k_near_mfma": {"fetch_kib": 1073548.25, "write_kib": 524288.0}}},
     ],
 }
 
@@ -102,12 +113,14 @@ def sources_digest(scope: str = "all") -> str:
     return h.hexdigest()
 
 
-def traffic_bytes(kernel: str, workload: str, factor_dtype: str, nrhs: int):
+def traffic_bytes(kernel: str, workload: str, factor_dtype: str, nrhs: int,
+                  adjoint: bool = False):
     """HBM bytes per launch from the stored counter readings, or None."""
     for r in TRAFFIC["readings"]:
         k = r["kernels"].get(kernel)
         if (k is None or r["workload"] != workload or r["factor_dtype"] != factor_dtype
-                or r["nrhs"] != nrhs or r["sources_sha256"] != sources_digest(r["scope"])):
+                or r["nrhs"] != nrhs or r.get("adjoint", False) != adjoint
+                or r["sources_sha256"] != sources_digest(r["scope"])):
             continue
         return (k["fetch_kib"] * 1024.0 / TRAFFIC["fetch_scale"]
                 + k["write_kib"] * 1024.0 / TRAFFIC["write_scale"])
@@ -180,13 +193,13 @@ def time_products(op, x, steps, warmup, adjoint=False, profile=False, levels=Fal
     return sec, y, prof
 
 
-def roofline_of(prof, workload, dt, nrhs):
+def roofline_of(prof, workload, dt, nrhs, adjoint=False):
     """Roofline object of the dominant kernel of a profiled product: matrix-core
     bound (FLOP/s) for the many-RHS kernels, HBM bound (GB/s) otherwise."""
     dom = max(prof, key=lambda p: p["total_ms"])
     avg_ms = dom["total_ms"] / max(dom["launches"], 1)
     gbs = dom["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
-    traffic = traffic_bytes(dom["name"], workload, dt, nrhs)
+    traffic = traffic_bytes(dom["name"], workload, dt, nrhs, adjoint)
     common = {"traffic": None if traffic is None else round(traffic, 0), "kernel": dom["name"],
               "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": dom["bytes_per_launch"]}
     if dom["name"].startswith("k_lu"):
@@ -370,7 +383,7 @@ def main():
     ms = 1e3 * sec
     value = n * nrhs / sec
     log(f"headline {dt} {nrhs} RHS: {ms:.3f} ms, {value:.3e} {UNIT}")
-    roofline = roofline_of(prof, wname, dt, nrhs)
+    roofline = roofline_of(prof, wname, dt, nrhs, args.adjoint)
     kernels = kernel_table(prof)
     head_form = f"{dt}_{nrhs}rhs"
     sampled[head_form] = ("h", y.detach().reshape(n, -1)[torch.as_tensor(rows_err, device=dev)]
@@ -414,7 +427,7 @@ def main():
         if extra:
             rec.update(extra)
         if prof_v:
-            rec["roofline"] = roofline_of(prof_v, wl, dtv, nr)
+            rec["roofline"] = roofline_of(prof_v, wl, dtv, nr, adjoint)
             rec["kernel_ms"] = kernel_table(prof_v)
         variants[name] = rec
         log(f"{name}: {1e3 * sec_v:.3f} ms, {nn * nr / sec_v:.3e} {UNIT}")
