@@ -10,7 +10,8 @@
 //   [stage 1 of every problem and level, one launch per stage-1 shape]
 //   [stage 2 of every problem]
 //
-// Each launch is as large as the sum of the problems' items, so small
+// (Stage 1 is followed by one launch that adds up the parts of split
+// columns.)  Each launch is as large as the sum of the problems' items, so small
 // problems fill the GPU together, and each carries only its own kind of work:
 // the registers, and so the occupancy, of the per-phase kernels.  The stream
 // orders the phases.  A launch's work items are numbered consecutively over a
@@ -20,14 +21,13 @@
 // their shape, its chunk boxes to the stage-2 launch of its wave count.  The
 // arithmetic of each item is the code of the per-phase kernels
 // (product_items.hpp), so a member's own product through h3d_matvec gives
-// bitwise the same result.  (Members choose among whole-column stage-1
-// shapes and do not fuse the finest level: the batch launches carry neither
-// the reduction of split columns nor the fused form.)
+// bitwise the same result.  (Members do not fuse the finest level: the batch
+// launches do not carry the fused form.)
 #include "stage1_items.hpp"
 
 namespace h3d {
 
-enum : int32_t { kSegGather = 0, kSegNear = 1, kSegS1 = 2, kSegS2 = 3 };
+enum : int32_t { kSegGather = 0, kSegNear = 1, kSegS1 = 2, kSegS2 = 3, kSegReduce = 4 };
 
 struct BatchSeg {
     int64_t start;  // first unit of the run (units of one launch are consecutive)
@@ -49,6 +49,9 @@ struct BatchProb {
     const int32_t *rank;
     const int64_t *col0;
     dev::S1Args s1[kMaxLevels + 1];
+    // split stage-1 columns of a level: the column groups (first item, parts)
+    const int32_t *s1_grp[kMaxLevels + 1];
+    int64_t s1_ngrp[kMaxLevels + 1];
 };
 
 namespace {
@@ -56,10 +59,11 @@ namespace {
 using namespace dev;
 
 constexpr int kGatherRows = 1024;  // rows per gather item
+constexpr int kReduceCols = 256;   // split-column sums per reduction item
 
-// the stage-1 shapes the batch launches carry: every whole-column shape the
-// tuner may choose (split columns, which need a reduction pass, are not
-// offered to batch members)
+// the stage-1 shapes the batch launches carry: every shape the tuner may
+// choose (a split shape runs the wide form's items over parts of columns,
+// selected at run time by S1Args::part)
 struct ShapeDef {
     int packed, S, U;
 };
@@ -74,7 +78,7 @@ constexpr bool narrow_only(int id) {
 }
 
 int shape_id(const S1Shape &sh) {
-    if (sh.rows > 0)
+    if (sh.rows > 0 && sh.packed)
         return -1;
     for (int i = 0; i < kNumS1Shapes; ++i)
         if (kShapes[i].packed == sh.packed && kShapes[i].S == sh.S && kShapes[i].U == sh.U)
@@ -82,7 +86,9 @@ int shape_id(const S1Shape &sh) {
     return -1;
 }
 
-// the segment of unit u among segs[sb, se) (their first units ascending)
+// the segment of unit u among segs[sb, se) (their first units ascending);
+// u is the same in every lane, and so is the segment, which is read into
+// scalar registers
 __device__ __forceinline__ BatchSeg seg_of(const BatchSeg *__restrict__ segs, int sb, int se,
                                            int64_t u) {
     int lo = sb, hi = se - 1;
@@ -93,7 +99,7 @@ __device__ __forceinline__ BatchSeg seg_of(const BatchSeg *__restrict__ segs, in
         else
             hi = mid - 1;
     }
-    return segs[lo];
+    return segs[__builtin_amdgcn_readfirstlane(lo)];
 }
 
 // gather: one workgroup per 1024 rows of a problem
@@ -135,13 +141,27 @@ __global__ void __launch_bounds__(256)
     if (w >= units)
         return;
     const BatchSeg sg = seg_of(segs, sb, se, u0 + w);
-    const S1Args &a = probs[sg.prob].s1[sg.level];
+    // a copy, loaded before the item's first store: its fields stay in scalar
+    // registers as a kernel argument's do (read through a reference they were
+    // vector loads at each use, 25-40 more registers, one or two fewer waves)
+    const S1Args a = probs[sg.prob].s1[sg.level];
     const int64_t i = u0 + w - sg.start;
     constexpr ShapeDef sh = kShapes[SHAPE];
     if constexpr (sh.packed)
         s1_packed_item<sh.S, sh.U, DT, 1>(a, i);
     else
         s1_wide_item<sh.S, sh.U, DT, 1>(a, i);
+}
+
+// split stage-1 columns of one (problem, level): kReduceCols sums per item
+__global__ void __launch_bounds__(kReduceCols)
+    k_bs1_reduce(const BatchProb *__restrict__ probs, const BatchSeg *__restrict__ segs, int sb,
+                 int se, int64_t u0) {
+    const int64_t u = u0 + blockIdx.x;
+    const BatchSeg sg = seg_of(segs, sb, se, u);
+    const BatchProb &D = probs[sg.prob];
+    s1_reduce_column((u - sg.start) * kReduceCols + threadIdx.x, D.s1_ngrp[sg.level],
+                     D.s1_grp[sg.level], D.s1[sg.level]);
 }
 
 // stage 2: one workgroup of W waves per chunk box, written straight to y
@@ -181,7 +201,8 @@ enum : int { kLaunchKind, kLaunchShape, kLaunchSb, kLaunchSe, kLaunchU0, kLaunch
 }  // namespace
 
 // Builds the segments (one unit per work item), grouped by launch: gather,
-// near field, stage 1 by shape, stage 2 by waves per chunk box; one list of
+// near field, stage 1 by shape, the sums of split columns, stage 2 by waves
+// per chunk box; one list of
 // launches for one right-hand side (the members' tuned shapes) and one for
 // two to seven (their shapes for several right-hand sides).
 void batch_setup(h3d_plan &bp, hipStream_t s) {
@@ -231,6 +252,17 @@ void batch_setup(h3d_plan &bp, hipStream_t s) {
                             add(kSegS1, p, l, sh, Q.s1_nitems[cls][l]);
                 }
             });
+        // split columns (one right-hand side only), once every stage-1 launch
+        // has written its partial sums
+        launch(kSegReduce, 0, [&] {
+            for (int p = 0; p < nprob; ++p) {
+                const Plan &Q = B.subs[size_t(p)]->P;
+                for (int l = 1; l <= Q.L; ++l)
+                    if (cls == 0 && Q.s1_nitems[0][l] > 0 && Q.s1_part[l])
+                        add(kSegReduce, p, l, 0,
+                            ceil_div(Q.s1_ngrp[l] * Q.s1_span[0][l], int64_t(kReduceCols)));
+            }
+        });
         for (int w : {1, 2, 4, 8})
             launch(kSegS2, w, [&] {
                 for (int p = 0; p < nprob; ++p) {
@@ -306,6 +338,14 @@ static void write_descriptors(BatchState &B, int64_t nrhs) {
             a.n = Q.n;
             a.z = Q.z;
             a.ldz = Q.ncols;
+            // split columns, as the member's own stage 1 (stage1_args)
+            if (cls == 0 && Q.s1_part[l]) {
+                a.part = Q.s1_part[l];
+                a.rows = Q.s1_shape[0][l].rows;
+                a.zp = Q.s1_zp[l];
+                D.s1_grp[l] = Q.s1_grp[l];
+                D.s1_ngrp[l] = Q.s1_ngrp[l];
+            }
         }
         scr.push_back(Q.xp);
         scr.push_back(Q.yp);
@@ -351,6 +391,9 @@ static void batch_launches(const BatchState &B, int nprob, int nrhs, int io_f32,
             break;
         case kSegS1:
             launch_bs1<DT>(shape, int((units + 3) / 4), B, sb, se, u0, units, s);
+            break;
+        case kSegReduce:
+            k_bs1_reduce<<<int(units), kReduceCols, 0, s>>>(B.probs, B.segs, sb, se, u0);
             break;
         default:
 #define H3D_BS2(W)                                                                              \

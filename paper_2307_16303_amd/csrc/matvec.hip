@@ -82,23 +82,9 @@ __global__ void __launch_bounds__(256) k_s1_packed(S1Args a) {
 
 // split columns: z of every column group = its parts' partial sums, added in
 // part order (one thread per column of a group)
-__global__ void k_s1_reduce(int64_t ngrp, const int32_t *__restrict__ grp,
-                            const int2 *__restrict__ items, int span,
-                            const int32_t *__restrict__ rank, const int64_t *__restrict__ col0,
-                            const double *__restrict__ zp, double *__restrict__ z) {
-    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t g = t / span;
-    const int u = int(t - g * span);
-    if (g >= ngrp)
-        return;
-    const int32_t first = grp[2 * g], np = grp[2 * g + 1];
-    const int2 it = items[first];
-    if (it.y + u >= rank[it.x])
-        return;
-    double v = 0.0;
-    for (int32_t pp = 0; pp < np; ++pp)
-        v += zp[int64_t(first + pp) * span + u];
-    z[col0[it.x] + it.y + u] = v;
+__global__ void __launch_bounds__(256)
+    k_s1_reduce(int64_t ngrp, const int32_t *__restrict__ grp, S1Args a) {
+    s1_reduce_column(int64_t(blockIdx.x) * blockDim.x + threadIdx.x, ngrp, grp, a);
 }
 
 // one launch of level l's stage 1 with its current shape
@@ -140,8 +126,7 @@ void launch_s1_level(const Plan &P, int l, const S1Shape &sh, const S1Args &a, h
     if (a.part) {
         H3D_LAUNCH_CHECK();
         const int64_t nt = P.s1_ngrp[l] * a.span;
-        k_s1_reduce<<<grid_for(nt, 256), 256, 0, s>>>(
-            P.s1_ngrp[l], P.s1_grp[l], a.items, a.span, a.rank, a.blk_col0, a.zp, a.z);
+        k_s1_reduce<<<grid_for(nt, 256), 256, 0, s>>>(P.s1_ngrp[l], P.s1_grp[l], a);
     }
 }
 
@@ -394,9 +379,7 @@ void autotune_dt(Plan &P, int nrhs, hipStream_t s) {
             continue;
         S1Shape best_sh = P.s1_shape[cls][l];
         float best_ms = 1e30f;
-        // (a batch member keeps whole columns: the batch launches carry no
-        // reduction of split columns)
-        for (const S1Shape &sh : s1_candidates(P, l, NR == 1 && DT != H3D_F64, NR == 1 && !P.in_batch)) {
+        for (const S1Shape &sh : s1_candidates(P, l, NR == 1 && DT != H3D_F64, NR == 1)) {
             set_level_shape(P, cls, l, sh, s);
             const S1Args a = stage1_args<DT, NR>(P, cls, l, false, nrhs, P.xp, P.z);
             const float ms = time_it([&] { launch_s1_level<DT, NR>(P, l, sh, a, s); });
@@ -502,7 +485,7 @@ void ensure_scratch(Plan &P, int64_t nrhs, hipStream_t s) {
 // ---- the tuner's cache ------------------------------------------------------
 // H3D_TUNE_CACHE names a JSON file mapping a plan's key (GPU architecture,
 // factor type, one or several right-hand sides, depth, batch membership (a
-// member chooses among fewer shapes), and per level the
+// member does not fuse the finest level), and per level the
 // half-octave buckets of the mean box size and the mean rank) to the shapes
 // the tuner chose: [finest-level fusion, stage-2 waves, then per level
 // packed, S, U, passes, rows].  A plan whose key is found takes the stored
@@ -610,7 +593,7 @@ bool tune_cache_apply(Plan &P, int cls, const std::vector<int> &v, bool narrow, 
         sh.reps = e[3];
         sh.rows = e[4];
         bool known = P.lvl_blk[l + 1] <= P.lvl_blk[l];  // empty levels keep any shape
-        for (const S1Shape &c : s1_candidates(P, l, narrow, cls == 0 && !P.in_batch))
+        for (const S1Shape &c : s1_candidates(P, l, narrow, cls == 0))
             known = known || (c.packed == sh.packed && c.S == sh.S && c.U == sh.U &&
                               c.reps == sh.reps && c.rows == sh.rows);
         known = known || (sh.packed == P.s1_shape[cls][l].packed && sh.S == P.s1_shape[cls][l].S &&

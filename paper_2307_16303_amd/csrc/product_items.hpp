@@ -58,6 +58,14 @@ __device__ __forceinline__ typename Fac<DT>::T fac_raw(const typename Fac<DT>::T
     else
         return *(G *)p;
 }
+// p as a pointer to global memory: accesses through it compile to global
+// loads and stores.  (A pointer read from device memory, as from a batch's
+// descriptors, is otherwise accessed with flat instructions, which also count
+// against the scalar and LDS counter and cost registers.)
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *glob(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
 template <int DT, bool NT = false>
 __device__ __forceinline__ double fac_ld(const typename Fac<DT>::T *p) {
     return Fac<DT>::cvt(fac_raw<DT, NT>(p));
@@ -271,14 +279,14 @@ __device__ __forceinline__ void stage2_block(const typename Fac<DT>::T *__restri
 #pragma unroll
             for (int q = 0; q < NR; ++q)
                 if (NR == 1 || rb + q < nrhs)
-                    acc[q] += Fac<DT>::cvt(v[u]) * zz[(rb + q) * ldz + c + u];
+                    acc[q] += Fac<DT>::cvt(v[u]) * glob(zz)[(rb + q) * ldz + c + u];
     }
     for (; c < k; ++c) {
         const double v = fac_ld<DT, kS2NonTemporal>(p + int64_t(c) * bm);
 #pragma unroll
         for (int q = 0; q < NR; ++q)
             if (NR == 1 || rb + q < nrhs)
-                acc[q] += v * zz[(rb + q) * ldz + c];
+                acc[q] += v * glob(zz)[(rb + q) * ldz + c];
     }
 }
 
@@ -303,7 +311,7 @@ __device__ __forceinline__ void stage2_block2(const typename Fac<DT>::T *__restr
 #pragma unroll
             for (int q = 0; q < NR; ++q)
                 if (NR == 1 || rb + q < nrhs) {
-                    const double zq = zz[(rb + q) * ldz + c + u];
+                    const double zq = glob(zz)[(rb + q) * ldz + c + u];
                     a0[q] += Fac<DT>::cvt(v[u]) * zq;
                     a1[q] += Fac<DT>::cvt(w[u]) * zq;
                 }
@@ -314,7 +322,7 @@ __device__ __forceinline__ void stage2_block2(const typename Fac<DT>::T *__restr
 #pragma unroll
         for (int q = 0; q < NR; ++q)
             if (NR == 1 || rb + q < nrhs) {
-                const double zq = zz[(rb + q) * ldz + c];
+                const double zq = glob(zz)[(rb + q) * ldz + c];
                 a0[q] += v * zq;
                 a1[q] += w * zq;
             }
@@ -323,14 +331,23 @@ __device__ __forceinline__ void stage2_block2(const typename Fac<DT>::T *__restr
 
 template <int DT, int NR, int kS2Waves>
 __device__ __forceinline__ void
-    stage2_chunk(int64_t B, const S2Tab &tab, const int32_t *__restrict__ leaf_off,
-                 const int32_t *__restrict__ leaf_of, const int64_t *__restrict__ grp_begin,
-                 const int64_t *__restrict__ grp_blk, void *const *__restrict__ fptr,
-                 const int32_t *__restrict__ rank, const int64_t *__restrict__ blk_col0,
-                 const double *__restrict__ z, int64_t ldz, const double *yn, int64_t n, int nrhs,
-                 const int32_t *__restrict__ perm, void *__restrict__ yout, int64_t ldy, int io_f32,
-                 int lb, int le, double *ypart) {
+    stage2_chunk(int64_t B, const S2Tab &tab, const int32_t *__restrict__ leaf_off_,
+                 const int32_t *__restrict__ leaf_of_, const int64_t *__restrict__ grp_begin_,
+                 const int64_t *__restrict__ grp_blk_, void *const *__restrict__ fptr_,
+                 const int32_t *__restrict__ rank_, const int64_t *__restrict__ blk_col0_,
+                 const double *__restrict__ z, int64_t ldz, const double *yn_, int64_t n, int nrhs,
+                 const int32_t *__restrict__ perm_, void *__restrict__ yout, int64_t ldy,
+                 int io_f32, int lb, int le, double *ypart) {
     using T = typename Fac<DT>::T;
+    // the tables as pointers to global memory (glob), also when they were
+    // read from device memory
+    const auto leaf_off = glob(leaf_off_), leaf_of = glob(leaf_of_);
+    const auto grp_begin = glob(grp_begin_), grp_blk = glob(grp_blk_);
+    const auto fptr = glob(fptr_);
+    const auto rank = glob(rank_);
+    const auto blk_col0 = glob(blk_col0_);
+    const auto yn = glob(yn_);
+    const auto perm = glob(perm_);
     __shared__ double part[kS2Waves][NR][64];
     const int L = tab.L, lc = tab.lc;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -452,16 +469,16 @@ __device__ __forceinline__ void
 #pragma unroll
                         for (int q = 0; q < NR; ++q)
                             if (NR == 1 || rb + q < nrhs)
-                                ypart[(rb + q) * n + row] = y[q];
+                                glob(ypart)[(rb + q) * n + row] = y[q];
                     } else if (act) {
                         const int64_t dst = perm[row];
 #pragma unroll
                         for (int q = 0; q < NR; ++q)
                             if (NR == 1 || rb + q < nrhs) {
                                 if (io_f32)
-                                    static_cast<float *>(yout)[(rb + q) * ldy + dst] = float(y[q]);
+                                    glob(static_cast<float *>(yout))[(rb + q) * ldy + dst] = float(y[q]);
                                 else
-                                    static_cast<double *>(yout)[(rb + q) * ldy + dst] = y[q];
+                                    glob(static_cast<double *>(yout))[(rb + q) * ldy + dst] = y[q];
                             }
                     }
                 }

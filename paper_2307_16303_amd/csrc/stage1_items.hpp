@@ -83,28 +83,34 @@ struct S1Args {
     double *zp;
 };
 
+// item w of a level: (block, first column), one 8-byte global load
+__device__ __forceinline__ int2 item_of(const int2 *items, int64_t w) {
+    const uint64_t v = glob(reinterpret_cast<const uint64_t *>(items))[w];
+    return make_int2(int(uint32_t(v)), int(uint32_t(v >> 32)));
+}
+
 template <int S, int U, int DT, int NR>
 __device__ __forceinline__ void s1_wide_item(const S1Args &a, int64_t w) {
     using T = typename Fac<DT>::T;
     constexpr int NS = 64 / S;
-    const int2 item = a.items[w];
+    const int2 item = item_of(a.items, w);
     const int lane = threadIdx.x & 63;
     const int r = lane % S, sub = lane / S;
     const int b = item.x;
-    const int len = a.seg_len[b];
-    const int64_t off = a.seg_off[b];
-    const int64_t col0 = a.blk_col0[b];
-    const int k = a.rank[b];
-    const T *__restrict__ p = static_cast<const T *>(a.seg_ptr[b]);
+    const int len = glob(a.seg_len)[b];
+    const int64_t off = glob(a.seg_off)[b];
+    const int64_t col0 = glob(a.blk_col0)[b];
+    const int k = glob(a.rank)[b];
+    const T *__restrict__ p = static_cast<const T *>(glob(a.seg_ptr)[b]);
     double sc = 1.0;
     if (DT == H3D_BF16_SCALED)
-        sc = double(a.scale2[2 * b]) * double(a.scale2[2 * b + 1]);
+        sc = double(glob(a.scale2)[2 * b]) * double(glob(a.scale2)[2 * b + 1]);
     const int cend = min(item.y + a.span, k);
-    const double *__restrict__ xp = a.xp;
+    const auto xp = glob(a.xp);
     // rows of this item: a part of the column when columns are split
     int j0 = 0, j1 = len;
     if (a.part) {
-        j0 = a.part[w] * a.rows;
+        j0 = glob(a.part)[w] * a.rows;
         j1 = min(len, j0 + a.rows);
     }
     for (int rb = 0; rb < a.nrhs; rb += NR) {
@@ -159,12 +165,12 @@ __device__ __forceinline__ void s1_wide_item(const S1Args &a, int64_t w) {
                 for (int u = 0; u < U; ++u) {
                     const int c = cb + sub + u * NS;
                     if (a.part)  // one pass of span columns per item
-                        a.zp[w * int64_t(a.span) + (c - item.y)] = acc[u][0] * sc;
+                        glob(a.zp)[w * int64_t(a.span) + (c - item.y)] = acc[u][0] * sc;
                     else if (c < cend)
 #pragma unroll
                         for (int q = 0; q < NR; ++q)
                             if (NR == 1 || rb + q < a.nrhs)
-                                a.z[(rb + q) * a.ldz + col0 + c] = acc[u][q] * sc;
+                                glob(a.z)[(rb + q) * a.ldz + col0 + c] = acc[u][q] * sc;
                 }
             }
         }
@@ -174,24 +180,24 @@ __device__ __forceinline__ void s1_wide_item(const S1Args &a, int64_t w) {
 template <int S, int U, int DT, int NR>
 __device__ __forceinline__ void s1_packed_item(const S1Args &a, int64_t w) {
     using T = typename Fac<DT>::T;
-    const int2 item = a.items[w];
+    const int2 item = item_of(a.items, w);
     const int lane = threadIdx.x & 63;
     const int r = lane % S, sub = lane / S;
     const bool valid = sub < item.y;
     const int b = item.x + (valid ? sub : 0);
-    const int k = valid ? a.rank[b] : 0;
-    const int len = k > 0 ? a.seg_len[b] : 0;  // no rows, so no loads, without columns
-    const int64_t off = a.seg_off[b];
-    const int64_t col0 = a.blk_col0[b];
-    const T *__restrict__ p = static_cast<const T *>(a.seg_ptr[b]);
+    const int k = valid ? glob(a.rank)[b] : 0;
+    const int len = k > 0 ? glob(a.seg_len)[b] : 0;  // no rows, so no loads, without columns
+    const int64_t off = glob(a.seg_off)[b];
+    const int64_t col0 = glob(a.blk_col0)[b];
+    const T *__restrict__ p = static_cast<const T *>(glob(a.seg_ptr)[b]);
     double sc = 1.0;
     if (DT == H3D_BF16_SCALED)
-        sc = double(a.scale2[2 * b]) * double(a.scale2[2 * b + 1]);
+        sc = double(glob(a.scale2)[2 * b]) * double(glob(a.scale2)[2 * b + 1]);
     int kmax = k;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1)
         kmax = max(kmax, __shfl_xor(kmax, o, 64));
-    const double *__restrict__ xp = a.xp;
+    const auto xp = glob(a.xp);
     for (int rb = 0; rb < a.nrhs; rb += NR) {
         for (int cb = 0; cb < kmax; cb += U) {
             double acc[U][NR];
@@ -243,7 +249,7 @@ __device__ __forceinline__ void s1_packed_item(const S1Args &a, int64_t w) {
 #pragma unroll
                         for (int q = 0; q < NR; ++q)
                             if (NR == 1 || rb + q < a.nrhs)
-                                a.z[(rb + q) * a.ldz + col0 + cb + u] = acc[u][q] * sc;
+                                glob(a.z)[(rb + q) * a.ldz + col0 + cb + u] = acc[u][q] * sc;
             }
         }
     }
@@ -324,6 +330,26 @@ __device__ __forceinline__ void s1_panel_item(const S1Args &a, const int32_t *__
                             a.z[(rb + q) * a.ldz + col0 + cb + u] = acc[u][q] * sc;
         }
     }
+}
+
+// Split columns: column u of column group g of a level gets the sum of its
+// parts' partial sums, added in part order (grp[2 g] = the group's first item,
+// grp[2 g + 1] = its part count; one thread per (group, column)).
+__device__ __forceinline__ void s1_reduce_column(int64_t t, int64_t ngrp,
+                                                 const int32_t *__restrict__ grp,
+                                                 const S1Args &a) {
+    const int64_t g = t / a.span;
+    const int u = int(t - g * a.span);
+    if (g >= ngrp)
+        return;
+    const int32_t first = glob(grp)[2 * g], np = glob(grp)[2 * g + 1];
+    const int2 it = item_of(a.items, first);
+    if (it.y + u >= glob(a.rank)[it.x])
+        return;
+    double v = 0.0;
+    for (int32_t pp = 0; pp < np; ++pp)
+        v += glob(a.zp)[int64_t(first + pp) * a.span + u];
+    glob(a.z)[glob(a.blk_col0)[it.x] + it.y + u] = v;
 }
 
 }  // namespace dev

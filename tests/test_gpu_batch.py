@@ -9,6 +9,7 @@ checked against the CPU oracle's HODLR3D (same ACA decisions, summation order
 only) and against exact dense rows (compression error).
 """
 import ctypes
+import json
 
 import numpy as np
 import pytest
@@ -161,6 +162,49 @@ def test_batch_graph_replay(nrhs):
     g.close()
     bop.matvec(other)  # allowed once the graph is gone
     torch.cuda.synchronize()
+    bop.close()
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_batch_split_columns(dtype, tmp_path, monkeypatch):
+    """Stage-1 columns split into parts of 512 rows (summed by the batch's
+    reduction launch) on level 1 of two members, forced through the tuner's
+    cache: every problem bitwise equal to its own product, and against the
+    oracle (FP64 factors: same ACA decisions) or exact dense rows (FP32)."""
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("H3D_TUNE_CACHE", str(path))
+    clouds = [inputs.uniform_points(n, s) for n, s in [(20000, 13), (12000, 12), (3000, 11)]]
+    kw = dict(leaf_size=32, tol=1e-8, factor_dtype=dtype, **CUBE)
+    build_batch(clouds, **kw).close()
+    entries = json.loads(path.read_text())
+    forced = 0
+    for key, v in entries.items():
+        # key: arch|dt..|nr..|L..|batch|<half-octave of the mean box>:<of the
+        # mean rank> per level; level 1 of the two larger members holds boxes of
+        # 2,500 and 1,500 points (bucket 22 and 21), of the smallest 375 (17)
+        f = key.split("|")
+        if "nr1" in f and "batch" in f and int(f[f.index("batch") + 1].split(":")[0]) >= 19:
+            # level 1: the wide form, 64 lanes per column, 8 columns per pass,
+            # parts of 512 rows
+            v[2:7] = [0, 64, 8, 1, 512]
+            forced += 1
+    assert forced == 2, entries
+    path.write_text(json.dumps(entries))
+    bop = build_batch(clouds, **kw)
+    assert [p.stats()["tune_source"] for p in bop.plans[:2]] == [2, 2]
+    xs = [inputs.normal_rhs(len(c), seed=60 + i) for i, c in enumerate(clouds)]
+    ys = batch_apply(bop, xs)
+    for i, (x, y) in enumerate(zip(xs, ys)):
+        np.testing.assert_array_equal(y, solo_apply(bop.plans[i], x), err_msg=f"problem {i}")
+    for i in (0, 1):
+        if dtype == "fp64":
+            ref = oracle.HODLR3D(clouds[i], kernel="laplace", leaf_size=kw["leaf_size"],
+                                 tol=kw["tol"], box_lo=kw["box_lo"], box_side=kw["box_side"])
+            assert rel(ys[i], ref.matvec(xs[i])) <= 1e-13, i
+        rows = inputs.sample_rows(len(clouds[i]), 256, seed=5)
+        yd = oracle.dense_rows(clouds[i], xs[i], rows)
+        assert rel(ys[i][rows], yd) <= (10 * kw["tol"] if dtype == "fp64" else 1e-6), i
+    np.testing.assert_array_equal(batch_apply(bop, xs)[0], ys[0])  # reproducible
     bop.close()
 
 
