@@ -75,21 +75,21 @@ TRAFFIC = {
     "write_scale": 1.000000,
     "readings": [
         {"workload": "uniform262k", "factor_dtype": "fp64", "nrhs": 1,
-         "sources_sha256": "c26bd6a6f1da06e71dd99ed05899a4613ea90f77bba3e8beed6a11814197a7d3",
+         "sources_sha256": "7fb9ac2bbb872b53748b9f6619f5b3f5f274665bb061a16ef63b6383c4760929",
          "scope": "stream",
-         "kernels": {"k_stage2": {"fetch_kib": 10105433.125, "write_kib": 8198.9375},
-                     "k_s1_wide": {"fetch_kib": 2545312.3438, "write_kib": 35339.5156},
-                     "k_leaf": {"fetch_kib": 1854402.8125, "write_kib": 2839.5312}}},
+         "kernels": {"k_stage2": {"fetch_kib": 10105573.1875, "write_kib": 8198.0938},
+                     "k_s1_wide": {"fetch_kib": 2560271.7656, "write_kib": 35383.5391},
+                     "k_leaf": {"fetch_kib": 1903345.375, "write_kib": 2846.7188}}},
         # the headline: 64 right-hand sides on the matrix cores (per launch:
         # a level of stage 1 or stage 2; the finest level and the near field
         # are one launch group each)
         {"workload": "uniform1m", "factor_dtype": "fp32", "nrhs": 64,
-         "sources_sha256": "82c82b1751465f1c8d28a10b39401090af9781d06734c8617d804d758a3e134d",
+         "sources_sha256": "94aa1be0b3308796842464b78292afe58eada60ac25e350ca0b91cfa07d6e0ad",
          "scope": "all",
-         "kernels": {"k_s1_mfma": {"fetch_kib": 5705423.0156, "write_kib": 1019414.2344},
-                     "k_s2_mfma": {"fetch_kib": 5464061.9219, "write_kib": 524288.0625},
-                     "k_leaf_fused": {"fetch_kib": 16534871.125, "write_kib": 524288.5},
-                     "k_near_mfma": {"fetch_kib": 1073548.25, "write_kib": 524288.0}}},
+         "kernels": {"k_s1_mfma": {"fetch_kib": 5739502.875, "write_kib": 1019414.4062},
+                     "k_s2_mfma": {"fetch_kib": 5461342.0312, "write_kib": 524288.0},
+                     "k_leaf_fused": {"fetch_kib": 16546339.9375, "write_kib": 524288.0},
+                     "k_near_mfma": {"fetch_kib": 1068406.5625, "write_kib": 524288.125}}},
     ],
 }
 

@@ -218,8 +218,9 @@ h3d_status h3d_graph_destroy(h3d_graph *graph);
 /*
  * Multi-problem batching: independent operators, one per point cloud, all
  * with the same configuration, whose products run together: one launch per
- * phase of the product (gather, near field, stage 1 per launch shape,
- * stage 2), each over the work items of every problem.
+ * phase of the product (gather, near field, stage 1 per launch shape, the
+ * sums of split stage-1 columns, stage 2), each over the work items of every
+ * problem.
  *   nprob  : number of problems (>= 1).
  *   points : host array of nprob device pointers; points[i] is n[i] x 3
  *            FP64 row-major, read only during the call.
@@ -227,9 +228,9 @@ h3d_status h3d_graph_destroy(h3d_graph *graph);
  * cfg, alloc, hip_stream and the errors are those of h3d_build (a failure of
  * any problem fails the call and frees everything).  Every problem is built
  * as h3d_build builds it, tuned on its own factors unless
- * H3D_FLAG_NO_AUTOTUNE is set, except that it chooses among the forms the
- * batch launches carry: stage-1 shapes that keep whole columns, and the
- * finest level not fused.  *out receives the batch plan, which
+ * H3D_FLAG_NO_AUTOTUNE is set, except that its finest level is not fused
+ * (the batch launches do not carry that form).  *out receives the batch
+ * plan, which
  * accepts h3d_matvec_batch, h3d_batch_plan, h3d_batch_check, h3d_get_stats
  * (sums over the problems; depth and rank_max are maxima), the profiling
  * calls and h3d_destroy; other calls return H3D_EINVAL.

@@ -60,6 +60,8 @@ using namespace dev;
 
 constexpr int kGatherRows = 1024;  // rows per gather item
 constexpr int kReduceCols = 256;   // split-column sums per reduction item
+// workgroups per XCD chunk (xcd_chunks) of the stage-1 and stage-2 launches
+constexpr int kS1Chunk = 16, kS2Chunk = 8;
 
 // the stage-1 shapes the batch launches carry: every shape the tuner may
 // choose (a split shape runs the wide form's items over parts of columns,
@@ -136,7 +138,7 @@ template <int DT, int SHAPE>
 __global__ void __launch_bounds__(256)
     k_bs1(const BatchProb *__restrict__ probs, const BatchSeg *__restrict__ segs, int sb, int se,
           int64_t u0, int64_t units) {
-    const int64_t b = xcd_run(blockIdx.x, gridDim.x);
+    const int64_t b = xcd_chunks<kS1Chunk>(blockIdx.x, gridDim.x);
     const int64_t w = uniform64((b * blockDim.x + threadIdx.x) >> 6);
     if (w >= units)
         return;
@@ -171,7 +173,7 @@ __global__ void __launch_bounds__(64 * W)
     __attribute__((amdgpu_waves_per_eu(DT == H3D_F64 ? 4 : 1)))
     k_bs2(const BatchProb *__restrict__ probs, const BatchSeg *__restrict__ segs, int sb, int se,
           int64_t u0, int nprob, const void *const *__restrict__ io, int nrhs, int io_f32) {
-    const int64_t u = u0 + xcd_run(blockIdx.x, gridDim.x);
+    const int64_t u = u0 + xcd_chunks<kS2Chunk>(blockIdx.x, gridDim.x);
     const BatchSeg sg = seg_of(segs, sb, se, u);
     const BatchProb &D = probs[sg.prob];
     stage2_chunk<DT, 1, W>(u - sg.start, D.tab, D.leaf_off, D.leaf_of, D.grp_begin, nullptr,

@@ -19,6 +19,24 @@ __device__ __forceinline__ int64_t xcd_run(int64_t b, int64_t nwg) {
     return x * q + min(x, r) + (b >> 3);
 }
 
+// The grid dealt to the XCDs in chunks of C consecutive workgroups in turn
+// (chunk j to XCD j mod 8): where the cost of an item changes along the grid,
+// as over the problems of a batch, every XCD still gets an even share, and
+// neighbouring items still meet in one L2.  The workgroups past the last whole
+// round of 8 C chunks are split as by xcd_run; C = 0 is xcd_run itself.
+template <int C> __device__ __forceinline__ int64_t xcd_chunks(int64_t b, int64_t nwg) {
+    if constexpr (C == 0) {
+        return xcd_run(b, nwg);
+    } else {
+        const int64_t round = 8 * C, full = nwg / round;
+        if (b < full * round) {
+            const int64_t x = b & 7, k = b >> 3;  // the k-th workgroup of XCD x
+            return ((k / C) * 8 + x) * C + k % C;
+        }
+        return full * round + xcd_run(b - full * round, nwg - full * round);
+    }
+}
+
 // A load from a table that no wave writes during the kernel: through the
 // constant address space it stays a scalar load when the index is uniform,
 // also after the kernel's own global stores or atomics.
@@ -116,11 +134,11 @@ __device__ __forceinline__ float kernel_f32(int kind, float kp, float r2) {
 __device__ __forceinline__ void gather_row(const void *__restrict__ x, int io_f32, int64_t ldx,
                                            int64_t n, int nrhs, const int32_t *__restrict__ perm,
                                            double *__restrict__ xp, int64_t p) {
-    const int64_t src = perm[p];
+    const int64_t src = glob(perm)[p];
     for (int q = 0; q < nrhs; ++q) {
-        double v = io_f32 ? double(static_cast<const float *>(x)[q * ldx + src])
-                          : static_cast<const double *>(x)[q * ldx + src];
-        xp[q * n + p] = v;
+        double v = io_f32 ? double(glob(static_cast<const float *>(x))[q * ldx + src])
+                          : glob(static_cast<const double *>(x))[q * ldx + src];
+        glob(xp)[q * n + p] = v;
     }
 }
 
@@ -137,14 +155,19 @@ constexpr int kChunk = 128;
 // accumulated in FP64.  KIND >= 0 fixes the kernel at compile time (only its
 // formula is inlined into the loop); -1 takes `kind`.
 template <int NR, bool E32 = false, int KIND = -1>
-__device__ __forceinline__ void near_leaf(int64_t t, const int32_t *__restrict__ leaf_off,
-                                          const int32_t *__restrict__ near_ptr,
-                                          const int32_t *__restrict__ near_s,
-                                          const double *__restrict__ px,
-                                          const double *__restrict__ py,
-                                          const double *__restrict__ pz, int kind, double kp,
-                                          int nrhs, const double *__restrict__ xp, int64_t n,
-                                          double *__restrict__ yn) {
+__device__ __forceinline__ void near_leaf(int64_t t, const int32_t *__restrict__ leaf_off_,
+                                          const int32_t *__restrict__ near_ptr_,
+                                          const int32_t *__restrict__ near_s_,
+                                          const double *__restrict__ px_,
+                                          const double *__restrict__ py_,
+                                          const double *__restrict__ pz_, int kind, double kp,
+                                          int nrhs, const double *__restrict__ xp_, int64_t n,
+                                          double *__restrict__ yn_) {
+    // global-typed pointers (glob): the batch reads them from device memory
+    const auto leaf_off = glob(leaf_off_), near_ptr = glob(near_ptr_), near_s = glob(near_s_);
+    const auto px = glob(px_), py = glob(py_), pz = glob(pz_);
+    const auto xp = glob(xp_);
+    const auto yn = glob(yn_);
     __shared__ double sx[kChunk], sy[kChunk], sz[kChunk];
     __shared__ double sv[NR][kChunk];
     __shared__ int32_t sg[kChunk];        // sorted index of each staged source
