@@ -69,13 +69,15 @@ GATE = 1e-6
 # Counter readings, KiB per dispatch (a kernel launched once per level: the
 # mean over its dispatches of one product), with the copy-kernel scale of each
 # counter.  The runs that produced them are listed in profiles/;
-# sources_sha256 identifies the library sources they were taken on.
+# sources_sha256 identifies the code of the library sources they were taken
+# on (sources_digest: comments and layout left out, so that rewording a comment
+# keeps them; the compiled code of every source is the same either way).
 TRAFFIC = {
     "fetch_scale": 0.500016,
     "write_scale": 1.000000,
     "readings": [
         {"workload": "uniform262k", "factor_dtype": "fp64", "nrhs": 1,
-         "sources_sha256": "7fb9ac2bbb872b53748b9f6619f5b3f5f274665bb061a16ef63b6383c4760929",
+         "sources_sha256": "a0162748c17231bcc1d54d4578e5c26e8a87cea858efad8f47f54f7b3d5a9393",
          "scope": "stream",
          "kernels": {"k_stage2": {"fetch_kib": 10105573.1875, "write_kib": 8198.0938},
                      "k_s1_wide": {"fetch_kib": 2560271.7656, "write_kib": 35383.5391},
@@ -84,7 +86,7 @@ TRAFFIC = {
         # a level of stage 1 or stage 2; the finest level and the near field
         # are one launch group each)
         {"workload": "uniform1m", "factor_dtype": "fp32", "nrhs": 64,
-         "sources_sha256": "94aa1be0b3308796842464b78292afe58eada60ac25e350ca0b91cfa07d6e0ad",
+         "sources_sha256": "d8b3039b713dff9d9fde327c3721087beba4c3bbc1168c8a8e68087c9b5a4d85",
          "scope": "all",
          "kernels": {"k_s1_mfma": {"fetch_kib": 5739502.875, "write_kib": 1019414.4062},
                      "k_s2_mfma": {"fetch_kib": 5461342.0312, "write_kib": 524288.0},
@@ -99,17 +101,59 @@ TRAFFIC = {
 OTHER_PATHS = ("batched.hip", "batch.hip", "truncate.hip", "leaf.hip")
 
 
+def code_only(text: str) -> str:
+    """C/C++ text without its comments, with each run of blanks outside string
+    and character literals made one space, lines trimmed and empty lines left
+    out: the code alone, so that a reading stays keyed to the code it was taken
+    on, not to the wording or layout of its comments."""
+    out, i, n = [], 0, len(text)
+
+    def blank():
+        if out and out[-1] not in " \n":
+            out.append(" ")
+
+    while i < n:
+        c = text[i]
+        if text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            blank()
+            i = n if j < 0 else j + 2
+        elif c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif c in " \t\r\f\v":
+            blank()
+            i += 1
+        elif c == "\n":
+            if out and out[-1] == " ":
+                out.pop()
+            if out and out[-1] != "\n":
+                out.append("\n")
+            i += 1
+        else:
+            out.append(c)
+            i += 1
+    return "".join(out).strip()
+
+
 def sources_digest(scope: str = "all") -> str:
-    """sha256, in name order, over the library sources and header.  scope
-    'stream': without the files of kernels launched on their own."""
+    """sha256, in name order, over the code (code_only) of the library sources
+    and header.  scope 'stream': without the files of kernels launched on their
+    own."""
     h = hashlib.sha256()
     files = sorted(f for f in glob.glob(os.path.join(ROOT, "paper_2307_16303_amd", "csrc", "*"))
                    if scope != "stream" or os.path.basename(f) not in OTHER_PATHS)
     files.append(os.path.join(ROOT, "include", "hodlr3d.h"))
     for f in files:
         h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            h.update(code_only(fh.read()).encode())
     return h.hexdigest()
 
 

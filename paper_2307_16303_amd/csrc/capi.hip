@@ -180,8 +180,8 @@ h3d_status check_config(const h3d_config *cfg, const h3d_allocator *alloc) {
 }
 
 // Builds one operator (throws h3d::Error).  A member of a batch is tuned as
-// well, among the forms the batch launches carry (whole-column stage-1
-// shapes, the finest level not fused).
+// well, among the forms the batch launches carry (every stage-1 shape; the
+// finest level not fused).
 h3d_plan *build_plan(const double *points, int64_t n, const h3d_config &cfg,
                      const h3d_allocator *alloc, hipStream_t s, bool in_batch) {
     const auto t0 = std::chrono::steady_clock::now();
