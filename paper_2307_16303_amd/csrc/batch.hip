@@ -143,9 +143,10 @@ __global__ void __launch_bounds__(256)
     if (w >= units)
         return;
     const BatchSeg sg = seg_of(segs, sb, se, u0 + w);
-    // a copy, loaded before the item's first store: its fields stay in scalar
-    // registers as a kernel argument's do (read through a reference they were
-    // vector loads at each use, 25-40 more registers, one or two fewer waves)
+    // the level's arguments, read once with scalar loads; the item code reads
+    // through their pointers with global (not flat) instructions (glob), which
+    // gives this kernel the registers of the single-problem k_s1_wide and
+    // k_s1_packed
     const S1Args a = probs[sg.prob].s1[sg.level];
     const int64_t i = u0 + w - sg.start;
     constexpr ShapeDef sh = kShapes[SHAPE];
