@@ -78,3 +78,37 @@ def test_more_than_one_gpu_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", ["scan", "tree", "stage2_ring"])
+def test_code_only_keeps_the_compiled_code(name, tmp_path):
+    """A library source and its code_only text compile to the same gfx950
+    device code (symbol names derived from the file path aside)."""
+    import re
+    import shutil
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    if not shutil.which(hipcc):
+        pytest.skip("hipcc not found")
+    csrc = os.path.join(bench.ROOT, "paper_2307_16303_amd", "csrc")
+    (tmp_path / "include").mkdir()
+    (tmp_path / "pk" / "csrc").mkdir(parents=True)
+    with open(os.path.join(bench.ROOT, "include", "hodlr3d.h")) as f:
+        (tmp_path / "include" / "hodlr3d.h").write_text(bench.code_only(f.read()) + "\n")
+    for fn in os.listdir(csrc):
+        with open(os.path.join(csrc, fn)) as f:
+            (tmp_path / "pk" / "csrc" / fn).write_text(bench.code_only(f.read()) + "\n")
+
+    def asm(src, out):
+        cmd = [hipcc, "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Xclang",
+               "-target-feature", "-Xclang", "-packed-fp32-ops",
+               "-Wno-unused-command-line-argument", "--cuda-device-only", "-S", "-o", str(out), src]
+        subprocess.run(cmd, check=True, capture_output=True, timeout=600)
+        keep = [ln for ln in out.read_text().split("\n")
+                if not re.match(r"\s*(\.file|\.ident|;)", ln)]
+        return re.sub(r"__hip_(cuid|gpubin_handle|fatbin)_[0-9a-f]+", "X", "\n".join(keep))
+
+    a = asm(os.path.join(csrc, name + ".hip"), tmp_path / "a.s")
+    b = asm(str(tmp_path / "pk" / "csrc" / (name + ".hip")), tmp_path / "b.s")
+    assert "s_endpgm" in a
+    assert a == b
